@@ -1,0 +1,211 @@
+/*
+ * nesa.h -- C ABI of the MI355X NESA EFIE library.
+ *
+ * The library builds, once, the nested equivalent source approximation (NESA)
+ * of the Galerkin EFIE matrix of a closed PEC surface meshed with triangles,
+ * and applies it on one GPU (gfx950) at every iteration of a GMRES solve.
+ * Operation names follow the paper (Zafari et al., "Task parallel
+ * implementation of a solver for electromagnetic scattering problems"):
+ *
+ *   Sec. 2, Eq. (1)-(3)   EFIE, Galerkin testing, dense system Z j = b
+ *   Sec. 2, Eq. (4)-(7)   Z_far ~ U B..B D C..C V over an oct-tree
+ *   Sec. 3, Eq. (9)       near-field product
+ *   Sec. 3, Eq. (10)-(14) radiation, source transfer, translation,
+ *                         potential transfer, reception
+ *   Sec. 2 / Sec. 4       the product is applied many times inside an
+ *                         iterative solver while the structure is built once
+ *
+ * Conventions
+ *   - Lengths are in wavelengths; k = 2 pi; eta = 376.730313668 ohm.
+ *   - Unknowns are RWG functions on the interior edges of the mesh, numbered in
+ *     increasing (min vertex, max vertex) order ("canonical order"); the plus
+ *     triangle of an edge is the lower-index one.
+ *   - Complex vectors are interleaved (re, im) pairs: complex128 (double2) in
+ *     NESA_C128 mode, complex64 (float2) otherwise.  Vectors of several
+ *     right-hand sides are stored RHS-major: x[r * n + i].
+ *   - Pointers named *_dev are device pointers on the current HIP device;
+ *     the caller owns them.  Handles are owned by the library and released
+ *     with the matching *_free call.  `stream` is a hipStream_t (NULL = the
+ *     default stream); calls enqueue work on it and return without waiting,
+ *     except where stated.
+ *   - Every call returns a nesa_status; on failure nesa_last_error() gives a
+ *     message (thread-local).  No exception crosses the ABI.
+ */
+#ifndef NESA_H
+#define NESA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NESA_OK = 0,
+  NESA_EINVAL = -1,      /* bad argument (null pointer, size, parameter) */
+  NESA_ENOMEM = -2,      /* host or device allocation failed */
+  NESA_EHIP = -3,        /* a HIP runtime call failed */
+  NESA_EMESH = -4,       /* mesh is not a closed 2-manifold, or too coarse */
+  NESA_ENOCONV = -5,     /* GMRES stopped at max_iters above tolerance */
+  NESA_EBREAKDOWN = -6,  /* non-finite value in the solver */
+  NESA_ENOTIMPL = -7
+} nesa_status;
+
+typedef enum {
+  NESA_C128 = 0,         /* complex FP64 storage and arithmetic */
+  NESA_C64 = 1,          /* complex FP32 storage and arithmetic */
+  NESA_C64_SPLIT = 2     /* complex FP32 vectors; translation and aggregation
+                            contractions as split-bf16 (hi*hi + hi*lo + lo*hi)
+                            matrix-core products with FP32 accumulation */
+} nesa_precision;
+
+typedef struct nesa_tree nesa_tree;
+typedef struct nesa_near nesa_near;
+typedef struct nesa_far nesa_far;
+typedef struct nesa_op nesa_op;
+
+/* Oct-tree parameters (Sec. 2 partition, Sec. 3 level rules).
+ *   leaf_size: leaf box side in wavelengths (> 0); L = ceil(log2(longest
+ *     bounding-box side / leaf_size)), root cube anchored 1e-9 below the
+ *     vertex bounding-box minimum.
+ *   l0_max: coarsest far level is min(l0_max, L) (2 = four boxes along the
+ *     root side).
+ *   buffer: near boxes are those at Chebyshev index distance <= buffer
+ *     (1 = adjacent boxes including diagonal ones and the box itself). */
+typedef struct {
+  double leaf_size;
+  int l0_max;
+  int buffer;
+} nesa_tree_params;
+
+/* Medium: wavenumber k and impedance eta (Sec. 2, Eq. 1). */
+typedef struct {
+  double k;
+  double eta;
+} nesa_em_params;
+
+/* Far-field operator construction (Sec. 2, Eq. 4-7: equivalence on
+ * fictitious spheres around the boxes).
+ *   d0: accuracy digits of the per-level equivalent-source count
+ *     Q_l = (ceil(kr + 1.8 d0^(2/3) (kr)^(1/3)) + 1)^2, r = (sqrt3/2) a_l.
+ *   q_min: lower bound on Q_l (0 = none).
+ *   tau: Tikhonov parameter of the fitting operator, relative to the largest
+ *     singular value of G(check points, equivalent points). */
+typedef struct {
+  int d0;
+  int q_min;
+  double tau;
+} nesa_far_params;
+
+typedef struct {
+  int64_t n_rwg;
+  int64_t n_tri;
+  int L;                 /* leaf level */
+  int l0;                /* coarsest far level */
+  int64_t n_box[32];     /* boxes at level l0 + i, i = 0 .. L - l0 */
+  int64_t near_entries;  /* stored near-field matrix entries */
+  int64_t n_pairs[32];   /* translation pairs at level l0 + i */
+  int Q[32];             /* equivalent sources per box at level l0 + i
+                            (0 until nesa_assemble_translations) */
+} nesa_tree_info;
+
+/* Build the RWG basis and the oct-tree of a closed triangle mesh.
+ *   verts: host [nv][3] doubles (wavelengths); tris: host [nt][3] int32,
+ *   vertex ids; orientation is irrelevant.  Returns NESA_EMESH if an edge is
+ *   not shared by exactly two triangles.  Host-only; copies its inputs. */
+int nesa_build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
+                    const nesa_tree_params* params, nesa_tree** out);
+int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info);
+/* perm[i] = canonical RWG index of leaf-order position i (host [n_rwg]). */
+int nesa_tree_perm(const nesa_tree* tree, int64_t* perm);
+void nesa_tree_free(nesa_tree* tree);
+
+/* Near-field Galerkin blocks Z_ab, b in the near list of leaf a (Sec. 2;
+ * Sec. 3, Eq. 9), computed on the host with the 3-point triangle rule and
+ * closed-form static singular integrals for triangle pairs that share a
+ * vertex (mean of both integration orders, so Z = Z^T).  Host-only. */
+int nesa_assemble_near(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out);
+/* Copy the entries Z[rows[i]][cols[j]] (canonical indices, both RWGs in near
+ * leaves) into host out[i * ncols + j] (complex128); missing entries -> 0. */
+int nesa_near_entries(const nesa_tree* tree, const nesa_near* near, const int64_t* rows,
+                      int64_t nrows, const int64_t* cols, int64_t ncols, double* out);
+void nesa_near_free(nesa_near* near);
+
+/* Radiation V, transfer C (and B = C^T), translation D (Sec. 2, Eq. 4-7;
+ * U = V^T).  Host-only. */
+int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em,
+                               const nesa_far_params* params, nesa_far** out);
+/* Q of every level l0..L into Q[0 .. nmax-1]. */
+int nesa_far_get_q(const nesa_far* far, int* Q, int nmax);
+void nesa_far_free(nesa_far* far);
+
+/* Upload near and far operators to the current device in the given precision
+ * and allocate work buffers for up to max_nrhs right-hand sides. */
+int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far* far,
+                   int precision, int max_nrhs, nesa_op** out);
+void nesa_op_free(nesa_op* op);
+
+/* y = Z_NESA x for nrhs right-hand sides (1 <= nrhs <= max_nrhs), x and y in
+ * canonical order, RHS-major.  Applies the near-field product (Eq. 9) and the
+ * five far-field stages (Eq. 10-14) with GPU kernels on `stream`. */
+int nesa_matvec(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream);
+
+/* Same product in leaf order (no permutation), for callers that keep their
+ * vectors in the order of nesa_tree_perm. */
+int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream);
+
+/* One product (nrhs = 1, leaf order) with hipEvents recorded between the
+ * stages on `stream`; blocks, then writes the elapsed milliseconds of
+ * ms[0] radiation (Eq. 10), ms[1] source transfer (Eq. 11), ms[2] translation
+ * (Eq. 12), ms[3] potential transfer (Eq. 13), ms[4] near field + reception
+ * (Eq. 9, 14). */
+int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms);
+
+/* Plane-wave right-hand sides b_m = -<e_inc, phi_m> (Sec. 2, Eq. 2),
+ * e_inc = pol exp(-i k khat.r); khat, pol: host [nrhs][3].  Writes device b
+ * in canonical order, RHS-major, in the op's vector precision. */
+int nesa_rhs_plane_wave(nesa_op* op, const double* khat, const double* pol, int64_t nrhs,
+                        void* b_dev, void* stream);
+
+/* Host version of the right-hand side: b (host, complex128 interleaved,
+ * [nrhs][n_rwg], canonical order). */
+int nesa_rhs_plane_wave_host(const nesa_tree* tree, double k, const double* khat, const double* pol,
+                             int64_t nrhs, double* b);
+
+typedef enum { NESA_PRECOND_NONE = 0, NESA_PRECOND_BLOCKDIAG = 1, NESA_PRECOND_LEARNED = 2 } nesa_precond;
+
+/* Restarted GMRES(m) (flexible when a preconditioner is used) around the
+ * NESA product: Arnoldi with two passes of classical Gram-Schmidt, FP64 dot
+ * products, norms, Hessenberg matrix and Givens rotations; stop when the
+ * estimated relative residual <= tol, confirmed by the true residual
+ * ||b - Z_NESA x|| / ||b|| recomputed at every restart and at exit. */
+typedef struct {
+  int restart;           /* m */
+  int max_iters;
+  double tol;
+  int precond;           /* nesa_precond */
+} nesa_gmres_params;
+
+typedef struct {
+  int iters;
+  int restarts;
+  double true_rel_residual;
+  double seconds;
+  int fell_back;         /* learned preconditioner replaced by block-diagonal */
+} nesa_gmres_report;
+
+/* Solve Z_NESA x = b for nrhs right-hand sides (each its own Krylov space).
+ * b_dev, x_dev: canonical order, RHS-major; x_dev holds x0 on entry.
+ * history (host, nullable): estimated relative residual after each iteration
+ * of RHS 0, up to history_len values.  Blocks until the solve ends. */
+int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,
+                     const nesa_gmres_params* params, nesa_gmres_report* report,
+                     double* history, int64_t history_len, void* stream);
+
+const char* nesa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NESA_H */

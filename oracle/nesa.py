@@ -21,7 +21,8 @@ the groups, with auxiliary sources on spheres in 3D.  Reading taken here:
   (excess-bandwidth count);
 * r_e at the leaf level = 1.02 x the largest distance from a leaf centre to a
   quadrature point of its RWGs; r_e one level up = 1.02 x (child-centre offset
-  + child r_e); r_c = a_l (midway between r_e and 2 a_l - r_e);
+  + child r_e); r_c = a_l (midway between r_e and 2 a_l - r_e), raised to
+  1.05 r_e where the mesh is too coarse for r_e < a_l / 1.05;
 * fitting operator R_l = Tikhonov pseudo-inverse of G(X, E) with
   lambda = tau * sigma_max:  R = V diag(s/(s^2 + lambda^2)) U^H from the SVD;
 * V^c_b = R_L G^c_src (field of each RWG channel density at the check points),
@@ -94,11 +95,11 @@ class NesaOracle:
         self.re = {t.L: 1.02 * rmax}
         for l in range(t.L - 1, t.l0 - 1, -1):
             self.re[l] = 1.02 * (math.sqrt(3.0) / 2.0 * t.side(l + 1) + self.re[l + 1])
-        self.rc = {l: t.side(l) for l in self.levels}
+        self.rc = {l: max(t.side(l), 1.05 * self.re[l]) for l in self.levels}
         for l in self.levels:
-            if self.re[l] >= self.rc[l]:
-                raise ValueError("equivalent sphere does not fit inside the check sphere "
-                                 "at level %d (mesh too coarse for this leaf size)" % l)
+            if self.re[l] >= 1.5 * t.side(l):
+                raise ValueError("equivalent sphere radius exceeds 1.5 box sides at level %d "
+                                 "(mesh too coarse for this leaf size)" % l)
         self.E = {l: self.re[l] * fibonacci_sphere(self.Q[l]) for l in self.levels}
         self.X = {l: self.rc[l] * fibonacci_sphere(4 * self.Q[l]) for l in self.levels}
         self.R = {l: tikhonov_pinv(gmat(self.X[l], self.E[l], k), tau) for l in self.levels}

@@ -1,0 +1,681 @@
+// C ABI of the NESA library (declared in include/nesa.h): handle management,
+// device upload of the operators, the matvec driver and the GMRES driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nesa.h"
+#include "kernels.h"
+#include "nesa_host.h"
+
+using nesa::cd;
+using nesa::Error;
+
+struct nesa_tree {
+  std::unique_ptr<nesa::Tree> t;
+};
+struct nesa_near {
+  std::unique_ptr<nesa::Near> n;
+};
+struct nesa_far {
+  std::unique_ptr<nesa::Far> f;
+};
+
+struct nesa_op {
+  int precision = NESA_C64;
+  int max_nrhs = 1;
+  double k = 0, eta = 0;
+  nesa::Tree geo;                       // copy of the RWG geometry (right-hand sides)
+  nesa::DevOp<float> f;
+  nesa::DevOp<double> d;
+  std::vector<void*> allocs;
+  void* xl = nullptr;                   // leaf-order work vectors
+  void* yl = nullptr;
+  size_t esize = 8;                     // bytes per complex element
+  ~nesa_op() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+template <class F>
+static int guarded(F&& fn) {
+  try {
+    return fn();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(NESA_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(NESA_EINVAL, e.what());
+  }
+}
+
+static void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw Error(NESA_ENOMEM, std::string(what) + ": out of device memory");
+    throw Error(NESA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+template <typename X>
+static X* upload(nesa_op* op, const std::vector<X>& h) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(sizeof(X), h.size() * sizeof(X));
+  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  op->allocs.push_back(p);
+  if (!h.empty()) hip_check(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice), "hipMemcpy");
+  return static_cast<X*>(p);
+}
+
+static void* dev_alloc(nesa_op* op, size_t bytes) {
+  void* p = nullptr;
+  hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
+  op->allocs.push_back(p);
+  return p;
+}
+
+template <typename T>
+static void* upload_complex(nesa_op* op, const std::vector<cd>& h) {
+  std::vector<T> buf(2 * h.size());
+  for (size_t i = 0; i < h.size(); ++i) {
+    buf[2 * i] = (T)h[i].real();
+    buf[2 * i + 1] = (T)h[i].imag();
+  }
+  return upload(op, buf);
+}
+
+static std::vector<int32_t> to_i32(const std::vector<int64_t>& v) {
+  std::vector<int32_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (v[i] > INT32_MAX || v[i] < INT32_MIN) throw Error(NESA_EINVAL, "index exceeds 32 bits");
+    o[i] = (int32_t)v[i];
+  }
+  return o;
+}
+
+// Inverse of a dense complex matrix (column-major), Gauss-Jordan with partial pivoting.
+static void invert(std::vector<cd>& A, int64_t S) {
+  std::vector<cd> I(S * S, cd(0, 0));
+  for (int64_t i = 0; i < S; ++i) I[i * S + i] = 1.0;
+  for (int64_t c = 0; c < S; ++c) {
+    int64_t piv = c;
+    for (int64_t r = c + 1; r < S; ++r)
+      if (std::abs(A[c * S + r]) > std::abs(A[c * S + piv])) piv = r;
+    if (std::abs(A[c * S + piv]) == 0) throw Error(NESA_EINVAL, "singular near-field self block");
+    if (piv != c)
+      for (int64_t j = 0; j < S; ++j) {
+        std::swap(A[j * S + c], A[j * S + piv]);
+        std::swap(I[j * S + c], I[j * S + piv]);
+      }
+    cd inv = 1.0 / A[c * S + c];
+    for (int64_t j = 0; j < S; ++j) {
+      A[j * S + c] *= inv;
+      I[j * S + c] *= inv;
+    }
+    for (int64_t r = 0; r < S; ++r) {
+      if (r == c) continue;
+      cd f = A[c * S + r];
+      if (f == cd(0, 0)) continue;
+      for (int64_t j = 0; j < S; ++j) {
+        A[j * S + r] -= f * A[j * S + c];
+        I[j * S + r] -= f * I[j * S + c];
+      }
+    }
+  }
+  A.swap(I);
+}
+
+template <typename T>
+static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const nesa::Near& nr,
+                      const nesa::Far& fr) {
+  const auto& LL = t.level(t.L);
+  d.n = t.rwg.n;
+  d.nleaf = LL.nbox;
+  d.L = t.L;
+  d.l0 = t.l0;
+  const int QL = fr.lev[t.L - t.l0].Q;
+  // limits of the kernels' fixed shapes
+  int64_t smax = 0;
+  for (int64_t b = 0; b < d.nleaf; ++b) smax = std::max(smax, t.leaf_ptr[b + 1] - t.leaf_ptr[b]);
+  if (smax > 256) throw Error(NESA_EINVAL, "a leaf holds more than 256 RWGs; use a smaller leaf size");
+  if (QL > 128) throw Error(NESA_EINVAL, "more than 128 equivalent sources per leaf");
+  for (const auto& fl : fr.lev)
+    if (fl.Q > 512) throw Error(NESA_EINVAL, "more than 512 equivalent sources per box");
+  for (int64_t b = 0; b < d.nleaf; ++b)
+    if (t.near_ptr[b + 1] - t.near_ptr[b] > 128) throw Error(NESA_EINVAL, "near list longer than 128");
+  d.perm = upload(op, to_i32(t.perm));
+  d.leaf_ptr = upload(op, to_i32(t.leaf_ptr));
+  d.near_ptr = upload(op, to_i32(t.near_ptr));
+  d.near_idx = upload(op, to_i32(t.near_idx));
+  d.zoff = upload(op, nr.off);
+  d.Z = upload_complex<T>(op, nr.z);
+  d.V = upload_complex<T>(op, fr.V);
+  d.w[0] = 0.0;
+  d.w[1] = -fr.eta * fr.k;
+  d.w[2] = 0.0;
+  d.w[3] = fr.eta / fr.k;
+  d.lev.resize(t.L - t.l0 + 1);
+  int64_t soff = 0;
+  for (int l = t.l0; l <= t.L; ++l) {
+    const nesa::Level& lv = t.level(l);
+    const nesa::FarLevel& fl = fr.lev[l - t.l0];
+    nesa::DevLevel& dl = d.lev[l - t.l0];
+    dl.Q = fl.Q;
+    dl.nbox = lv.nbox;
+    dl.s_off = soff;
+    soff += lv.nbox * 4 * fl.Q;
+    dl.npairs = (int64_t)lv.il_src.size();
+    // compact translation table
+    std::vector<int32_t> compact(t.nslot(), -1);
+    std::vector<cd> Dc;
+    int nused = 0;
+    for (int s = 0; s < t.nslot(); ++s) {
+      if (!fl.slot_used[s]) continue;
+      compact[s] = nused++;
+      const cd* Ds = &fl.D[(size_t)s * fl.Q * fl.Q];
+      for (int q = 0; q < fl.Q; ++q)
+        for (int p = 0; p < fl.Q; ++p) Dc.push_back(Ds[(size_t)p * fl.Q + q]);
+    }
+    dl.D = upload_complex<T>(op, Dc);
+    std::vector<int32_t> slot(lv.il_slot.size());
+    for (size_t i = 0; i < slot.size(); ++i) slot[i] = compact[lv.il_slot[i]];
+    dl.il_slot = upload(op, slot);
+    dl.il_ptr = upload(op, to_i32(lv.il_ptr));
+    dl.il_src = upload(op, to_i32(lv.il_src));
+    if (l < t.L) dl.child_ptr = upload(op, to_i32(lv.child_ptr));
+    if (l > t.l0) {
+      dl.parent = upload(op, to_i32(lv.parent));
+      dl.octant = upload(op, lv.octant);
+      const int Qp = fr.lev[l - 1 - t.l0].Q, Qc = fl.Q;
+      std::vector<cd> ccm((size_t)8 * Qp * Qc);
+      for (int o = 0; o < 8; ++o)
+        for (int p = 0; p < Qp; ++p)
+          for (int q = 0; q < Qc; ++q)
+            ccm[((size_t)o * Qc + q) * Qp + p] = fl.Cup[((size_t)o * Qp + p) * Qc + q];
+      dl.Ccm = upload_complex<T>(op, ccm);
+      dl.Crm = upload_complex<T>(op, fl.Cup);
+    }
+  }
+  d.s = dev_alloc(op, (size_t)soff * 2 * sizeof(T));
+  d.o = dev_alloc(op, (size_t)soff * 2 * sizeof(T));
+  // block-diagonal preconditioner: inverses of the self blocks
+  std::vector<int64_t> moff(d.nleaf + 1, 0);
+  for (int64_t a = 0; a < d.nleaf; ++a) {
+    int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+    moff[a + 1] = moff[a] + S * S;
+  }
+  std::vector<cd> minv(moff[d.nleaf]);
+  nesa::parallel_for(d.nleaf, [&](int64_t a) {
+    const int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+    int64_t col0 = 0;
+    for (int64_t j = t.near_ptr[a]; j < t.near_ptr[a + 1]; ++j) {
+      int64_t b = t.near_idx[j];
+      if (b == a) break;
+      col0 += t.leaf_ptr[b + 1] - t.leaf_ptr[b];
+    }
+    std::vector<cd> A(S * S);
+    const cd* Z = &nr.z[nr.off[a]];
+    for (int64_t c = 0; c < S; ++c)
+      for (int64_t r = 0; r < S; ++r) A[c * S + r] = Z[(col0 + c) * S + r];
+    invert(A, S);
+    std::copy(A.begin(), A.end(), minv.begin() + moff[a]);
+  });
+  d.Minv = upload_complex<T>(op, minv);
+  d.moff = upload(op, moff);
+  op->xl = dev_alloc(op, (size_t)d.n * 2 * sizeof(T));
+  op->yl = dev_alloc(op, (size_t)d.n * 2 * sizeof(T));
+}
+
+// ------------------------------------------------------------------ GMRES driver
+template <typename T>
+static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c, const nesa_gmres_params& prm,
+                     nesa_gmres_report& rep, double* history, int64_t hist_len, hipStream_t st) {
+  const int64_t n = d.n;
+  const int m = prm.restart;
+  const size_t es = 2 * sizeof(T);
+  auto t0 = std::chrono::steady_clock::now();
+  const bool flex = prm.precond != NESA_PRECOND_NONE;
+  std::vector<void*> mine;
+  auto alloc = [&](size_t bytes) {
+    void* p = nullptr;
+    hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
+    mine.push_back(p);
+    return p;
+  };
+  struct Free {
+    std::vector<void*>& v;
+    double2* host;
+    ~Free() {
+      for (void* p : v) (void)hipFree(p);
+      if (host) (void)hipHostFree(host);
+    }
+  };
+  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  char* Vb = static_cast<char*>(alloc((size_t)(m + 1) * n * es));
+  char* Zb = flex ? static_cast<char*>(alloc((size_t)m * n * es)) : nullptr;
+  void* bl = alloc(n * es);
+  void* xl = alloc(n * es);
+  void* w = alloc(n * es);
+  void* tmp = alloc(n * es);
+  double2* hd = static_cast<double2*>(alloc(sizeof(double2) * (2 * (m + 2) + 2)));
+  double2* partial = static_cast<double2*>(alloc(sizeof(double2) * nblocks * (m + 2)));
+  double2* hh = nullptr;
+  hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * (2 * (m + 2) + 2)), "hipHostMalloc");
+  Free guard{mine, hh};
+  auto vec = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
+  auto matvec = [&](const void* src, void* dst) { nesa::launch_matvec_leaf<T>(d, src, dst, st, nullptr); };
+  auto norm = [&](const void* v) {
+    nesa::launch_multidot<T>(v, n, 1, v, n, partial, nblocks, hd, 0, st);
+    hip_check(hipMemcpyAsync(hh, hd, sizeof(double2), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return std::sqrt(std::max(0.0, hh[0].x));
+  };
+  auto precond = [&](const void* r, void* z) {
+    if (prm.precond == NESA_PRECOND_BLOCKDIAG || prm.precond == NESA_PRECOND_LEARNED) {
+      nesa::launch_blockdiag<T>(d, r, z, st);
+    } else {
+      hip_check(hipMemcpyAsync(z, r, n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    }
+  };
+  nesa::launch_gather<T>(b_c, bl, d.perm, n, st);
+  nesa::launch_gather<T>(x_c, xl, d.perm, n, st);
+  const double nb = norm(bl);
+  rep = nesa_gmres_report{0, 0, 0.0, 0.0, 0};
+  if (nb == 0) {
+    hip_check(hipMemsetAsync(x_c, 0, n * es, st), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return NESA_OK;
+  }
+  int64_t nh = 0;
+  auto push_hist = [&](double v) {
+    if (history && nh < hist_len) history[nh] = v;
+    ++nh;
+  };
+  matvec(xl, tmp);
+  nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
+  double beta = norm(vec(Vb, 0));
+  push_hist(beta / nb);
+  int iters = 0;
+  std::vector<cd> H((size_t)(m + 1) * m), g(m + 1), sn(m);
+  std::vector<double> cs(m);
+  int status = NESA_OK;
+  while (beta / nb > prm.tol && iters < prm.max_iters) {
+    rep.restarts++;
+    nesa::launch_scale<T>(vec(Vb, 0), vec(Vb, 0), n, 1.0 / beta, st);
+    std::fill(H.begin(), H.end(), cd(0, 0));
+    std::fill(g.begin(), g.end(), cd(0, 0));
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      const void* src = vec(Vb, j);
+      if (flex) {
+        precond(vec(Vb, j), vec(Zb, j));
+        src = vec(Zb, j);
+      }
+      matvec(src, w);
+      // two passes of classical Gram-Schmidt, FP64 dot products
+      nesa::launch_multidot<T>(Vb, n, j + 1, w, n, partial, nblocks, hd, 0, st);
+      nesa::launch_combine<T>(Vb, n, j + 1, hd, w, n, -1.0, st);
+      nesa::launch_multidot<T>(Vb, n, j + 1, w, n, partial, nblocks, hd + (m + 2), 0, st);
+      nesa::launch_combine<T>(Vb, n, j + 1, hd + (m + 2), w, n, -1.0, st);
+      nesa::launch_multidot<T>(w, n, 1, w, n, partial, nblocks, hd + 2 * (m + 2), 0, st);
+      hip_check(hipMemcpyAsync(hh, hd, sizeof(double2) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, st),
+                "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      for (int i = 0; i <= j; ++i)
+        H[(size_t)j * (m + 1) + i] = cd(hh[i].x + hh[m + 2 + i].x, hh[i].y + hh[m + 2 + i].y);
+      const double hn = std::sqrt(std::max(0.0, hh[2 * (m + 2)].x));
+      if (!std::isfinite(hn)) {
+        status = fail(NESA_EBREAKDOWN, "non-finite value in GMRES");
+        break;
+      }
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      cd* Hj = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i < j; ++i) {
+        cd t0v = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+        Hj[i + 1] = -std::conj(sn[i]) * Hj[i] + cs[i] * Hj[i + 1];
+        Hj[i] = t0v;
+      }
+      cd a = Hj[j], bb = Hj[j + 1];
+      double c;
+      cd s, r;
+      if (bb == cd(0, 0)) {
+        c = 1;
+        s = 0;
+        r = a;
+      } else if (a == cd(0, 0)) {
+        c = 0;
+        s = 1;
+        r = bb;
+      } else {
+        double rho = std::hypot(std::abs(a), std::abs(bb));
+        c = std::abs(a) / rho;
+        s = a * std::conj(bb) / (std::abs(a) * rho);
+        r = a * rho / std::abs(a);
+      }
+      cs[j] = c;
+      sn[j] = s;
+      Hj[j] = r;
+      Hj[j + 1] = 0;
+      g[j + 1] = -std::conj(s) * g[j];
+      g[j] = c * g[j];
+      ++iters;
+      k = j + 1;
+      push_hist(std::abs(g[j + 1]) / nb);
+      if (std::abs(g[j + 1]) / nb <= prm.tol || iters >= prm.max_iters || hn == 0) break;
+      nesa::launch_scale<T>(w, vec(Vb, j + 1), n, 1.0 / hn, st);
+    }
+    if (status != NESA_OK) break;
+    std::vector<cd> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int c2 = i + 1; c2 < k; ++c2) acc -= H[(size_t)c2 * (m + 1) + i] * y[c2];
+      y[i] = acc / H[(size_t)i * (m + 1) + i];
+    }
+    for (int i = 0; i < k; ++i) hh[i] = make_double2(y[i].real(), y[i].imag());
+    hip_check(hipMemcpyAsync(hd, hh, sizeof(double2) * k, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    nesa::launch_combine<T>(flex ? Zb : Vb, n, k, hd, xl, n, +1.0, st);
+    matvec(xl, tmp);
+    nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
+    beta = norm(vec(Vb, 0));
+  }
+  nesa::launch_scatter<T>(xl, x_c, d.perm, n, st);
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  rep.iters = iters;
+  rep.true_rel_residual = beta / nb;
+  rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status != NESA_OK) return status;
+  if (beta / nb > prm.tol) return fail(NESA_ENOCONV, "GMRES reached max_iters above tolerance");
+  return NESA_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* nesa_last_error(void) { return g_err.c_str(); }
+
+int nesa_build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
+                    const nesa_tree_params* params, nesa_tree** out) {
+  return guarded([&]() {
+    if (!verts || !tris || !params || !out) return fail(NESA_EINVAL, "null argument");
+    std::unique_ptr<nesa_tree> h(new nesa_tree());
+    h->t.reset(nesa::build_tree(verts, nv, tris, nt, params->leaf_size, params->l0_max, params->buffer));
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info) {
+  return guarded([&]() {
+    if (!tree || !info) return fail(NESA_EINVAL, "null argument");
+    const nesa::Tree& t = *tree->t;
+    std::memset(info, 0, sizeof(*info));
+    info->n_rwg = t.rwg.n;
+    info->n_tri = t.rwg.nt;
+    info->L = t.L;
+    info->l0 = t.l0;
+    int64_t ne = 0;
+    const auto& LL = t.level(t.L);
+    for (int64_t a = 0; a < LL.nbox; ++a) {
+      int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a], W = 0;
+      for (int64_t j = t.near_ptr[a]; j < t.near_ptr[a + 1]; ++j)
+        W += t.leaf_ptr[t.near_idx[j] + 1] - t.leaf_ptr[t.near_idx[j]];
+      ne += S * W;
+    }
+    info->near_entries = ne;
+    for (int l = t.l0; l <= t.L && l - t.l0 < 32; ++l) {
+      info->n_box[l - t.l0] = t.level(l).nbox;
+      info->n_pairs[l - t.l0] = (int64_t)t.level(l).il_src.size();
+    }
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_tree_perm(const nesa_tree* tree, int64_t* perm) {
+  return guarded([&]() {
+    if (!tree || !perm) return fail(NESA_EINVAL, "null argument");
+    std::copy(tree->t->perm.begin(), tree->t->perm.end(), perm);
+    return (int)NESA_OK;
+  });
+}
+
+void nesa_tree_free(nesa_tree* tree) { delete tree; }
+
+int nesa_assemble_near(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out) {
+  return guarded([&]() {
+    if (!tree || !em || !out) return fail(NESA_EINVAL, "null argument");
+    if (!(em->k > 0) || !(em->eta > 0)) return fail(NESA_EINVAL, "k and eta must be positive");
+    std::unique_ptr<nesa_near> h(new nesa_near());
+    h->n.reset(nesa::assemble_near(*tree->t, em->k, em->eta));
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_near_entries(const nesa_tree* tree, const nesa_near* near, const int64_t* rows, int64_t nrows,
+                      const int64_t* cols, int64_t ncols, double* out) {
+  return guarded([&]() {
+    if (!tree || !near || !rows || !cols || !out) return fail(NESA_EINVAL, "null argument");
+    const nesa::Tree& t = *tree->t;
+    const nesa::Near& nr = *near->n;
+    const int64_t n = t.rwg.n;
+    // leaf of each leaf-order position
+    std::vector<int64_t> leaf_of(n);
+    const auto& LL = t.level(t.L);
+    for (int64_t a = 0; a < LL.nbox; ++a)
+      for (int64_t p = t.leaf_ptr[a]; p < t.leaf_ptr[a + 1]; ++p) leaf_of[p] = a;
+    for (int64_t i = 0; i < nrows; ++i) {
+      if (rows[i] < 0 || rows[i] >= n) return fail(NESA_EINVAL, "row index out of range");
+      const int64_t pr = t.pos[rows[i]], a = leaf_of[pr], S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+      const int64_t ri = pr - t.leaf_ptr[a];
+      for (int64_t j = 0; j < ncols; ++j) {
+        if (cols[j] < 0 || cols[j] >= n) return fail(NESA_EINVAL, "column index out of range");
+        const int64_t pc = t.pos[cols[j]], b = leaf_of[pc];
+        cd v(0, 0);
+        int64_t c0 = 0;
+        for (int64_t q = t.near_ptr[a]; q < t.near_ptr[a + 1]; ++q) {
+          const int64_t bb = t.near_idx[q];
+          if (bb == b) {
+            v = nr.z[nr.off[a] + (c0 + pc - t.leaf_ptr[b]) * S + ri];
+            break;
+          }
+          c0 += t.leaf_ptr[bb + 1] - t.leaf_ptr[bb];
+        }
+        out[2 * (i * ncols + j)] = v.real();
+        out[2 * (i * ncols + j) + 1] = v.imag();
+      }
+    }
+    return (int)NESA_OK;
+  });
+}
+
+void nesa_near_free(nesa_near* near) { delete near; }
+
+int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em, const nesa_far_params* params,
+                               nesa_far** out) {
+  return guarded([&]() {
+    if (!tree || !em || !params || !out) return fail(NESA_EINVAL, "null argument");
+    if (!(em->k > 0) || !(em->eta > 0)) return fail(NESA_EINVAL, "k and eta must be positive");
+    std::unique_ptr<nesa_far> h(new nesa_far());
+    h->f.reset(nesa::assemble_far(*tree->t, em->k, em->eta, params->d0, params->q_min, params->tau));
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_far_get_q(const nesa_far* far, int* Q, int nmax) {
+  return guarded([&]() {
+    if (!far || !Q) return fail(NESA_EINVAL, "null argument");
+    for (int i = 0; i < nmax && i < (int)far->f->lev.size(); ++i) Q[i] = far->f->lev[i].Q;
+    return (int)NESA_OK;
+  });
+}
+
+void nesa_far_free(nesa_far* far) { delete far; }
+
+int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far* far, int precision, int max_nrhs,
+                   nesa_op** out) {
+  return guarded([&]() {
+    if (!tree || !near || !far || !out) return fail(NESA_EINVAL, "null argument");
+    if (precision != NESA_C128 && precision != NESA_C64 && precision != NESA_C64_SPLIT)
+      return fail(NESA_EINVAL, "unknown precision");
+    if (max_nrhs < 1) return fail(NESA_EINVAL, "max_nrhs must be >= 1");
+    if (precision == NESA_C64_SPLIT) return fail(NESA_ENOTIMPL, "split precision not available");
+    std::unique_ptr<nesa_op> op(new nesa_op());
+    op->precision = precision;
+    op->max_nrhs = max_nrhs;
+    op->k = far->f->k;
+    op->eta = far->f->eta;
+    op->geo.rwg = tree->t->rwg;
+    if (precision == NESA_C128) {
+      op->esize = 16;
+      build_dev<double>(op.get(), op->d, *tree->t, *near->n, *far->f);
+    } else {
+      op->esize = 8;
+      build_dev<float>(op.get(), op->f, *tree->t, *near->n, *far->f);
+    }
+    hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    *out = op.release();
+    return (int)NESA_OK;
+  });
+}
+
+void nesa_op_free(nesa_op* op) {
+  if (op) (void)hipDeviceSynchronize();
+  delete op;
+}
+
+static int matvec_impl(nesa_op* op, const void* x, void* y, int64_t nrhs, void* stream, bool canonical) {
+  return guarded([&]() {
+    if (!op || !x || !y) return fail(NESA_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = op->precision == NESA_C128 ? op->d.n : op->f.n;
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const char* xr = static_cast<const char*>(x) + (size_t)r * n * op->esize;
+      char* yr = static_cast<char*>(y) + (size_t)r * n * op->esize;
+      if (op->precision == NESA_C128) {
+        if (canonical) {
+          nesa::launch_gather<double>(xr, op->xl, op->d.perm, n, st);
+          nesa::launch_matvec_leaf<double>(op->d, op->xl, op->yl, st, nullptr);
+          nesa::launch_scatter<double>(op->yl, yr, op->d.perm, n, st);
+        } else {
+          nesa::launch_matvec_leaf<double>(op->d, xr, yr, st, nullptr);
+        }
+      } else {
+        if (canonical) {
+          nesa::launch_gather<float>(xr, op->xl, op->f.perm, n, st);
+          nesa::launch_matvec_leaf<float>(op->f, op->xl, op->yl, st, nullptr);
+          nesa::launch_scatter<float>(op->yl, yr, op->f.perm, n, st);
+        } else {
+          nesa::launch_matvec_leaf<float>(op->f, xr, yr, st, nullptr);
+        }
+      }
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_matvec(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream) {
+  return matvec_impl(op, x_dev, y_dev, nrhs, stream, true);
+}
+int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream) {
+  return matvec_impl(op, x_dev, y_dev, nrhs, stream, false);
+}
+
+int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms) {
+  return guarded([&]() {
+    if (!op || !x_dev || !y_dev || !ms) return fail(NESA_EINVAL, "null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    nesa::PhaseTimer tm;
+    for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    if (op->precision == NESA_C128)
+      nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, st, &tm);
+    else
+      nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, st, &tm);
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipEventSynchronize(tm.ev[nesa::PhaseTimer::NMARK - 1]), "hipEventSynchronize");
+    for (int i = 0; i + 1 < nesa::PhaseTimer::NMARK; ++i)
+      hip_check(hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]), "hipEventElapsedTime");
+    for (auto& e : tm.ev) (void)hipEventDestroy(e);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_rhs_plane_wave_host(const nesa_tree* tree, double k, const double* khat, const double* pol,
+                             int64_t nrhs, double* b) {
+  return guarded([&]() {
+    if (!tree || !khat || !pol || !b) return fail(NESA_EINVAL, "null argument");
+    const int64_t n = tree->t->rwg.n;
+    for (int64_t r = 0; r < nrhs; ++r)
+      nesa::plane_wave_rhs(*tree->t, k, khat + 3 * r, pol + 3 * r, reinterpret_cast<cd*>(b) + r * n);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_rhs_plane_wave(nesa_op* op, const double* khat, const double* pol, int64_t nrhs, void* b_dev,
+                        void* stream) {
+  return guarded([&]() {
+    if (!op || !khat || !pol || !b_dev) return fail(NESA_EINVAL, "null argument");
+    if (nrhs < 1) return fail(NESA_EINVAL, "nrhs must be >= 1");
+    const int64_t n = op->geo.rwg.n;
+    std::vector<cd> b((size_t)n * nrhs);
+    for (int64_t r = 0; r < nrhs; ++r) nesa::plane_wave_rhs(op->geo, op->k, khat + 3 * r, pol + 3 * r, &b[r * n]);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (op->precision == NESA_C128) {
+      hip_check(hipMemcpyAsync(b_dev, b.data(), b.size() * 16, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    } else {
+      std::vector<float> bf(2 * b.size());
+      for (size_t i = 0; i < b.size(); ++i) {
+        bf[2 * i] = (float)b[i].real();
+        bf[2 * i + 1] = (float)b[i].imag();
+      }
+      hip_check(hipMemcpyAsync(b_dev, bf.data(), bf.size() * 4, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    }
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, const nesa_gmres_params* params,
+                     nesa_gmres_report* report, double* history, int64_t history_len, void* stream) {
+  return guarded([&]() {
+    if (!op || !b_dev || !x_dev || !params || !report) return fail(NESA_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
+    if (params->restart < 1 || params->restart > 250 || params->max_iters < 1 || !(params->tol > 0))
+      return fail(NESA_EINVAL, "bad GMRES parameters");
+    if (params->precond < 0 || params->precond > 2) return fail(NESA_EINVAL, "unknown preconditioner");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = op->geo.rwg.n;
+    int worst = NESA_OK;
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const char* br = static_cast<const char*>(b_dev) + (size_t)r * n * op->esize;
+      char* xr = static_cast<char*>(x_dev) + (size_t)r * n * op->esize;
+      int rc;
+      if (op->precision == NESA_C128)
+        rc = gmres_one<double>(op, op->d, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st);
+      else
+        rc = gmres_one<float>(op, op->f, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st);
+      if (rc != NESA_OK && worst == NESA_OK) worst = rc;
+    }
+    return worst;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,534 @@
+// gfx950 kernels of the NESA product (Sec. 3, Eq. 9-14) and of the vector
+// operations used by GMRES.
+//
+// Every output segment is written by exactly one workgroup per stage (owner
+// computes), so results are deterministic and no atomics are used:
+//   radiate     one workgroup per leaf b:      s_b = V_b x_b              (Eq. 10)
+//   upward      one workgroup per parent P:    s_P = sum_children C s_c   (Eq. 11)
+//   translate   one workgroup per (box, 64-row tile): o_a = sum_IL D s_b  (Eq. 12)
+//   downward    one workgroup per child a:     o_a += C^T o_P             (Eq. 13)
+//   near_recv   one workgroup per leaf a:      y_a = Z_near x + sum_c w_c V_a^T o_a
+//                                                                     (Eq. 9 + 14)
+// Complex numbers are interleaved (re, im) pairs of T = float or double.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace nesa {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ typename C2<T>::type cmk(T x, T y) {
+  typename C2<T>::type r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+// acc += a * b
+template <typename V>
+__device__ __forceinline__ void cfma(V& acc, const V a, const V b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+template <typename V>
+__device__ __forceinline__ V cmul(const V a, const V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+constexpr int NT = 256;     // threads per workgroup
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------------ permutation
+template <typename V>
+__global__ void k_gather(const V* __restrict__ x, V* __restrict__ xl, const int32_t* __restrict__ perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) xl[i] = x[perm[i]];
+}
+template <typename V>
+__global__ void k_scatter(const V* __restrict__ yl, V* __restrict__ y, const int32_t* __restrict__ perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) y[perm[i]] = yl[i];
+}
+
+// ------------------------------------------------------------------ radiation (Eq. 10)
+// V in leaf order: row p (one RWG) holds its 4*Q coefficients contiguously.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_radiate(const typename C2<T>::type* __restrict__ V,
+                                                const typename C2<T>::type* __restrict__ x,
+                                                const int32_t* __restrict__ leaf_ptr,
+                                                typename C2<T>::type* __restrict__ s, int Q) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 xs[NT];
+  const int b = blockIdx.x;
+  const int p0 = leaf_ptr[b], S = leaf_ptr[b + 1] - p0;
+  const int J = 4 * Q;
+  V2 acc[2];
+  acc[0] = cmk<T>(0, 0);
+  acc[1] = cmk<T>(0, 0);
+  for (int i0 = 0; i0 < S; i0 += NT) {
+    const int ni = min(NT, S - i0);
+    __syncthreads();
+    if ((int)threadIdx.x < ni) xs[threadIdx.x] = x[p0 + i0 + threadIdx.x];
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      const int j = threadIdx.x + r * NT;
+      if (j < J) {
+        const V2* Vp = V + (size_t)(p0 + i0) * J + j;
+        V2 a = acc[r];
+        for (int i = 0; i < ni; ++i) cfma(a, Vp[(size_t)i * J], xs[i]);
+        acc[r] = a;
+      }
+    }
+  }
+  for (int r = 0; r < 2; ++r) {
+    const int j = threadIdx.x + r * NT;
+    if (j < J) s[(size_t)b * J + j] = acc[r];
+  }
+}
+
+// ------------------------------------------------------------------ source transfer (Eq. 11)
+// Parent P at level l-1 gathers its children at level l.  Ccm[o][q][p] = C_o[p][q].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_upward(const typename C2<T>::type* __restrict__ Ccm,
+                                               const typename C2<T>::type* __restrict__ s_child,
+                                               typename C2<T>::type* __restrict__ s_par,
+                                               const int32_t* __restrict__ child_ptr,
+                                               const int32_t* __restrict__ octant, int Qp, int Qc) {
+  using V2 = typename C2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  V2* sl = reinterpret_cast<V2*>(smem_raw);     // [4][Qc]
+  const int P = blockIdx.x;
+  const int c0 = child_ptr[P], c1 = child_ptr[P + 1];
+  constexpr int RP = 2;                          // rows per thread (Qp <= 512)
+  V2 acc[RP][4];
+  for (int r = 0; r < RP; ++r)
+    for (int c = 0; c < 4; ++c) acc[r][c] = cmk<T>(0, 0);
+  for (int ch = c0; ch < c1; ++ch) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < 4 * Qc; j += NT) sl[j] = s_child[(size_t)ch * 4 * Qc + j];
+    __syncthreads();
+    const V2* C = Ccm + (size_t)octant[ch] * Qp * Qc;
+    for (int r = 0; r < RP; ++r) {
+      const int p = threadIdx.x + r * NT;
+      if (p < Qp) {
+        for (int q = 0; q < Qc; ++q) {
+          const V2 cv = C[(size_t)q * Qp + p];
+          for (int c = 0; c < 4; ++c) cfma(acc[r][c], cv, sl[c * Qc + q]);
+        }
+      }
+    }
+  }
+  for (int r = 0; r < RP; ++r) {
+    const int p = threadIdx.x + r * NT;
+    if (p < Qp)
+      for (int c = 0; c < 4; ++c) s_par[(size_t)P * 4 * Qp + c * Qp + p] = acc[r][c];
+  }
+}
+
+// ------------------------------------------------------------------ translation (Eq. 12)
+// o_a = sum over the interaction list of D_slot s_b.  Dcm[slot][q][p] = D[p][q].
+// Workgroup = (64-row tile, target box); wave w takes list entries w, w+4, ...
+template <typename T>
+__global__ __launch_bounds__(NT) void k_translate(const typename C2<T>::type* __restrict__ Dcm,
+                                                  const typename C2<T>::type* __restrict__ s,
+                                                  typename C2<T>::type* __restrict__ o,
+                                                  const int32_t* __restrict__ il_ptr,
+                                                  const int32_t* __restrict__ il_src,
+                                                  const int32_t* __restrict__ il_slot, int Q) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 red[NT / WAVE][4][WAVE];
+  const int a = blockIdx.y;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int p = blockIdx.x * WAVE + lane;
+  const int k0 = il_ptr[a], k1 = il_ptr[a + 1];
+  V2 acc[4];
+  for (int c = 0; c < 4; ++c) acc[c] = cmk<T>(0, 0);
+  if (p < Q) {
+    for (int kk = k0 + w; kk < k1; kk += NT / WAVE) {
+      const int b = il_src[kk];
+      const V2* D = Dcm + (size_t)il_slot[kk] * Q * Q + p;
+      const V2* sb = s + (size_t)b * 4 * Q;
+      for (int q = 0; q < Q; ++q) {
+        const V2 d = D[(size_t)q * Q];
+        for (int c = 0; c < 4; ++c) cfma(acc[c], d, sb[c * Q + q]);
+      }
+    }
+  }
+  for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
+  __syncthreads();
+  if (w == 0 && p < Q) {
+    for (int c = 0; c < 4; ++c) {
+      V2 t = red[0][c][lane];
+      for (int ww = 1; ww < NT / WAVE; ++ww) {
+        t.x += red[ww][c][lane].x;
+        t.y += red[ww][c][lane].y;
+      }
+      o[(size_t)a * 4 * Q + c * Q + p] = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ potential transfer (Eq. 13)
+// Child a at level l: o_a += B o_P with B = C^T.  Crm[o][p][q] = C_o[p][q].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_downward(const typename C2<T>::type* __restrict__ Crm,
+                                                 const typename C2<T>::type* __restrict__ o_par,
+                                                 typename C2<T>::type* __restrict__ o_child,
+                                                 const int32_t* __restrict__ parent,
+                                                 const int32_t* __restrict__ octant, int Qp, int Qc) {
+  using V2 = typename C2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  V2* ol = reinterpret_cast<V2*>(smem_raw);     // [4][Qp]
+  const int a = blockIdx.x;
+  const int P = parent[a];
+  for (int j = threadIdx.x; j < 4 * Qp; j += NT) ol[j] = o_par[(size_t)P * 4 * Qp + j];
+  __syncthreads();
+  const V2* C = Crm + (size_t)octant[a] * Qp * Qc;
+  for (int q = threadIdx.x; q < Qc; q += NT) {
+    V2 acc[4];
+    for (int c = 0; c < 4; ++c) acc[c] = o_child[(size_t)a * 4 * Qc + c * Qc + q];
+    for (int p = 0; p < Qp; ++p) {
+      const V2 cv = C[(size_t)p * Qc + q];
+      for (int c = 0; c < 4; ++c) cfma(acc[c], cv, ol[c * Qp + p]);
+    }
+    for (int c = 0; c < 4; ++c) o_child[(size_t)a * 4 * Qc + c * Qc + q] = acc[c];
+  }
+}
+
+// ------------------------------------------------------------------ near field + reception (Eq. 9, 14)
+// Z block of leaf a: S x W column-major at Z + zoff[a]; its columns are the
+// RWGs of the near leaves in list order.  Rows split over G = NT/S column
+// groups; each thread reads Z contiguously (address k*G*S + tid).
+constexpr int NEAR_CW = 1024;   // x columns staged in LDS per pass
+constexpr int MAX_NEAR = 128;   // near-list entries per leaf
+constexpr int MAX_QL = 256;     // equivalent sources per leaf
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __restrict__ Z,
+                                                  const int64_t* __restrict__ zoff,
+                                                  const int32_t* __restrict__ leaf_ptr,
+                                                  const int32_t* __restrict__ near_ptr,
+                                                  const int32_t* __restrict__ near_idx,
+                                                  const typename C2<T>::type* __restrict__ x,
+                                                  const typename C2<T>::type* __restrict__ V,
+                                                  const typename C2<T>::type* __restrict__ o,
+                                                  typename C2<T>::type* __restrict__ y, int Q,
+                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 xs[NEAR_CW];
+  __shared__ V2 red[NT];
+  __shared__ int seg_col[MAX_NEAR + 1];
+  __shared__ int seg_x[MAX_NEAR];
+  __shared__ V2 ow[4 * MAX_QL];            // weighted o_a
+  const int a = blockIdx.x;
+  const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
+  const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int k = 0; k < nn; ++k) {
+      const int b = near_idx[n0 + k];
+      seg_col[k] = c;
+      seg_x[k] = leaf_ptr[b];
+      c += leaf_ptr[b + 1] - leaf_ptr[b];
+    }
+    seg_col[nn] = c;
+  }
+  __syncthreads();
+  const int W = seg_col[nn];
+  const V2* Za = Z + zoff[a];
+  const int G = NT / S;                 // column groups (S <= NT checked on the host)
+  const int t = threadIdx.x;
+  const int g = t / S;
+  V2 acc = cmk<T>(0, 0);
+  for (int c0 = 0; c0 < W; c0 += NEAR_CW) {
+    const int cw = min(NEAR_CW, W - c0);
+    __syncthreads();
+    for (int j = t; j < cw; j += NT) {
+      const int col = c0 + j;
+      int k = 0;
+      while (seg_col[k + 1] <= col) ++k;
+      xs[j] = x[seg_x[k] + (col - seg_col[k])];
+    }
+    __syncthreads();
+    if (g < G) {
+      const V2* Zp = Za + (size_t)c0 * S + t;
+      for (int j = g; j < cw; j += G) cfma(acc, Zp[(size_t)(j - g) * S], xs[j]);
+    }
+  }
+  red[t] = acc;
+  // weighted equivalent potentials of the leaf (channel weights of the
+  // mixed-potential split: w_xyz = -i eta k, w_div = +i eta / k)
+  const int J = 4 * Q;
+  for (int j = t; j < J; j += NT) {
+    const V2 ov = o[(size_t)a * J + j];
+    const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
+    ow[j] = cmul(ov, wv);
+  }
+  __syncthreads();
+  // reduce the column groups (fixed order) -> near result of row r in red[r]
+  V2 yn = cmk<T>(0, 0);
+  if (t < S) {
+    yn = red[t];
+    for (int gg = 1; gg < G; ++gg) {
+      yn.x += red[gg * S + t].x;
+      yn.y += red[gg * S + t].y;
+    }
+  }
+  __syncthreads();
+  if (t < S) red[t] = yn;
+  __syncthreads();
+  // reception: one wave per row
+  const int lane = t % WAVE, wv = t / WAVE;
+  for (int row = wv; row < S; row += NT / WAVE) {
+    const V2* Vr = V + (size_t)(p0 + row) * J;
+    V2 s = cmk<T>(0, 0);
+    for (int j = lane; j < J; j += WAVE) cfma(s, Vr[j], ow[j]);
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+      s.x += __shfl_xor(s.x, off);
+      s.y += __shfl_xor(s.y, off);
+    }
+    if (lane == 0) {
+      V2 out = red[row];
+      out.x += s.x;
+      out.y += s.y;
+      y[p0 + row] = out;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ vector ops (GMRES)
+// partial[blk][i] = sum over the block's chunk of conj(basis_i) * w, FP64
+// accumulation; basis vectors taken 8 at a time.
+constexpr int MD_CH = 8;
+template <typename V>
+__global__ __launch_bounds__(NT) void k_multidot(const V* __restrict__ basis, int64_t ld, int nvec,
+                                                 const V* __restrict__ w, int64_t n, double2* __restrict__ partial) {
+  __shared__ double2 red[NT / WAVE][MD_CH];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  for (int i0 = 0; i0 < nvec; i0 += MD_CH) {
+    const int ni = min(MD_CH, nvec - i0);
+    double2 acc[MD_CH];
+    for (int i = 0; i < MD_CH; ++i) acc[i] = make_double2(0, 0);
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
+      const V we = w[e];
+      for (int i = 0; i < MD_CH; ++i) {
+        if (i < ni) {
+          const V b = basis[(size_t)(i0 + i) * ld + e];
+          acc[i].x += (double)b.x * (double)we.x + (double)b.y * (double)we.y;
+          acc[i].y += (double)b.x * (double)we.y - (double)b.y * (double)we.x;
+        }
+      }
+    }
+    for (int i = 0; i < MD_CH; ++i) {
+      double2 s = acc[i];
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        s.x += __shfl_xor(s.x, off);
+        s.y += __shfl_xor(s.y, off);
+      }
+      if (lane == 0) red[wv][i] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ni) {
+      double2 s = red[0][threadIdx.x];
+      for (int ww = 1; ww < NT / WAVE; ++ww) {
+        s.x += red[ww][threadIdx.x].x;
+        s.y += red[ww][threadIdx.x].y;
+      }
+      partial[(size_t)blockIdx.x * nvec + i0 + threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// out[i] (+)= sum over blocks of partial[blk][i]
+__global__ void k_reduce_partials(const double2* __restrict__ partial, int nblk, int nvec,
+                                  double2* __restrict__ out, int accumulate) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= nvec) return;
+  double2 s = make_double2(0, 0);
+  for (int b = 0; b < nblk; ++b) {
+    s.x += partial[(size_t)b * nvec + i].x;
+    s.y += partial[(size_t)b * nvec + i].y;
+  }
+  if (accumulate) {
+    out[i].x += s.x;
+    out[i].y += s.y;
+  } else {
+    out[i] = s;
+  }
+}
+
+// w[e] -= sum_i h[i] * basis_i[e]   (sign = -1), or x[e] += sum_i h[i] basis_i[e] (sign = +1)
+template <typename V>
+__global__ void k_combine(const V* __restrict__ basis, int64_t ld, int nvec, const double2* __restrict__ h,
+                          V* __restrict__ w, int64_t n, double sign) {
+  __shared__ double2 hs[256];
+  for (int i = threadIdx.x; i < nvec && i < 256; i += NT) hs[i] = h[i];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  double ax = 0, ay = 0;
+  for (int i = 0; i < nvec; ++i) {
+    const V b = basis[(size_t)i * ld + e];
+    ax += hs[i].x * (double)b.x - hs[i].y * (double)b.y;
+    ay += hs[i].x * (double)b.y + hs[i].y * (double)b.x;
+  }
+  V we = w[e];
+  we.x = (decltype(we.x))((double)we.x + sign * ax);
+  we.y = (decltype(we.y))((double)we.y + sign * ay);
+  w[e] = we;
+}
+
+// y = alpha * x  (alpha real)
+template <typename V>
+__global__ void k_scale(const V* __restrict__ x, V* __restrict__ y, int64_t n, double alpha) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  V v = x[e];
+  v.x = (decltype(v.x))((double)v.x * alpha);
+  v.y = (decltype(v.y))((double)v.y * alpha);
+  y[e] = v;
+}
+
+// y = a - b
+template <typename V>
+__global__ void k_sub(const V* __restrict__ a, const V* __restrict__ b, V* __restrict__ y, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  V u = a[e], v = b[e];
+  u.x -= v.x;
+  u.y -= v.y;
+  y[e] = u;
+}
+
+// Block-diagonal preconditioner: z_a = Minv_a r_a, Minv_a S x S column-major.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_blockdiag(const typename C2<T>::type* __restrict__ Minv,
+                                                  const int64_t* __restrict__ moff,
+                                                  const int32_t* __restrict__ leaf_ptr,
+                                                  const typename C2<T>::type* __restrict__ r,
+                                                  typename C2<T>::type* __restrict__ z) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 rs[NT];
+  const int a = blockIdx.x;
+  const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
+  if ((int)threadIdx.x < S) rs[threadIdx.x] = r[p0 + threadIdx.x];
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    const V2* M = Minv + moff[a] + threadIdx.x;
+    V2 acc = cmk<T>(0, 0);
+    for (int j = 0; j < S; ++j) cfma(acc, M[(size_t)j * S], rs[j]);
+    z[p0 + threadIdx.x] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+template <typename T>
+void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream_t st, PhaseTimer* tm) {
+  using V2 = typename C2<T>::type;
+  const V2* xl = static_cast<const V2*>(xl_);
+  V2* yl = static_cast<V2*>(yl_);
+  V2* s = static_cast<V2*>(d.s);
+  V2* o = static_cast<V2*>(d.o);
+  const int L = d.L, l0 = d.l0;
+  const auto& LL = d.lev[L - l0];
+  if (tm) tm->mark(st, 0);
+  k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr,
+                                                 s + LL.s_off, LL.Q);
+  if (tm) tm->mark(st, 1);
+  for (int l = L; l > l0; --l) {
+    const auto& c = d.lev[l - l0];
+    const auto& p = d.lev[l - 1 - l0];
+    size_t sh = sizeof(V2) * 4 * c.Q;
+    k_upward<T><<<(unsigned)p.nbox, NT, sh, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off,
+                                                  p.child_ptr, c.octant, p.Q, c.Q);
+  }
+  if (tm) tm->mark(st, 2);
+  for (int l = l0; l <= L; ++l) {
+    const auto& lv = d.lev[l - l0];
+    dim3 grid((unsigned)((lv.Q + WAVE - 1) / WAVE), (unsigned)lv.nbox);
+    k_translate<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(lv.D), s + lv.s_off, o + lv.s_off, lv.il_ptr,
+                                        lv.il_src, lv.il_slot, lv.Q);
+  }
+  if (tm) tm->mark(st, 3);
+  for (int l = l0 + 1; l <= L; ++l) {
+    const auto& c = d.lev[l - l0];
+    const auto& p = d.lev[l - 1 - l0];
+    size_t sh = sizeof(V2) * 4 * p.Q;
+    k_downward<T><<<(unsigned)c.nbox, NT, sh, st>>>(static_cast<const V2*>(c.Crm), o + p.s_off, o + c.s_off,
+                                                    c.parent, c.octant, p.Q, c.Q);
+  }
+  if (tm) tm->mark(st, 4);
+  k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
+                                                   d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
+                                                   LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+  if (tm) tm->mark(st, 5);
+}
+
+template <typename T>
+void launch_gather(const void* x, void* xl, const int32_t* perm, int64_t n, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_gather<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(x), static_cast<V2*>(xl), perm, n);
+}
+template <typename T>
+void launch_scatter(const void* yl, void* y, const int32_t* perm, int64_t n, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_scatter<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(yl), static_cast<V2*>(y), perm, n);
+}
+
+template <typename T>
+void launch_multidot(const void* basis, int64_t ld, int nvec, const void* w, int64_t n, double2* partial,
+                     int nblocks, double2* out, int accumulate, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_multidot<V2><<<nblocks, NT, 0, st>>>(static_cast<const V2*>(basis), ld, nvec, static_cast<const V2*>(w), n,
+                                         partial);
+  k_reduce_partials<<<nblk(nvec), NT, 0, st>>>(partial, nblocks, nvec, out, accumulate);
+}
+template <typename T>
+void launch_combine(const void* basis, int64_t ld, int nvec, const double2* h, void* w, int64_t n, double sign,
+                    hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_combine<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(basis), ld, nvec, h, static_cast<V2*>(w), n, sign);
+}
+template <typename T>
+void launch_scale(const void* x, void* y, int64_t n, double alpha, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_scale<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(x), static_cast<V2*>(y), n, alpha);
+}
+template <typename T>
+void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_sub<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(a), static_cast<const V2*>(b), static_cast<V2*>(y), n);
+}
+template <typename T>
+void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_blockdiag<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Minv), d.moff, d.leaf_ptr,
+                                                   static_cast<const V2*>(r), static_cast<V2*>(z));
+}
+
+#define NESA_INST(T)                                                                                         \
+  template void launch_matvec_leaf<T>(const DevOp<T>&, const void*, void*, hipStream_t, PhaseTimer*);         \
+  template void launch_gather<T>(const void*, void*, const int32_t*, int64_t, hipStream_t);                  \
+  template void launch_scatter<T>(const void*, void*, const int32_t*, int64_t, hipStream_t);                 \
+  template void launch_multidot<T>(const void*, int64_t, int, const void*, int64_t, double2*, int, double2*, \
+                                   int, hipStream_t);                                                        \
+  template void launch_combine<T>(const void*, int64_t, int, const double2*, void*, int64_t, double,        \
+                                  hipStream_t);                                                              \
+  template void launch_scale<T>(const void*, void*, int64_t, double, hipStream_t);                           \
+  template void launch_sub<T>(const void*, const void*, void*, int64_t, hipStream_t);                       \
+  template void launch_blockdiag<T>(const DevOp<T>&, const void*, void*, hipStream_t);
+NESA_INST(float)
+NESA_INST(double)
+
+}  // namespace nesa

@@ -1,0 +1,108 @@
+// Host-side data structures of the NESA library: mesh, RWG basis, oct-tree,
+// near-field blocks and far-field operators (all FP64, host memory).
+#pragma once
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace nesa {
+
+using cd = std::complex<double>;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// RWG functions on the interior edges of a closed mesh (canonical order).
+struct Rwg {
+  int64_t n = 0, nt = 0;
+  std::vector<double> v;            // [nv][3]
+  std::vector<int32_t> t;           // [nt][3]
+  std::vector<int64_t> edge;        // [n][2] (min, max) vertex ids
+  std::vector<int64_t> tri;         // [n][2] (T+, T-)
+  std::vector<int64_t> freev;       // [n][2] free vertex of T+, T-
+  std::vector<double> len;          // [n]
+  std::vector<double> area;         // [nt]
+  std::vector<double> normal;       // [nt][3]
+  std::vector<int64_t> tri_rwg;     // [nt][3] RWG on the edge opposite local vertex a
+  std::vector<double> tri_sign;     // [nt][3] +1 (T+) / -1 (T-)
+  std::vector<double> qp;           // [nt][3][3] quadrature points (3-point rule)
+};
+
+struct Level {
+  int l = 0;
+  double side = 0;
+  int64_t nbox = 0;
+  std::vector<std::array<int32_t, 3>> key;
+  std::vector<int64_t> parent;      // box index at level l-1 (empty at l0)
+  std::vector<int32_t> octant;      // position inside the parent (bit0 x, bit1 y, bit2 z)
+  std::vector<int64_t> child_ptr;   // children at level l+1: [child_ptr[b], child_ptr[b+1])
+  std::vector<int64_t> il_ptr;      // interaction list (Sec. 3): CSR by target
+  std::vector<int64_t> il_src;
+  std::vector<int32_t> il_slot;     // offset slot of (target key - source key)
+};
+
+struct Tree {
+  Rwg rwg;
+  double leaf = 0.25;
+  int L = 0, l0 = 0, buffer = 1;
+  double lo[3] = {0, 0, 0};
+  std::vector<Level> lev;           // lev[l - l0]
+  std::vector<int64_t> perm;        // leaf-order position -> canonical RWG
+  std::vector<int64_t> pos;         // canonical RWG -> leaf-order position
+  std::vector<int64_t> leaf_ptr;    // RWGs of leaf b: positions [leaf_ptr[b], leaf_ptr[b+1])
+  std::vector<int64_t> near_ptr, near_idx;   // leaf-level near lists
+  int slot_w() const { return 4 * buffer + 3; }   // offsets in [-(2b+1), 2b+1] per axis
+  int nslot() const { return slot_w() * slot_w() * slot_w(); }
+  const Level& level(int l) const { return lev[l - l0]; }
+  Level& level(int l) { return lev[l - l0]; }
+  std::array<double, 3> center(int l, int64_t b) const {
+    const Level& lv = level(l);
+    return {lo[0] + (lv.key[b][0] + 0.5) * lv.side, lo[1] + (lv.key[b][1] + 0.5) * lv.side,
+            lo[2] + (lv.key[b][2] + 0.5) * lv.side};
+  }
+};
+
+// Near-field blocks: for target leaf a, a dense S_a x W_a column-major block
+// (W_a = sum of the sizes of the leaves in its near list, in list order).
+struct Near {
+  double k = 0, eta = 0;
+  std::vector<int64_t> off;         // [nleaf + 1] offsets into z
+  std::vector<cd> z;
+  int64_t entries() const { return (int64_t)z.size(); }
+};
+
+struct FarLevel {
+  int Q = 0, M = 0;
+  double re = 0, rc = 0;
+  std::vector<double> E, X;         // [Q][3], [M][3] on spheres of radius re, rc
+  std::vector<cd> Cup;              // [8][Q_{l-1}][Q_l] row-major (l > l0)
+  std::vector<cd> D;                // [nslot][Q][Q] row-major, D[p][q] = g(E_p + d - E_q)
+  std::vector<uint8_t> slot_used;
+};
+
+struct Far {
+  double k = 0, eta = 0;
+  int d0 = 3;
+  double tau = 1e-8;
+  std::vector<FarLevel> lev;        // lev[l - l0]
+  std::vector<cd> V;                // [N leaf order][4][Q_L]
+};
+
+// thread pool helper: fn(i) for i in [0, n)
+void parallel_for(int64_t n, const std::function<void(int64_t)>& fn);
+
+Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
+                 double leaf, int l0_max, int buffer);
+Near* assemble_near(const Tree& t, double k, double eta);
+Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau);
+void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
+                    cd* b_canonical);
+
+}  // namespace nesa

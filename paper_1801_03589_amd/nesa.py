@@ -1,0 +1,245 @@
+"""ctypes binding of the C ABI in include/nesa.h (argument marshalling only).
+
+Device vectors are torch tensors (complex64 / complex128, contiguous, on the
+current HIP device); streams are torch streams.  Every call raises NesaError
+when the library returns a non-zero status.  The library must have been built
+(paper_1801_03589_amd/build.py): there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnesa.so")
+
+C128, C64, C64_SPLIT = 0, 1, 2
+PRECOND_NONE, PRECOND_BLOCKDIAG, PRECOND_LEARNED = 0, 1, 2
+ETA0 = 376.730313668
+K0 = 2.0 * np.pi
+
+
+class NesaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("nesa error %d: %s" % (code, msg))
+        self.code = code
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("leaf_size", C.c_double), ("l0_max", C.c_int), ("buffer", C.c_int)]
+
+
+class EmParams(C.Structure):
+    _fields_ = [("k", C.c_double), ("eta", C.c_double)]
+
+
+class FarParams(C.Structure):
+    _fields_ = [("d0", C.c_int), ("q_min", C.c_int), ("tau", C.c_double)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_rwg", C.c_int64), ("n_tri", C.c_int64), ("L", C.c_int), ("l0", C.c_int),
+                ("n_box", C.c_int64 * 32), ("near_entries", C.c_int64),
+                ("n_pairs", C.c_int64 * 32), ("Q", C.c_int * 32)]
+
+
+class GmresParams(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("tol", C.c_double),
+                ("precond", C.c_int)]
+
+
+class GmresReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("true_rel_residual", C.c_double),
+                ("seconds", C.c_double), ("fell_back", C.c_int)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "nesa_build_tree": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(TreeParams), C.POINTER(_P)]),
+    "nesa_tree_get_info": (C.c_int, [_P, C.POINTER(TreeInfo)]),
+    "nesa_tree_perm": (C.c_int, [_P, _P]),
+    "nesa_tree_free": (None, [_P]),
+    "nesa_assemble_near": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
+    "nesa_near_entries": (C.c_int, [_P, _P, _P, C.c_int64, _P, C.c_int64, _P]),
+    "nesa_near_free": (None, [_P]),
+    "nesa_assemble_translations": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(FarParams), C.POINTER(_P)]),
+    "nesa_far_get_q": (C.c_int, [_P, _P, C.c_int]),
+    "nesa_far_free": (None, [_P]),
+    "nesa_op_create": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.POINTER(_P)]),
+    "nesa_op_free": (None, [_P]),
+    "nesa_matvec": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "nesa_matvec_leaf": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "nesa_matvec_phase_times": (C.c_int, [_P, _P, _P, _P, _P]),
+    "nesa_rhs_plane_wave_host": (C.c_int, [_P, C.c_double, _P, _P, C.c_int64, _P]),
+    "nesa_rhs_plane_wave": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
+    "nesa_gmres_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
+                                   C.POINTER(GmresReport), _P, C.c_int64, _P]),
+    "nesa_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libnesa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NesaError(-7, "libnesa.so not built (run paper_1801_03589_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise NesaError(rc, lib().nesa_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, h):
+        self.h = h
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            getattr(_lib, self._free)(self.h)
+            self.h = None
+
+
+class Tree(_Handle):
+    _free = "nesa_tree_free"
+
+    def info(self):
+        i = TreeInfo()
+        _check(lib().nesa_tree_get_info(self.h, C.byref(i)))
+        nl = i.L - i.l0 + 1
+        return {"n_rwg": i.n_rwg, "n_tri": i.n_tri, "L": i.L, "l0": i.l0,
+                "n_box": list(i.n_box[:nl]), "n_pairs": list(i.n_pairs[:nl]),
+                "near_entries": i.near_entries}
+
+    def perm(self):
+        p = np.zeros(self.info()["n_rwg"], dtype=np.int64)
+        _check(lib().nesa_tree_perm(self.h, _ptr(p)))
+        return p
+
+
+class Near(_Handle):
+    _free = "nesa_near_free"
+
+
+class Far(_Handle):
+    _free = "nesa_far_free"
+
+    def q(self, nlevels):
+        out = np.zeros(nlevels, dtype=np.int32)
+        _check(lib().nesa_far_get_q(self.h, _ptr(out), nlevels))
+        return out
+
+
+class Op(_Handle):
+    _free = "nesa_op_free"
+
+
+def build_tree(verts, tris, leaf_size=0.25, l0_max=2, buffer=1):
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    h = C.c_void_p()
+    prm = TreeParams(leaf_size, l0_max, buffer)
+    _check(lib().nesa_build_tree(_ptr(v), len(v), _ptr(t), len(t), C.byref(prm), C.byref(h)))
+    return Tree(h)
+
+
+def assemble_near(tree, k=K0, eta=ETA0):
+    h = C.c_void_p()
+    _check(lib().nesa_assemble_near(tree.h, C.byref(EmParams(k, eta)), C.byref(h)))
+    return Near(h)
+
+
+def near_entries(tree, near, rows, cols):
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros((len(r), len(c)), dtype=np.complex128)
+    _check(lib().nesa_near_entries(tree.h, near.h, _ptr(r), len(r), _ptr(c), len(c), _ptr(out)))
+    return out
+
+
+def assemble_translations(tree, k=K0, eta=ETA0, d0=3, q_min=0, tau=1e-8):
+    h = C.c_void_p()
+    _check(lib().nesa_assemble_translations(tree.h, C.byref(EmParams(k, eta)),
+                                            C.byref(FarParams(d0, q_min, tau)), C.byref(h)))
+    return Far(h)
+
+
+def op_create(tree, near, far, precision=C64, max_nrhs=1):
+    h = C.c_void_p()
+    _check(lib().nesa_op_create(tree.h, near.h, far.h, precision, max_nrhs, C.byref(h)))
+    op = Op(h)
+    op.keep = (tree, near, far)
+    op.precision = precision
+    return op
+
+
+def matvec(op, x, y, nrhs=1, stream=None):
+    _check(lib().nesa_matvec(op.h, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+
+
+def matvec_leaf(op, x, y, nrhs=1, stream=None):
+    _check(lib().nesa_matvec_leaf(op.h, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+
+
+def matvec_phase_times(op, x, y, stream=None):
+    ms = np.zeros(5, dtype=np.float32)
+    _check(lib().nesa_matvec_phase_times(op.h, _dptr(x), _dptr(y), _stream(stream), _ptr(ms)))
+    return ms
+
+
+def rhs_plane_wave_host(tree, khat, pol, k=K0):
+    kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+    po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+    n = tree.info()["n_rwg"]
+    b = np.zeros((len(kh), n), dtype=np.complex128)
+    _check(lib().nesa_rhs_plane_wave_host(tree.h, k, _ptr(kh), _ptr(po), len(kh), _ptr(b)))
+    return b
+
+
+def rhs_plane_wave(op, khat, pol, b, stream=None):
+    kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+    po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+    _check(lib().nesa_rhs_plane_wave(op.h, _ptr(kh), _ptr(po), len(kh), _dptr(b), _stream(stream)))
+
+
+def gmres_solve(op, b, x, nrhs=1, restart=30, max_iters=1000, tol=1e-6, precond=PRECOND_NONE,
+                history_len=0, stream=None, check=True):
+    prm = GmresParams(restart, max_iters, tol, precond)
+    rep = (GmresReport * nrhs)()
+    hist = np.zeros(max(1, history_len), dtype=np.float64)
+    rc = lib().nesa_gmres_solve(op.h, _dptr(b), _dptr(x), nrhs, C.byref(prm), rep,
+                                _ptr(hist), history_len, _stream(stream))
+    if check and rc not in (0, -5):
+        _check(rc)
+    reports = [{"iters": r.iters, "restarts": r.restarts, "true_rel_residual": r.true_rel_residual,
+                "seconds": r.seconds, "fell_back": r.fell_back} for r in rep]
+    return rc, reports, hist[:history_len]

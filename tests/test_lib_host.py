@@ -1,0 +1,104 @@
+"""CPU tests of the library's host side through the C ABI: exported symbols,
+tree, near-field entries and right-hand sides against the oracle, error paths.
+No GPU compute calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import efie
+from oracle.tree import Octree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nesa():
+    from paper_1801_03589_amd import nesa as n
+    n.lib()
+    return n
+
+
+def test_every_declared_symbol_is_exported(nesa):
+    hdr = open(os.path.join(ROOT, "include", "nesa.h")).read()
+    names = set(re.findall(r"\b(nesa_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) > 15
+    so = ctypes.CDLL(nesa.LIB_PATH)
+    for name in sorted(names):
+        assert hasattr(so, name), name
+
+
+@pytest.mark.parametrize("leaf", [0.25, 0.125])
+def test_tree_matches_oracle(nesa, sphere1, leaf):
+    v, t = sphere1
+    tr = nesa.build_tree(v, t, leaf)
+    info = tr.info()
+    m = efie.RWG(v, t)
+    ot = Octree(v, m.midpoints(), leaf=leaf)
+    assert (info["L"], info["l0"], info["n_rwg"]) == (ot.L, ot.l0, m.n)
+    assert info["n_box"] == [len(ot.boxes[l]) for l in range(ot.l0, ot.L + 1)]
+    assert info["n_pairs"] == [sum(len(x) for x in ot.il[l]) for l in range(ot.l0, ot.L + 1)]
+    # leaf order groups exactly the oracle's leaves
+    perm = tr.perm()
+    assert np.array_equal(np.sort(perm), np.arange(m.n))
+    leaf_seq = ot.rwg_leaf[perm]
+    changes = np.count_nonzero(np.diff(leaf_seq)) + 1
+    assert changes == len(ot.boxes[ot.L])
+
+
+def test_near_entries_match_oracle(nesa, sphere1, dense1):
+    v, t = sphere1
+    tr = nesa.build_tree(v, t, 0.25)
+    nr = nesa.assemble_near(tr)
+    m = efie.RWG(v, t)
+    ot = Octree(v, m.midpoints(), leaf=0.25)
+    for r in (0, 5, 100, 1500, 2999):
+        a = ot.rwg_leaf[r]
+        cols = np.concatenate([ot.leaf_rwgs[b] for b in ot.near[a]])
+        z = nesa.near_entries(tr, nr, [r], cols)[0]
+        assert np.abs(z - dense1[r, cols]).max() <= 1e-13 * np.abs(dense1[r, cols]).max()
+
+
+def test_rhs_matches_oracle(nesa, sphere1, rwg1):
+    tr = nesa.build_tree(*sphere1, 0.25)
+    kh = np.array([[0, 0, 1.0], [0.6, 0, 0.8]])
+    po = np.array([[1.0, 0, 0], [0, 1.0, 0]])
+    b = nesa.rhs_plane_wave_host(tr, kh, po)
+    for i in range(2):
+        bo = efie.plane_wave_rhs(rwg1, kh[i], po[i])
+        assert np.abs(b[i] - bo).max() <= 1e-13 * np.abs(bo).max()
+
+
+def test_q_rule_matches_oracle(nesa, sphere1):
+    from oracle import nesa as onesa
+    tr = nesa.build_tree(*sphere1, 0.125)
+    for d0 in (1, 3, 5):
+        far = nesa.assemble_translations(tr, d0=d0)
+        assert list(far.q(2)) == [onesa.q_rule(0.25, d0), onesa.q_rule(0.125, d0)]
+
+
+def test_error_paths(nesa):
+    v, t = synth.icosphere(2, 1.0)
+    with pytest.raises(nesa.NesaError) as e:
+        nesa.build_tree(v, t[:-1], 0.25)           # open surface
+    assert e.value.code == -4
+    bad = t.copy()
+    bad[0, 0] = len(v) + 5
+    with pytest.raises(nesa.NesaError) as e:
+        nesa.build_tree(v, bad, 0.25)
+    assert e.value.code == -1
+    with pytest.raises(nesa.NesaError):
+        nesa.build_tree(v, t, -1.0)
+    lib = nesa.lib()
+    assert lib.nesa_build_tree(None, 0, None, 0, None, None) == -1
+    assert lib.nesa_matvec(None, None, None, 1, None) == -1
+    tr = nesa.build_tree(v, t, 0.25)
+    with pytest.raises(nesa.NesaError):
+        nesa.assemble_translations(tr, d0=0)
+    # a mesh far too coarse for the leaf: equivalent sphere outside the check sphere
+    with pytest.raises(nesa.NesaError) as e:
+        nesa.assemble_translations(nesa.build_tree(*synth.icosphere(2, 1.0), 0.05))
+    assert e.value.code == -4
