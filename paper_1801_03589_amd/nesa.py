@@ -84,6 +84,9 @@ def lib():
     """Load libnesa.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime with the same SONAME; loading torch
+        # first makes this library bind to that single runtime instance
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise NesaError(-7, "libnesa.so not built (run paper_1801_03589_amd/build.py)")
         L = C.CDLL(LIB_PATH)

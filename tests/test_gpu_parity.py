@@ -142,21 +142,29 @@ def test_gmres_matches_oracle(torch_dev, nesa):
 
 
 def test_blockdiag_preconditioned_fgmres(torch_dev, nesa):
+    """Flexible GMRES with the near-field block-diagonal preconditioner against
+    the oracle's FGMRES with the per-leaf inverses of the same self blocks.
+    (For the EFIE this preconditioner slows convergence; the oracle shows the
+    same iteration count.)"""
     torch = torch_dev
     ref, tr, near, far = _case(nesa, "sphere1")
-    op = nesa.op_create(tr, near, far, nesa.C64)
-    b = torch.empty(ref.m.n, dtype=torch.complex64, device="cuda")
-    nesa.rhs_plane_wave(op, [0, 0, 1], [1, 0, 0], b)
-    x0 = torch.zeros_like(b)
-    rc0, rep0, _ = nesa.gmres_solve(op, b, x0, restart=30, max_iters=3000, tol=1e-4)
-    x1 = torch.zeros_like(b)
-    rc1, rep1, _ = nesa.gmres_solve(op, b, x1, restart=30, max_iters=3000, tol=1e-4,
+    op = nesa.op_create(tr, near, far, nesa.C128)
+    b = efie.plane_wave_rhs(ref.m, [0, 0, 1], [1, 0, 0])
+    blocks = []
+    for a, rw in enumerate(ref.t.leaf_rwgs):
+        rows, cols, Z = ref.near_block(a)
+        pos = np.array([np.nonzero(cols == r)[0][0] for r in rw])
+        blocks.append((rw, Z[:, pos]))
+    M = krylov.block_diagonal(blocks)
+    xo, info = krylov.gmres(ref.matvec, b, m=30, tol=1e-4, max_iters=3000, M=M)
+    bd = torch.from_numpy(b).cuda()
+    x1 = torch.zeros_like(bd)
+    rc1, rep1, _ = nesa.gmres_solve(op, bd, x1, restart=30, max_iters=3000, tol=1e-4,
                                     precond=nesa.PRECOND_BLOCKDIAG)
-    print("plain %d iters, block-diagonal %d iters" % (rep0[0]["iters"], rep1[0]["iters"]))
-    assert rc0 == 0 and rc1 == 0
-    assert rep1[0]["iters"] < rep0[0]["iters"]
+    print("block-diagonal FGMRES: gpu %d iters, oracle %d" % (rep1[0]["iters"], info["iters"]))
+    assert rc1 == 0
+    assert abs(rep1[0]["iters"] - info["iters"]) <= 2
     assert rep1[0]["true_rel_residual"] <= 1e-4
-    # oracle residual of the preconditioned solution
-    x = x1.cpu().numpy().astype(complex)
-    bb = b.cpu().numpy().astype(complex)
-    assert np.linalg.norm(bb - ref.matvec(x)) / np.linalg.norm(bb) <= 2e-4
+    x = x1.cpu().numpy()
+    assert np.linalg.norm(b - ref.matvec(x)) / np.linalg.norm(b) <= 1.01e-4
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
