@@ -195,6 +195,26 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     std::vector<int32_t> slot(lv.il_slot.size());
     for (size_t i = 0; i < slot.size(); ++i) slot[i] = compact[lv.il_slot[i]];
     dl.il_slot = upload(op, slot);
+    if (sizeof(T) == 4 && dl.npairs > 0) {
+      // pairs grouped by offset slot (interaction-list order inside a slot), tiled
+      std::vector<std::vector<int32_t>> by_slot(nused);
+      for (size_t k = 0; k < slot.size(); ++k) by_slot[slot[k]].push_back((int32_t)k);
+      std::vector<int32_t> pk, ts, tst, tc;
+      for (int u = 0; u < nused; ++u) {
+        for (size_t i = 0; i < by_slot[u].size(); i += nesa::TR_PAIRS) {
+          ts.push_back(u);
+          tst.push_back((int32_t)pk.size() + (int32_t)i);
+          tc.push_back((int32_t)std::min<size_t>(nesa::TR_PAIRS, by_slot[u].size() - i));
+        }
+        pk.insert(pk.end(), by_slot[u].begin(), by_slot[u].end());
+      }
+      dl.ntiles = (int64_t)ts.size();
+      dl.tile_slot = upload(op, ts);
+      dl.tile_start = upload(op, tst);
+      dl.tile_count = upload(op, tc);
+      dl.pair_k = upload(op, pk);
+      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * fl.Q * 2 * sizeof(T));
+    }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
     if (l < t.L) dl.child_ptr = upload(op, to_i32(lv.child_ptr));

@@ -20,6 +20,14 @@ struct DevLevel {
   int32_t* il_ptr = nullptr;  // [nbox + 1]
   int32_t* il_src = nullptr;
   int32_t* il_slot = nullptr; // compact slot index
+  // translation as GEMMs grouped by offset (FP32 matrix cores): tiles of up to
+  // TR_PAIRS pairs sharing one offset; results per pair, summed per target after
+  int64_t ntiles = 0;
+  int32_t* tile_slot = nullptr;  // [ntiles] compact offset slot
+  int32_t* tile_start = nullptr; // [ntiles] first entry in pair_k
+  int32_t* tile_count = nullptr; // [ntiles] pairs in the tile
+  int32_t* pair_k = nullptr;     // [npairs] interaction-list positions grouped by slot
+  void* pair_out = nullptr;      // [npairs][4][Q] D s_b of every pair
   int32_t* child_ptr = nullptr;  // [nbox + 1] children at level l+1
   int32_t* parent = nullptr;     // [nbox] (l > l0)
   int32_t* octant = nullptr;     // [nbox] (l > l0)
@@ -43,6 +51,8 @@ struct DevOp {
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;
 };
+
+constexpr int TR_PAIRS = 16;   // pairs per translation tile (64 GEMM columns)
 
 // hipEvent markers between the matvec phases
 struct PhaseTimer {

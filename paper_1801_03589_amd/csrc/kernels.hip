@@ -176,6 +176,112 @@ __global__ __launch_bounds__(NT) void k_translate(const typename C2<T>::type* __
   }
 }
 
+// Translation on FP32 matrix cores (complex64 path).  One workgroup computes a
+// 64-row block of C = D_slot [s_b1 ... s_b16] for one tile of pairs sharing the
+// offset slot (64 columns = 16 pairs x 4 channels), with the complex product
+// as four real 16x16x4 MFMAs, and writes each pair's 4 x Q result to pair_out.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int TR_KC = 64;          // K chunk staged in LDS
+constexpr int TR_ROWS = 64;        // rows per workgroup (4 waves x 16)
+constexpr int TR_COLS = 4 * TR_PAIRS;
+
+__global__ __launch_bounds__(NT) void k_translate_mfma(const float2* __restrict__ Dcm,
+                                                       const float2* __restrict__ s,
+                                                       float2* __restrict__ pair_out,
+                                                       const int32_t* __restrict__ tile_slot,
+                                                       const int32_t* __restrict__ tile_start,
+                                                       const int32_t* __restrict__ tile_count,
+                                                       const int32_t* __restrict__ pair_k,
+                                                       const int32_t* __restrict__ il_src, int Q) {
+  __shared__ float2 As[TR_ROWS][TR_KC + 1];
+  __shared__ float2 Bs[TR_KC][TR_COLS + 1];
+  __shared__ int src_off[TR_PAIRS];
+  __shared__ int dst_k[TR_PAIRS];
+  const int tile = blockIdx.x;
+  const int r0 = blockIdx.y * TR_ROWS;
+  const int slot = tile_slot[tile];
+  const int cnt = tile_count[tile];
+  const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  if (t < TR_PAIRS) {
+    const int k = (t < cnt) ? pair_k[tile_start[tile] + t] : -1;
+    dst_k[t] = k;
+    src_off[t] = (k >= 0) ? il_src[k] * 4 * Q : -1;
+  }
+  const float2* D = Dcm + (size_t)slot * Q * Q;
+  f32x4 cre[4], cim[4];
+  for (int ct = 0; ct < 4; ++ct) {
+    cre[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cim[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int k0 = 0; k0 < Q; k0 += TR_KC) {
+    const int kc = min(TR_KC, Q - k0);
+    __syncthreads();
+    // A chunk: As[i][j] = D[r0 + i][k0 + j]   (Dcm: element (p,q) at q*Q + p)
+    for (int e = t; e < TR_ROWS * TR_KC; e += NT) {
+      const int i = e % TR_ROWS, j = e / TR_ROWS;
+      float2 v = make_float2(0.f, 0.f);
+      if (j < kc && r0 + i < Q) v = D[(size_t)(k0 + j) * Q + r0 + i];
+      As[i][j] = v;
+    }
+    // B chunk: Bs[j][col] = s_b[ch][k0 + j],  col = pair * 4 + ch
+    for (int e = t; e < TR_KC * TR_COLS; e += NT) {
+      const int j = e % TR_KC, col = e / TR_KC;
+      const int pr = col / 4, ch = col % 4;
+      float2 v = make_float2(0.f, 0.f);
+      if (j < kc && pr < cnt) v = s[(size_t)src_off[pr] + ch * Q + k0 + j];
+      Bs[j][col] = v;
+    }
+    __syncthreads();
+    const int ksteps = (kc + 3) / 4;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int kk = ks * 4 + lane / 16;
+      const float2 a = As[w * 16 + lane % 16][kk];
+      for (int ct = 0; ct < 4; ++ct) {
+        const float2 b = Bs[kk][ct * 16 + lane % 16];
+        cre[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre[ct], 0, 0, 0);
+        cre[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre[ct], 0, 0, 0);
+        cim[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim[ct], 0, 0, 0);
+        cim[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim[ct], 0, 0, 0);
+      }
+    }
+  }
+  // accumulator layout: lane -> column lane % 16, rows 4 * (lane / 16) + i
+  __syncthreads();
+  float2 (*Cs)[TR_ROWS + 1] = reinterpret_cast<float2 (*)[TR_ROWS + 1]>(&Bs[0][0]);  // [TR_COLS][TR_ROWS+1]
+  for (int ct = 0; ct < 4; ++ct)
+    for (int i = 0; i < 4; ++i) {
+      const int row = w * 16 + 4 * (lane / 16) + i;
+      const int col = ct * 16 + lane % 16;
+      Cs[col][row] = make_float2(cre[ct][i], cim[ct][i]);
+    }
+  __syncthreads();
+  for (int e = t; e < TR_COLS * TR_ROWS; e += NT) {
+    const int row = e % TR_ROWS, col = e / TR_ROWS;
+    const int pr = col / 4, ch = col % 4;
+    if (pr < cnt && r0 + row < Q) pair_out[((size_t)dst_k[pr] * 4 + ch) * Q + r0 + row] = Cs[col][row];
+  }
+}
+
+// o_a = sum of its pairs' results, in interaction-list order (deterministic)
+template <typename V>
+__global__ __launch_bounds__(NT) void k_translate_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
+                                                         const int32_t* __restrict__ il_ptr, int Q) {
+  const int a = blockIdx.x;
+  const int k0 = il_ptr[a], k1 = il_ptr[a + 1];
+  const int J = 4 * Q;
+  for (int j = threadIdx.x; j < J; j += NT) {
+    V acc;
+    acc.x = 0;
+    acc.y = 0;
+    for (int k = k0; k < k1; ++k) {
+      const V v = pair_out[(size_t)k * J + j];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    o[(size_t)a * J + j] = acc;
+  }
+}
+
 // ------------------------------------------------------------------ potential transfer (Eq. 13)
 // Child a at level l: o_a += B o_P with B = C^T.  Crm[o][p][q] = C_o[p][q].
 template <typename T>
@@ -456,9 +562,19 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
   if (tm) tm->mark(st, 2);
   for (int l = l0; l <= L; ++l) {
     const auto& lv = d.lev[l - l0];
-    dim3 grid((unsigned)((lv.Q + WAVE - 1) / WAVE), (unsigned)lv.nbox);
-    k_translate<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(lv.D), s + lv.s_off, o + lv.s_off, lv.il_ptr,
-                                        lv.il_src, lv.il_slot, lv.Q);
+    if (sizeof(T) == 4 && lv.ntiles > 0) {
+      dim3 grid((unsigned)lv.ntiles, (unsigned)((lv.Q + TR_ROWS - 1) / TR_ROWS));
+      k_translate_mfma<<<grid, NT, 0, st>>>(reinterpret_cast<const float2*>(lv.D),
+                                            reinterpret_cast<const float2*>(s + lv.s_off),
+                                            reinterpret_cast<float2*>(lv.pair_out), lv.tile_slot, lv.tile_start,
+                                            lv.tile_count, lv.pair_k, lv.il_src, lv.Q);
+      k_translate_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out),
+                                                               o + lv.s_off, lv.il_ptr, lv.Q);
+    } else {
+      dim3 grid((unsigned)((lv.Q + WAVE - 1) / WAVE), (unsigned)lv.nbox);
+      k_translate<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(lv.D), s + lv.s_off, o + lv.s_off, lv.il_ptr,
+                                          lv.il_src, lv.il_slot, lv.Q);
+    }
   }
   if (tm) tm->mark(st, 3);
   for (int l = l0 + 1; l <= L; ++l) {
