@@ -161,6 +161,15 @@ int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, 
  * (Eq. 9, 14). */
 int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms);
 
+/* One product (nrhs = 1, leaf order) with a hipEvent after every kernel
+ * launch; blocks, then writes for each launch i < *count (at most
+ * max_launches): its duration ms[i], its kind[i] (1 radiation, 2 upward GEMM,
+ * 3 upward sum, 4 upward (FP64), 5 translation GEMM, 6 translation sum,
+ * 7 translation (FP64), 8 downward GEMM, 9 downward (FP64), 10 near field +
+ * reception) and the tree level[i] it works on. */
+int nesa_matvec_launch_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms,
+                             int32_t* kind, int32_t* level, int32_t max_launches, int32_t* count);
+
 /* Plane-wave right-hand sides b_m = -<e_inc, phi_m> (Sec. 2, Eq. 2),
  * e_inc = pol exp(-i k khat.r); khat, pol: host [nrhs][3].  Writes device b
  * in canonical order, RHS-major, in the op's vector precision. */

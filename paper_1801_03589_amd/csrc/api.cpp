@@ -140,6 +140,43 @@ static void invert(std::vector<cd>& A, int64_t S) {
   A.swap(I);
 }
 
+// Tiles of up to TR_PAIRS items sharing a group (items in their given order
+// inside a group).
+static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, int M, int K, int Mr, int nrt,
+                                int accumulate,
+                                const std::vector<int32_t>& group, int ngroups, const std::vector<int32_t>& src,
+                                const std::vector<int32_t>& dst) {
+  nesa::GemmPlan p;
+  p.A = A;
+  p.a_stride = a_stride;
+  p.M = M;
+  p.K = K;
+  p.Mr = Mr;
+  p.nrt = nrt;
+  p.accumulate = accumulate;
+  std::vector<std::vector<int32_t>> by(ngroups);
+  for (size_t i = 0; i < group.size(); ++i) by[group[i]].push_back((int32_t)i);
+  std::vector<int32_t> ps, pd, tg, tst, tc;
+  for (int u = 0; u < ngroups; ++u) {
+    for (size_t i = 0; i < by[u].size(); i += nesa::TR_PAIRS) {
+      tg.push_back(u);
+      tst.push_back((int32_t)ps.size() + (int32_t)i);
+      tc.push_back((int32_t)std::min<size_t>(nesa::TR_PAIRS, by[u].size() - i));
+    }
+    for (int32_t i : by[u]) {
+      ps.push_back(src[i]);
+      pd.push_back(dst[i]);
+    }
+  }
+  p.ntiles = (int64_t)tg.size();
+  p.tile_group = upload(op, tg);
+  p.tile_start = upload(op, tst);
+  p.tile_count = upload(op, tc);
+  p.pair_src = upload(op, ps);
+  p.pair_dst = upload(op, pd);
+  return p;
+}
+
 template <typename T>
 static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const nesa::Near& nr,
                       const nesa::Far& fr) {
@@ -187,32 +224,26 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     for (int s = 0; s < t.nslot(); ++s) {
       if (!fl.slot_used[s]) continue;
       compact[s] = nused++;
+      // column-major; for complex64 the rows are padded for the row blocking
       const cd* Ds = &fl.D[(size_t)s * fl.Q * fl.Q];
+      int nrt_d = 1, Qr = fl.Q;
+      if (sizeof(T) == 4) nesa::row_blocking(fl.Q, nrt_d, Qr);
       for (int q = 0; q < fl.Q; ++q)
-        for (int p = 0; p < fl.Q; ++p) Dc.push_back(Ds[(size_t)p * fl.Q + q]);
+        for (int p = 0; p < Qr; ++p) Dc.push_back(p < fl.Q ? Ds[(size_t)p * fl.Q + q] : cd(0, 0));
     }
     dl.D = upload_complex<T>(op, Dc);
     std::vector<int32_t> slot(lv.il_slot.size());
     for (size_t i = 0; i < slot.size(); ++i) slot[i] = compact[lv.il_slot[i]];
     dl.il_slot = upload(op, slot);
     if (sizeof(T) == 4 && dl.npairs > 0) {
-      // pairs grouped by offset slot (interaction-list order inside a slot), tiled
-      std::vector<std::vector<int32_t>> by_slot(nused);
-      for (size_t k = 0; k < slot.size(); ++k) by_slot[slot[k]].push_back((int32_t)k);
-      std::vector<int32_t> pk, ts, tst, tc;
-      for (int u = 0; u < nused; ++u) {
-        for (size_t i = 0; i < by_slot[u].size(); i += nesa::TR_PAIRS) {
-          ts.push_back(u);
-          tst.push_back((int32_t)pk.size() + (int32_t)i);
-          tc.push_back((int32_t)std::min<size_t>(nesa::TR_PAIRS, by_slot[u].size() - i));
-        }
-        pk.insert(pk.end(), by_slot[u].begin(), by_slot[u].end());
+      std::vector<int32_t> src(dl.npairs), dst(dl.npairs);
+      for (int64_t k = 0; k < dl.npairs; ++k) {
+        src[k] = (int32_t)lv.il_src[k];
+        dst[k] = (int32_t)k;
       }
-      dl.ntiles = (int64_t)ts.size();
-      dl.tile_slot = upload(op, ts);
-      dl.tile_start = upload(op, tst);
-      dl.tile_count = upload(op, tc);
-      dl.pair_k = upload(op, pk);
+      int nrt = 1, Qr = 0;
+      nesa::row_blocking(fl.Q, nrt, Qr);
+      dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst);
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * fl.Q * 2 * sizeof(T));
     }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
@@ -229,6 +260,29 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
             ccm[((size_t)o * Qc + q) * Qp + p] = fl.Cup[((size_t)o * Qp + p) * Qc + q];
       dl.Ccm = upload_complex<T>(op, ccm);
       dl.Crm = upload_complex<T>(op, fl.Cup);
+      if (sizeof(T) == 4) {
+        // upward: A_o = C_o (Qp x Qc), column-major, rows padded to Qpr
+        int nrt_u = 1, nrt_d = 1, Qpr = 0, Qcr = 0;
+        nesa::row_blocking(Qp, nrt_u, Qpr);
+        nesa::row_blocking(Qc, nrt_d, Qcr);
+        std::vector<cd> au((size_t)8 * Qc * Qpr, cd(0, 0)), ad((size_t)8 * Qp * Qcr, cd(0, 0));
+        for (int o = 0; o < 8; ++o)
+          for (int p = 0; p < Qp; ++p)
+            for (int q = 0; q < Qc; ++q) {
+              const cd c = fl.Cup[((size_t)o * Qp + p) * Qc + q];
+              au[((size_t)o * Qc + q) * Qpr + p] = c;      // C_o[p][q]
+              ad[((size_t)o * Qp + p) * Qcr + q] = c;      // (C_o^T)[q][p]
+            }
+        std::vector<int32_t> grp(lv.nbox), idx(lv.nbox), par(lv.nbox);
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+          grp[b] = lv.octant[b];
+          idx[b] = (int32_t)b;
+          par[b] = (int32_t)lv.parent[b];
+        }
+        dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx);
+        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * Qp * 2 * sizeof(T));
+        dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx);
+      }
     }
   }
   d.s = dev_alloc(op, (size_t)soff * 2 * sizeof(T));
@@ -619,20 +673,44 @@ int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, 
   return matvec_impl(op, x_dev, y_dev, nrhs, stream, false);
 }
 
+static void timed_matvec(nesa_op* op, const void* x_dev, void* y_dev, hipStream_t st, nesa::PhaseTimer& tm) {
+  for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+  if (op->precision == NESA_C128)
+    nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, st, &tm);
+  else
+    nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, st, &tm);
+  hip_check(hipGetLastError(), "kernel launch");
+  hip_check(hipEventSynchronize(tm.ev[tm.n - 1]), "hipEventSynchronize");
+}
+
 int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms) {
   return guarded([&]() {
     if (!op || !x_dev || !y_dev || !ms) return fail(NESA_EINVAL, "null argument");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     nesa::PhaseTimer tm;
-    for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
-    if (op->precision == NESA_C128)
-      nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, st, &tm);
-    else
-      nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, st, &tm);
-    hip_check(hipGetLastError(), "kernel launch");
-    hip_check(hipEventSynchronize(tm.ev[nesa::PhaseTimer::NMARK - 1]), "hipEventSynchronize");
+    timed_matvec(op, x_dev, y_dev, static_cast<hipStream_t>(stream), tm);
     for (int i = 0; i + 1 < nesa::PhaseTimer::NMARK; ++i)
-      hip_check(hipEventElapsedTime(&ms[i], tm.ev[i], tm.ev[i + 1]), "hipEventElapsedTime");
+      hip_check(hipEventElapsedTime(&ms[i], tm.ev[tm.phase_ev[i]], tm.ev[tm.phase_ev[i + 1]]),
+                "hipEventElapsedTime");
+    for (auto& e : tm.ev) (void)hipEventDestroy(e);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_matvec_launch_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms,
+                             int32_t* kind, int32_t* level, int32_t max_launches, int32_t* count) {
+  return guarded([&]() {
+    if (!op || !x_dev || !y_dev || !ms || !kind || !level || !count) return fail(NESA_EINVAL, "null argument");
+    nesa::PhaseTimer tm;
+    timed_matvec(op, x_dev, y_dev, static_cast<hipStream_t>(stream), tm);
+    int c = 0;
+    for (int i = 1; i < tm.n && c < max_launches; ++i) {
+      if (tm.kind[i] == 0) continue;
+      hip_check(hipEventElapsedTime(&ms[c], tm.ev[i - 1], tm.ev[i]), "hipEventElapsedTime");
+      kind[c] = tm.kind[i];
+      level[c] = tm.level[i];
+      ++c;
+    }
+    *count = c;
     for (auto& e : tm.ev) (void)hipEventDestroy(e);
     return (int)NESA_OK;
   });

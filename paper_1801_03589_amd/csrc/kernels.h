@@ -8,6 +8,22 @@
 
 namespace nesa {
 
+// Tiles of a grouped complex GEMM on the matrix cores (see k_cgemm_tiles):
+// C_pair = A_group x_src(pair), written to dst(pair) or added to it.
+struct GemmPlan {
+  const void* A = nullptr;       // [groups][K][Mr] column-major, rows padded with zeros
+  int64_t a_stride = 0;
+  int M = 0, K = 0, Mr = 0;      // Mr = row blocks x nrt x 16
+  int nrt = 1;                    // row tiles of 16 per workgroup (1..8)
+  int accumulate = 0;
+  int64_t ntiles = 0;
+  int32_t* tile_group = nullptr;
+  int32_t* tile_start = nullptr;
+  int32_t* tile_count = nullptr;
+  int32_t* pair_src = nullptr;
+  int32_t* pair_dst = nullptr;
+};
+
 // One level of the far-field hierarchy on the device.
 struct DevLevel {
   int Q = 0;
@@ -20,14 +36,11 @@ struct DevLevel {
   int32_t* il_ptr = nullptr;  // [nbox + 1]
   int32_t* il_src = nullptr;
   int32_t* il_slot = nullptr; // compact slot index
-  // translation as GEMMs grouped by offset (FP32 matrix cores): tiles of up to
-  // TR_PAIRS pairs sharing one offset; results per pair, summed per target after
-  int64_t ntiles = 0;
-  int32_t* tile_slot = nullptr;  // [ntiles] compact offset slot
-  int32_t* tile_start = nullptr; // [ntiles] first entry in pair_k
-  int32_t* tile_count = nullptr; // [ntiles] pairs in the tile
-  int32_t* pair_k = nullptr;     // [npairs] interaction-list positions grouped by slot
-  void* pair_out = nullptr;      // [npairs][4][Q] D s_b of every pair
+  GemmPlan trans;               // translation tiles (complex64): groups = offset slots
+  void* pair_out = nullptr;     // [npairs][4][Q] D s_b of every pair
+  GemmPlan up;                  // this level's children -> parents (groups = octants)
+  void* child_out = nullptr;    // [nbox][4][Q_{l-1}] C s_child of every child
+  GemmPlan down;                // parents -> this level's boxes (groups = octants, accumulate)
   int32_t* child_ptr = nullptr;  // [nbox + 1] children at level l+1
   int32_t* parent = nullptr;     // [nbox] (l > l0)
   int32_t* octant = nullptr;     // [nbox] (l > l0)
@@ -54,11 +67,36 @@ struct DevOp {
 
 constexpr int TR_PAIRS = 16;   // pairs per translation tile (64 GEMM columns)
 
-// hipEvent markers between the matvec phases
+// Row blocking of a GEMM with M rows: tiles of 16, at most 8 per workgroup,
+// every block the same size; returns (nrt, padded rows).
+inline void row_blocking(int M, int& nrt, int& Mr) {
+  const int tiles = (M + 15) / 16;
+  const int blocks = (tiles + 7) / 8;
+  nrt = (tiles + blocks - 1) / blocks;
+  Mr = blocks * nrt * 16;
+}
+
+// kernel kinds of the per-launch timing
+enum { K_RADIATE = 1, K_UP_GEMM, K_UP_REDUCE, K_UP_VALU, K_TRANS_GEMM, K_TRANS_REDUCE, K_TRANS_VALU,
+       K_DOWN_GEMM, K_DOWN_VALU, K_NEAR_RECV };
+
+// hipEvent markers between the matvec stages (phase >= 0) and after every
+// launch (kind > 0); events are recorded on the launch stream.
 struct PhaseTimer {
   static constexpr int NMARK = 6;
-  hipEvent_t ev[NMARK];
-  void mark(hipStream_t st, int i) { (void)hipEventRecord(ev[i], st); }
+  static constexpr int MAXEV = 128;
+  hipEvent_t ev[MAXEV];
+  int phase_ev[NMARK];
+  int kind[MAXEV], level[MAXEV];
+  int n = 0;
+  void mark(hipStream_t st, int phase, int lev, int k) {
+    if (n >= MAXEV) return;
+    (void)hipEventRecord(ev[n], st);
+    if (phase >= 0) phase_ev[phase] = n;
+    kind[n] = k;
+    level[n] = lev;
+    ++n;
+  }
 };
 
 template <typename T>

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(NT) void k_radiate(const typename C2<T>::type* __re
 
 // ------------------------------------------------------------------ source transfer (Eq. 11)
 // Parent P at level l-1 gathers its children at level l.  Ccm[o][q][p] = C_o[p][q].
+// Workgroup = (64-row tile of the parent, parent); wave w takes children w, w+4, ...
 template <typename T>
 __global__ __launch_bounds__(NT) void k_upward(const typename C2<T>::type* __restrict__ Ccm,
                                                const typename C2<T>::type* __restrict__ s_child,
@@ -103,33 +104,35 @@ __global__ __launch_bounds__(NT) void k_upward(const typename C2<T>::type* __res
                                                const int32_t* __restrict__ child_ptr,
                                                const int32_t* __restrict__ octant, int Qp, int Qc) {
   using V2 = typename C2<T>::type;
-  extern __shared__ unsigned char smem_raw[];
-  V2* sl = reinterpret_cast<V2*>(smem_raw);     // [4][Qc]
-  const int P = blockIdx.x;
+  __shared__ V2 red[NT / WAVE][4][WAVE];
+  const int P = blockIdx.y;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int p = blockIdx.x * WAVE + lane;
   const int c0 = child_ptr[P], c1 = child_ptr[P + 1];
-  constexpr int RP = 2;                          // rows per thread (Qp <= 512)
-  V2 acc[RP][4];
-  for (int r = 0; r < RP; ++r)
-    for (int c = 0; c < 4; ++c) acc[r][c] = cmk<T>(0, 0);
-  for (int ch = c0; ch < c1; ++ch) {
-    __syncthreads();
-    for (int j = threadIdx.x; j < 4 * Qc; j += NT) sl[j] = s_child[(size_t)ch * 4 * Qc + j];
-    __syncthreads();
-    const V2* C = Ccm + (size_t)octant[ch] * Qp * Qc;
-    for (int r = 0; r < RP; ++r) {
-      const int p = threadIdx.x + r * NT;
-      if (p < Qp) {
-        for (int q = 0; q < Qc; ++q) {
-          const V2 cv = C[(size_t)q * Qp + p];
-          for (int c = 0; c < 4; ++c) cfma(acc[r][c], cv, sl[c * Qc + q]);
-        }
+  V2 acc[4];
+  for (int c = 0; c < 4; ++c) acc[c] = cmk<T>(0, 0);
+  if (p < Qp) {
+    for (int ch = c0 + w; ch < c1; ch += NT / WAVE) {
+      const V2* C = Ccm + (size_t)octant[ch] * Qp * Qc + p;
+      const V2* sc = s_child + (size_t)ch * 4 * Qc;
+#pragma unroll 4
+      for (int q = 0; q < Qc; ++q) {
+        const V2 cv = C[(size_t)q * Qp];
+        for (int c = 0; c < 4; ++c) cfma(acc[c], cv, sc[c * Qc + q]);
       }
     }
   }
-  for (int r = 0; r < RP; ++r) {
-    const int p = threadIdx.x + r * NT;
-    if (p < Qp)
-      for (int c = 0; c < 4; ++c) s_par[(size_t)P * 4 * Qp + c * Qp + p] = acc[r][c];
+  for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
+  __syncthreads();
+  if (w == 0 && p < Qp) {
+    for (int c = 0; c < 4; ++c) {
+      V2 t = red[0][c][lane];
+      for (int ww = 1; ww < NT / WAVE; ++ww) {
+        t.x += red[ww][c][lane].x;
+        t.y += red[ww][c][lane].y;
+      }
+      s_par[(size_t)P * 4 * Qp + c * Qp + p] = t;
+    }
   }
 }
 
@@ -176,103 +179,186 @@ __global__ __launch_bounds__(NT) void k_translate(const typename C2<T>::type* __
   }
 }
 
-// Translation on FP32 matrix cores (complex64 path).  One workgroup computes a
-// 64-row block of C = D_slot [s_b1 ... s_b16] for one tile of pairs sharing the
-// offset slot (64 columns = 16 pairs x 4 channels), with the complex product
-// as four real 16x16x4 MFMAs, and writes each pair's 4 x Q result to pair_out.
+// Grouped complex GEMM on FP32 matrix cores (complex64 path), used for the
+// translations (groups = offset slots, Eq. 12) and the transfers (groups =
+// child octants, Eq. 11 and 13).  A tile holds up to 16 (source box,
+// destination) pairs sharing one group matrix A_g (M x K, stored column-major
+// with rows padded to Mr, a multiple of 16, zero rows).  One workgroup computes
+// a block of up to 8 row tiles of C = A_g [x_src1 ... x_src16] (64 columns =
+// 16 pairs x 4 channels); wave w owns column tile w (pairs 4w .. 4w+3).  The
+// complex product is four real 16x16x4 MFMAs.  Each destination is written by
+// exactly one lane in the grid (written, or added to when `accumulate`).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int TR_KC = 64;          // K chunk staged in LDS
-constexpr int TR_ROWS = 64;        // rows per workgroup (4 waves x 16)
+constexpr int TR_KC = 32;          // K chunk staged in LDS
 constexpr int TR_COLS = 4 * TR_PAIRS;
+constexpr int TR_NB = TR_KC * TR_COLS / NT;     // float2 of B per thread per chunk
 
-__global__ __launch_bounds__(NT) void k_translate_mfma(const float2* __restrict__ Dcm,
-                                                       const float2* __restrict__ s,
-                                                       float2* __restrict__ pair_out,
-                                                       const int32_t* __restrict__ tile_slot,
-                                                       const int32_t* __restrict__ tile_start,
-                                                       const int32_t* __restrict__ tile_count,
-                                                       const int32_t* __restrict__ pair_k,
-                                                       const int32_t* __restrict__ il_src, int Q) {
-  __shared__ float2 As[TR_ROWS][TR_KC + 1];
-  __shared__ float2 Bs[TR_KC][TR_COLS + 1];
+struct GemmTiles {
+  const float2* __restrict__ A;       // group matrices
+  int64_t a_stride;      // complex elements per group matrix (K * Mr)
+  int M, K, Mr;
+  const float2* __restrict__ src;     // source boxes, [box][4][K]
+  float2* __restrict__ dst;           // destinations, [index][4][M]
+  int accumulate;
+  const int32_t* tile_group;
+  const int32_t* tile_start;
+  const int32_t* tile_count;
+  const int32_t* pair_src;
+  const int32_t* pair_dst;
+};
+
+template <int NRT>
+__device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
+  constexpr int NA = TR_KC * NRT * 8 / NT;        // float4 of A per thread per chunk (NRT*16 rows)
+  constexpr int HALF = NRT * 8;                   // float4 per A column in a block
+  static_assert(TR_KC * NRT * 8 % NT == 0, "A chunk must split evenly");
+  __shared__ float4 As4[TR_KC][HALF];             // [k][row pair]
+  __shared__ float2 Bs[TR_COLS][TR_KC + 1];       // [column][k]
   __shared__ int src_off[TR_PAIRS];
-  __shared__ int dst_k[TR_PAIRS];
+  __shared__ int dst_off[TR_PAIRS];
   const int tile = blockIdx.x;
-  const int r0 = blockIdx.y * TR_ROWS;
-  const int slot = tile_slot[tile];
-  const int cnt = tile_count[tile];
+  const int r0 = blockIdx.y * NRT * 16;
+  const int cnt = g.tile_count[tile];
   const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  const int K = g.K, M = g.M;
   if (t < TR_PAIRS) {
-    const int k = (t < cnt) ? pair_k[tile_start[tile] + t] : -1;
-    dst_k[t] = k;
-    src_off[t] = (k >= 0) ? il_src[k] * 4 * Q : -1;
+    const int p = g.tile_start[tile] + min(t, cnt - 1);
+    src_off[t] = g.pair_src[p] * 4 * K;
+    dst_off[t] = g.pair_dst[p] * 4 * M;
   }
-  const float2* D = Dcm + (size_t)slot * Q * Q;
-  f32x4 cre[4], cim[4];
-  for (int ct = 0; ct < 4; ++ct) {
-    cre[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    cim[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+  const float4* A4 = reinterpret_cast<const float4*>(g.A + (size_t)g.tile_group[tile] * g.a_stride + r0);
+  const bool active = 4 * w < cnt;
+  f32x4 cre[NRT], cim[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) {
+    cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  for (int k0 = 0; k0 < Q; k0 += TR_KC) {
-    const int kc = min(TR_KC, Q - k0);
-    __syncthreads();
-    // A chunk: As[i][j] = D[r0 + i][k0 + j]   (Dcm: element (p,q) at q*Q + p)
-    for (int e = t; e < TR_ROWS * TR_KC; e += NT) {
-      const int i = e % TR_ROWS, j = e / TR_ROWS;
-      float2 v = make_float2(0.f, 0.f);
-      if (j < kc && r0 + i < Q) v = D[(size_t)(k0 + j) * Q + r0 + i];
-      As[i][j] = v;
+  float4 ra[NA];
+  float2 rb[TR_NB];
+  // per-thread staging addresses, fixed over the K loop; every load reads a
+  // valid (clamped) address and invalid elements are zeroed by a 0/1 factor
+  int a_k[NA], a_off[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int e = t + i * NT;
+    a_k[i] = e / HALF;
+    a_off[i] = e % HALF;
+  }
+  const float2* b_ptr[TR_NB];
+  int b_k[TR_NB];
+  float b_ok[TR_NB];
+#pragma unroll
+  for (int i = 0; i < TR_NB; ++i) {
+    const int e = t + i * NT;
+    const int col = e / TR_KC;
+    const int pr = col / 4, ch = col % 4;
+    b_k[i] = e % TR_KC;
+    b_ptr[i] = g.src + (size_t)src_off[pr] + ch * K;
+    b_ok[i] = pr < cnt ? 1.f : 0.f;
+  }
+  const int mr2 = g.Mr / 2;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int k = k0 + a_k[i];
+      const float4 v = A4[(size_t)min(k, K - 1) * mr2 + a_off[i]];
+      const float f = k < K ? 1.f : 0.f;
+      ra[i] = make_float4(v.x * f, v.y * f, v.z * f, v.w * f);
     }
-    // B chunk: Bs[j][col] = s_b[ch][k0 + j],  col = pair * 4 + ch
-    for (int e = t; e < TR_KC * TR_COLS; e += NT) {
-      const int j = e % TR_KC, col = e / TR_KC;
-      const int pr = col / 4, ch = col % 4;
-      float2 v = make_float2(0.f, 0.f);
-      if (j < kc && pr < cnt) v = s[(size_t)src_off[pr] + ch * Q + k0 + j];
-      Bs[j][col] = v;
+#pragma unroll
+    for (int i = 0; i < TR_NB; ++i) {
+      const int k = k0 + b_k[i];
+      const float2 v = b_ptr[i][min(k, K - 1)];
+      const float f = k < K ? b_ok[i] : 0.f;
+      rb[i] = make_float2(v.x * f, v.y * f);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += TR_KC) {
+    const int kc = min(TR_KC, K - k0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = t + i * NT;
+      As4[e / HALF][e % HALF] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < TR_NB; ++i) {
+      const int e = t + i * NT;
+      Bs[e / TR_KC][e % TR_KC] = rb[i];
     }
     __syncthreads();
-    const int ksteps = (kc + 3) / 4;
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int kk = ks * 4 + lane / 16;
-      const float2 a = As[w * 16 + lane % 16][kk];
-      for (int ct = 0; ct < 4; ++ct) {
-        const float2 b = Bs[kk][ct * 16 + lane % 16];
-        cre[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre[ct], 0, 0, 0);
-        cre[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre[ct], 0, 0, 0);
-        cim[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim[ct], 0, 0, 0);
-        cim[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim[ct], 0, 0, 0);
+    if (k0 + TR_KC < K) load(k0 + TR_KC);     // next chunk in flight during the MFMAs
+    if (active) {
+      const float2* As = reinterpret_cast<const float2*>(&As4[0][0]);
+      const int ksteps = (kc + 3) / 4;
+      for (int ks = 0; ks < ksteps; ++ks) {
+        const int kk = ks * 4 + lane / 16;
+        const float2 b = Bs[w * 16 + lane % 16][kk];
+        float2 a[NRT];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) a[r] = As[kk * (NRT * 16) + r * 16 + lane % 16];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
+          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
+        }
       }
     }
   }
-  // accumulator layout: lane -> column lane % 16, rows 4 * (lane / 16) + i
-  __syncthreads();
-  float2 (*Cs)[TR_ROWS + 1] = reinterpret_cast<float2 (*)[TR_ROWS + 1]>(&Bs[0][0]);  // [TR_COLS][TR_ROWS+1]
-  for (int ct = 0; ct < 4; ++ct)
-    for (int i = 0; i < 4; ++i) {
-      const int row = w * 16 + 4 * (lane / 16) + i;
-      const int col = ct * 16 + lane % 16;
-      Cs[col][row] = make_float2(cre[ct][i], cim[ct][i]);
+  // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
+  const int col = w * 16 + lane % 16;
+  const int pr = col / 4, ch = col % 4;
+  if (pr < cnt) {
+    float2* out = g.dst + (size_t)dst_off[pr] + ch * M;
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+        if (row < M) {
+          float2 v = make_float2(cre[r][i], cim[r][i]);
+          if (g.accumulate) {
+            const float2 o = out[row];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          out[row] = v;
+        }
+      }
     }
-  __syncthreads();
-  for (int e = t; e < TR_COLS * TR_ROWS; e += NT) {
-    const int row = e % TR_ROWS, col = e / TR_ROWS;
-    const int pr = col / 4, ch = col % 4;
-    if (pr < cnt && r0 + row < Q) pair_out[((size_t)dst_k[pr] * 4 + ch) * Q + r0 + row] = Cs[col][row];
   }
 }
 
-// o_a = sum of its pairs' results, in interaction-list order (deterministic)
+// translations (groups = offset slots) and transfers (groups = octants) get
+// their own kernel names so that profiles separate them
+template <int NRT>
+__global__ __launch_bounds__(NT) void k_translate_gemm(GemmTiles g) {
+  cgemm_tiles_body<NRT>(g);
+}
+template <int NRT>
+__global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
+  cgemm_tiles_body<NRT>(g);
+}
+
+// dst_a = sum over [ptr[a], ptr[a+1]) of the per-pair results, in order (deterministic)
 template <typename V>
-__global__ __launch_bounds__(NT) void k_translate_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
-                                                         const int32_t* __restrict__ il_ptr, int Q) {
+__global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
+                                                   const int32_t* __restrict__ ptr, int J) {
   const int a = blockIdx.x;
-  const int k0 = il_ptr[a], k1 = il_ptr[a + 1];
-  const int J = 4 * Q;
+  const int k0 = ptr[a], k1 = ptr[a + 1];
   for (int j = threadIdx.x; j < J; j += NT) {
     V acc;
     acc.x = 0;
     acc.y = 0;
+#pragma unroll 8
     for (int k = k0; k < k1; ++k) {
       const V v = pair_out[(size_t)k * J + j];
       acc.x += v.x;
@@ -284,6 +370,7 @@ __global__ __launch_bounds__(NT) void k_translate_reduce(const V* __restrict__ p
 
 // ------------------------------------------------------------------ potential transfer (Eq. 13)
 // Child a at level l: o_a += B o_P with B = C^T.  Crm[o][p][q] = C_o[p][q].
+// Workgroup = (64-row tile of the child, child); wave w takes parent rows p = w, w+4, ...
 template <typename T>
 __global__ __launch_bounds__(NT) void k_downward(const typename C2<T>::type* __restrict__ Crm,
                                                  const typename C2<T>::type* __restrict__ o_par,
@@ -291,21 +378,34 @@ __global__ __launch_bounds__(NT) void k_downward(const typename C2<T>::type* __r
                                                  const int32_t* __restrict__ parent,
                                                  const int32_t* __restrict__ octant, int Qp, int Qc) {
   using V2 = typename C2<T>::type;
-  extern __shared__ unsigned char smem_raw[];
-  V2* ol = reinterpret_cast<V2*>(smem_raw);     // [4][Qp]
-  const int a = blockIdx.x;
+  __shared__ V2 red[NT / WAVE][4][WAVE];
+  const int a = blockIdx.y;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int q = blockIdx.x * WAVE + lane;
   const int P = parent[a];
-  for (int j = threadIdx.x; j < 4 * Qp; j += NT) ol[j] = o_par[(size_t)P * 4 * Qp + j];
-  __syncthreads();
-  const V2* C = Crm + (size_t)octant[a] * Qp * Qc;
-  for (int q = threadIdx.x; q < Qc; q += NT) {
-    V2 acc[4];
-    for (int c = 0; c < 4; ++c) acc[c] = o_child[(size_t)a * 4 * Qc + c * Qc + q];
-    for (int p = 0; p < Qp; ++p) {
-      const V2 cv = C[(size_t)p * Qc + q];
-      for (int c = 0; c < 4; ++c) cfma(acc[c], cv, ol[c * Qp + p]);
+  const V2* C = Crm + (size_t)octant[a] * Qp * Qc + q;
+  const V2* op = o_par + (size_t)P * 4 * Qp;
+  V2 acc[4];
+  for (int c = 0; c < 4; ++c) acc[c] = cmk<T>(0, 0);
+  if (q < Qc) {
+#pragma unroll 4
+    for (int p = w; p < Qp; p += NT / WAVE) {
+      const V2 cv = C[(size_t)p * Qc];
+      for (int c = 0; c < 4; ++c) cfma(acc[c], cv, op[c * Qp + p]);
     }
-    for (int c = 0; c < 4; ++c) o_child[(size_t)a * 4 * Qc + c * Qc + q] = acc[c];
+  }
+  for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
+  __syncthreads();
+  if (w == 0 && q < Qc) {
+    V2* oc = o_child + (size_t)a * 4 * Qc;
+    for (int c = 0; c < 4; ++c) {
+      V2 t = oc[c * Qc + q];
+      for (int ww = 0; ww < NT / WAVE; ++ww) {
+        t.x += red[ww][c][lane].x;
+        t.y += red[ww][c][lane].y;
+      }
+      oc[c * Qc + q] = t;
+    }
   }
 }
 
@@ -366,6 +466,7 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
     __syncthreads();
     if (g < G) {
       const V2* Zp = Za + (size_t)c0 * S + t;
+#pragma unroll 8
       for (int j = g; j < cw; j += G) cfma(acc, Zp[(size_t)(j - g) * S], xs[j]);
     }
   }
@@ -454,21 +555,33 @@ __global__ __launch_bounds__(NT) void k_multidot(const V* __restrict__ basis, in
   }
 }
 
-// out[i] (+)= sum over blocks of partial[blk][i]
-__global__ void k_reduce_partials(const double2* __restrict__ partial, int nblk, int nvec,
-                                  double2* __restrict__ out, int accumulate) {
-  const int i = blockIdx.x * NT + threadIdx.x;
-  if (i >= nvec) return;
+// out[i] (+)= sum over blocks of partial[blk][i]; one workgroup per i, fixed
+// summation tree (deterministic)
+__global__ __launch_bounds__(NT) void k_reduce_partials(const double2* __restrict__ partial, int nblk, int nvec,
+                                                        double2* __restrict__ out, int accumulate) {
+  __shared__ double2 red[NT];
+  const int i = blockIdx.x;
   double2 s = make_double2(0, 0);
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += NT) {
     s.x += partial[(size_t)b * nvec + i].x;
     s.y += partial[(size_t)b * nvec + i].y;
   }
-  if (accumulate) {
-    out[i].x += s.x;
-    out[i].y += s.y;
-  } else {
-    out[i] = s;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[threadIdx.x].x += red[threadIdx.x + off].x;
+      red[threadIdx.x].y += red[threadIdx.x + off].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (accumulate) {
+      out[i].x += red[0].x;
+      out[i].y += red[0].y;
+    } else {
+      out[i] = red[0];
+    }
   }
 }
 
@@ -539,6 +652,41 @@ __global__ __launch_bounds__(NT) void k_blockdiag(const typename C2<T>::type* __
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+static void launch_tiles(const GemmPlan& p, const void* src, void* dst, hipStream_t st, bool translation) {
+  GemmTiles g;
+  g.A = static_cast<const float2*>(p.A);
+  g.a_stride = p.a_stride;
+  g.M = p.M;
+  g.K = p.K;
+  g.Mr = p.Mr;
+  g.src = static_cast<const float2*>(src);
+  g.dst = static_cast<float2*>(dst);
+  g.accumulate = p.accumulate;
+  g.tile_group = p.tile_group;
+  g.tile_start = p.tile_start;
+  g.tile_count = p.tile_count;
+  g.pair_src = p.pair_src;
+  g.pair_dst = p.pair_dst;
+  dim3 grid((unsigned)p.ntiles, (unsigned)(p.Mr / 16 / p.nrt));
+#define NESA_TILES(N)                                                   \
+  if (translation)                                                      \
+    k_translate_gemm<N><<<grid, NT, 0, st>>>(g);                        \
+  else                                                                  \
+    k_transfer_gemm<N><<<grid, NT, 0, st>>>(g);                         \
+  break;
+  switch (p.nrt) {
+    case 1: NESA_TILES(1)
+    case 2: NESA_TILES(2)
+    case 3: NESA_TILES(3)
+    case 4: NESA_TILES(4)
+    case 5: NESA_TILES(5)
+    case 6: NESA_TILES(6)
+    case 7: NESA_TILES(7)
+    default: NESA_TILES(8)
+  }
+#undef NESA_TILES
+}
+
 template <typename T>
 void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream_t st, PhaseTimer* tm) {
   using V2 = typename C2<T>::type;
@@ -548,47 +696,62 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
   V2* o = static_cast<V2*>(d.o);
   const int L = d.L, l0 = d.l0;
   const auto& LL = d.lev[L - l0];
-  if (tm) tm->mark(st, 0);
+  const bool mfma = sizeof(T) == 4;
+  if (tm) tm->mark(st, 0, -1, 0);
   k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr,
                                                  s + LL.s_off, LL.Q);
-  if (tm) tm->mark(st, 1);
+  if (tm) tm->mark(st, 1, L, K_RADIATE);
   for (int l = L; l > l0; --l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
-    size_t sh = sizeof(V2) * 4 * c.Q;
-    k_upward<T><<<(unsigned)p.nbox, NT, sh, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off,
-                                                  p.child_ptr, c.octant, p.Q, c.Q);
+    if (mfma) {
+      launch_tiles(c.up, s + c.s_off, c.child_out, st, false);
+      if (tm) tm->mark(st, -1, l, K_UP_GEMM);
+      k_csr_reduce<V2><<<(unsigned)p.nbox, NT, 0, st>>>(static_cast<const V2*>(c.child_out), s + p.s_off,
+                                                        p.child_ptr, 4 * p.Q);
+      if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
+    } else {
+      dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
+      k_upward<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off, p.child_ptr,
+                                       c.octant, p.Q, c.Q);
+      if (tm) tm->mark(st, -1, l, K_UP_VALU);
+    }
   }
-  if (tm) tm->mark(st, 2);
+  if (tm) tm->mark(st, 2, -1, 0);
   for (int l = l0; l <= L; ++l) {
     const auto& lv = d.lev[l - l0];
-    if (sizeof(T) == 4 && lv.ntiles > 0) {
-      dim3 grid((unsigned)lv.ntiles, (unsigned)((lv.Q + TR_ROWS - 1) / TR_ROWS));
-      k_translate_mfma<<<grid, NT, 0, st>>>(reinterpret_cast<const float2*>(lv.D),
-                                            reinterpret_cast<const float2*>(s + lv.s_off),
-                                            reinterpret_cast<float2*>(lv.pair_out), lv.tile_slot, lv.tile_start,
-                                            lv.tile_count, lv.pair_k, lv.il_src, lv.Q);
-      k_translate_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out),
-                                                               o + lv.s_off, lv.il_ptr, lv.Q);
+    if (mfma && lv.trans.ntiles > 0) {
+      launch_tiles(lv.trans, s + lv.s_off, lv.pair_out, st, true);
+      if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
+      k_csr_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out), o + lv.s_off,
+                                                         lv.il_ptr, 4 * lv.Q);
+      if (tm) tm->mark(st, -1, l, K_TRANS_REDUCE);
     } else {
       dim3 grid((unsigned)((lv.Q + WAVE - 1) / WAVE), (unsigned)lv.nbox);
       k_translate<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(lv.D), s + lv.s_off, o + lv.s_off, lv.il_ptr,
                                           lv.il_src, lv.il_slot, lv.Q);
+      if (tm) tm->mark(st, -1, l, K_TRANS_VALU);
     }
   }
-  if (tm) tm->mark(st, 3);
+  if (tm) tm->mark(st, 3, -1, 0);
   for (int l = l0 + 1; l <= L; ++l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
-    size_t sh = sizeof(V2) * 4 * p.Q;
-    k_downward<T><<<(unsigned)c.nbox, NT, sh, st>>>(static_cast<const V2*>(c.Crm), o + p.s_off, o + c.s_off,
-                                                    c.parent, c.octant, p.Q, c.Q);
+    if (mfma) {
+      launch_tiles(c.down, o + p.s_off, o + c.s_off, st, false);
+      if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
+    } else {
+      dim3 grid((unsigned)((c.Q + WAVE - 1) / WAVE), (unsigned)c.nbox);
+      k_downward<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(c.Crm), o + p.s_off, o + c.s_off, c.parent,
+                                         c.octant, p.Q, c.Q);
+      if (tm) tm->mark(st, -1, l, K_DOWN_VALU);
+    }
   }
-  if (tm) tm->mark(st, 4);
+  if (tm) tm->mark(st, 4, -1, 0);
   k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
                                                    d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
                                                    LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
-  if (tm) tm->mark(st, 5);
+  if (tm) tm->mark(st, 5, L, K_NEAR_RECV);
 }
 
 template <typename T>
@@ -608,7 +771,7 @@ void launch_multidot(const void* basis, int64_t ld, int nvec, const void* w, int
   using V2 = typename C2<T>::type;
   k_multidot<V2><<<nblocks, NT, 0, st>>>(static_cast<const V2*>(basis), ld, nvec, static_cast<const V2*>(w), n,
                                          partial);
-  k_reduce_partials<<<nblk(nvec), NT, 0, st>>>(partial, nblocks, nvec, out, accumulate);
+  k_reduce_partials<<<nvec, NT, 0, st>>>(partial, nblocks, nvec, out, accumulate);
 }
 template <typename T>
 void launch_combine(const void* basis, int64_t ld, int nvec, const double2* h, void* w, int64_t n, double sign,

@@ -70,6 +70,7 @@ _SIGS = {
     "nesa_matvec": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "nesa_matvec_leaf": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "nesa_matvec_phase_times": (C.c_int, [_P, _P, _P, _P, _P]),
+    "nesa_matvec_launch_times": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, _P]),
     "nesa_rhs_plane_wave_host": (C.c_int, [_P, C.c_double, _P, _P, C.c_int64, _P]),
     "nesa_rhs_plane_wave": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "nesa_gmres_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
@@ -217,6 +218,22 @@ def matvec_phase_times(op, x, y, stream=None):
     ms = np.zeros(5, dtype=np.float32)
     _check(lib().nesa_matvec_phase_times(op.h, _dptr(x), _dptr(y), _stream(stream), _ptr(ms)))
     return ms
+
+
+KIND_NAMES = {1: "radiate", 2: "upward_gemm", 3: "upward_sum", 4: "upward_fp64", 5: "translate_gemm",
+              6: "translate_sum", 7: "translate_fp64", 8: "downward_gemm", 9: "downward_fp64",
+              10: "near_recv"}
+
+
+def matvec_launch_times(op, x, y, stream=None, max_launches=128):
+    """[(kind name, level, ms)] for every kernel launch of one product."""
+    ms = np.zeros(max_launches, dtype=np.float32)
+    kind = np.zeros(max_launches, dtype=np.int32)
+    lev = np.zeros(max_launches, dtype=np.int32)
+    cnt = C.c_int32()
+    _check(lib().nesa_matvec_launch_times(op.h, _dptr(x), _dptr(y), _stream(stream), _ptr(ms), _ptr(kind),
+                                          _ptr(lev), max_launches, C.byref(cnt)))
+    return [(KIND_NAMES[int(kind[i])], int(lev[i]), float(ms[i])) for i in range(cnt.value)]
 
 
 def rhs_plane_wave_host(tree, khat, pol, k=K0):
