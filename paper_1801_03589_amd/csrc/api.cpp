@@ -140,12 +140,11 @@ static void invert(std::vector<cd>& A, int64_t S) {
   A.swap(I);
 }
 
-// Tiles of up to TR_PAIRS items sharing a group (items in their given order
-// inside a group).
+// Grouped pair lists of a GEMM plan (items in their given order inside a group);
+// the tiles for a number of right-hand sides are made by ensure_tiles.
 static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, int M, int K, int Mr, int nrt,
-                                int accumulate,
-                                const std::vector<int32_t>& group, int ngroups, const std::vector<int32_t>& src,
-                                const std::vector<int32_t>& dst) {
+                                int accumulate, const std::vector<int32_t>& group, int ngroups,
+                                const std::vector<int32_t>& src, const std::vector<int32_t>& dst) {
   nesa::GemmPlan p;
   p.A = A;
   p.a_stride = a_stride;
@@ -154,27 +153,56 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
   p.Mr = Mr;
   p.nrt = nrt;
   p.accumulate = accumulate;
+  p.ngroups = ngroups;
   std::vector<std::vector<int32_t>> by(ngroups);
   for (size_t i = 0; i < group.size(); ++i) by[group[i]].push_back((int32_t)i);
-  std::vector<int32_t> ps, pd, tg, tst, tc;
+  std::vector<int32_t> ps, pd, gs(1, 0);
+  p.group_count.resize(ngroups);
   for (int u = 0; u < ngroups; ++u) {
-    for (size_t i = 0; i < by[u].size(); i += nesa::TR_PAIRS) {
-      tg.push_back(u);
-      tst.push_back((int32_t)ps.size() + (int32_t)i);
-      tc.push_back((int32_t)std::min<size_t>(nesa::TR_PAIRS, by[u].size() - i));
-    }
     for (int32_t i : by[u]) {
       ps.push_back(src[i]);
       pd.push_back(dst[i]);
     }
+    p.group_count[u] = (int32_t)by[u].size();
+    gs.push_back((int32_t)ps.size());
   }
-  p.ntiles = (int64_t)tg.size();
-  p.tile_group = upload(op, tg);
-  p.tile_start = upload(op, tst);
-  p.tile_count = upload(op, tc);
+  p.grp_start = upload(op, gs);
   p.pair_src = upload(op, ps);
   p.pair_dst = upload(op, pd);
+  p.by_nrhs.resize(op->max_nrhs + 1);
   return p;
+}
+
+// Tiles of up to 64 (pair, channel) columns of one group for nrhs right-hand sides.
+static void ensure_tiles(nesa_op* op, nesa::GemmPlan& p, int nrhs) {
+  nesa::TileList& tl = p.by_nrhs[nrhs];
+  if (tl.tile_group) return;
+  std::vector<int32_t> tg, t0, tn;
+  for (int u = 0; u < p.ngroups; ++u) {
+    const int64_t ncols = (int64_t)p.group_count[u] * 4 * nrhs;
+    for (int64_t c = 0; c < ncols; c += 64) {
+      tg.push_back(u);
+      t0.push_back((int32_t)c);
+      tn.push_back((int32_t)std::min<int64_t>(64, ncols - c));
+    }
+  }
+  tl.ntiles = (int64_t)tg.size();
+  tl.tile_group = upload(op, tg);
+  tl.tile_col0 = upload(op, t0);
+  tl.tile_ncols = upload(op, tn);
+}
+
+template <typename T>
+static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs) {
+  if (sizeof(T) != 4) return;
+  for (size_t i = 0; i < d.lev.size(); ++i) {
+    auto& dl = d.lev[i];
+    if (dl.npairs > 0) ensure_tiles(op, dl.trans, nrhs);
+    if (i > 0) {
+      ensure_tiles(op, dl.up, nrhs);
+      ensure_tiles(op, dl.down, nrhs);
+    }
+  }
 }
 
 template <typename T>
@@ -244,7 +272,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       int nrt = 1, Qr = 0;
       nesa::row_blocking(fl.Q, nrt, Qr);
       dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst);
-      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * fl.Q * 2 * sizeof(T));
+      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * op->max_nrhs * fl.Q * 2 * sizeof(T));
     }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
@@ -280,13 +308,14 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
           par[b] = (int32_t)lv.parent[b];
         }
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx);
-        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * Qp * 2 * sizeof(T));
+        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * op->max_nrhs * Qp * 2 * sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx);
       }
     }
   }
-  d.s = dev_alloc(op, (size_t)soff * 2 * sizeof(T));
-  d.o = dev_alloc(op, (size_t)soff * 2 * sizeof(T));
+  d.max_nrhs = op->max_nrhs;
+  d.s = dev_alloc(op, (size_t)soff * op->max_nrhs * 2 * sizeof(T));
+  d.o = dev_alloc(op, (size_t)soff * op->max_nrhs * 2 * sizeof(T));
   // block-diagonal preconditioner: inverses of the self blocks
   std::vector<int64_t> moff(d.nleaf + 1, 0);
   for (int64_t a = 0; a < d.nleaf; ++a) {
@@ -311,8 +340,9 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   });
   d.Minv = upload_complex<T>(op, minv);
   d.moff = upload(op, moff);
-  op->xl = dev_alloc(op, (size_t)d.n * 2 * sizeof(T));
-  op->yl = dev_alloc(op, (size_t)d.n * 2 * sizeof(T));
+  op->xl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
+  op->yl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
+  ensure_all_tiles<T>(op, d, 1);
 }
 
 // ------------------------------------------------------------------ GMRES driver
@@ -352,7 +382,7 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * (2 * (m + 2) + 2)), "hipHostMalloc");
   Free guard{mine, hh};
   auto vec = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
-  auto matvec = [&](const void* src, void* dst) { nesa::launch_matvec_leaf<T>(d, src, dst, st, nullptr); };
+  auto matvec = [&](const void* src, void* dst) { nesa::launch_matvec_leaf<T>(d, src, dst, 1, st, nullptr); };
   auto norm = [&](const void* v) {
     nesa::launch_multidot<T>(v, n, 1, v, n, partial, nblocks, hd, 0, st);
     hip_check(hipMemcpyAsync(hh, hd, sizeof(double2), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
@@ -613,6 +643,7 @@ int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far*
     std::unique_ptr<nesa_op> op(new nesa_op());
     op->precision = precision;
     op->max_nrhs = max_nrhs;
+    if (max_nrhs > 1024) return fail(NESA_EINVAL, "max_nrhs above 1024");
     op->k = far->f->k;
     op->eta = far->f->eta;
     op->geo.rwg = tree->t->rwg;
@@ -639,26 +670,32 @@ static int matvec_impl(nesa_op* op, const void* x, void* y, int64_t nrhs, void* 
     if (!op || !x || !y) return fail(NESA_EINVAL, "null argument");
     if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n = op->precision == NESA_C128 ? op->d.n : op->f.n;
-    for (int64_t r = 0; r < nrhs; ++r) {
-      const char* xr = static_cast<const char*>(x) + (size_t)r * n * op->esize;
-      char* yr = static_cast<char*>(y) + (size_t)r * n * op->esize;
-      if (op->precision == NESA_C128) {
+    if (op->precision == NESA_C128) {
+      const int64_t n = op->d.n;
+      for (int64_t r = 0; r < nrhs; ++r) {
+        const char* xr = static_cast<const char*>(x) + (size_t)r * n * op->esize;
+        char* yr = static_cast<char*>(y) + (size_t)r * n * op->esize;
         if (canonical) {
           nesa::launch_gather<double>(xr, op->xl, op->d.perm, n, st);
-          nesa::launch_matvec_leaf<double>(op->d, op->xl, op->yl, st, nullptr);
+          nesa::launch_matvec_leaf<double>(op->d, op->xl, op->yl, 1, st, nullptr);
           nesa::launch_scatter<double>(op->yl, yr, op->d.perm, n, st);
         } else {
-          nesa::launch_matvec_leaf<double>(op->d, xr, yr, st, nullptr);
+          nesa::launch_matvec_leaf<double>(op->d, xr, yr, 1, st, nullptr);
         }
+      }
+    } else {
+      const int64_t n = op->f.n;
+      ensure_all_tiles<float>(op, op->f, (int)nrhs);
+      if (canonical) {
+        for (int64_t r = 0; r < nrhs; ++r)
+          nesa::launch_gather<float>(static_cast<const char*>(x) + (size_t)r * n * 8,
+                                     static_cast<char*>(op->xl) + (size_t)r * n * 8, op->f.perm, n, st);
+        nesa::launch_matvec_leaf<float>(op->f, op->xl, op->yl, (int)nrhs, st, nullptr);
+        for (int64_t r = 0; r < nrhs; ++r)
+          nesa::launch_scatter<float>(static_cast<const char*>(op->yl) + (size_t)r * n * 8,
+                                      static_cast<char*>(y) + (size_t)r * n * 8, op->f.perm, n, st);
       } else {
-        if (canonical) {
-          nesa::launch_gather<float>(xr, op->xl, op->f.perm, n, st);
-          nesa::launch_matvec_leaf<float>(op->f, op->xl, op->yl, st, nullptr);
-          nesa::launch_scatter<float>(op->yl, yr, op->f.perm, n, st);
-        } else {
-          nesa::launch_matvec_leaf<float>(op->f, xr, yr, st, nullptr);
-        }
+        nesa::launch_matvec_leaf<float>(op->f, x, y, (int)nrhs, st, nullptr);
       }
     }
     hip_check(hipGetLastError(), "kernel launch");
@@ -676,9 +713,9 @@ int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, 
 static void timed_matvec(nesa_op* op, const void* x_dev, void* y_dev, hipStream_t st, nesa::PhaseTimer& tm) {
   for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
   if (op->precision == NESA_C128)
-    nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, st, &tm);
+    nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, 1, st, &tm);
   else
-    nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, st, &tm);
+    nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, 1, st, &tm);
   hip_check(hipGetLastError(), "kernel launch");
   hip_check(hipEventSynchronize(tm.ev[tm.n - 1]), "hipEventSynchronize");
 }

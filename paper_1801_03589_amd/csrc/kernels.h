@@ -8,20 +8,29 @@
 
 namespace nesa {
 
-// Tiles of a grouped complex GEMM on the matrix cores (see k_cgemm_tiles):
-// C_pair = A_group x_src(pair), written to dst(pair) or added to it.
+// Tiles of a grouped complex GEMM on the matrix cores (see cgemm_tiles_body):
+// C_pair = A_group x_src(pair) for every channel, written to dst(pair) or added
+// to it.  Pairs are listed group by group; a tile is up to 64 consecutive
+// (pair, channel) columns of one group, so the tiling depends on the number of
+// right-hand sides (channels = 4 x nrhs) and is built per nrhs on first use.
+struct TileList {
+  int64_t ntiles = 0;
+  int32_t* tile_group = nullptr;
+  int32_t* tile_col0 = nullptr;
+  int32_t* tile_ncols = nullptr;
+};
 struct GemmPlan {
   const void* A = nullptr;       // [groups][K][Mr] column-major, rows padded with zeros
   int64_t a_stride = 0;
   int M = 0, K = 0, Mr = 0;      // Mr = row blocks x nrt x 16
   int nrt = 1;                    // row tiles of 16 per workgroup (1..8)
   int accumulate = 0;
-  int64_t ntiles = 0;
-  int32_t* tile_group = nullptr;
-  int32_t* tile_start = nullptr;
-  int32_t* tile_count = nullptr;
+  int ngroups = 0;
+  std::vector<int32_t> group_count;   // host copy: pairs per group
+  int32_t* grp_start = nullptr;   // [ngroups + 1]
   int32_t* pair_src = nullptr;
   int32_t* pair_dst = nullptr;
+  std::vector<TileList> by_nrhs;  // index nrhs
 };
 
 // One level of the far-field hierarchy on the device.
@@ -61,11 +70,12 @@ struct DevOp {
   void* o = nullptr;             // equivalent potentials, all levels
   void* Minv = nullptr;          // block-diagonal preconditioner (inverse self blocks)
   int64_t* moff = nullptr;
+  int max_nrhs = 1;              // right-hand sides the work buffers hold
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;
 };
 
-constexpr int TR_PAIRS = 16;   // pairs per translation tile (64 GEMM columns)
+
 
 // Row blocking of a GEMM with M rows: tiles of 16, at most 8 per workgroup,
 // every block the same size; returns (nrt, padded rows).
@@ -99,8 +109,10 @@ struct PhaseTimer {
   }
 };
 
+// y = Z_NESA x for nrhs right-hand sides in leaf order, RHS-major ([nrhs][n]).
+// The complex64 path needs the GEMM tiles of this nrhs (TileList) built.
 template <typename T>
-void launch_matvec_leaf(const DevOp<T>& d, const void* xl, void* yl, hipStream_t st, PhaseTimer* tm);
+void launch_matvec_leaf(const DevOp<T>& d, const void* xl, void* yl, int nrhs, hipStream_t st, PhaseTimer* tm);
 template <typename T>
 void launch_gather(const void* x, void* xl, const int32_t* perm, int64_t n, hipStream_t st);
 template <typename T>

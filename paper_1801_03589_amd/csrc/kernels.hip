@@ -190,19 +190,21 @@ __global__ __launch_bounds__(NT) void k_translate(const typename C2<T>::type* __
 // exactly one lane in the grid (written, or added to when `accumulate`).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int TR_KC = 32;          // K chunk staged in LDS
-constexpr int TR_COLS = 4 * TR_PAIRS;
+constexpr int TR_COLS = 64;        // GEMM columns per tile ((pair, channel) columns of one group)
 constexpr int TR_NB = TR_KC * TR_COLS / NT;     // float2 of B per thread per chunk
 
 struct GemmTiles {
   const float2* __restrict__ A;       // group matrices
   int64_t a_stride;      // complex elements per group matrix (K * Mr)
   int M, K, Mr;
-  const float2* __restrict__ src;     // source boxes, [box][4][K]
-  float2* __restrict__ dst;           // destinations, [index][4][M]
+  int NC;                // channels per box: 4 x right-hand sides
+  const float2* __restrict__ src;     // source boxes, [box][NC][K]
+  float2* __restrict__ dst;           // destinations, [index][NC][M]
   int accumulate;
   const int32_t* tile_group;
-  const int32_t* tile_start;
-  const int32_t* tile_count;
+  const int32_t* tile_col0;           // first column of the tile inside its group
+  const int32_t* tile_ncols;          // columns in the tile (<= 64)
+  const int32_t* grp_start;           // first pair of every group
   const int32_t* pair_src;
   const int32_t* pair_dst;
 };
@@ -214,21 +216,22 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   static_assert(TR_KC * NRT * 8 % NT == 0, "A chunk must split evenly");
   __shared__ float4 As4[TR_KC][HALF];             // [k][row pair]
   __shared__ float2 Bs[TR_COLS][TR_KC + 1];       // [column][k]
-  __shared__ int src_off[TR_PAIRS];
-  __shared__ int dst_off[TR_PAIRS];
+  __shared__ int col_src[TR_COLS];
+  __shared__ int col_dst[TR_COLS];
   const int tile = blockIdx.x;
   const int r0 = blockIdx.y * NRT * 16;
-  const int cnt = g.tile_count[tile];
+  const int cnt = g.tile_ncols[tile];              // valid columns
   const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
-  const int K = g.K, M = g.M;
-  if (t < TR_PAIRS) {
-    const int p = g.tile_start[tile] + min(t, cnt - 1);
-    src_off[t] = g.pair_src[p] * 4 * K;
-    dst_off[t] = g.pair_dst[p] * 4 * M;
+  const int K = g.K, M = g.M, NC = g.NC;
+  if (t < TR_COLS) {
+    const int gc = g.tile_col0[tile] + min(t, cnt - 1);   // column inside the group
+    const int p = g.grp_start[g.tile_group[tile]] + gc / NC, c = gc % NC;
+    col_src[t] = (g.pair_src[p] * NC + c) * K;
+    col_dst[t] = (g.pair_dst[p] * NC + c) * M;
   }
   __syncthreads();
   const float4* A4 = reinterpret_cast<const float4*>(g.A + (size_t)g.tile_group[tile] * g.a_stride + r0);
-  const bool active = 4 * w < cnt;
+  const bool active = 16 * w < cnt;
   f32x4 cre[NRT], cim[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) {
@@ -253,10 +256,9 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   for (int i = 0; i < TR_NB; ++i) {
     const int e = t + i * NT;
     const int col = e / TR_KC;
-    const int pr = col / 4, ch = col % 4;
     b_k[i] = e % TR_KC;
-    b_ptr[i] = g.src + (size_t)src_off[pr] + ch * K;
-    b_ok[i] = pr < cnt ? 1.f : 0.f;
+    b_ptr[i] = g.src + (size_t)col_src[col];
+    b_ok[i] = col < cnt ? 1.f : 0.f;
   }
   const int mr2 = g.Mr / 2;
   auto load = [&](int k0) {
@@ -315,9 +317,8 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   }
   // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
   const int col = w * 16 + lane % 16;
-  const int pr = col / 4, ch = col % 4;
-  if (pr < cnt) {
-    float2* out = g.dst + (size_t)dst_off[pr] + ch * M;
+  if (col < cnt) {
+    float2* out = g.dst + (size_t)col_dst[col];
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
 #pragma unroll
@@ -511,6 +512,181 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
   }
 }
 
+template <typename V>
+__global__ void k_fill_zero(V* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) {
+    V z;
+    z.x = 0;
+    z.y = 0;
+    p[i] = z;
+  }
+}
+
+// ------------------------------------------------------------------ several right-hand sides
+// Equivalent vectors hold NC = 4 R channels per box, channel c of RHS r at
+// c * R + r.  Radiation, near field and reception read V and Z once per block
+// of RB right-hand sides.
+constexpr int RB = 8;
+
+template <typename V2>
+__global__ __launch_bounds__(NT) void k_radiate_multi(const V2* __restrict__ V, const V2* __restrict__ x,
+                                                      const int32_t* __restrict__ leaf_ptr, V2* __restrict__ s,
+                                                      int Q, int R, int64_t n) {
+  __shared__ V2 xs[RB][64];
+  const int b = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
+  const int p0 = leaf_ptr[b], S = leaf_ptr[b + 1] - p0;
+  const int J = 4 * Q;
+  V2 acc[2][RB];
+  for (int u = 0; u < 2; ++u)
+    for (int r = 0; r < RB; ++r) acc[u][r].x = acc[u][r].y = 0;
+  for (int i0 = 0; i0 < S; i0 += 64) {
+    const int ni = min(64, S - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < RB * 64; e += NT) {
+      const int r = e / 64, i = e % 64;
+      if (r < nr && i < ni) xs[r][i] = x[(size_t)(r0 + r) * n + p0 + i0 + i];
+    }
+    __syncthreads();
+    for (int u = 0; u < 2; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < J) {
+        for (int i = 0; i < ni; ++i) {
+          const V2 v = V[(size_t)(p0 + i0 + i) * J + j];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) cfma(acc[u][r], v, xs[r][i]);
+        }
+      }
+    }
+  }
+  for (int u = 0; u < 2; ++u) {
+    const int j = threadIdx.x + u * NT;
+    if (j < J) {
+      const int c = j / Q, q = j % Q;
+      for (int r = 0; r < nr; ++r) s[((size_t)b * 4 * R + c * R + r0 + r) * Q + q] = acc[u][r];
+    }
+  }
+}
+
+template <typename V2>
+__global__ __launch_bounds__(NT) void k_near_multi(const V2* __restrict__ Z, const int64_t* __restrict__ zoff,
+                                                   const int32_t* __restrict__ leaf_ptr,
+                                                   const int32_t* __restrict__ near_ptr,
+                                                   const int32_t* __restrict__ near_idx, const V2* __restrict__ x,
+                                                   V2* __restrict__ y, int R, int64_t n) {
+  constexpr int CW = 256;
+  __shared__ V2 xs[RB][CW];
+  __shared__ V2 red[RB][NT];
+  __shared__ int seg_col[MAX_NEAR + 1];
+  __shared__ int seg_x[MAX_NEAR];
+  const int a = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
+  const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
+  const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int k = 0; k < nn; ++k) {
+      const int b = near_idx[n0 + k];
+      seg_col[k] = c;
+      seg_x[k] = leaf_ptr[b];
+      c += leaf_ptr[b + 1] - leaf_ptr[b];
+    }
+    seg_col[nn] = c;
+  }
+  __syncthreads();
+  const int W = seg_col[nn];
+  const V2* Za = Z + zoff[a];
+  const int G = NT / S;
+  const int t = threadIdx.x, g = t / S;
+  V2 acc[RB];
+  for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = 0;
+  for (int c0 = 0; c0 < W; c0 += CW) {
+    const int cw = min(CW, W - c0);
+    __syncthreads();
+    for (int e = t; e < RB * CW; e += NT) {
+      const int r = e / CW, j = e % CW;
+      if (r < nr && j < cw) {
+        const int col = c0 + j;
+        int k = 0;
+        while (seg_col[k + 1] <= col) ++k;
+        xs[r][j] = x[(size_t)(r0 + r) * n + seg_x[k] + (col - seg_col[k])];
+      }
+    }
+    __syncthreads();
+    if (g < G) {
+      const V2* Zp = Za + (size_t)c0 * S + t;
+      for (int j = g; j < cw; j += G) {
+        const V2 zv = Zp[(size_t)(j - g) * S];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cfma(acc[r], zv, xs[r][j]);
+      }
+    }
+  }
+  for (int r = 0; r < RB; ++r) red[r][t] = acc[r];
+  __syncthreads();
+  for (int e = t; e < nr * S; e += NT) {
+    const int r = e / S, m = e % S;
+    V2 v = red[r][m];
+    for (int gg = 1; gg < G; ++gg) {
+      v.x += red[r][gg * S + m].x;
+      v.y += red[r][gg * S + m].y;
+    }
+    y[(size_t)(r0 + r) * n + p0 + m] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_recv_multi(const typename C2<T>::type* __restrict__ V,
+                                                   const typename C2<T>::type* __restrict__ o,
+                                                   const int32_t* __restrict__ leaf_ptr,
+                                                   typename C2<T>::type* __restrict__ y, int Q, int R, int64_t n,
+                                                   T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 ow[RB][4 * MAX_QL / 2];
+  const int a = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
+  const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
+  const int J = 4 * Q;
+  for (int e = threadIdx.x; e < RB * J; e += NT) {
+    const int r = e / J, j = e % J;
+    if (r < nr) {
+      const int c = j / Q, q = j % Q;
+      const V2 ov = o[((size_t)a * 4 * R + c * R + r0 + r) * Q + q];
+      const V2 wv = (c < 3) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
+      ow[r][j] = cmul(ov, wv);
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  constexpr int PL = 4 * MAX_QL / 2 / WAVE;      // V values per lane
+  for (int row = wv; row < S; row += NT / WAVE) {
+    const V2* Vr = V + (size_t)(p0 + row) * J;
+    V2 vv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int j = lane + k * WAVE;
+      vv[k] = (j < J) ? Vr[j] : cmk<T>(0, 0);
+    }
+    for (int r = 0; r < nr; ++r) {
+      V2 sum = cmk<T>(0, 0);
+#pragma unroll
+      for (int k = 0; k < PL; ++k) {
+        const int j = lane + k * WAVE;
+        if (j < J) cfma(sum, vv[k], ow[r][j]);
+      }
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        sum.x += __shfl_xor(sum.x, off);
+        sum.y += __shfl_xor(sum.y, off);
+      }
+      if (lane == 0) {
+        V2* yp = y + (size_t)(r0 + r) * n + p0 + row;
+        V2 out = *yp;
+        out.x += sum.x;
+        out.y += sum.y;
+        *yp = out;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ vector ops (GMRES)
 // partial[blk][i] = sum over the block's chunk of conj(basis_i) * w, FP64
 // accumulation; basis vectors taken 8 at a time.
@@ -652,22 +828,27 @@ __global__ __launch_bounds__(NT) void k_blockdiag(const typename C2<T>::type* __
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
-static void launch_tiles(const GemmPlan& p, const void* src, void* dst, hipStream_t st, bool translation) {
+static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st,
+                         bool translation) {
+  const TileList& tl = p.by_nrhs[nrhs];
   GemmTiles g;
   g.A = static_cast<const float2*>(p.A);
   g.a_stride = p.a_stride;
   g.M = p.M;
   g.K = p.K;
   g.Mr = p.Mr;
+  g.NC = 4 * nrhs;
   g.src = static_cast<const float2*>(src);
   g.dst = static_cast<float2*>(dst);
   g.accumulate = p.accumulate;
-  g.tile_group = p.tile_group;
-  g.tile_start = p.tile_start;
-  g.tile_count = p.tile_count;
+  g.tile_group = tl.tile_group;
+  g.tile_col0 = tl.tile_col0;
+  g.tile_ncols = tl.tile_ncols;
+  g.grp_start = p.grp_start;
   g.pair_src = p.pair_src;
   g.pair_dst = p.pair_dst;
-  dim3 grid((unsigned)p.ntiles, (unsigned)(p.Mr / 16 / p.nrt));
+  if (tl.ntiles == 0) return;
+  dim3 grid((unsigned)tl.ntiles, (unsigned)(p.Mr / 16 / p.nrt));
 #define NESA_TILES(N)                                                   \
   if (translation)                                                      \
     k_translate_gemm<N><<<grid, NT, 0, st>>>(g);                        \
@@ -688,7 +869,7 @@ static void launch_tiles(const GemmPlan& p, const void* src, void* dst, hipStrea
 }
 
 template <typename T>
-void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream_t st, PhaseTimer* tm) {
+void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hipStream_t st, PhaseTimer* tm) {
   using V2 = typename C2<T>::type;
   const V2* xl = static_cast<const V2*>(xl_);
   V2* yl = static_cast<V2*>(yl_);
@@ -697,18 +878,26 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
   const int L = d.L, l0 = d.l0;
   const auto& LL = d.lev[L - l0];
   const bool mfma = sizeof(T) == 4;
+  const int NC = 4 * R;
+  const unsigned rblk = (unsigned)((R + RB - 1) / RB);
+  if (!mfma && R != 1) return;   // the complex128 path takes one right-hand side at a time
   if (tm) tm->mark(st, 0, -1, 0);
-  k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr,
-                                                 s + LL.s_off, LL.Q);
+  if (R == 1) {
+    k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr, s + LL.s_off, LL.Q);
+  } else {
+    if constexpr (sizeof(T) == 4)
+      k_radiate_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr,
+                                                                       s + LL.s_off * R, LL.Q, R, d.n);
+  }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
   for (int l = L; l > l0; --l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
     if (mfma) {
-      launch_tiles(c.up, s + c.s_off, c.child_out, st, false);
+      launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
-      k_csr_reduce<V2><<<(unsigned)p.nbox, NT, 0, st>>>(static_cast<const V2*>(c.child_out), s + p.s_off,
-                                                        p.child_ptr, 4 * p.Q);
+      k_csr_reduce<V2><<<(unsigned)p.nbox, NT, 0, st>>>(static_cast<const V2*>(c.child_out), s + p.s_off * R,
+                                                        p.child_ptr, NC * p.Q);
       if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
     } else {
       dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
@@ -720,12 +909,15 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
   if (tm) tm->mark(st, 2, -1, 0);
   for (int l = l0; l <= L; ++l) {
     const auto& lv = d.lev[l - l0];
-    if (mfma && lv.trans.ntiles > 0) {
-      launch_tiles(lv.trans, s + lv.s_off, lv.pair_out, st, true);
+    if (mfma && lv.npairs > 0) {
+      launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, st, true);
       if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
-      k_csr_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out), o + lv.s_off,
-                                                         lv.il_ptr, 4 * lv.Q);
+      k_csr_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out), o + lv.s_off * R,
+                                                         lv.il_ptr, NC * lv.Q);
       if (tm) tm->mark(st, -1, l, K_TRANS_REDUCE);
+    } else if (mfma) {
+      const int64_t cnt = lv.nbox * NC * lv.Q;
+      k_fill_zero<V2><<<(unsigned)((cnt + NT - 1) / NT), NT, 0, st>>>(o + lv.s_off * R, cnt);
     } else {
       dim3 grid((unsigned)((lv.Q + WAVE - 1) / WAVE), (unsigned)lv.nbox);
       k_translate<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(lv.D), s + lv.s_off, o + lv.s_off, lv.il_ptr,
@@ -738,7 +930,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
     if (mfma) {
-      launch_tiles(c.down, o + p.s_off, o + c.s_off, st, false);
+      launch_tiles(c.down, R, o + p.s_off * R, o + c.s_off * R, st, false);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
     } else {
       dim3 grid((unsigned)((c.Q + WAVE - 1) / WAVE), (unsigned)c.nbox);
@@ -748,9 +940,20 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, hipStream
     }
   }
   if (tm) tm->mark(st, 4, -1, 0);
-  k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
-                                                   d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
-                                                   LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+  if (R == 1) {
+    k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
+                                                     d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
+                                                     LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+  } else {
+    if constexpr (sizeof(T) == 4) {
+      k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,
+                                                                    d.leaf_ptr, d.near_ptr, d.near_idx, xl, yl, R,
+                                                                    d.n);
+      k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off * R,
+                                                                   d.leaf_ptr, yl, LL.Q, R, d.n, (T)d.w[0],
+                                                                   (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+    }
+  }
   if (tm) tm->mark(st, 5, L, K_NEAR_RECV);
 }
 
@@ -797,7 +1000,7 @@ void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st)
 }
 
 #define NESA_INST(T)                                                                                         \
-  template void launch_matvec_leaf<T>(const DevOp<T>&, const void*, void*, hipStream_t, PhaseTimer*);         \
+  template void launch_matvec_leaf<T>(const DevOp<T>&, const void*, void*, int, hipStream_t, PhaseTimer*);    \
   template void launch_gather<T>(const void*, void*, const int32_t*, int64_t, hipStream_t);                  \
   template void launch_scatter<T>(const void*, void*, const int32_t*, int64_t, hipStream_t);                 \
   template void launch_multidot<T>(const void*, int64_t, int, const void*, int64_t, double2*, int, double2*, \
