@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--nu", type=int, default=82, help="icosphere frequency (82: 201,720 unknowns)")
     p.add_argument("--radius", type=float, default=4.0)
     p.add_argument("--precision", default="c64", choices=["c64", "c128", "split"])
+    p.add_argument("--nrhs", type=int, default=1)
     p.add_argument("--gmres-iters", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-leaves", type=int, default=24)

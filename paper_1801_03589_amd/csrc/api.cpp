@@ -140,6 +140,39 @@ static void invert(std::vector<cd>& A, int64_t S) {
   A.swap(I);
 }
 
+// bf16 split planes of group matrices given column-major ([g][k][Mr]) on the host
+static uint16_t bf16_rne_host(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+static float bf16_to_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float v;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+static void attach_split(nesa_op* op, nesa::GemmPlan& p, const std::vector<cd>& Acm, int ngroups) {
+  const int Kp = (p.K + 31) / 32 * 32;
+  const size_t plane = (size_t)p.Mr * Kp;
+  std::vector<uint16_t> As((size_t)ngroups * 4 * plane, 0);
+  for (int gi = 0; gi < ngroups; ++gi)
+    for (int k = 0; k < p.K; ++k)
+      for (int m = 0; m < p.Mr; ++m) {
+        const cd v = Acm[((size_t)gi * p.K + k) * p.Mr + m];
+        const float re = (float)v.real(), im = (float)v.imag();
+        const uint16_t rh = bf16_rne_host(re), ih = bf16_rne_host(im);
+        const uint16_t rl = bf16_rne_host(re - bf16_to_float(rh)), il = bf16_rne_host(im - bf16_to_float(ih));
+        const size_t base = (size_t)gi * 4 * plane + (size_t)m * Kp + k;
+        As[base] = rh;
+        As[base + plane] = rl;
+        As[base + 2 * plane] = ih;
+        As[base + 3 * plane] = il;
+      }
+  p.A_split = upload(op, As);
+  p.Kp = Kp;
+}
+
 // Grouped pair lists of a GEMM plan (items in their given order inside a group);
 // the tiles for a number of right-hand sides are made by ensure_tiles.
 static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, int M, int K, int Mr, int nrt,
@@ -156,6 +189,9 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
   p.ngroups = ngroups;
   std::vector<std::vector<int32_t>> by(ngroups);
   for (size_t i = 0; i < group.size(); ++i) by[group[i]].push_back((int32_t)i);
+  // inside a group, pairs ordered by source box (neighbouring tiles read
+  // neighbouring source vectors)
+  for (auto& v : by) std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) { return src[x] < src[y]; });
   std::vector<int32_t> ps, pd, gs(1, 0);
   p.group_count.resize(ngroups);
   for (int u = 0; u < ngroups; ++u) {
@@ -166,30 +202,41 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
     p.group_count[u] = (int32_t)by[u].size();
     gs.push_back((int32_t)ps.size());
   }
-  p.grp_start = upload(op, gs);
-  p.pair_src = upload(op, ps);
-  p.pair_dst = upload(op, pd);
+  p.h_src = ps;
+  p.h_dst = pd;
   p.by_nrhs.resize(op->max_nrhs + 1);
   return p;
 }
 
-// Tiles of up to 64 (pair, channel) columns of one group for nrhs right-hand sides.
+// Tiles of up to 64 (pair, channel) columns of one group for nrhs right-hand
+// sides, with the source / destination offset of every column precomputed.
 static void ensure_tiles(nesa_op* op, nesa::GemmPlan& p, int nrhs) {
   nesa::TileList& tl = p.by_nrhs[nrhs];
   if (tl.tile_group) return;
-  std::vector<int32_t> tg, t0, tn;
+  const int NC = 4 * nrhs;
+  std::vector<int32_t> tg, tn;
+  std::vector<int64_t> cs, cdst;
+  int64_t pstart = 0;
   for (int u = 0; u < p.ngroups; ++u) {
-    const int64_t ncols = (int64_t)p.group_count[u] * 4 * nrhs;
-    for (int64_t c = 0; c < ncols; c += 64) {
+    const int64_t ncols = (int64_t)p.group_count[u] * NC;
+    for (int64_t c0 = 0; c0 < ncols; c0 += 64) {
+      const int64_t nc = std::min<int64_t>(64, ncols - c0);
       tg.push_back(u);
-      t0.push_back((int32_t)c);
-      tn.push_back((int32_t)std::min<int64_t>(64, ncols - c));
+      tn.push_back((int32_t)nc);
+      for (int j = 0; j < 64; ++j) {
+        const int64_t gc = c0 + std::min<int64_t>(j, nc - 1);
+        const int64_t pi = pstart + gc / NC, c = gc % NC;
+        cs.push_back(((int64_t)p.h_src[pi] * NC + c) * p.K);
+        cdst.push_back(((int64_t)p.h_dst[pi] * NC + c) * p.M);
+      }
     }
+    pstart += p.group_count[u];
   }
   tl.ntiles = (int64_t)tg.size();
   tl.tile_group = upload(op, tg);
-  tl.tile_col0 = upload(op, t0);
   tl.tile_ncols = upload(op, tn);
+  tl.col_src = upload(op, cs);
+  tl.col_dst = upload(op, cdst);
 }
 
 template <typename T>
@@ -272,6 +319,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       int nrt = 1, Qr = 0;
       nesa::row_blocking(fl.Q, nrt, Qr);
       dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst);
+      if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.trans, Dc, nused);
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * op->max_nrhs * fl.Q * 2 * sizeof(T));
     }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
@@ -308,8 +356,10 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
           par[b] = (int32_t)lv.parent[b];
         }
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx);
+        if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
         dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * op->max_nrhs * Qp * 2 * sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx);
+        if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.down, ad, 8);
       }
     }
   }
@@ -639,7 +689,6 @@ int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far*
     if (precision != NESA_C128 && precision != NESA_C64 && precision != NESA_C64_SPLIT)
       return fail(NESA_EINVAL, "unknown precision");
     if (max_nrhs < 1) return fail(NESA_EINVAL, "max_nrhs must be >= 1");
-    if (precision == NESA_C64_SPLIT) return fail(NESA_ENOTIMPL, "split precision not available");
     std::unique_ptr<nesa_op> op(new nesa_op());
     op->precision = precision;
     op->max_nrhs = max_nrhs;

@@ -16,20 +16,21 @@ namespace nesa {
 struct TileList {
   int64_t ntiles = 0;
   int32_t* tile_group = nullptr;
-  int32_t* tile_col0 = nullptr;
   int32_t* tile_ncols = nullptr;
+  int64_t* col_src = nullptr;     // [ntiles][64] source offsets
+  int64_t* col_dst = nullptr;     // [ntiles][64] destination offsets
 };
 struct GemmPlan {
   const void* A = nullptr;       // [groups][K][Mr] column-major, rows padded with zeros
+  const void* A_split = nullptr; // split precision: [groups][4 planes][Mr][Kp] bf16 (re hi, re lo, im hi, im lo)
+  int Kp = 0;                    // K rounded up to 32
   int64_t a_stride = 0;
   int M = 0, K = 0, Mr = 0;      // Mr = row blocks x nrt x 16
   int nrt = 1;                    // row tiles of 16 per workgroup (1..8)
   int accumulate = 0;
   int ngroups = 0;
-  std::vector<int32_t> group_count;   // host copy: pairs per group
-  int32_t* grp_start = nullptr;   // [ngroups + 1]
-  int32_t* pair_src = nullptr;
-  int32_t* pair_dst = nullptr;
+  std::vector<int32_t> group_count;   // host: pairs per group
+  std::vector<int32_t> h_src, h_dst;  // host: pairs, group by group
   std::vector<TileList> by_nrhs;  // index nrhs
 };
 

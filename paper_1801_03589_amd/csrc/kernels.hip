@@ -197,17 +197,24 @@ struct GemmTiles {
   const float2* __restrict__ A;       // group matrices
   int64_t a_stride;      // complex elements per group matrix (K * Mr)
   int M, K, Mr;
-  int NC;                // channels per box: 4 x right-hand sides
   const float2* __restrict__ src;     // source boxes, [box][NC][K]
   float2* __restrict__ dst;           // destinations, [index][NC][M]
   int accumulate;
+  int64_t ntiles;
   const int32_t* tile_group;
-  const int32_t* tile_col0;           // first column of the tile inside its group
-  const int32_t* tile_ncols;          // columns in the tile (<= 64)
-  const int32_t* grp_start;           // first pair of every group
-  const int32_t* pair_src;
-  const int32_t* pair_dst;
+  const int32_t* tile_ncols;          // valid columns of the tile (<= 64)
+  const int64_t* col_src;             // [tile][64] source offsets (complex elements)
+  const int64_t* col_dst;             // [tile][64] destination offsets
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin; tile = xcd_tile(blockIdx)
+// gives every XCD a contiguous range of tiles, so the group matrices (tiles
+// are ordered by group) and source boxes stay in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t t = (bid % 8) * per + bid / 8;
+  return t;
+}
 
 template <int NRT>
 __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
@@ -216,18 +223,17 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   static_assert(TR_KC * NRT * 8 % NT == 0, "A chunk must split evenly");
   __shared__ float4 As4[TR_KC][HALF];             // [k][row pair]
   __shared__ float2 Bs[TR_COLS][TR_KC + 1];       // [column][k]
-  __shared__ int col_src[TR_COLS];
-  __shared__ int col_dst[TR_COLS];
-  const int tile = blockIdx.x;
+  __shared__ int64_t col_src[TR_COLS];
+  __shared__ int64_t col_dst[TR_COLS];
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
+  if (tile >= g.ntiles) return;
   const int r0 = blockIdx.y * NRT * 16;
   const int cnt = g.tile_ncols[tile];              // valid columns
   const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
-  const int K = g.K, M = g.M, NC = g.NC;
+  const int K = g.K, M = g.M;
   if (t < TR_COLS) {
-    const int gc = g.tile_col0[tile] + min(t, cnt - 1);   // column inside the group
-    const int p = g.grp_start[g.tile_group[tile]] + gc / NC, c = gc % NC;
-    col_src[t] = (g.pair_src[p] * NC + c) * K;
-    col_dst[t] = (g.pair_dst[p] * NC + c) * M;
+    col_src[t] = g.col_src[tile * TR_COLS + t];
+    col_dst[t] = g.col_dst[tile * TR_COLS + t];
   }
   __syncthreads();
   const float4* A4 = reinterpret_cast<const float4*>(g.A + (size_t)g.tile_group[tile] * g.a_stride + r0);
@@ -257,7 +263,7 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
     const int e = t + i * NT;
     const int col = e / TR_KC;
     b_k[i] = e % TR_KC;
-    b_ptr[i] = g.src + (size_t)col_src[col];
+    b_ptr[i] = g.src + col_src[col];
     b_ok[i] = col < cnt ? 1.f : 0.f;
   }
   const int mr2 = g.Mr / 2;
@@ -318,7 +324,7 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
   const int col = w * 16 + lane % 16;
   if (col < cnt) {
-    float2* out = g.dst + (size_t)col_dst[col];
+    float2* out = g.dst + col_dst[col];
 #pragma unroll
     for (int r = 0; r < NRT; ++r) {
 #pragma unroll
@@ -336,6 +342,170 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       }
     }
   }
+}
+
+// Split-precision variant (complex64 vectors, bf16x3 products): every FP32
+// value v is split as hi = bf16(v), lo = bf16(v - hi); a real product is
+// hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMAs with FP32 accumulation.  A is
+// pre-split on the host into four planes (re hi, re lo, im hi, im lo), each
+// [Mr][Kp] with k contiguous (Kp = K rounded up to 32, zero padded); B is split
+// in the kernel from the FP32 tile in LDS.  Fragment layout of the 16x16x32
+// instruction: lane l holds rows/columns l % 16 and k = 8 (l / 16) .. +7.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float v) {
+  const unsigned u = __float_as_uint(v);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ void split_bf16(float v, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_rne(v);
+  lo = bf16_rne(v - __uint_as_float((unsigned)hi << 16));
+}
+
+template <int NRT>
+__device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, const unsigned short* __restrict__ As,
+                                                        int Kp) {
+  static_assert(TR_KC == 32, "one bf16 MFMA k-step per chunk");
+  __shared__ uint4 Al[4][NRT * 16][4];                        // [plane][row][8 k], split planes of A
+  __shared__ float2 Bs[TR_COLS][TR_KC + 1];                   // [column][k] FP32 B, split in place
+  __shared__ int64_t col_src[TR_COLS];
+  __shared__ int64_t col_dst[TR_COLS];
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
+  if (tile >= g.ntiles) return;
+  const int r0 = blockIdx.y * NRT * 16;
+  const int cnt = g.tile_ncols[tile];
+  const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  const int K = g.K, M = g.M;
+  if (t < TR_COLS) {
+    col_src[t] = g.col_src[tile * TR_COLS + t];
+    col_dst[t] = g.col_dst[tile * TR_COLS + t];
+  }
+  __syncthreads();
+  const bool active = 16 * w < cnt;
+  const size_t plane = (size_t)g.Mr * Kp;
+  const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 4 * plane + (size_t)r0 * Kp;
+  f32x4 cre[NRT], cim[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) {
+    cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  // A staging: NRT x 16 B per thread per chunk (4 planes x NRT*16 rows x 4 quarters of 8 k)
+  uint4 ra[NRT];
+  const uint4* a_ptr[NRT];
+#pragma unroll
+  for (int i = 0; i < NRT; ++i) {
+    const int e = t + i * NT;
+    const int pl = e / (NRT * 16 * 4), row = (e / 4) % (NRT * 16), qu = e % 4;
+    a_ptr[i] = reinterpret_cast<const uint4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
+  }
+  // B staging: TR_NB float2 per thread per chunk
+  float2 rb[TR_NB];
+  const float2* b_ptr[TR_NB];
+  int b_k[TR_NB];
+  float b_ok[TR_NB];
+#pragma unroll
+  for (int i = 0; i < TR_NB; ++i) {
+    const int e = t + i * NT;
+    const int col = e / TR_KC;
+    b_k[i] = e % TR_KC;
+    b_ptr[i] = g.src + col_src[col];
+    b_ok[i] = col < cnt ? 1.f : 0.f;
+  }
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NRT; ++i) ra[i] = a_ptr[i][k0 / 8];
+#pragma unroll
+    for (int i = 0; i < TR_NB; ++i) {
+      const int k = k0 + b_k[i];
+      const float2 v = b_ptr[i][min(k, K - 1)];
+      const float f = k < K ? b_ok[i] : 0.f;
+      rb[i] = make_float2(v.x * f, v.y * f);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += TR_KC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NRT; ++i) {
+      const int e = t + i * NT;
+      Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < TR_NB; ++i) {
+      const int e = t + i * NT;
+      Bs[e / TR_KC][e % TR_KC] = rb[i];
+    }
+    __syncthreads();
+    if (k0 + TR_KC < K) load(k0 + TR_KC);
+    if (active) {
+      // B fragments of this wave's column tile as bf16 hi / lo planes
+      bf16x8 brh, brl, bih, bil, nbih, nbil;
+      const float2* bcol = &Bs[w * 16 + lane % 16][8 * (lane / 16)];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float2 v = bcol[j];
+        unsigned short h, l;
+        split_bf16(v.x, h, l);
+        brh[j] = __builtin_bit_cast(__bf16, h);
+        brl[j] = __builtin_bit_cast(__bf16, l);
+        split_bf16(v.y, h, l);
+        bih[j] = __builtin_bit_cast(__bf16, h);
+        bil[j] = __builtin_bit_cast(__bf16, l);
+        nbih[j] = __builtin_bit_cast(__bf16, (unsigned short)(h ^ 0x8000u));
+        nbil[j] = __builtin_bit_cast(__bf16, (unsigned short)(l ^ 0x8000u));
+      }
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        const int row = r * 16 + lane % 16, qu = lane / 16;
+        const bf16x8 arh = __builtin_bit_cast(bf16x8, Al[0][row][qu]);
+        const bf16x8 arl = __builtin_bit_cast(bf16x8, Al[1][row][qu]);
+        const bf16x8 aih = __builtin_bit_cast(bf16x8, Al[2][row][qu]);
+        const bf16x8 ail = __builtin_bit_cast(bf16x8, Al[3][row][qu]);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbih, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbil, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nbih, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, cim[r], 0, 0, 0);
+      }
+    }
+  }
+  const int col = w * 16 + lane % 16;
+  if (col < cnt) {
+    float2* out = g.dst + col_dst[col];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+        if (row < M) {
+          float2 v = make_float2(cre[r][i], cim[r][i]);
+          if (g.accumulate) {
+            const float2 o = out[row];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          out[row] = v;
+        }
+      }
+    }
+  }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(NT) void k_translate_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp) {
+  cgemm_tiles_bf16x3_body<NRT>(g, As, Kp);
+}
+template <int NRT>
+__global__ __launch_bounds__(NT) void k_transfer_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp) {
+  cgemm_tiles_bf16x3_body<NRT>(g, As, Kp);
 }
 
 // translations (groups = offset slots) and transfers (groups = octants) get
@@ -837,23 +1007,28 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
   g.M = p.M;
   g.K = p.K;
   g.Mr = p.Mr;
-  g.NC = 4 * nrhs;
   g.src = static_cast<const float2*>(src);
   g.dst = static_cast<float2*>(dst);
   g.accumulate = p.accumulate;
+  g.ntiles = tl.ntiles;
   g.tile_group = tl.tile_group;
-  g.tile_col0 = tl.tile_col0;
   g.tile_ncols = tl.tile_ncols;
-  g.grp_start = p.grp_start;
-  g.pair_src = p.pair_src;
-  g.pair_dst = p.pair_dst;
+  g.col_src = tl.col_src;
+  g.col_dst = tl.col_dst;
   if (tl.ntiles == 0) return;
-  dim3 grid((unsigned)tl.ntiles, (unsigned)(p.Mr / 16 / p.nrt));
-#define NESA_TILES(N)                                                   \
-  if (translation)                                                      \
-    k_translate_gemm<N><<<grid, NT, 0, st>>>(g);                        \
-  else                                                                  \
-    k_transfer_gemm<N><<<grid, NT, 0, st>>>(g);                         \
+  dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)(p.Mr / 16 / p.nrt));
+#define NESA_TILES(N)                                                                        \
+  if (p.A_split) {                                                                           \
+    const unsigned short* As = static_cast<const unsigned short*>(p.A_split);                \
+    if (translation)                                                                         \
+      k_translate_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                          \
+    else                                                                                     \
+      k_transfer_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                           \
+  } else if (translation) {                                                                  \
+    k_translate_gemm<N><<<grid, NT, 0, st>>>(g);                                             \
+  } else {                                                                                   \
+    k_transfer_gemm<N><<<grid, NT, 0, st>>>(g);                                              \
+  }                                                                                          \
   break;
   switch (p.nrt) {
     case 1: NESA_TILES(1)

@@ -184,3 +184,19 @@ def test_matvec_multi_rhs(torch_dev, nesa, nrhs):
         assert err <= TOL["c64"], (r, err)
     Y1 = _run(torch_dev, nesa, op, X[nrhs - 1])
     assert np.linalg.norm(Y1 - Y[nrhs - 1]) <= 1e-6 * np.linalg.norm(Y1)
+
+
+@pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
+def test_matvec_split_precision(torch_dev, nesa, name):
+    """Translations and transfers as split-bf16 (hi*hi + hi*lo + lo*hi) matrix-core
+    products with FP32 accumulation: error against the FP64 oracle is reported
+    and bounded by the bf16x3 product error (about 2^-16 per product)."""
+    ref, tr, near, far = _case(nesa, name)
+    op = nesa.op_create(tr, near, far, nesa.C64_SPLIT, max_nrhs=2)
+    X = synth.complex_normal((2, ref.m.n), 20)
+    Y = _run(torch_dev, nesa, op, X, nrhs=2)
+    for r in range(2):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("%s split-bf16x3 rhs %d: rel err vs FP64 oracle %.3e" % (name, r, err))
+        assert err <= 1e-4
