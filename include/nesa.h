@@ -181,7 +181,21 @@ int nesa_rhs_plane_wave(nesa_op* op, const double* khat, const double* pol, int6
 int nesa_rhs_plane_wave_host(const nesa_tree* tree, double k, const double* khat, const double* pol,
                              int64_t nrhs, double* b);
 
-typedef enum { NESA_PRECOND_NONE = 0, NESA_PRECOND_BLOCKDIAG = 1, NESA_PRECOND_LEARNED = 2 } nesa_precond;
+/* Preconditioners (right, inside flexible GMRES):
+ *   BLOCKDIAG  z_a = Z_aa^-1 r_a with Z_aa the near-field self block of leaf a;
+ *   SCHWARZ    restricted additive Schwarz over the near lists: z_a = rows of
+ *              leaf a of Z_N^-1 r_N, Z_N the near-field matrix restricted to
+ *              the RWGs of the near list of a (setup on the host at first use);
+ *   LEARNED    a base preconditioner plus a per-leaf MLP correction (nesa_mlp);
+ *              falls back to BLOCKDIAG when a restart does not reduce the true
+ *              residual or the network output is not finite. */
+typedef enum { NESA_PRECOND_NONE = 0, NESA_PRECOND_BLOCKDIAG = 1, NESA_PRECOND_LEARNED = 2,
+               NESA_PRECOND_SCHWARZ = 3 } nesa_precond;
+
+/* Build the data of a preconditioner now instead of at its first use. */
+int nesa_precond_setup(nesa_op* op, int precond);
+/* z = M r for one vector in leaf order (BLOCKDIAG or SCHWARZ), on `stream`. */
+int nesa_precond_apply(nesa_op* op, int precond, const void* r_dev, void* z_dev, void* stream);
 
 /* Restarted GMRES(m) (flexible when a preconditioner is used) around the
  * NESA product: Arnoldi with two passes of classical Gram-Schmidt, FP64 dot

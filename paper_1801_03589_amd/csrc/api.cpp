@@ -31,6 +31,9 @@ struct nesa_far {
 
 struct nesa_op {
   int precision = NESA_C64;
+  const nesa::Tree* tree = nullptr;     // setup data for preconditioners built on demand
+  const nesa::Near* near = nullptr;
+  void* schwarz = nullptr;              // device arena of the Schwarz preconditioner (lazy)
   int max_nrhs = 1;
   double k = 0, eta = 0;
   nesa::Tree geo;                       // copy of the RWG geometry (right-hand sides)
@@ -395,6 +398,19 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   ensure_all_tiles<T>(op, d, 1);
 }
 
+// Schwarz preconditioner: built on the host at first use, uploaded in the
+// near-block layout of the op's precision
+static void ensure_schwarz(nesa_op* op) {
+  if (op->schwarz) return;
+  std::unique_ptr<nesa::Near> P(nesa::near_schwarz(*op->tree, *op->near, op->precision != NESA_C128));
+  if (op->precision == NESA_C128)
+    op->schwarz = upload_complex<double>(op, P->z);
+  else
+    op->schwarz = upload_complex<float>(op, P->z);
+}
+
+int nesa_precond_setup(nesa_op* op, int precond);
+
 // ------------------------------------------------------------------ GMRES driver
 template <typename T>
 static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c, const nesa_gmres_params& prm,
@@ -440,7 +456,9 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
     return std::sqrt(std::max(0.0, hh[0].x));
   };
   auto precond = [&](const void* r, void* z) {
-    if (prm.precond == NESA_PRECOND_BLOCKDIAG || prm.precond == NESA_PRECOND_LEARNED) {
+    if (prm.precond == NESA_PRECOND_SCHWARZ) {
+      nesa::launch_near_apply<T>(d, op->schwarz, r, z, st);
+    } else if (prm.precond == NESA_PRECOND_BLOCKDIAG || prm.precond == NESA_PRECOND_LEARNED) {
       nesa::launch_blockdiag<T>(d, r, z, st);
     } else {
       hip_check(hipMemcpyAsync(z, r, n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
@@ -696,6 +714,8 @@ int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far*
     op->k = far->f->k;
     op->eta = far->f->eta;
     op->geo.rwg = tree->t->rwg;
+    op->tree = tree->t.get();
+    op->near = near->n.get();
     if (precision == NESA_C128) {
       op->esize = 16;
       build_dev<double>(op.get(), op->d, *tree->t, *near->n, *far->f);
@@ -837,6 +857,37 @@ int nesa_rhs_plane_wave(nesa_op* op, const double* khat, const double* pol, int6
   });
 }
 
+int nesa_precond_setup(nesa_op* op, int precond) {
+  return guarded([&]() {
+    if (!op) return fail(NESA_EINVAL, "null argument");
+    if (precond == NESA_PRECOND_SCHWARZ) ensure_schwarz(op);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_precond_apply(nesa_op* op, int precond, const void* r_dev, void* z_dev, void* stream) {
+  return guarded([&]() {
+    if (!op || !r_dev || !z_dev) return fail(NESA_EINVAL, "null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (precond == NESA_PRECOND_SCHWARZ) {
+      ensure_schwarz(op);
+      if (op->precision == NESA_C128)
+        nesa::launch_near_apply<double>(op->d, op->schwarz, r_dev, z_dev, st);
+      else
+        nesa::launch_near_apply<float>(op->f, op->schwarz, r_dev, z_dev, st);
+    } else if (precond == NESA_PRECOND_BLOCKDIAG) {
+      if (op->precision == NESA_C128)
+        nesa::launch_blockdiag<double>(op->d, r_dev, z_dev, st);
+      else
+        nesa::launch_blockdiag<float>(op->f, r_dev, z_dev, st);
+    } else {
+      return fail(NESA_EINVAL, "preconditioner cannot be applied on its own");
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+    return (int)NESA_OK;
+  });
+}
+
 int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, const nesa_gmres_params* params,
                      nesa_gmres_report* report, double* history, int64_t history_len, void* stream) {
   return guarded([&]() {
@@ -844,7 +895,8 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
     if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
     if (params->restart < 1 || params->restart > 250 || params->max_iters < 1 || !(params->tol > 0))
       return fail(NESA_EINVAL, "bad GMRES parameters");
-    if (params->precond < 0 || params->precond > 2) return fail(NESA_EINVAL, "unknown preconditioner");
+    if (params->precond < 0 || params->precond > 3) return fail(NESA_EINVAL, "unknown preconditioner");
+    if (params->precond == NESA_PRECOND_SCHWARZ) ensure_schwarz(op);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = op->geo.rwg.n;
     int worst = NESA_OK;

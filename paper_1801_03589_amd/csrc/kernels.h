@@ -130,5 +130,8 @@ template <typename T>
 void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st);
 template <typename T>
 void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st);
+// y = arena x with an arena in the near-block layout (leaf order, one RHS)
+template <typename T>
+void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st);
 
 }  // namespace nesa

@@ -104,5 +104,8 @@ Near* assemble_near(const Tree& t, double k, double eta);
 Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);
+// Rows of the restricted near-field inverses (Schwarz preconditioner), in the
+// layout of the near blocks; `single` computes the factorisations in FP32.
+Near* near_schwarz(const Tree& t, const Near& near, bool single);
 
 }  // namespace nesa

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnesa.so")
 
 C128, C64, C64_SPLIT = 0, 1, 2
-PRECOND_NONE, PRECOND_BLOCKDIAG, PRECOND_LEARNED = 0, 1, 2
+PRECOND_NONE, PRECOND_BLOCKDIAG, PRECOND_LEARNED, PRECOND_SCHWARZ = 0, 1, 2, 3
 ETA0 = 376.730313668
 K0 = 2.0 * np.pi
 
@@ -75,6 +75,8 @@ _SIGS = {
     "nesa_rhs_plane_wave": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "nesa_gmres_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
                                    C.POINTER(GmresReport), _P, C.c_int64, _P]),
+    "nesa_precond_setup": (C.c_int, [_P, C.c_int]),
+    "nesa_precond_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "nesa_last_error": (C.c_char_p, []),
 }
 
@@ -249,6 +251,15 @@ def rhs_plane_wave(op, khat, pol, b, stream=None):
     kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
     po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
     _check(lib().nesa_rhs_plane_wave(op.h, _ptr(kh), _ptr(po), len(kh), _dptr(b), _stream(stream)))
+
+
+def precond_setup(op, precond):
+    _check(lib().nesa_precond_setup(op.h, precond))
+
+
+def precond_apply(op, precond, r, z, stream=None):
+    """z = M r (leaf order, one vector)."""
+    _check(lib().nesa_precond_apply(op.h, precond, _dptr(r), _dptr(z), _stream(stream)))
 
 
 def gmres_solve(op, b, x, nrhs=1, restart=30, max_iters=1000, tol=1e-6, precond=PRECOND_NONE,

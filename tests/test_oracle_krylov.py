@@ -54,3 +54,47 @@ def test_block_diagonal_preconditioner_is_blockwise_inverse():
     A = block_diag(*[B for _, B in blocks])
     x, info = krylov.gmres(lambda v: A @ v, r, m=5, tol=1e-12, M=M)
     assert info["iters"] == 1
+
+
+def test_near_schwarz_exact_when_blocks_decouple():
+    """With a block-diagonal system whose near lists hold only the leaf itself,
+    the Schwarz preconditioner is the exact inverse."""
+    rng = np.random.default_rng(5)
+    sizes = [4, 6, 5]
+    leaf_rwgs, off = [], 0
+    for s_ in sizes:
+        leaf_rwgs.append(np.arange(off, off + s_))
+        off += s_
+    Z = np.zeros((off, off), dtype=complex)
+    for rw in leaf_rwgs:
+        Z[np.ix_(rw, rw)] = np.eye(len(rw)) * 2 + 0.3 * rng.standard_normal((len(rw), len(rw)))
+    near = [[0], [1], [2]]
+    M = krylov.near_schwarz(leaf_rwgs, near, lambda a: (leaf_rwgs[a], leaf_rwgs[a], Z[np.ix_(leaf_rwgs[a], leaf_rwgs[a])]),
+                            lambda b, c: b == c)
+    r = synth.complex_normal(off, 6)
+    assert np.linalg.norm(Z @ M(r) - r) <= 1e-12 * np.linalg.norm(r)
+
+
+def test_near_schwarz_chain_matches_restricted_inverse():
+    """Three leaves in a chain, near lists = neighbours: z_a equals the rows of
+    the inverse of the restricted near-field matrix, built here by hand."""
+    rng = np.random.default_rng(7)
+    leaf_rwgs = [np.arange(0, 3), np.arange(3, 7), np.arange(7, 9)]
+    n = 9
+    Z = np.eye(n) * 3 + 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    near = [[0, 1], [0, 1, 2], [1, 2]]
+    is_near = lambda b, c: abs(b - c) <= 1
+    nb_fn = lambda a: (leaf_rwgs[a], np.concatenate([leaf_rwgs[b] for b in near[a]]),
+                       Z[np.ix_(leaf_rwgs[a], np.concatenate([leaf_rwgs[b] for b in near[a]]))])
+    M = krylov.near_schwarz(leaf_rwgs, near, nb_fn, is_near)
+    r = synth.complex_normal(n, 8)
+    z = M(r)
+    # leaf 1: all three leaves, but leaves 0 and 2 are not near each other
+    cols = np.arange(9)
+    ZN = Z.copy()
+    ZN[np.ix_(leaf_rwgs[0], leaf_rwgs[2])] = 0
+    ZN[np.ix_(leaf_rwgs[2], leaf_rwgs[0])] = 0
+    assert np.allclose(z[leaf_rwgs[1]], (np.linalg.inv(ZN) @ r)[leaf_rwgs[1]], atol=1e-12)
+    cols0 = np.arange(7)
+    assert np.allclose(z[leaf_rwgs[0]], (np.linalg.inv(Z[np.ix_(cols0, cols0)]) @ r[cols0])[leaf_rwgs[0]],
+                       atol=1e-12)
