@@ -90,11 +90,17 @@ typedef struct {
  *     Q_l = (ceil(kr + 1.8 d0^(2/3) (kr)^(1/3)) + 1)^2, r = (sqrt3/2) a_l.
  *   q_min: lower bound on Q_l (0 = none).
  *   tau: Tikhonov parameter of the fitting operator, relative to the largest
- *     singular value of G(check points, equivalent points). */
+ *     singular value of G(check points, equivalent points).
+ *   eps: the equivalent points of a box sit on the complex radius
+ *     r_e (1 + i eps) (complex source points, distance = principal square root
+ *     of the summed squared coordinate differences); 0 gives real points,
+ *     which lose accuracy on every box whose k r_e is near a zero of a
+ *     spherical Bessel function j_n.  Range [0, 1); 0.1 is the usual value. */
 typedef struct {
   int d0;
   int q_min;
   double tau;
+  double eps;
 } nesa_far_params;
 
 typedef struct {

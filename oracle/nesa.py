@@ -14,9 +14,14 @@ the groups, with auxiliary sources on spheres in 3D.  Reading taken here:
 * channels: the mixed-potential EFIE kernel splits into four scalar channels
   sharing g, densities f = (phi_x, phi_y, phi_z, div phi) with weights
   w = (-i eta k, -i eta k, -i eta k, +i eta / k);
-* per level l: Q_l equivalent points on a sphere of radius r_e and 4 Q_l check
-  points on radius r_c (Fibonacci spirals), the same for every box of the level
-  (translated to the box centre);
+* per level l: Q_l equivalent points on a sphere of complex radius
+  r_e (1 + i eps) (complex source points; eps = 0.1) and 4 Q_l check points on
+  the real radius r_c (Fibonacci spirals), the same for every box of the level
+  (translated to the box centre).  The Green's function of a complex point
+  uses the principal square root of sum_d (x_d - e_d)^2.  Monopoles on a real
+  sphere cannot radiate the spherical modes n with j_n(k r_e) = 0, which spoils
+  the fit of every box whose k r_e sits near such a zero; the complex radius
+  keeps every mode strength j_n(k r_e (1 + i eps)) away from zero;
 * Q_l = (ceil(kr + 1.8 d0^(2/3) (kr)^(1/3)) + 1)^2, r = (sqrt 3 / 2) a_l
   (excess-bandwidth count);
 * r_e at the leaf level = 1.02 x the largest distance from a leaf centre to a
@@ -68,8 +73,13 @@ def tikhonov_pinv(G, tau):
 
 
 def gmat(A, B, k=efie.K0):
-    """G[i, j] = g(|A_i - B_j|)."""
-    R = np.linalg.norm(A[:, None, :] - B[None, :, :], axis=-1)
+    """G[i, j] = g(R_ij), R_ij = sqrt(sum_d (A_id - B_jd)^2); the points may be
+    complex (complex source points), then R is the principal square root."""
+    d = A[:, None, :] - B[None, :, :]
+    if np.iscomplexobj(d):
+        R = np.sqrt((d * d).sum(axis=-1))
+    else:
+        R = np.linalg.norm(d, axis=-1)
     return efie.green(R, k)
 
 
@@ -77,7 +87,7 @@ class NesaOracle:
     """NESA operator of a closed mesh, built from the mesh alone."""
 
     def __init__(self, verts, tris, leaf=0.25, d0=3, tau=1e-9, buffer=1,
-                 k=efie.K0, eta=efie.ETA0, l0_max=2):
+                 k=efie.K0, eta=efie.ETA0, l0_max=2, eps=0.1):
         self.m = efie.RWG(verts, tris)
         self.k, self.eta, self.tau, self.d0 = k, eta, tau, d0
         self.w = weights(k, eta)
@@ -100,7 +110,8 @@ class NesaOracle:
             if self.re[l] >= 1.5 * t.side(l):
                 raise ValueError("equivalent sphere radius exceeds 1.5 box sides at level %d "
                                  "(mesh too coarse for this leaf size)" % l)
-        self.E = {l: self.re[l] * fibonacci_sphere(self.Q[l]) for l in self.levels}
+        self.eps = eps
+        self.E = {l: self.re[l] * (1.0 + 1j * eps) * fibonacci_sphere(self.Q[l]) for l in self.levels}
         self.X = {l: self.rc[l] * fibonacci_sphere(4 * self.Q[l]) for l in self.levels}
         self.R = {l: tikhonov_pinv(gmat(self.X[l], self.E[l], k), tau) for l in self.levels}
         self._V = {}

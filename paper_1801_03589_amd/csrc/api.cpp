@@ -684,7 +684,8 @@ int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em, 
     if (!tree || !em || !params || !out) return fail(NESA_EINVAL, "null argument");
     if (!(em->k > 0) || !(em->eta > 0)) return fail(NESA_EINVAL, "k and eta must be positive");
     std::unique_ptr<nesa_far> h(new nesa_far());
-    h->f.reset(nesa::assemble_far(*tree->t, em->k, em->eta, params->d0, params->q_min, params->tau));
+    h->f.reset(nesa::assemble_far(*tree->t, em->k, em->eta, params->d0, params->q_min, params->tau,
+                                          params->eps));
     *out = h.release();
     return (int)NESA_OK;
   });

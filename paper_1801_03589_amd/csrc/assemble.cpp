@@ -271,7 +271,7 @@ static int q_rule(double side, int d0, int q_min, double k) {
   return std::max(p * p, q_min);
 }
 
-static void fibonacci(int n, double radius, std::vector<double>& out) {
+static void fibonacci(int n, cd radius, std::vector<cd>& out) {
   out.resize(3 * n);
   const double ga = PI * (3.0 - std::sqrt(5.0));
   for (int i = 0; i < n; ++i) {
@@ -294,15 +294,22 @@ struct CMat {
   const cd& operator()(int64_t i, int64_t j) const { return a[j * m + i]; }
 };
 
-// G[i][j] = g(|A_i + shift - B_j|)
-static CMat gmat(const std::vector<double>& A, P3 shift, const std::vector<double>& B, double k) {
+// G[i][j] = g(R_ij) with R_ij the principal square root of
+// sum_d (A_id + shift_d - B_jd)^2; the points may be complex (complex source
+// points), real points are complex with zero imaginary part.
+static CMat gmat(const std::vector<cd>& A, P3 shift, const std::vector<cd>& B, double k) {
   int64_t na = A.size() / 3, nb = B.size() / 3;
   CMat G(na, nb);
+  const double sh[3] = {shift.x, shift.y, shift.z};
   for (int64_t j = 0; j < nb; ++j)
     for (int64_t i = 0; i < na; ++i) {
-      P3 d = {A[3 * i] + shift.x - B[3 * j], A[3 * i + 1] + shift.y - B[3 * j + 1],
-              A[3 * i + 2] + shift.z - B[3 * j + 2]};
-      G(i, j) = green(norm(d), k);
+      cd r2 = 0;
+      for (int d = 0; d < 3; ++d) {
+        cd e = A[3 * i + d] + sh[d] - B[3 * j + d];
+        r2 += e * e;
+      }
+      cd R = std::sqrt(r2);
+      G(i, j) = std::exp(cd(0.0, -k) * R) / (4.0 * PI * R);
     }
   return G;
 }
@@ -388,13 +395,15 @@ static CMat tikhonov_fit(const CMat& G, double tau) {
   return X;
 }
 
-Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau) {
-  if (d0 < 1 || q_min < 0 || !(tau > 0) || !(tau < 1)) throw Error(-1, "bad far-field parameters");
+Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau, double eps) {
+  if (d0 < 1 || q_min < 0 || !(tau > 0) || !(tau < 1) || !(eps >= 0) || !(eps < 1))
+    throw Error(-1, "bad far-field parameters");
   std::unique_ptr<Far> F(new Far());
   F->k = k;
   F->eta = eta;
   F->d0 = d0;
   F->tau = tau;
+  F->eps = eps;
   const Rwg& r = t.rwg;
   const int nl = t.L - t.l0 + 1;
   F->lev.resize(nl);
@@ -428,8 +437,8 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
                           " (mesh too coarse for the leaf size)");
     fl.Q = q_rule(side, d0, q_min, k);
     fl.M = 4 * fl.Q;
-    fibonacci(fl.Q, fl.re, fl.E);
-    fibonacci(fl.M, fl.rc, fl.X);
+    fibonacci(fl.Q, cd(fl.re, eps * fl.re), fl.E);
+    fibonacci(fl.M, cd(fl.rc, 0.0), fl.X);
     R[l - t.l0] = tikhonov_fit(gmat(fl.X, {0, 0, 0}, fl.E, k), tau);
   }
   // radiation matrices V: [pos][4][Q_L]
@@ -457,7 +466,8 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
             P3 rq = {r.qp[9 * T + 3 * q], r.qp[9 * T + 3 * q + 1], r.qp[9 * T + 3 * q + 2]};
             P3 ph = mul(sub(rq, pv), cv);
             for (int j = 0; j < M; ++j) {
-              P3 x = {c[0] + fl.X[3 * j], c[1] + fl.X[3 * j + 1], c[2] + fl.X[3 * j + 2]};
+              P3 x = {c[0] + fl.X[3 * j].real(), c[1] + fl.X[3 * j + 1].real(),
+                      c[2] + fl.X[3 * j + 2].real()};
               cd g = green(norm(sub(x, rq)), k) * w;
               Gs[((size_t)0 * M + j) * S + i] += g * ph.x;
               Gs[((size_t)1 * M + j) * S + i] += g * ph.y;

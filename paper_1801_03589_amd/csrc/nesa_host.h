@@ -81,7 +81,7 @@ struct Near {
 struct FarLevel {
   int Q = 0, M = 0;
   double re = 0, rc = 0;
-  std::vector<double> E, X;         // [Q][3], [M][3] on spheres of radius re, rc
+  std::vector<cd> E, X;             // [Q][3] on the complex radius re (1 + i eps), [M][3] on rc
   std::vector<cd> Cup;              // [8][Q_{l-1}][Q_l] row-major (l > l0)
   std::vector<cd> D;                // [nslot][Q][Q] row-major, D[p][q] = g(E_p + d - E_q)
   std::vector<uint8_t> slot_used;
@@ -91,6 +91,7 @@ struct Far {
   double k = 0, eta = 0;
   int d0 = 3;
   double tau = 1e-8;
+  double eps = 0.1;
   std::vector<FarLevel> lev;        // lev[l - l0]
   std::vector<cd> V;                // [N leaf order][4][Q_L]
 };
@@ -101,7 +102,7 @@ void parallel_for(int64_t n, const std::function<void(int64_t)>& fn);
 Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
                  double leaf, int l0_max, int buffer);
 Near* assemble_near(const Tree& t, double k, double eta);
-Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau);
+Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau, double eps);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);
 // Rows of the restricted near-field inverses (Schwarz preconditioner), in the

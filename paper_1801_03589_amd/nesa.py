@@ -34,7 +34,7 @@ class EmParams(C.Structure):
 
 
 class FarParams(C.Structure):
-    _fields_ = [("d0", C.c_int), ("q_min", C.c_int), ("tau", C.c_double)]
+    _fields_ = [("d0", C.c_int), ("q_min", C.c_int), ("tau", C.c_double), ("eps", C.c_double)]
 
 
 class TreeInfo(C.Structure):
@@ -192,10 +192,10 @@ def near_entries(tree, near, rows, cols):
     return out
 
 
-def assemble_translations(tree, k=K0, eta=ETA0, d0=3, q_min=0, tau=1e-8):
+def assemble_translations(tree, k=K0, eta=ETA0, d0=3, q_min=0, tau=1e-8, eps=0.1):
     h = C.c_void_p()
     _check(lib().nesa_assemble_translations(tree.h, C.byref(EmParams(k, eta)),
-                                            C.byref(FarParams(d0, q_min, tau)), C.byref(h)))
+                                            C.byref(FarParams(d0, q_min, tau, eps)), C.byref(h)))
     return Far(h)
 
 
