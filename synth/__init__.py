@@ -6,7 +6,7 @@ function, no tree.  Both sides of every parity test take their inputs from
 here and nothing else.
 """
 from .meshes import icosphere, capped_cylinder, box_mesh, spheroid, aircraft_like, body_family
-from .vectors import complex_normal
+from .vectors import complex_normal, mlp_weights
 
 __all__ = ["icosphere", "capped_cylinder", "box_mesh", "spheroid", "aircraft_like",
-           "body_family", "complex_normal"]
+           "body_family", "complex_normal", "mlp_weights"]
