@@ -192,9 +192,11 @@ int nesa_rhs_plane_wave_host(const nesa_tree* tree, double k, const double* khat
  *   SCHWARZ    restricted additive Schwarz over the near lists: z_a = rows of
  *              leaf a of Z_N^-1 r_N, Z_N the near-field matrix restricted to
  *              the RWGs of the near list of a (setup on the host at first use);
- *   LEARNED    a base preconditioner plus a per-leaf MLP correction (nesa_mlp);
- *              falls back to BLOCKDIAG when a restart does not reduce the true
- *              residual or the network output is not finite. */
+ *   LEARNED    a base preconditioner (BLOCKDIAG or SCHWARZ) plus the
+ *              correction of the per-leaf network attached with
+ *              nesa_op_set_mlp; falls back to the base when a restart cycle
+ *              does not reduce the true residual or yields a non-finite value
+ *              (that cycle is then discarded). */
 typedef enum { NESA_PRECOND_NONE = 0, NESA_PRECOND_BLOCKDIAG = 1, NESA_PRECOND_LEARNED = 2,
                NESA_PRECOND_SCHWARZ = 3 } nesa_precond;
 
@@ -220,7 +222,7 @@ typedef struct {
   int restarts;
   double true_rel_residual;
   double seconds;
-  int fell_back;         /* learned preconditioner replaced by block-diagonal */
+  int fell_back;         /* learned preconditioner replaced by its base */
 } nesa_gmres_report;
 
 /* Solve Z_NESA x = b for nrhs right-hand sides (each its own Krylov space).
@@ -230,6 +232,60 @@ typedef struct {
 int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,
                      const nesa_gmres_params* params, nesa_gmres_report* report,
                      double* history, int64_t history_len, void* stream);
+
+/* Learned per-leaf preconditioner network (no counterpart in the paper,
+ * which does not precondition; flexible GMRES after Saad 1993).
+ *   features of leaf a for a vector r and the base output b = M_base r
+ *   (leaf order, S_a RWGs of the leaf, zero padded to s_max):
+ *     u = [Re r_a, Im r_a] / ||r_a||, [Re b_a, Im b_a] / ||b_a||   (4 s_max;
+ *     a block whose norm is zero is zero);
+ *   network, weights shared by all leaves, FP16 weights and activations with
+ *   FP32 accumulation on the matrix cores, FP32 biases:
+ *     y = W3 relu(W2 relu(W1 u + c1) + c2) + c3,
+ *     W1 [hidden][4 s_max], W2 [hidden][hidden], W3 [2 s_max][hidden];
+ *   z_a = b_a + ||b_a|| (y[0:S_a] + i y[s_max:s_max+S_a]).
+ * Parameters: FP32 host vector W1, c1, W2, c2, W3, c3 (row-major, in this
+ * order; nesa_mlp_num_params gives the length).  With W3 = 0 and c3 = 0 the
+ * network is its base preconditioner.
+ * Training pairs (r, e) satisfy Z_NESA e = r (residuals and errors of the
+ * method's own solves); target of leaf a: (e_a - b_a) / ||b_a||; loss = mean
+ * over leaves with ||b_a|| > 0 of the squared error on the S_a valid entries;
+ * the optimiser is Adam with bias correction (FP32 master weights). */
+typedef struct nesa_mlp nesa_mlp;
+typedef struct {
+  int s_max;             /* multiple of 32 in [32, 512], >= the largest leaf */
+  int hidden;            /* multiple of 64 in [64, 512] */
+  int base;              /* NESA_PRECOND_BLOCKDIAG or NESA_PRECOND_SCHWARZ */
+} nesa_mlp_params;
+typedef struct {
+  double lr, beta1, beta2, eps;
+} nesa_adam_params;
+
+int nesa_mlp_num_params(const nesa_mlp_params* params, int64_t* count);
+/* Network for the leaves of `op` with initial parameters theta0 (host).
+ * Freeing op first leaves the network usable only for nesa_mlp_free and the
+ * parameter calls. */
+int nesa_mlp_create(nesa_op* op, const nesa_mlp_params* params, const float* theta0, nesa_mlp** out);
+void nesa_mlp_free(nesa_mlp* net);
+/* Replace the parameters (host FP32) and reset the optimiser state. */
+int nesa_mlp_set_params(nesa_mlp* net, const float* theta);
+int nesa_mlp_get_params(const nesa_mlp* net, float* theta);
+/* Training set: nsamples pairs (r, e), device, canonical order, sample-major
+ * [nsamples][n_rwg], in the op's vector precision.  The base preconditioner is
+ * applied to every r here; features and targets stay on the device. */
+int nesa_mlp_set_data(nesa_mlp* net, const void* r_dev, const void* e_dev, int64_t nsamples, void* stream);
+/* `steps` full-batch Adam steps; loss_history (host, nullable) gets the loss
+ * before each step. */
+int nesa_mlp_train(nesa_mlp* net, const nesa_adam_params* adam, int steps, double* loss_history, void* stream);
+/* Loss and gradient (host FP32, parameter order) at the current parameters. */
+int nesa_mlp_gradient(nesa_mlp* net, float* grad, double* loss);
+/* Network outputs y of the training rows (host [nsamples * n_leaf][2 s_max],
+ * row = sample * n_leaf + leaf). */
+int nesa_mlp_outputs(nesa_mlp* net, float* y);
+/* z = M_base r + correction for one vector in leaf order, on `stream`. */
+int nesa_mlp_apply(nesa_mlp* net, const void* r_dev, void* z_dev, void* stream);
+/* Network used by NESA_PRECOND_LEARNED (NULL detaches; not owned by op). */
+int nesa_op_set_mlp(nesa_op* op, nesa_mlp* net);
 
 const char* nesa_last_error(void);
 

@@ -14,6 +14,7 @@
 
 #include "../../include/nesa.h"
 #include "kernels.h"
+#include "mlp.h"
 #include "nesa_host.h"
 
 using nesa::cd;
@@ -34,6 +35,8 @@ struct nesa_op {
   const nesa::Tree* tree = nullptr;     // setup data for preconditioners built on demand
   const nesa::Near* near = nullptr;
   void* schwarz = nullptr;              // device arena of the Schwarz preconditioner (lazy)
+  nesa_mlp* mlp = nullptr;              // network of NESA_PRECOND_LEARNED (not owned)
+  std::vector<nesa_mlp*> nets;          // networks created for this op (detached when it is freed)
   int max_nrhs = 1;
   double k = 0, eta = 0;
   nesa::Tree geo;                       // copy of the RWG geometry (right-hand sides)
@@ -43,9 +46,7 @@ struct nesa_op {
   void* xl = nullptr;                   // leaf-order work vectors
   void* yl = nullptr;
   size_t esize = 8;                     // bytes per complex element
-  ~nesa_op() {
-    for (void* p : allocs) (void)hipFree(p);
-  }
+  ~nesa_op();
 };
 
 static thread_local std::string g_err;
@@ -411,6 +412,79 @@ static void ensure_schwarz(nesa_op* op) {
 
 int nesa_precond_setup(nesa_op* op, int precond);
 
+// ------------------------------------------------------------------ learned preconditioner
+struct nesa_mlp {
+  nesa_op* op = nullptr;
+  int base = NESA_PRECOND_BLOCKDIAG;
+  nesa::MlpDev net;
+  nesa::MlpRows app;                    // one row per leaf (inference inside GMRES)
+  nesa::MlpRows trn;                    // samples x leaves (training data)
+  void* trn_vec = nullptr;              // leaf-order r, e, base output of the training samples
+  int64_t trn_cap = 0;                  // samples the training buffers hold
+  int64_t nsamples = 0, nvalid = 0;
+  int t = 0;                            // Adam steps taken
+  std::vector<void*> allocs;            // parameter and inference buffers
+  std::vector<void*> trn_allocs;
+  ~nesa_mlp() {
+    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : trn_allocs) (void)hipFree(p);
+  }
+};
+
+nesa_op::~nesa_op() {
+  for (nesa_mlp* m : nets) m->op = nullptr;
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+template <typename X>
+static X* net_alloc(std::vector<void*>& list, int64_t count) {
+  void* p = nullptr;
+  hip_check(hipMalloc(&p, std::max<size_t>(256, (size_t)count * sizeof(X))), "hipMalloc");
+  list.push_back(p);
+  return static_cast<X*>(p);
+}
+
+// activation buffers of `rows` rows (training adds the transposed copies)
+static void alloc_rows(std::vector<void*>& list, nesa::MlpRows& R, int S, int H, int64_t rows, bool training) {
+  R.rows = rows;
+  R.rows_pad = (rows + 63) / 64 * 64;
+  const int64_t P = R.rows_pad;
+  R.U = net_alloc<_Float16>(list, P * 4 * S);
+  R.scale = net_alloc<float>(list, P);
+  R.rowS = net_alloc<int32_t>(list, P);
+  R.h1 = net_alloc<_Float16>(list, P * H);
+  R.h2 = net_alloc<_Float16>(list, P * H);
+  R.Y = net_alloc<float>(list, P * 2 * S);
+  if (training) {
+    R.UT = net_alloc<_Float16>(list, P * 4 * S);
+    R.Tg = net_alloc<float>(list, P * 2 * S);
+    R.h1T = net_alloc<_Float16>(list, P * H);
+    R.h2T = net_alloc<_Float16>(list, P * H);
+    R.dY = net_alloc<_Float16>(list, P * 2 * S);
+    R.dYT = net_alloc<_Float16>(list, P * 2 * S);
+    R.dp2 = net_alloc<_Float16>(list, P * H);
+    R.dp2T = net_alloc<_Float16>(list, P * H);
+    R.dp1T = net_alloc<_Float16>(list, P * H);
+  }
+}
+
+template <typename T>
+static void base_apply(nesa_op* op, nesa::DevOp<T>& d, int base, const void* r, void* z, hipStream_t st) {
+  if (base == NESA_PRECOND_SCHWARZ)
+    nesa::launch_near_apply<T>(d, op->schwarz, r, z, st);
+  else
+    nesa::launch_blockdiag<T>(d, r, z, st);
+}
+
+// z = M_base r + network correction (one vector, leaf order)
+template <typename T>
+static void learned_apply(nesa_mlp* h, nesa::DevOp<T>& d, const void* r, void* z, hipStream_t st) {
+  base_apply<T>(h->op, d, h->base, r, z, st);
+  nesa::launch_mlp_features<T>(h->net, h->app, r, z, nullptr, d.leaf_ptr, d.nleaf, d.n, 1, false, st);
+  nesa::launch_mlp_forward(h->net, h->app, false, st);
+  nesa::launch_mlp_combine<T>(h->net, h->app, d.leaf_ptr, d.nleaf, z, st);
+}
+
 // ------------------------------------------------------------------ GMRES driver
 template <typename T>
 static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c, const nesa_gmres_params& prm,
@@ -455,11 +529,14 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     return std::sqrt(std::max(0.0, hh[0].x));
   };
+  // the learned preconditioner falls back to its base when a cycle yields a
+  // non-finite value or does not reduce the true residual
+  int active = prm.precond;
   auto precond = [&](const void* r, void* z) {
-    if (prm.precond == NESA_PRECOND_SCHWARZ) {
-      nesa::launch_near_apply<T>(d, op->schwarz, r, z, st);
-    } else if (prm.precond == NESA_PRECOND_BLOCKDIAG || prm.precond == NESA_PRECOND_LEARNED) {
-      nesa::launch_blockdiag<T>(d, r, z, st);
+    if (active == NESA_PRECOND_LEARNED) {
+      learned_apply<T>(op->mlp, d, r, z, st);
+    } else if (active == NESA_PRECOND_SCHWARZ || active == NESA_PRECOND_BLOCKDIAG) {
+      base_apply<T>(op, d, active, r, z, st);
     } else {
       hip_check(hipMemcpyAsync(z, r, n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
     }
@@ -488,6 +565,7 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   int status = NESA_OK;
   while (beta / nb > prm.tol && iters < prm.max_iters) {
     rep.restarts++;
+    bool discard = false;                 // learned cycle that produced a non-finite value
     nesa::launch_scale<T>(vec(Vb, 0), vec(Vb, 0), n, 1.0 / beta, st);
     std::fill(H.begin(), H.end(), cd(0, 0));
     std::fill(g.begin(), g.end(), cd(0, 0));
@@ -512,8 +590,16 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       for (int i = 0; i <= j; ++i)
         H[(size_t)j * (m + 1) + i] = cd(hh[i].x + hh[m + 2 + i].x, hh[i].y + hh[m + 2 + i].y);
       const double hn = std::sqrt(std::max(0.0, hh[2 * (m + 2)].x));
-      if (!std::isfinite(hn)) {
-        status = fail(NESA_EBREAKDOWN, "non-finite value in GMRES");
+      bool finite = std::isfinite(hn);
+      for (int i = 0; i <= j && finite; ++i) finite = std::isfinite(std::abs(H[(size_t)j * (m + 1) + i]));
+      if (!finite) {
+        if (active == NESA_PRECOND_LEARNED) {
+          active = op->mlp->base;
+          rep.fell_back = 1;
+          discard = true;
+        } else {
+          status = fail(NESA_EBREAKDOWN, "non-finite value in GMRES");
+        }
         break;
       }
       H[(size_t)j * (m + 1) + j + 1] = hn;
@@ -553,6 +639,10 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       nesa::launch_scale<T>(w, vec(Vb, j + 1), n, 1.0 / hn, st);
     }
     if (status != NESA_OK) break;
+    if (discard) {                        // restart from the same x with the base preconditioner
+      nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
+      continue;
+    }
     std::vector<cd> y(k);
     for (int i = k - 1; i >= 0; --i) {
       cd acc = g[i];
@@ -564,7 +654,12 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
     nesa::launch_combine<T>(flex ? Zb : Vb, n, k, hd, xl, n, +1.0, st);
     matvec(xl, tmp);
     nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
+    const double beta_prev = beta;
     beta = norm(vec(Vb, 0));
+    if (active == NESA_PRECOND_LEARNED && !(beta < beta_prev)) {
+      active = op->mlp->base;
+      rep.fell_back = 1;
+    }
   }
   nesa::launch_scatter<T>(xl, x_c, d.perm, n, st);
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -898,6 +993,8 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
       return fail(NESA_EINVAL, "bad GMRES parameters");
     if (params->precond < 0 || params->precond > 3) return fail(NESA_EINVAL, "unknown preconditioner");
     if (params->precond == NESA_PRECOND_SCHWARZ) ensure_schwarz(op);
+    if (params->precond == NESA_PRECOND_LEARNED && !op->mlp)
+      return fail(NESA_EINVAL, "no network attached for the learned preconditioner");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = op->geo.rwg.n;
     int worst = NESA_OK;
@@ -912,6 +1009,249 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
       if (rc != NESA_OK && worst == NESA_OK) worst = rc;
     }
     return worst;
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned preconditioner API
+static int64_t max_leaf(const nesa::Tree& t) {
+  int64_t m = 0;
+  for (size_t a = 0; a + 1 < t.leaf_ptr.size(); ++a) m = std::max(m, t.leaf_ptr[a + 1] - t.leaf_ptr[a]);
+  return m;
+}
+
+static void check_mlp_params(const nesa_mlp_params* p) {
+  if (p->s_max < 32 || p->s_max > 512 || p->s_max % 32)
+    throw Error(NESA_EINVAL, "s_max must be a multiple of 32 in [32, 512]");
+  if (p->hidden < 64 || p->hidden > 512 || p->hidden % 64)
+    throw Error(NESA_EINVAL, "hidden must be a multiple of 64 in [64, 512]");
+  if (p->base != NESA_PRECOND_BLOCKDIAG && p->base != NESA_PRECOND_SCHWARZ)
+    throw Error(NESA_EINVAL, "base must be BLOCKDIAG or SCHWARZ");
+}
+
+static void mlp_upload_params(nesa_mlp* h, const float* theta) {
+  nesa::MlpDev& N = h->net;
+  hip_check(hipMemcpy(N.theta, theta, N.np * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  std::vector<float> zero(N.np, 0.f);
+  hip_check(hipMemcpy(N.m, zero.data(), N.np * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  hip_check(hipMemcpy(N.v, zero.data(), N.np * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  h->t = 0;
+  nesa::launch_mlp_refresh(N, nullptr);
+  hip_check(hipGetLastError(), "kernel launch");
+  hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+}
+
+static void require_data(const nesa_mlp* h) {
+  if (h->nsamples == 0) throw Error(NESA_EINVAL, "no training data set");
+  if (h->nvalid == 0) throw Error(NESA_EINVAL, "training data has no leaf with a non-zero base output");
+}
+
+// forward (+ loss, + backward) over the training rows; returns the mean loss
+static double mlp_pass(nesa_mlp* h, bool backward, hipStream_t st) {
+  require_data(h);
+  nesa::launch_mlp_forward(h->net, h->trn, true, st);
+  nesa::launch_mlp_loss(h->net, h->trn, st);
+  if (backward) nesa::launch_mlp_backward(h->net, h->trn, (float)(1.0 / (double)h->nvalid), st);
+  hip_check(hipGetLastError(), "kernel launch");
+  double loss = 0;
+  hip_check(hipMemcpyAsync(&loss, h->net.loss, sizeof(double), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return loss / (double)h->nvalid;
+}
+
+template <typename T>
+static void mlp_set_data_t(nesa_mlp* h, nesa::DevOp<T>& d, const void* r, const void* e, int64_t ns,
+                           hipStream_t st) {
+  const int64_t n = d.n;
+  const size_t es = 2 * sizeof(T);
+  if (ns > h->trn_cap) {
+    for (void* p : h->trn_allocs) (void)hipFree(p);
+    h->trn_allocs.clear();
+    h->trn_cap = 0;
+    h->trn_vec = net_alloc<char>(h->trn_allocs, (int64_t)3 * ns * n * es);
+    alloc_rows(h->trn_allocs, h->trn, h->net.S, h->net.H, ns * d.nleaf, true);
+    h->net.partial_elems = nesa::mlp_partial_elems(h->net.S, h->net.H, h->trn.rows_pad);
+    h->net.partial = net_alloc<float>(h->trn_allocs, h->net.partial_elems);
+    h->net.loss_blocks = h->trn.rows_pad / 4;
+    h->net.loss_part = net_alloc<double>(h->trn_allocs, h->net.loss_blocks);
+    h->trn_cap = ns;
+  } else {
+    // rows of a smaller set inside the same buffers: keep rows_pad of the
+    // allocation, the extra rows are masked by rowS = 0
+    h->trn.rows = ns * d.nleaf;
+  }
+  char* rl = static_cast<char*>(h->trn_vec);
+  char* el = rl + (size_t)h->trn_cap * n * es;
+  char* bl = el + (size_t)h->trn_cap * n * es;
+  for (int64_t s = 0; s < ns; ++s) {
+    nesa::launch_gather<T>(static_cast<const char*>(r) + s * n * es, rl + s * n * es, d.perm, n, st);
+    nesa::launch_gather<T>(static_cast<const char*>(e) + s * n * es, el + s * n * es, d.perm, n, st);
+    base_apply<T>(h->op, d, h->base, rl + s * n * es, bl + s * n * es, st);
+  }
+  nesa::launch_mlp_features<T>(h->net, h->trn, rl, bl, el, d.leaf_ptr, d.nleaf, n, ns, true, st);
+  hip_check(hipGetLastError(), "kernel launch");
+  std::vector<int32_t> rowS(h->trn.rows_pad);
+  hip_check(hipMemcpyAsync(rowS.data(), h->trn.rowS, rowS.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+            "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  h->nvalid = 0;
+  for (int32_t v : rowS) h->nvalid += v > 0;
+  h->nsamples = ns;
+}
+
+extern "C" {
+
+int nesa_mlp_num_params(const nesa_mlp_params* params, int64_t* count) {
+  return guarded([&]() {
+    if (!params || !count) return fail(NESA_EINVAL, "null argument");
+    check_mlp_params(params);
+    *count = nesa::mlp_nparams(params->s_max, params->hidden);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_create(nesa_op* op, const nesa_mlp_params* params, const float* theta0, nesa_mlp** out) {
+  return guarded([&]() {
+    if (!op || !params || !theta0 || !out) return fail(NESA_EINVAL, "null argument");
+    check_mlp_params(params);
+    if (max_leaf(*op->tree) > params->s_max) return fail(NESA_EINVAL, "a leaf holds more RWGs than s_max");
+    std::unique_ptr<nesa_mlp> h(new nesa_mlp());
+    h->op = op;
+    h->base = params->base;
+    nesa::MlpDev& N = h->net;
+    const int S = params->s_max, H = params->hidden;
+    N.S = S;
+    N.H = H;
+    N.np = nesa::mlp_nparams(S, H);
+    const int64_t sz[6] = {(int64_t)H * 4 * S, H, (int64_t)H * H, H, (int64_t)2 * S * H, 2 * S};
+    N.off[0] = 0;
+    for (int i = 0; i < 6; ++i) N.off[i + 1] = N.off[i] + sz[i];
+    N.theta = net_alloc<float>(h->allocs, N.np);
+    N.m = net_alloc<float>(h->allocs, N.np);
+    N.v = net_alloc<float>(h->allocs, N.np);
+    N.grad = net_alloc<float>(h->allocs, N.np);
+    N.W1h = net_alloc<_Float16>(h->allocs, sz[0]);
+    N.W2h = net_alloc<_Float16>(h->allocs, sz[2]);
+    N.W3h = net_alloc<_Float16>(h->allocs, sz[4]);
+    N.W2t = net_alloc<_Float16>(h->allocs, sz[2]);
+    N.W3t = net_alloc<_Float16>(h->allocs, sz[4]);
+    N.loss = net_alloc<double>(h->allocs, 1);
+    const int64_t nleaf = (int64_t)op->tree->leaf_ptr.size() - 1;
+    alloc_rows(h->allocs, h->app, S, H, nleaf, false);
+    if (h->base == NESA_PRECOND_SCHWARZ) ensure_schwarz(op);
+    mlp_upload_params(h.get(), theta0);
+    op->nets.push_back(h.get());
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
+void nesa_mlp_free(nesa_mlp* net) {
+  if (net && net->op) {
+    if (net->op->mlp == net) net->op->mlp = nullptr;
+    auto& v = net->op->nets;
+    v.erase(std::remove(v.begin(), v.end(), net), v.end());
+  }
+  delete net;
+}
+
+int nesa_mlp_set_params(nesa_mlp* net, const float* theta) {
+  return guarded([&]() {
+    if (!net || !theta) return fail(NESA_EINVAL, "null argument");
+    mlp_upload_params(net, theta);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_get_params(const nesa_mlp* net, float* theta) {
+  return guarded([&]() {
+    if (!net || !theta) return fail(NESA_EINVAL, "null argument");
+    hip_check(hipMemcpy(theta, net->net.theta, net->net.np * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_set_data(nesa_mlp* net, const void* r_dev, const void* e_dev, int64_t nsamples, void* stream) {
+  return guarded([&]() {
+    if (!net || !r_dev || !e_dev) return fail(NESA_EINVAL, "null argument");
+    if (!net->op) return fail(NESA_EINVAL, "the operator of this network has been freed");
+    if (nsamples < 1) return fail(NESA_EINVAL, "nsamples must be positive");
+    nesa_op* op = net->op;
+    const int64_t nleaf = (int64_t)op->tree->leaf_ptr.size() - 1;
+    if (nsamples * nleaf > ((int64_t)1 << 31) / (4 * net->net.S))
+      return fail(NESA_EINVAL, "too many training rows");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (op->precision == NESA_C128)
+      mlp_set_data_t<double>(net, op->d, r_dev, e_dev, nsamples, st);
+    else
+      mlp_set_data_t<float>(net, op->f, r_dev, e_dev, nsamples, st);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_train(nesa_mlp* net, const nesa_adam_params* adam, int steps, double* loss_history, void* stream) {
+  return guarded([&]() {
+    if (!net || !adam) return fail(NESA_EINVAL, "null argument");
+    if (steps < 0 || !(adam->lr > 0) || !(adam->beta1 >= 0 && adam->beta1 < 1) ||
+        !(adam->beta2 >= 0 && adam->beta2 < 1) || !(adam->eps > 0))
+      return fail(NESA_EINVAL, "bad Adam parameters");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < steps; ++i) {
+      const double loss = mlp_pass(net, true, st);
+      if (loss_history) loss_history[i] = loss;
+      net->t += 1;
+      nesa::launch_mlp_adam(net->net, (float)adam->lr, (float)adam->beta1, (float)adam->beta2, (float)adam->eps,
+                            net->t, st);
+      nesa::launch_mlp_refresh(net->net, st);
+      hip_check(hipGetLastError(), "kernel launch");
+    }
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_gradient(nesa_mlp* net, float* grad, double* loss) {
+  return guarded([&]() {
+    if (!net || !grad || !loss) return fail(NESA_EINVAL, "null argument");
+    *loss = mlp_pass(net, true, nullptr);
+    hip_check(hipMemcpy(grad, net->net.grad, net->net.np * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_outputs(nesa_mlp* net, float* y) {
+  return guarded([&]() {
+    if (!net || !y) return fail(NESA_EINVAL, "null argument");
+    if (!net->op) return fail(NESA_EINVAL, "the operator of this network has been freed");
+    (void)mlp_pass(net, false, nullptr);
+    const int64_t rows = net->nsamples * ((int64_t)net->op->tree->leaf_ptr.size() - 1);
+    hip_check(hipMemcpy(y, net->trn.Y, (size_t)rows * 2 * net->net.S * sizeof(float), hipMemcpyDeviceToHost),
+              "hipMemcpy");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_apply(nesa_mlp* net, const void* r_dev, void* z_dev, void* stream) {
+  return guarded([&]() {
+    if (!net || !r_dev || !z_dev) return fail(NESA_EINVAL, "null argument");
+    if (!net->op) return fail(NESA_EINVAL, "the operator of this network has been freed");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (net->op->precision == NESA_C128)
+      learned_apply<double>(net, net->op->d, r_dev, z_dev, st);
+    else
+      learned_apply<float>(net, net->op->f, r_dev, z_dev, st);
+    hip_check(hipGetLastError(), "kernel launch");
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_op_set_mlp(nesa_op* op, nesa_mlp* net) {
+  return guarded([&]() {
+    if (!op) return fail(NESA_EINVAL, "null argument");
+    if (net && net->op != op) return fail(NESA_EINVAL, "network belongs to another operator");
+    op->mlp = net;
+    return (int)NESA_OK;
   });
 }
 

@@ -53,6 +53,14 @@ class GmresReport(C.Structure):
                 ("seconds", C.c_double), ("fell_back", C.c_int)]
 
 
+class MlpParams(C.Structure):
+    _fields_ = [("s_max", C.c_int), ("hidden", C.c_int), ("base", C.c_int)]
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "nesa_build_tree": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(TreeParams), C.POINTER(_P)]),
@@ -77,6 +85,17 @@ _SIGS = {
                                    C.POINTER(GmresReport), _P, C.c_int64, _P]),
     "nesa_precond_setup": (C.c_int, [_P, C.c_int]),
     "nesa_precond_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "nesa_mlp_num_params": (C.c_int, [C.POINTER(MlpParams), C.POINTER(C.c_int64)]),
+    "nesa_mlp_create": (C.c_int, [_P, C.POINTER(MlpParams), _P, C.POINTER(_P)]),
+    "nesa_mlp_free": (None, [_P]),
+    "nesa_mlp_set_params": (C.c_int, [_P, _P]),
+    "nesa_mlp_get_params": (C.c_int, [_P, _P]),
+    "nesa_mlp_set_data": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "nesa_mlp_train": (C.c_int, [_P, C.POINTER(AdamParams), C.c_int, _P, _P]),
+    "nesa_mlp_gradient": (C.c_int, [_P, _P, _P]),
+    "nesa_mlp_outputs": (C.c_int, [_P, _P]),
+    "nesa_mlp_apply": (C.c_int, [_P, _P, _P, _P]),
+    "nesa_op_set_mlp": (C.c_int, [_P, _P]),
     "nesa_last_error": (C.c_char_p, []),
 }
 
@@ -274,3 +293,69 @@ def gmres_solve(op, b, x, nrhs=1, restart=30, max_iters=1000, tol=1e-6, precond=
     reports = [{"iters": r.iters, "restarts": r.restarts, "true_rel_residual": r.true_rel_residual,
                 "seconds": r.seconds, "fell_back": r.fell_back} for r in rep]
     return rc, reports, hist[:history_len]
+
+
+def mlp_num_params(s_max, hidden, base=PRECOND_SCHWARZ):
+    c = C.c_int64()
+    _check(lib().nesa_mlp_num_params(C.byref(MlpParams(s_max, hidden, base)), C.byref(c)))
+    return c.value
+
+
+class Mlp(_Handle):
+    """Learned per-leaf preconditioner network of one operator."""
+    _free = "nesa_mlp_free"
+
+    def __init__(self, op, s_max, hidden, base, theta0):
+        theta0 = np.ascontiguousarray(theta0, dtype=np.float32)
+        n = mlp_num_params(s_max, hidden, base)
+        if theta0.size != n:
+            raise ValueError("expected %d parameters" % n)
+        h = C.c_void_p()
+        _check(lib().nesa_mlp_create(op.h, C.byref(MlpParams(s_max, hidden, base)), _ptr(theta0),
+                                     C.byref(h)))
+        super().__init__(h)
+        self.op, self.s_max, self.hidden, self.base, self.n_params = op, s_max, hidden, base, n
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.size != self.n_params:
+            raise ValueError("expected %d parameters" % self.n_params)
+        _check(lib().nesa_mlp_set_params(self.h, _ptr(theta)))
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().nesa_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_data(self, r, e, stream=None):
+        """r, e: device tensors [nsamples][n_rwg] (canonical order)."""
+        if r.shape != e.shape or r.dim() != 2:
+            raise ValueError("r and e must be [nsamples][n_rwg]")
+        _check(lib().nesa_mlp_set_data(self.h, _dptr(r), _dptr(e), r.shape[0], _stream(stream)))
+        self.nsamples = r.shape[0]
+
+    def train(self, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        hist = np.zeros(max(1, steps), dtype=np.float64)
+        _check(lib().nesa_mlp_train(self.h, C.byref(AdamParams(lr, beta1, beta2, eps)), steps, _ptr(hist),
+                                    _stream(stream)))
+        return hist[:steps]
+
+    def gradient(self):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(lib().nesa_mlp_gradient(self.h, _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def outputs(self, nleaf):
+        y = np.zeros((self.nsamples * nleaf, 2 * self.s_max), dtype=np.float32)
+        _check(lib().nesa_mlp_outputs(self.h, _ptr(y)))
+        return y
+
+    def apply(self, r, z, stream=None):
+        """z = M_base r + correction (one vector, leaf order)."""
+        _check(lib().nesa_mlp_apply(self.h, _dptr(r), _dptr(z), _stream(stream)))
+
+
+def op_set_mlp(op, net):
+    _check(lib().nesa_op_set_mlp(op.h, net.h if net is not None else None))
+    op._mlp = net

@@ -1,0 +1,216 @@
+"""GPU parity of the learned per-leaf preconditioner network (through the C ABI)
+against the FP64 oracle: features and forward pass, loss and gradient, Adam
+steps, the preconditioner inside flexible GMRES and its run-time fallback."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import efie, krylov, mlp
+from oracle import nesa as onesa
+from oracle.tree import cheb
+
+pytestmark = pytest.mark.gpu
+
+S, H = 96, 64          # s_max (largest leaf of the 3000-unknown sphere: 80) and width
+# FP16 inputs, weights and hidden activations with FP32 accumulation: each
+# rounding is within 2^-11 relative; three of them in sequence give about
+# 1e-3 on the outputs, bounded here with margin
+TOL_Y = 4e-3
+TOL_GRAD = 1.5e-2      # backward adds FP16 output gradients and two more roundings
+
+
+def morton(k):
+    c = 0
+    for b in range(21):
+        for d in range(3):
+            c |= ((int(k[d]) >> b) & 1) << (3 * b + d)
+    return c
+
+
+def leaf_order(t):
+    """Leaves in Morton order of their keys (x in the lowest bit), RWGs of a
+    leaf by canonical index: returns (perm, leaf_ptr, leaves)."""
+    leaves = sorted(range(len(t.boxes[t.L])), key=lambda a: morton(t.boxes[t.L][a]))
+    perm = np.concatenate([np.sort(np.asarray(t.leaf_rwgs[a], dtype=np.int64)) for a in leaves])
+    leaf_ptr = np.concatenate([[0], np.cumsum([len(t.leaf_rwgs[a]) for a in leaves])])
+    return perm, leaf_ptr, leaves
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_1801_03589_amd import nesa
+    nesa.lib()
+    v, t = synth.icosphere(10, 0.5)
+    ref = onesa.NesaOracle(v, t, leaf=0.25, d0=5, tau=1e-8)
+    tr = nesa.build_tree(v, t, 0.25)
+    near = nesa.assemble_near(tr)
+    far = nesa.assemble_translations(tr, d0=5, tau=1e-8)
+    op = nesa.op_create(tr, near, far, nesa.C128)
+    perm, leaf_ptr, leaves = leaf_order(ref.t)
+    assert np.array_equal(perm, tr.perm())
+    return nesa, ref, tr, op, perm, leaf_ptr
+
+
+def _oracle_base(ref, base):
+    t = ref.t
+    if base == "schwarz":
+        keys = t.boxes[t.L]
+        return krylov.near_schwarz(t.leaf_rwgs, t.near, ref.near_block,
+                                   lambda b, c: cheb(keys[b], keys[c]) <= t.buffer)
+    blocks = []
+    for a, rw in enumerate(t.leaf_rwgs):
+        rows, cols, Z = ref.near_block(a)
+        pos = np.array([np.nonzero(cols == r)[0][0] for r in rw])
+        blocks.append((rw, Z[:, pos]))
+    return krylov.block_diagonal(blocks)
+
+
+def _oracle_rows(ref, base, perm, leaf_ptr, R, E):
+    """Features, scales and targets of the samples (rows sample-major)."""
+    M = _oracle_base(ref, base)
+    us, ts, ms = [], [], []
+    for r, e in zip(R, E):
+        b = M(r)
+        u, _ = mlp.features(r[perm], b[perm], leaf_ptr, S)
+        tt, mk = mlp.targets(e[perm], b[perm], leaf_ptr, S)
+        us.append(u)
+        ts.append(tt)
+        ms.append(mk)
+    return np.concatenate(us), np.concatenate(ts), np.concatenate(ms)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("base", ["blockdiag", "schwarz"])
+def test_forward_matches_oracle(torch_dev, setup, base):
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    kind = nesa.PRECOND_SCHWARZ if base == "schwarz" else nesa.PRECOND_BLOCKDIAG
+    theta = synth.mlp_weights(S, H, seed=11, zero_last=False, bias_std=0.1)
+    net = nesa.Mlp(op, S, H, kind, theta)
+    R = synth.complex_normal((3, ref.m.n), 40)
+    E = synth.complex_normal((3, ref.m.n), 41)
+    net.set_data(_dev(torch_dev, R), _dev(torch_dev, E))
+    y = net.outputs(len(leaf_ptr) - 1).astype(np.float64)
+    u, _, _ = _oracle_rows(ref, base, perm, leaf_ptr, R, E)
+    yo, _ = mlp.forward(theta.astype(np.float64), u, S, H)
+    err = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    print("%s forward: rel err %.2e" % (base, err))
+    assert err <= TOL_Y
+    assert np.abs(y - yo).max() <= 10 * TOL_Y * np.abs(yo).max()
+
+
+def test_gradient_matches_oracle(torch_dev, setup):
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    theta = synth.mlp_weights(S, H, seed=12, zero_last=False, bias_std=0.1)
+    net = nesa.Mlp(op, S, H, nesa.PRECOND_SCHWARZ, theta)
+    R = synth.complex_normal((4, ref.m.n), 42)
+    E = synth.complex_normal((4, ref.m.n), 43)
+    net.set_data(_dev(torch_dev, R), _dev(torch_dev, E))
+    loss, g = net.gradient()
+    u, t, mk = _oracle_rows(ref, "schwarz", perm, leaf_ptr, R, E)
+    lo, go = mlp.loss_and_grad(theta.astype(np.float64), u, t, mk, S, H)
+    assert abs(loss - lo) <= 2e-3 * lo
+    gp, gop = mlp.unpack(g, S, H), mlp.unpack(go, S, H)
+    for name, a, b in zip(["W1", "c1", "W2", "c2", "W3", "c3"], gp, gop):
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print("grad %s rel err %.2e" % (name, err))
+        assert err <= TOL_GRAD, name
+
+
+def test_adam_steps_match_oracle(torch_dev, setup):
+    """One Adam step moves each parameter by about lr against the sign of its
+    gradient; then the losses of 60 GPU steps follow the oracle's 60 FP64
+    steps on the same data."""
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    theta = synth.mlp_weights(S, H, seed=13, zero_last=True)
+    net = nesa.Mlp(op, S, H, nesa.PRECOND_SCHWARZ, theta)
+    R = synth.complex_normal((2, ref.m.n), 44)
+    E = synth.complex_normal((2, ref.m.n), 45)
+    net.set_data(_dev(torch_dev, R), _dev(torch_dev, E))
+    lr = 1e-3
+    net.train(1, lr=lr)
+    th1 = net.get_params().astype(np.float64)
+    u, t, mk = _oracle_rows(ref, "schwarz", perm, leaf_ptr, R, E)
+    th = theta.astype(np.float64)
+    opt = mlp.Adam(len(th), lr=lr)
+    _, g = mlp.loss_and_grad(th, u, t, mk, S, H)
+    tho = opt.step(th, g)
+    # with the last layer zero only W3 and c3 have a gradient
+    big = np.abs(g) > 1e-2 * np.sqrt(np.mean(g * g))
+    assert big.sum() > 0.5 * 2 * S * H
+    assert np.abs((th1 - th) - (tho - th))[big].max() <= 0.05 * lr
+    assert np.abs(th1 - th).max() <= lr * (1 + 1e-5)
+    # 60 more steps on both sides
+    hist = net.train(60, lr=lr)
+    ho = []
+    for _ in range(60):
+        lo, g = mlp.loss_and_grad(tho, u, t, mk, S, H)
+        ho.append(lo)
+        tho = opt.step(tho, g)
+    print("loss gpu %.4f -> %.4f, oracle %.4f -> %.4f" % (hist[0], hist[-1], ho[0], ho[-1]))
+    assert hist[-1] < 0.9 * hist[0]
+    assert abs(hist[-1] - ho[-1]) <= 0.03 * ho[-1]
+
+
+def test_apply_matches_oracle_and_untrained_is_base(torch_dev, setup):
+    torch = torch_dev
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    r = synth.complex_normal(ref.m.n, 46)
+    rd = _dev(torch, r[perm])
+    zb = torch.empty_like(rd)
+    nesa.precond_apply(op, nesa.PRECOND_SCHWARZ, rd, zb)
+    net0 = nesa.Mlp(op, S, H, nesa.PRECOND_SCHWARZ, synth.mlp_weights(S, H, seed=14))
+    z0 = torch.empty_like(rd)
+    net0.apply(rd, z0)
+    torch.cuda.synchronize()
+    assert torch.equal(z0, zb)
+    theta = synth.mlp_weights(S, H, seed=15, zero_last=False, bias_std=0.1)
+    net = nesa.Mlp(op, S, H, nesa.PRECOND_SCHWARZ, theta)
+    z = torch.empty_like(rd)
+    net.apply(rd, z)
+    torch.cuda.synchronize()
+    M = _oracle_base(ref, "schwarz")
+    zo = mlp.apply(theta.astype(np.float64), r[perm], lambda v: M(r)[perm], leaf_ptr, S, H)
+    zz = z.cpu().numpy()
+    corr = zo - M(r)[perm]
+    assert np.linalg.norm(zz - zo) <= TOL_Y * np.linalg.norm(corr) + 1e-9 * np.linalg.norm(zo)
+
+
+def test_learned_fgmres_untrained_equals_base_and_falls_back(torch_dev, setup):
+    torch = torch_dev
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    b = efie.plane_wave_rhs(ref.m, [0, 0, 1], [1, 0, 0])
+    bd = _dev(torch, b)
+
+    def solve(pc):
+        x = torch.zeros_like(bd)
+        rc, rep, _ = nesa.gmres_solve(op, bd, x, restart=30, max_iters=500, tol=1e-6, precond=pc)
+        return rc, rep[0], x
+
+    rc0, rep0, x0 = solve(nesa.PRECOND_SCHWARZ)
+    net = nesa.Mlp(op, S, H, nesa.PRECOND_SCHWARZ, synth.mlp_weights(S, H, seed=16))
+    nesa.op_set_mlp(op, net)
+    rc1, rep1, x1 = solve(nesa.PRECOND_LEARNED)
+    assert rc0 == rc1 == 0 and rep1["fell_back"] == 0
+    assert rep1["iters"] == rep0["iters"]
+    assert torch.equal(x0, x1)
+    # non-finite network output: the cycle is discarded and the base takes over
+    bad = synth.mlp_weights(S, H, seed=17, zero_last=False, bias_std=0.1)
+    bad[-2 * S] = np.nan                  # c3[0]: the first entry of every leaf
+    net.set_params(bad)
+    rc2, rep2, x2 = solve(nesa.PRECOND_LEARNED)
+    print("fallback: %d iters (base alone %d)" % (rep2["iters"], rep0["iters"]))
+    assert rc2 == 0 and rep2["fell_back"] == 1
+    assert rep2["true_rel_residual"] <= 1e-6
+    x = x2.cpu().numpy()
+    assert np.linalg.norm(b - ref.matvec(x)) / np.linalg.norm(b) <= 1.01e-6
+    nesa.op_set_mlp(op, None)

@@ -49,6 +49,21 @@ def test_tree_matches_oracle(nesa, sphere1, leaf):
     assert changes == len(ot.boxes[ot.L])
 
 
+def test_leaf_order_is_morton_then_canonical(nesa, sphere1):
+    """Leaf order: leaves by the Morton code of their integer key (x in the
+    lowest bit of each triple), RWGs of a leaf by canonical index."""
+    v, t = sphere1
+    m = efie.RWG(v, t)
+    for leaf in (0.25, 0.125):
+        ot = Octree(v, m.midpoints(), leaf=leaf)
+
+        def morton(k):
+            return sum(((int(k[d]) >> b) & 1) << (3 * b + d) for b in range(21) for d in range(3))
+        leaves = sorted(range(len(ot.boxes[ot.L])), key=lambda a: morton(ot.boxes[ot.L][a]))
+        perm = np.concatenate([np.sort(np.asarray(ot.leaf_rwgs[a], dtype=np.int64)) for a in leaves])
+        assert np.array_equal(perm, nesa.build_tree(v, t, leaf).perm())
+
+
 def test_near_entries_match_oracle(nesa, sphere1, dense1):
     v, t = sphere1
     tr = nesa.build_tree(v, t, 0.25)
