@@ -113,6 +113,7 @@ typedef struct {
   int64_t n_pairs[32];   /* translation pairs at level l0 + i */
   int Q[32];             /* equivalent sources per box at level l0 + i
                             (0 until nesa_assemble_translations) */
+  int64_t max_leaf;      /* RWGs of the largest leaf */
 } nesa_tree_info;
 
 /* Build the RWG basis and the oct-tree of a closed triangle mesh.
@@ -215,6 +216,10 @@ typedef struct {
   int max_iters;
   double tol;
   int precond;           /* nesa_precond */
+  double fallback_ratio; /* LEARNED: a restart cycle whose true residual is
+                            above fallback_ratio x the previous one hands over
+                            to the base preconditioner (0 means 1: only a cycle
+                            that does not reduce it) */
 } nesa_gmres_params;
 
 typedef struct {
@@ -267,6 +272,12 @@ int nesa_mlp_num_params(const nesa_mlp_params* params, int64_t* count);
  * parameter calls. */
 int nesa_mlp_create(nesa_op* op, const nesa_mlp_params* params, const float* theta0, nesa_mlp** out);
 void nesa_mlp_free(nesa_mlp* net);
+/* Training pair of an iterate x of a solve with converged solution xs:
+ * r = b - Z_NESA x and e = xs - x (so Z_NESA e = r up to the solve
+ * tolerance).  One vector each, device, canonical order; r and e must not
+ * alias the inputs. */
+int nesa_residual_error(nesa_op* op, const void* b_dev, const void* xs_dev, const void* x_dev, void* r_dev,
+                        void* e_dev, void* stream);
 /* Replace the parameters (host FP32) and reset the optimiser state. */
 int nesa_mlp_set_params(nesa_mlp* net, const float* theta);
 int nesa_mlp_get_params(const nesa_mlp* net, float* theta);

@@ -49,6 +49,12 @@ struct nesa_op {
   ~nesa_op();
 };
 
+static int64_t max_leaf(const nesa::Tree& t) {
+  int64_t m = 0;
+  for (size_t a = 0; a + 1 < t.leaf_ptr.size(); ++a) m = std::max(m, t.leaf_ptr[a + 1] - t.leaf_ptr[a]);
+  return m;
+}
+
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string& msg) {
@@ -656,7 +662,8 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
     nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
     const double beta_prev = beta;
     beta = norm(vec(Vb, 0));
-    if (active == NESA_PRECOND_LEARNED && !(beta < beta_prev)) {
+    const double ratio = prm.fallback_ratio > 0 ? prm.fallback_ratio : 1.0;
+    if (active == NESA_PRECOND_LEARNED && !(beta < ratio * beta_prev)) {
       active = op->mlp->base;
       rep.fell_back = 1;
     }
@@ -705,6 +712,7 @@ int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info) {
       ne += S * W;
     }
     info->near_entries = ne;
+    info->max_leaf = max_leaf(t);
     for (int l = t.l0; l <= t.L && l - t.l0 < 32; ++l) {
       info->n_box[l - t.l0] = t.level(l).nbox;
       info->n_pairs[l - t.l0] = (int64_t)t.level(l).il_src.size();
@@ -875,6 +883,26 @@ int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, 
   return matvec_impl(op, x_dev, y_dev, nrhs, stream, false);
 }
 
+int nesa_residual_error(nesa_op* op, const void* b_dev, const void* xs_dev, const void* x_dev, void* r_dev,
+                        void* e_dev, void* stream) {
+  const int rc = matvec_impl(op, x_dev, r_dev, 1, stream, true);
+  if (rc != NESA_OK) return rc;
+  return guarded([&]() {
+    if (!b_dev || !xs_dev || !e_dev) return fail(NESA_EINVAL, "null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = op->geo.rwg.n;
+    if (op->precision == NESA_C128) {
+      nesa::launch_sub<double>(b_dev, r_dev, r_dev, n, st);
+      nesa::launch_sub<double>(xs_dev, x_dev, e_dev, n, st);
+    } else {
+      nesa::launch_sub<float>(b_dev, r_dev, r_dev, n, st);
+      nesa::launch_sub<float>(xs_dev, x_dev, e_dev, n, st);
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+    return (int)NESA_OK;
+  });
+}
+
 static void timed_matvec(nesa_op* op, const void* x_dev, void* y_dev, hipStream_t st, nesa::PhaseTimer& tm) {
   for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
   if (op->precision == NESA_C128)
@@ -989,7 +1017,8 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
   return guarded([&]() {
     if (!op || !b_dev || !x_dev || !params || !report) return fail(NESA_EINVAL, "null argument");
     if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
-    if (params->restart < 1 || params->restart > 250 || params->max_iters < 1 || !(params->tol > 0))
+    if (params->restart < 1 || params->restart > 250 || params->max_iters < 1 || !(params->tol > 0) ||
+        !(params->fallback_ratio >= 0 && params->fallback_ratio <= 1))
       return fail(NESA_EINVAL, "bad GMRES parameters");
     if (params->precond < 0 || params->precond > 3) return fail(NESA_EINVAL, "unknown preconditioner");
     if (params->precond == NESA_PRECOND_SCHWARZ) ensure_schwarz(op);
@@ -1015,12 +1044,6 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
 }  // extern "C"
 
 // ------------------------------------------------------------------ learned preconditioner API
-static int64_t max_leaf(const nesa::Tree& t) {
-  int64_t m = 0;
-  for (size_t a = 0; a + 1 < t.leaf_ptr.size(); ++a) m = std::max(m, t.leaf_ptr[a + 1] - t.leaf_ptr[a]);
-  return m;
-}
-
 static void check_mlp_params(const nesa_mlp_params* p) {
   if (p->s_max < 32 || p->s_max > 512 || p->s_max % 32)
     throw Error(NESA_EINVAL, "s_max must be a multiple of 32 in [32, 512]");

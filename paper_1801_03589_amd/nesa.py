@@ -40,12 +40,12 @@ class FarParams(C.Structure):
 class TreeInfo(C.Structure):
     _fields_ = [("n_rwg", C.c_int64), ("n_tri", C.c_int64), ("L", C.c_int), ("l0", C.c_int),
                 ("n_box", C.c_int64 * 32), ("near_entries", C.c_int64),
-                ("n_pairs", C.c_int64 * 32), ("Q", C.c_int * 32)]
+                ("n_pairs", C.c_int64 * 32), ("Q", C.c_int * 32), ("max_leaf", C.c_int64)]
 
 
 class GmresParams(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("tol", C.c_double),
-                ("precond", C.c_int)]
+                ("precond", C.c_int), ("fallback_ratio", C.c_double)]
 
 
 class GmresReport(C.Structure):
@@ -96,6 +96,7 @@ _SIGS = {
     "nesa_mlp_outputs": (C.c_int, [_P, _P]),
     "nesa_mlp_apply": (C.c_int, [_P, _P, _P, _P]),
     "nesa_op_set_mlp": (C.c_int, [_P, _P]),
+    "nesa_residual_error": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "nesa_last_error": (C.c_char_p, []),
 }
 
@@ -163,7 +164,7 @@ class Tree(_Handle):
         nl = i.L - i.l0 + 1
         return {"n_rwg": i.n_rwg, "n_tri": i.n_tri, "L": i.L, "l0": i.l0,
                 "n_box": list(i.n_box[:nl]), "n_pairs": list(i.n_pairs[:nl]),
-                "near_entries": i.near_entries}
+                "near_entries": i.near_entries, "max_leaf": i.max_leaf}
 
     def perm(self):
         p = np.zeros(self.info()["n_rwg"], dtype=np.int64)
@@ -282,8 +283,8 @@ def precond_apply(op, precond, r, z, stream=None):
 
 
 def gmres_solve(op, b, x, nrhs=1, restart=30, max_iters=1000, tol=1e-6, precond=PRECOND_NONE,
-                history_len=0, stream=None, check=True):
-    prm = GmresParams(restart, max_iters, tol, precond)
+                history_len=0, stream=None, check=True, fallback_ratio=0.5):
+    prm = GmresParams(restart, max_iters, tol, precond, fallback_ratio)
     rep = (GmresReport * nrhs)()
     hist = np.zeros(max(1, history_len), dtype=np.float64)
     rc = lib().nesa_gmres_solve(op.h, _dptr(b), _dptr(x), nrhs, C.byref(prm), rep,
@@ -359,3 +360,24 @@ class Mlp(_Handle):
 def op_set_mlp(op, net):
     _check(lib().nesa_op_set_mlp(op.h, net.h if net is not None else None))
     op._mlp = net
+
+
+def residual_error(op, b, xs, x, r, e, stream=None):
+    """r = b - Z x, e = xs - x (one vector each, canonical order)."""
+    _check(lib().nesa_residual_error(op.h, _dptr(b), _dptr(xs), _dptr(x), _dptr(r), _dptr(e), _stream(stream)))
+
+
+def solve_pairs(op, b, xs, iters, restart, precond):
+    """Training pairs from the method's own solves: for each k in `iters` the
+    iterate x_k of FGMRES(restart) with `precond` after k iterations from zero,
+    and (r_k, e_k) = (b - Z x_k, xs - x_k).  Returns r, e as [len(iters)][n]."""
+    import torch
+    n = b.shape[-1]
+    R = torch.empty((len(iters), n), dtype=b.dtype, device=b.device)
+    E = torch.empty_like(R)
+    for i, k in enumerate(iters):
+        x = torch.zeros_like(b)
+        if k > 0:
+            gmres_solve(op, b, x, restart=restart, max_iters=k, tol=1e-12, precond=precond, check=False)
+        residual_error(op, b, xs, x, R[i], E[i])
+    return R, E
