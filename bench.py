@@ -32,6 +32,11 @@ PEAK_FP32 = 157.3e12       # FLOP/s, dense FP32 matrix cores (and packed FP32 ve
 PEAK_BF16 = 2.5e15
 
 
+def log(msg):
+    """Progress on stderr (stdout carries the one JSON line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -42,6 +47,8 @@ def parse():
     p.add_argument("--precision", default="c64", choices=["c64", "c128", "split"])
     p.add_argument("--nrhs", type=int, default=8, help="right-hand sides of the batched product line")
     p.add_argument("--gmres-iters", type=int, default=1500)
+    p.add_argument("--bodies", type=int, default=32,
+                   help="uneven bodies in the batched-forest line (256: the full batch; 0: skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-leaves", type=int, default=24)
     return p.parse_args()
@@ -170,6 +177,7 @@ def gmres_section(args, nesa, torch, op, info, x, stream):
     t0 = time.perf_counter()
     nesa.precond_setup(op, nesa.PRECOND_SCHWARZ)
     setup_s = time.perf_counter() - t0
+    log("plain GMRES: %d iterations" % out["plain_fp32"]["iters"])
     out["schwarz_fp32"] = solve(nesa.PRECOND_SCHWARZ, args.gmres_iters)
     out["schwarz_fp32"]["setup_s"] = round(setup_s, 2)
     # training pairs: Schwarz solves of two other incidences
@@ -223,6 +231,44 @@ def batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream):
     ms = e0.elapsed_time(e1) / reps
     return {"nrhs": args.nrhs, "ms_per_product": round(ms, 4),
             "Munknowns_matvec_per_s": round(n * args.nrhs / (ms * 1e-3) / 1e6, 2)}
+
+
+def bodies_section(args, nesa, torch, prec, dt, stream):
+    """A batch of uneven seeded bodies (spheroids, boxes, capped cylinders with
+    2k to 50k unknowns, log-uniform) in one forest operator: every stage is one
+    launch for all bodies; `nrhs` incidences per body.  Munknowns * matvec / s
+    counted over all bodies and right-hand sides."""
+    import synth
+    if args.bodies <= 0:
+        return None
+    t0 = time.perf_counter()
+    bodies = synth.body_family(args.bodies, seed=4)
+    tree = nesa.build_forest([(v, t) for v, t, _ in bodies], 0.25)
+    near = nesa.assemble_near(tree)
+    far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
+    R = max(1, args.nrhs)
+    op = nesa.op_create(tree, near, far, prec, max_nrhs=R)
+    setup = time.perf_counter() - t0
+    info = tree.info()
+    n = info["n_rwg"]
+    X = torch.from_numpy(synth.complex_normal((R, n), 2)).to(dt).cuda()
+    Y = torch.empty_like(X)
+    for _ in range(2):
+        nesa.matvec(op, X, Y, R, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 4)
+    e0.record(stream)
+    for _ in range(reps):
+        nesa.matvec(op, X, Y, R, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    sizes = [len(t) * 3 // 2 for _, t, _ in bodies]
+    return {"bodies": args.bodies, "nrhs": R, "n_unknowns": n, "min_body": min(sizes), "max_body": max(sizes),
+            "levels": [info["l0"], info["L"]], "ms_per_product": round(ms, 4),
+            "Munknowns_matvec_per_s": round(n * R / (ms * 1e-3) / 1e6, 2), "setup_s": round(setup, 1)}
 
 
 def synth_rhs(n, nrhs):
@@ -339,8 +385,13 @@ def main():
         s_ = phase_ms[k] * 1e-3
         phases[k] = {"ms": phase_ms[k], "GB/s": round(alg[k]["bytes"] / s_ / 1e9, 1),
                      "TFLOP/s": round(alg[k]["flops"] / s_ / 1e12, 2)}
+    log("product: %.4f ms (%.1f Munknowns/s); GMRES section" % (ms, value))
     gm = gmres_section(args, nesa, torch, op, info, x, stream)
+    log("GMRES done; batched right-hand sides")
     batched = batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream)
+    del op
+    log("batch of %d bodies" % args.bodies)
+    bodies = bodies_section(args, nesa, torch, prec, dt, stream)
     out = {
         "metric": "NESA matvec Munknowns/s",
         "value": round(value, 3),
@@ -365,8 +416,10 @@ def main():
         "setup_s": {k: round(v_, 2) for k, v_ in setup.items()},
         "gmres": gm,
         "batched": batched,
+        "bodies": bodies,
     }
     if not args.no_cpu_baseline:
+        log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(v, t, args.cpu_sample_leaves)
     print(json.dumps(out))
 

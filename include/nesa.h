@@ -122,6 +122,21 @@ typedef struct {
  *   not shared by exactly two triangles.  Host-only; copies its inputs. */
 int nesa_build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
                     const nesa_tree_params* params, nesa_tree** out);
+/* Several closed meshes in one tree structure (batching of bodies; not in
+ * the paper, whose setting is one scatterer).  Body i keeps the partition
+ * rules of nesa_build_tree on its own grid; the levels of all bodies are
+ * aligned at the leaf level (same box side at every level), so one launch
+ * per stage serves every body, and the equivalent-source spheres of a level
+ * are shared (radius = the largest any body needs).  RWGs are numbered body
+ * by body (canonical order of body 0, then body 1, ...), leaves likewise;
+ * bodies do not interact (the operator is block-diagonal over bodies).
+ * verts[i], tris[i]: host arrays of body i as in nesa_build_tree. */
+int nesa_build_forest(int nbodies, const double* const* verts, const int64_t* nv, const int32_t* const* tris,
+                      const int64_t* nt, const nesa_tree_params* params, nesa_tree** out);
+/* Number of bodies and the canonical RWG range of each:
+ * rwg_ptr[i] .. rwg_ptr[i + 1] (host [nbodies + 1], nullable; at most nmax
+ * values written).  A tree from nesa_build_tree has one body. */
+int nesa_tree_bodies(const nesa_tree* tree, int64_t* rwg_ptr, int nmax, int* nbodies);
 int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info);
 /* perm[i] = canonical RWG index of leaf-order position i (host [n_rwg]). */
 int nesa_tree_perm(const nesa_tree* tree, int64_t* perm);

@@ -25,7 +25,8 @@ the groups, with auxiliary sources on spheres in 3D.  Reading taken here:
 * Q_l = (ceil(kr + 1.8 d0^(2/3) (kr)^(1/3)) + 1)^2, r = (sqrt 3 / 2) a_l
   (excess-bandwidth count);
 * r_e at the leaf level = 1.02 x the largest distance from a leaf centre to a
-  quadrature point of its RWGs; r_e one level up = 1.02 x (child-centre offset
+  quadrature point of its RWGs (a batch of bodies takes the largest over its
+  bodies, re_leaf); r_e one level up = 1.02 x (child-centre offset
   + child r_e); r_c = a_l (midway between r_e and 2 a_l - r_e), raised to
   1.05 r_e where the mesh is too coarse for r_e < a_l / 1.05;
 * fitting operator R_l = Tikhonov pseudo-inverse of G(X, E) with
@@ -87,7 +88,7 @@ class NesaOracle:
     """NESA operator of a closed mesh, built from the mesh alone."""
 
     def __init__(self, verts, tris, leaf=0.25, d0=3, tau=1e-9, buffer=1,
-                 k=efie.K0, eta=efie.ETA0, l0_max=2, eps=0.1):
+                 k=efie.K0, eta=efie.ETA0, l0_max=2, eps=0.1, re_leaf=None):
         self.m = efie.RWG(verts, tris)
         self.k, self.eta, self.tau, self.d0 = k, eta, tau, d0
         self.w = weights(k, eta)
@@ -103,6 +104,12 @@ class NesaOracle:
             pts = m.qp[m.tri[rw].ravel()].reshape(-1, 3)
             rmax = max(rmax, float(np.linalg.norm(pts - c, axis=1).max()))
         self.re = {t.L: 1.02 * rmax}
+        if re_leaf is not None:
+            # a batch of bodies shares the spheres of a level: the leaf radius
+            # is the largest any body of the batch needs
+            if re_leaf < self.re[t.L]:
+                raise ValueError("leaf equivalent radius smaller than this body needs")
+            self.re[t.L] = float(re_leaf)
         for l in range(t.L - 1, t.l0 - 1, -1):
             self.re[l] = 1.02 * (math.sqrt(3.0) / 2.0 * t.side(l + 1) + self.re[l + 1])
         self.rc = {l: max(t.side(l), 1.05 * self.re[l]) for l in self.levels}

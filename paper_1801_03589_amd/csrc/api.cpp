@@ -7,8 +7,13 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -195,6 +200,8 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
   p.K = K;
   p.Mr = Mr;
   p.nrt = nrt;
+  p.rblocks = ((M + 15) / 16 + nrt - 1) / nrt;
+  if (p.rblocks * nrt * 16 > Mr) throw Error(NESA_EINVAL, "row blocking exceeds the allocated rows");
   p.accumulate = accumulate;
   p.ngroups = ngroups;
   std::vector<std::vector<int32_t>> by(ngroups);
@@ -249,15 +256,128 @@ static void ensure_tiles(nesa_op* op, nesa::GemmPlan& p, int nrhs) {
   tl.col_dst = upload(op, cdst);
 }
 
+// ------------------------------------------------------------------ autotuner
+// The row blocking of every grouped GEMM (row tiles of 16 per workgroup,
+// 1..8, and the row blocks that cover M) is picked by timing the candidates
+// on the operator's own data the first time a plan runs for a number of
+// right-hand sides.  Results do not depend on the choice (every output is
+// one lane's sum in the same order).  Choices are kept per process, keyed by
+// (kernel kind, precision, M, K, nrhs, tile count), and in the file named by
+// NESA_TUNE_FILE when set; NESA_AUTOTUNE=0 keeps the default blocking.
+struct TuneKey {
+  int kind, split, M, K, nrhs;
+  int64_t ntiles;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kind, split, M, K, nrhs, ntiles) < std::tie(o.kind, o.split, o.M, o.K, o.nrhs, o.ntiles);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+static bool g_tune_loaded = false;
+
+static bool autotune_enabled() {
+  const char* e = std::getenv("NESA_AUTOTUNE");
+  return !(e && std::string(e) == "0");
+}
+
+static void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* f = std::getenv("NESA_TUNE_FILE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "r");
+  if (!fp) return;
+  TuneKey k;
+  long long nt;
+  int nrt;
+  while (std::fscanf(fp, "%d %d %d %d %d %lld %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &nrt) == 7) {
+    k.ntiles = nt;
+    if (nrt >= 1 && nrt <= 8) g_tune[k] = nrt;
+  }
+  std::fclose(fp);
+}
+
+static void tune_store_locked(const TuneKey& k, int nrt) {
+  g_tune[k] = nrt;
+  const char* f = std::getenv("NESA_TUNE_FILE");
+  if (!f) return;
+  FILE* fp = std::fopen(f, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%d %d %d %d %d %lld %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles, nrt);
+  std::fclose(fp);
+}
+
+static void set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, int nrt) {
+  tl.nrt = nrt;
+  tl.rblocks = ((p.M + 15) / 16 + nrt - 1) / nrt;
+}
+
+static void tune_plan(nesa::GemmPlan& p, int nrhs, const void* src, void* dst, bool translation, hipStream_t st) {
+  nesa::TileList& tl = p.by_nrhs[nrhs];
+  if (tl.nrt > 0 || tl.ntiles == 0) return;
+  if (!autotune_enabled()) {
+    set_blocking(p, tl, p.nrt);
+    return;
+  }
+  const TuneKey key{translation ? 1 : (p.accumulate ? 3 : 2), p.A_split ? 1 : 0, p.M, p.K, nrhs, tl.ntiles};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      set_blocking(p, tl, it->second);
+      return;
+    }
+  }
+  const int tiles = (p.M + 15) / 16;
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  int best = p.nrt;
+  float best_ms = 1e30f;
+  int last_blocks = -1;
+  for (int nrt = 8; nrt >= 1; --nrt) {
+    const int blocks = (tiles + nrt - 1) / nrt;
+    if (blocks * nrt * 16 > p.Mr || blocks == last_blocks) continue;
+    last_blocks = blocks;
+    set_blocking(p, tl, nrt);
+    nesa::launch_plan(p, nrhs, src, dst, st, translation);     // warm-up
+    hip_check(hipEventRecord(e0, st), "hipEventRecord");
+    for (int r = 0; r < 3; ++r) nesa::launch_plan(p, nrhs, src, dst, st, translation);
+    hip_check(hipEventRecord(e1, st), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nrt;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_blocking(p, tl, best);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_store_locked(key, best);
+}
+
 template <typename T>
-static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs) {
+static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs, hipStream_t st = nullptr) {
   if (sizeof(T) != 4) return;
+  using V2 = float2;
+  V2* s = static_cast<V2*>(d.s);
+  V2* o = static_cast<V2*>(d.o);
   for (size_t i = 0; i < d.lev.size(); ++i) {
     auto& dl = d.lev[i];
-    if (dl.npairs > 0) ensure_tiles(op, dl.trans, nrhs);
+    if (dl.npairs > 0) {
+      ensure_tiles(op, dl.trans, nrhs);
+      tune_plan(dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
+    }
     if (i > 0) {
+      auto& pl = d.lev[i - 1];
       ensure_tiles(op, dl.up, nrhs);
+      tune_plan(dl.up, nrhs, s + dl.s_off * nrhs, dl.child_out, false, st);
       ensure_tiles(op, dl.down, nrhs);
+      tune_plan(dl.down, nrhs, o + pl.s_off * nrhs, o + dl.s_off * nrhs, false, st);
     }
   }
 }
@@ -312,7 +432,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       // column-major; for complex64 the rows are padded for the row blocking
       const cd* Ds = &fl.D[(size_t)s * fl.Q * fl.Q];
       int nrt_d = 1, Qr = fl.Q;
-      if (sizeof(T) == 4) nesa::row_blocking(fl.Q, nrt_d, Qr);
+      if (sizeof(T) == 4) Qr = nesa::row_alloc(fl.Q);
       for (int q = 0; q < fl.Q; ++q)
         for (int p = 0; p < Qr; ++p) Dc.push_back(p < fl.Q ? Ds[(size_t)p * fl.Q + q] : cd(0, 0));
     }
@@ -326,15 +446,19 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         src[k] = (int32_t)lv.il_src[k];
         dst[k] = (int32_t)k;
       }
-      int nrt = 1, Qr = 0;
-      nesa::row_blocking(fl.Q, nrt, Qr);
+      int nrt = 1, Qdef = 0;
+      nesa::row_blocking(fl.Q, nrt, Qdef);
+      const int Qr = nesa::row_alloc(fl.Q);
       dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst);
       if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.trans, Dc, nused);
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * op->max_nrhs * fl.Q * 2 * sizeof(T));
     }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
-    if (l < t.L) dl.child_ptr = upload(op, to_i32(lv.child_ptr));
+    if (l < t.L) {
+      dl.child_ptr = upload(op, to_i32(lv.child_ptr));
+      dl.child_end = upload(op, to_i32(lv.child_end));
+    }
     if (l > t.l0) {
       dl.parent = upload(op, to_i32(lv.parent));
       dl.octant = upload(op, lv.octant);
@@ -348,9 +472,10 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       dl.Crm = upload_complex<T>(op, fl.Cup);
       if (sizeof(T) == 4) {
         // upward: A_o = C_o (Qp x Qc), column-major, rows padded to Qpr
-        int nrt_u = 1, nrt_d = 1, Qpr = 0, Qcr = 0;
-        nesa::row_blocking(Qp, nrt_u, Qpr);
-        nesa::row_blocking(Qc, nrt_d, Qcr);
+        int nrt_u = 1, nrt_d = 1, Qdef = 0;
+        nesa::row_blocking(Qp, nrt_u, Qdef);
+        nesa::row_blocking(Qc, nrt_d, Qdef);
+        const int Qpr = nesa::row_alloc(Qp), Qcr = nesa::row_alloc(Qc);
         std::vector<cd> au((size_t)8 * Qc * Qpr, cd(0, 0)), ad((size_t)8 * Qp * Qcr, cd(0, 0));
         for (int o = 0; o < 8; ++o)
           for (int p = 0; p < Qp; ++p)
@@ -359,11 +484,13 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
               au[((size_t)o * Qc + q) * Qpr + p] = c;      // C_o[p][q]
               ad[((size_t)o * Qp + p) * Qcr + q] = c;      // (C_o^T)[q][p]
             }
-        std::vector<int32_t> grp(lv.nbox), idx(lv.nbox), par(lv.nbox);
+        // boxes with a parent (in a forest the top box of a body has none)
+        std::vector<int32_t> grp, idx, par;
         for (int64_t b = 0; b < lv.nbox; ++b) {
-          grp[b] = lv.octant[b];
-          idx[b] = (int32_t)b;
-          par[b] = (int32_t)lv.parent[b];
+          if (lv.parent[b] < 0) continue;
+          grp.push_back(lv.octant[b]);
+          idx.push_back((int32_t)b);
+          par.push_back((int32_t)lv.parent[b]);
         }
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
@@ -694,6 +821,32 @@ int nesa_build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_
   });
 }
 
+int nesa_build_forest(int nbodies, const double* const* verts, const int64_t* nv, const int32_t* const* tris,
+                      const int64_t* nt, const nesa_tree_params* params, nesa_tree** out) {
+  return guarded([&]() {
+    if (nbodies < 1 || !verts || !nv || !tris || !nt || !params || !out) return fail(NESA_EINVAL, "null argument");
+    for (int i = 0; i < nbodies; ++i)
+      if (!verts[i] || !tris[i]) return fail(NESA_EINVAL, "null argument");
+    std::unique_ptr<nesa_tree> h(new nesa_tree());
+    h->t.reset(nesa::build_forest(nbodies, verts, nv, tris, nt, params->leaf_size, params->l0_max, params->buffer));
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_tree_bodies(const nesa_tree* tree, int64_t* rwg_ptr, int nmax, int* nbodies) {
+  return guarded([&]() {
+    if (!tree || !nbodies) return fail(NESA_EINVAL, "null argument");
+    const auto& br = tree->t->body_rwg;
+    const int nb = br.empty() ? 1 : (int)br.size() - 1;
+    *nbodies = nb;
+    if (rwg_ptr) {
+      for (int i = 0; i <= nb && i < nmax; ++i) rwg_ptr[i] = br.empty() ? (i == 0 ? 0 : tree->t->rwg.n) : br[i];
+    }
+    return (int)NESA_OK;
+  });
+}
+
 int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info) {
   return guarded([&]() {
     if (!tree || !info) return fail(NESA_EINVAL, "null argument");
@@ -858,7 +1011,7 @@ static int matvec_impl(nesa_op* op, const void* x, void* y, int64_t nrhs, void* 
       }
     } else {
       const int64_t n = op->f.n;
-      ensure_all_tiles<float>(op, op->f, (int)nrhs);
+      ensure_all_tiles<float>(op, op->f, (int)nrhs, st);
       if (canonical) {
         for (int64_t r = 0; r < nrhs; ++r)
           nesa::launch_gather<float>(static_cast<const char*>(x) + (size_t)r * n * 8,

@@ -14,6 +14,7 @@ namespace nesa {
 // (pair, channel) columns of one group, so the tiling depends on the number of
 // right-hand sides (channels = 4 x nrhs) and is built per nrhs on first use.
 struct TileList {
+  int nrt = 0, rblocks = 0;       // row tiles per workgroup and row blocks chosen by the autotuner (0: plan default)
   int64_t ntiles = 0;
   int32_t* tile_group = nullptr;
   int32_t* tile_ncols = nullptr;
@@ -25,8 +26,9 @@ struct GemmPlan {
   const void* A_split = nullptr; // split precision: [groups][4 planes][Mr][Kp] bf16 (re hi, re lo, im hi, im lo)
   int Kp = 0;                    // K rounded up to 32
   int64_t a_stride = 0;
-  int M = 0, K = 0, Mr = 0;      // Mr = row blocks x nrt x 16
-  int nrt = 1;                    // row tiles of 16 per workgroup (1..8)
+  int M = 0, K = 0, Mr = 0;      // Mr = rows of A allocated (row_alloc), >= rblocks x nrt x 16
+  int nrt = 1;                    // default row tiles of 16 per workgroup (1..8)
+  int rblocks = 1;                // default row blocks (grid y)
   int accumulate = 0;
   int ngroups = 0;
   std::vector<int32_t> group_count;   // host: pairs per group
@@ -51,7 +53,8 @@ struct DevLevel {
   GemmPlan up;                  // this level's children -> parents (groups = octants)
   void* child_out = nullptr;    // [nbox][4][Q_{l-1}] C s_child of every child
   GemmPlan down;                // parents -> this level's boxes (groups = octants, accumulate)
-  int32_t* child_ptr = nullptr;  // [nbox + 1] children at level l+1
+  int32_t* child_ptr = nullptr;  // [nbox] first child at level l+1
+  int32_t* child_end = nullptr;  // [nbox] end of the children
   int32_t* parent = nullptr;     // [nbox] (l > l0)
   int32_t* octant = nullptr;     // [nbox] (l > l0)
 };
@@ -85,6 +88,14 @@ inline void row_blocking(int M, int& nrt, int& Mr) {
   const int blocks = (tiles + 7) / 8;
   nrt = (tiles + blocks - 1) / blocks;
   Mr = blocks * nrt * 16;
+}
+
+// Rows allocated for A of a grouped GEMM with M rows: 16 x (row tiles rounded
+// up to 8), which holds every blocking with 1..8 row tiles per workgroup the
+// autotuner may pick except those that pad beyond it.
+inline int row_alloc(int M) {
+  const int tiles = (M + 15) / 16;
+  return 16 * ((tiles + 7) / 8 * 8);
 }
 
 // kernel kinds of the per-launch timing
@@ -130,6 +141,8 @@ template <typename T>
 void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st);
 template <typename T>
 void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st);
+// one grouped GEMM plan for nrhs right-hand sides (autotuner timing)
+void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st, bool translation);
 // y = arena x with an arena in the near-block layout (leaf order, one RHS)
 template <typename T>
 void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st);

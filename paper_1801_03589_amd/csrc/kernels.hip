@@ -102,13 +102,14 @@ __global__ __launch_bounds__(NT) void k_upward(const typename C2<T>::type* __res
                                                const typename C2<T>::type* __restrict__ s_child,
                                                typename C2<T>::type* __restrict__ s_par,
                                                const int32_t* __restrict__ child_ptr,
+                                               const int32_t* __restrict__ child_end,
                                                const int32_t* __restrict__ octant, int Qp, int Qc) {
   using V2 = typename C2<T>::type;
   __shared__ V2 red[NT / WAVE][4][WAVE];
   const int P = blockIdx.y;
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int p = blockIdx.x * WAVE + lane;
-  const int c0 = child_ptr[P], c1 = child_ptr[P + 1];
+  const int c0 = child_ptr[P], c1 = child_end[P];
   V2 acc[4];
   for (int c = 0; c < 4; ++c) acc[c] = cmk<T>(0, 0);
   if (p < Qp) {
@@ -519,12 +520,13 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
   cgemm_tiles_body<NRT>(g);
 }
 
-// dst_a = sum over [ptr[a], ptr[a+1]) of the per-pair results, in order (deterministic)
+// dst_a = sum over [beg[a], end[a]) of the per-pair results, in order (deterministic)
 template <typename V>
 __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
-                                                   const int32_t* __restrict__ ptr, int J) {
+                                                   const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
+                                                   int J) {
   const int a = blockIdx.x;
-  const int k0 = ptr[a], k1 = ptr[a + 1];
+  const int k0 = beg[a], k1 = end[a];
   for (int j = threadIdx.x; j < J; j += NT) {
     V acc;
     acc.x = 0;
@@ -554,6 +556,7 @@ __global__ __launch_bounds__(NT) void k_downward(const typename C2<T>::type* __r
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int q = blockIdx.x * WAVE + lane;
   const int P = parent[a];
+  if (P < 0) return;                     // top box of a body in a forest (whole workgroup)
   const V2* C = Crm + (size_t)octant[a] * Qp * Qc + q;
   const V2* op = o_par + (size_t)P * 4 * Qp;
   V2 acc[4];
@@ -1016,7 +1019,9 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
   g.col_src = tl.col_src;
   g.col_dst = tl.col_dst;
   if (tl.ntiles == 0) return;
-  dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)(p.Mr / 16 / p.nrt));
+  const int nrt = tl.nrt > 0 ? tl.nrt : p.nrt;
+  const int rblocks = tl.nrt > 0 ? tl.rblocks : p.rblocks;
+  dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
 #define NESA_TILES(N)                                                                        \
   if (p.A_split) {                                                                           \
     const unsigned short* As = static_cast<const unsigned short*>(p.A_split);                \
@@ -1030,7 +1035,7 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
     k_transfer_gemm<N><<<grid, NT, 0, st>>>(g);                                              \
   }                                                                                          \
   break;
-  switch (p.nrt) {
+  switch (nrt) {
     case 1: NESA_TILES(1)
     case 2: NESA_TILES(2)
     case 3: NESA_TILES(3)
@@ -1041,6 +1046,10 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
     default: NESA_TILES(8)
   }
 #undef NESA_TILES
+}
+
+void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st, bool translation) {
+  launch_tiles(p, nrhs, src, dst, st, translation);
 }
 
 template <typename T>
@@ -1072,12 +1081,12 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
       k_csr_reduce<V2><<<(unsigned)p.nbox, NT, 0, st>>>(static_cast<const V2*>(c.child_out), s + p.s_off * R,
-                                                        p.child_ptr, NC * p.Q);
+                                                        p.child_ptr, p.child_end, NC * p.Q);
       if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
     } else {
       dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
       k_upward<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off, p.child_ptr,
-                                       c.octant, p.Q, c.Q);
+                                       p.child_end, c.octant, p.Q, c.Q);
       if (tm) tm->mark(st, -1, l, K_UP_VALU);
     }
   }
@@ -1088,7 +1097,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, st, true);
       if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
       k_csr_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out), o + lv.s_off * R,
-                                                         lv.il_ptr, NC * lv.Q);
+                                                         lv.il_ptr, lv.il_ptr + 1, NC * lv.Q);
       if (tm) tm->mark(st, -1, l, K_TRANS_REDUCE);
     } else if (mfma) {
       const int64_t cnt = lv.nbox * NC * lv.Q;

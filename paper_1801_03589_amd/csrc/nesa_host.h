@@ -40,9 +40,12 @@ struct Level {
   double side = 0;
   int64_t nbox = 0;
   std::vector<std::array<int32_t, 3>> key;
-  std::vector<int64_t> parent;      // box index at level l-1 (empty at l0)
+  std::vector<int64_t> parent;      // box index at level l-1 (empty at l0; -1 for a body's top box)
   std::vector<int32_t> octant;      // position inside the parent (bit0 x, bit1 y, bit2 z)
-  std::vector<int64_t> child_ptr;   // children at level l+1: [child_ptr[b], child_ptr[b+1])
+  std::vector<int64_t> child_ptr;   // children at level l+1 start at child_ptr[b]
+  std::vector<int64_t> child_end;   // ... and end at child_end[b] (= child_ptr[b+1] in one body;
+                                    // in a forest other bodies' top boxes may follow)
+  std::vector<int32_t> body;        // body of every box (forests of several meshes)
   std::vector<int64_t> il_ptr;      // interaction list (Sec. 3): CSR by target
   std::vector<int64_t> il_src;
   std::vector<int32_t> il_slot;     // offset slot of (target key - source key)
@@ -58,14 +61,19 @@ struct Tree {
   std::vector<int64_t> pos;         // canonical RWG -> leaf-order position
   std::vector<int64_t> leaf_ptr;    // RWGs of leaf b: positions [leaf_ptr[b], leaf_ptr[b+1])
   std::vector<int64_t> near_ptr, near_idx;   // leaf-level near lists
+  // forest of several meshes: per-body grid origin and canonical RWG ranges
+  // (empty for a single mesh); levels are aligned at the leaves
+  std::vector<std::array<double, 3>> body_lo;
+  std::vector<int64_t> body_rwg;    // [nbodies + 1]
   int slot_w() const { return 4 * buffer + 3; }   // offsets in [-(2b+1), 2b+1] per axis
   int nslot() const { return slot_w() * slot_w() * slot_w(); }
   const Level& level(int l) const { return lev[l - l0]; }
   Level& level(int l) { return lev[l - l0]; }
   std::array<double, 3> center(int l, int64_t b) const {
     const Level& lv = level(l);
-    return {lo[0] + (lv.key[b][0] + 0.5) * lv.side, lo[1] + (lv.key[b][1] + 0.5) * lv.side,
-            lo[2] + (lv.key[b][2] + 0.5) * lv.side};
+    const double* o = body_lo.empty() ? lo : body_lo[lv.body[b]].data();
+    return {o[0] + (lv.key[b][0] + 0.5) * lv.side, o[1] + (lv.key[b][1] + 0.5) * lv.side,
+            o[2] + (lv.key[b][2] + 0.5) * lv.side};
   }
 };
 
@@ -101,6 +109,11 @@ void parallel_for(int64_t n, const std::function<void(int64_t)>& fn);
 
 Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t nt,
                  double leaf, int l0_max, int buffer);
+// Several meshes in one tree structure: each body keeps its own grid, levels
+// and lists; levels are aligned at the leaf level, boxes, RWGs and leaves are
+// numbered body by body.
+Tree* build_forest(int nbodies, const double* const* verts, const int64_t* nv, const int32_t* const* tris,
+                   const int64_t* nt, double leaf, int l0_max, int buffer);
 Near* assemble_near(const Tree& t, double k, double eta);
 Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau, double eps);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,

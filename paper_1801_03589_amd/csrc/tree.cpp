@@ -212,6 +212,7 @@ Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t n
     }
     P.child_ptr.push_back(C.nbox);
     P.nbox = (int64_t)P.key.size();
+    P.child_end.assign(P.child_ptr.begin() + 1, P.child_ptr.end());
   }
   // hash maps key -> box index per level
   std::vector<std::unordered_map<uint64_t, int64_t>> idx(t.lev.size());
@@ -274,6 +275,109 @@ Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t n
     }
   }
   return T.release();
+}
+
+static void append_rwg(Rwg& F, const Rwg& r) {
+  const int64_t vo = (int64_t)F.v.size() / 3, to = F.nt, ro = F.n;
+  F.v.insert(F.v.end(), r.v.begin(), r.v.end());
+  for (int32_t x : r.t) F.t.push_back((int32_t)(x + vo));
+  for (int64_t x : r.edge) F.edge.push_back(x + vo);
+  for (int64_t x : r.tri) F.tri.push_back(x + to);
+  for (int64_t x : r.freev) F.freev.push_back(x + vo);
+  F.len.insert(F.len.end(), r.len.begin(), r.len.end());
+  F.area.insert(F.area.end(), r.area.begin(), r.area.end());
+  F.normal.insert(F.normal.end(), r.normal.begin(), r.normal.end());
+  for (int64_t x : r.tri_rwg) F.tri_rwg.push_back(x + ro);
+  F.tri_sign.insert(F.tri_sign.end(), r.tri_sign.begin(), r.tri_sign.end());
+  F.qp.insert(F.qp.end(), r.qp.begin(), r.qp.end());
+  F.n += r.n;
+  F.nt += r.nt;
+}
+
+Tree* build_forest(int nbodies, const double* const* verts, const int64_t* nv, const int32_t* const* tris,
+                   const int64_t* nt, double leaf, int l0_max, int buffer) {
+  if (nbodies < 1) throw Error(-1, "a forest needs at least one body");
+  std::vector<std::unique_ptr<Tree>> B(nbodies);
+  parallel_for(nbodies, [&](int64_t i) {
+    B[i].reset(build_tree(verts[i], nv[i], tris[i], nt[i], leaf, l0_max, buffer));
+  });
+  std::unique_ptr<Tree> F(new Tree());
+  F->leaf = leaf;
+  F->buffer = buffer;
+  F->L = 0;
+  for (auto& b : B) F->L = std::max(F->L, b->L);
+  // body i's level li sits at forest level li + (L - L_i)
+  F->l0 = F->L;
+  for (auto& b : B) F->l0 = std::min(F->l0, b->l0 + F->L - b->L);
+  for (int c = 0; c < 3; ++c) F->lo[c] = B[0]->lo[c];
+  F->lev.resize(F->L - F->l0 + 1);
+  for (int l = F->l0; l <= F->L; ++l) {
+    F->level(l).l = l;
+    F->level(l).side = leaf * (double)(1LL << (F->L - l));
+  }
+  F->body_rwg.push_back(0);
+  // box offsets of every body at every forest level
+  std::vector<std::vector<int64_t>> boff(F->lev.size(), std::vector<int64_t>(nbodies + 1, 0));
+  for (int l = F->l0; l <= F->L; ++l)
+    for (int i = 0; i < nbodies; ++i) {
+      const int li = l - (F->L - B[i]->L);
+      const int64_t nb = (li >= B[i]->l0) ? B[i]->level(li).nbox : 0;
+      boff[l - F->l0][i + 1] = boff[l - F->l0][i] + nb;
+    }
+  int64_t leaf_off = 0;
+  for (int i = 0; i < nbodies; ++i) {
+    const Tree& b = *B[i];
+    const int64_t ro = F->rwg.n;
+    append_rwg(F->rwg, b.rwg);
+    F->body_rwg.push_back(F->rwg.n);
+    F->body_lo.push_back({b.lo[0], b.lo[1], b.lo[2]});
+    for (int64_t p : b.perm) F->perm.push_back(p + ro);
+    for (size_t a = 0; a + 1 < b.leaf_ptr.size(); ++a) F->leaf_ptr.push_back(b.leaf_ptr[a] + ro);
+    for (size_t a = 0; a + 1 < b.near_ptr.size(); ++a) F->near_ptr.push_back(b.near_ptr[a] + (int64_t)F->near_idx.size() - b.near_ptr[0]);
+    for (int64_t x : b.near_idx) F->near_idx.push_back(x + leaf_off);
+    leaf_off += b.level(b.L).nbox;
+    const int shift = F->L - b.L;
+    for (int li = b.l0; li <= b.L; ++li) {
+      const int l = li + shift;
+      const Level& s = b.level(li);
+      Level& d = F->level(l);
+      const int64_t off = boff[l - F->l0][i];
+      d.key.insert(d.key.end(), s.key.begin(), s.key.end());
+      d.body.insert(d.body.end(), s.nbox, i);
+      if (l > F->l0) {
+        if (li > b.l0) {
+          const int64_t poff = boff[l - 1 - F->l0][i];
+          for (int64_t p : s.parent) d.parent.push_back(p + poff);
+          d.octant.insert(d.octant.end(), s.octant.begin(), s.octant.end());
+        } else {
+          d.parent.insert(d.parent.end(), s.nbox, -1);
+          d.octant.insert(d.octant.end(), s.nbox, 0);
+        }
+      }
+      if (li < b.L) {
+        const int64_t coff = boff[l + 1 - F->l0][i];
+        for (int64_t k = 0; k < s.nbox; ++k) {
+          d.child_ptr.push_back(s.child_ptr[k] + coff);
+          d.child_end.push_back(s.child_ptr[k + 1] + coff);
+        }
+      }
+      const int64_t io = (int64_t)d.il_src.size();
+      for (int64_t k = 0; k < s.nbox; ++k) d.il_ptr.push_back(s.il_ptr[k] + io);
+      for (int64_t x : s.il_src) d.il_src.push_back(x + off);
+      d.il_slot.insert(d.il_slot.end(), s.il_slot.begin(), s.il_slot.end());
+    }
+  }
+  F->leaf_ptr.push_back(F->rwg.n);
+  F->near_ptr.push_back((int64_t)F->near_idx.size());
+  F->pos.resize(F->rwg.n);
+  for (int64_t i = 0; i < F->rwg.n; ++i) F->pos[F->perm[i]] = i;
+  for (int l = F->l0; l <= F->L; ++l) {
+    Level& d = F->level(l);
+    d.nbox = boff[l - F->l0][nbodies];
+    d.il_ptr.push_back((int64_t)d.il_src.size());
+    if (l < F->L) d.child_ptr.push_back(boff[l + 1 - F->l0][nbodies]);
+  }
+  return F.release();
 }
 
 }  // namespace nesa

@@ -65,6 +65,8 @@ _P = C.c_void_p
 _SIGS = {
     "nesa_build_tree": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(TreeParams), C.POINTER(_P)]),
     "nesa_tree_get_info": (C.c_int, [_P, C.POINTER(TreeInfo)]),
+    "nesa_build_forest": (C.c_int, [C.c_int, _P, _P, _P, _P, C.POINTER(TreeParams), C.POINTER(_P)]),
+    "nesa_tree_bodies": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_int)]),
     "nesa_tree_perm": (C.c_int, [_P, _P]),
     "nesa_tree_free": (None, [_P]),
     "nesa_assemble_near": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
@@ -166,6 +168,14 @@ class Tree(_Handle):
                 "n_box": list(i.n_box[:nl]), "n_pairs": list(i.n_pairs[:nl]),
                 "near_entries": i.near_entries, "max_leaf": i.max_leaf}
 
+    def bodies(self):
+        """Canonical RWG range of every body: array [nbodies + 1]."""
+        nb = C.c_int()
+        _check(lib().nesa_tree_bodies(self.h, None, 0, C.byref(nb)))
+        out = np.zeros(nb.value + 1, dtype=np.int64)
+        _check(lib().nesa_tree_bodies(self.h, _ptr(out), nb.value + 1, C.byref(nb)))
+        return out
+
     def perm(self):
         p = np.zeros(self.info()["n_rwg"], dtype=np.int64)
         _check(lib().nesa_tree_perm(self.h, _ptr(p)))
@@ -187,6 +197,24 @@ class Far(_Handle):
 
 class Op(_Handle):
     _free = "nesa_op_free"
+
+
+def build_forest(bodies, leaf_size=0.25, l0_max=2, buffer=1):
+    """bodies: list of (verts, tris)."""
+    vs = [np.ascontiguousarray(v, dtype=np.float64) for v, _ in bodies]
+    ts = [np.ascontiguousarray(t, dtype=np.int32) for _, t in bodies]
+    nb = len(bodies)
+    vp = (C.c_void_p * nb)(*[v.ctypes.data for v in vs])
+    tp = (C.c_void_p * nb)(*[t.ctypes.data for t in ts])
+    nv = np.array([len(v) for v in vs], dtype=np.int64)
+    nt = np.array([len(t) for t in ts], dtype=np.int64)
+    h = C.c_void_p()
+    prm = TreeParams(leaf_size, l0_max, buffer)
+    _check(lib().nesa_build_forest(nb, C.cast(vp, C.c_void_p), _ptr(nv), C.cast(tp, C.c_void_p), _ptr(nt),
+                                   C.byref(prm), C.byref(h)))
+    tr = Tree(h)
+    tr._keep = (vs, ts)
+    return tr
 
 
 def build_tree(verts, tris, leaf_size=0.25, l0_max=2, buffer=1):

@@ -242,3 +242,42 @@ def test_schwarz_fgmres_matches_oracle(torch_dev, nesa):
     x = xd.cpu().numpy()
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
     assert rep[0]["iters"] < 326 / 4
+
+
+_forest = {}
+
+
+def _forest_case(nesa):
+    """Four uneven bodies (sphere, box, spheroid, cylinder; 1 to 3 levels each)
+    in one forest, and per-body oracles sharing the forest's leaf radius."""
+    if not _forest:
+        bodies = [synth.icosphere(6, 0.3), synth.box_mesh((0.5, 0.3, 0.4), 0.06),
+                  synth.spheroid((0.6, 0.3, 0.3), 0.07), synth.capped_cylinder(0.2, 0.8, 0.07)]
+        own = [onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8) for v, t in bodies]
+        re = max(o.re[o.t.L] for o in own)
+        refs = [onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8, re_leaf=re) for v, t in bodies]
+        fr = nesa.build_forest(bodies, 0.25)
+        near = nesa.assemble_near(fr)
+        far = nesa.assemble_translations(fr, d0=3, tau=1e-8)
+        _forest.update(refs=refs, tree=fr, near=near, far=far, ptr=fr.bodies())
+    return _forest
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64", "split"])
+def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
+    """One product over a batch of uneven bodies (one launch per stage for all
+    of them) against each body's oracle product, for three right-hand sides."""
+    f = _forest_case(nesa)
+    p = {"c128": nesa.C128, "c64": nesa.C64, "split": nesa.C64_SPLIT}[prec]
+    op = nesa.op_create(f["tree"], f["near"], f["far"], p, max_nrhs=3)
+    ptr = f["ptr"]
+    X = synth.complex_normal((3, ptr[-1]), 50)
+    Y = _run(torch_dev, nesa, op, X, nrhs=3)
+    tol = TOL["c128"] if prec == "c128" else 1e-4 if prec == "split" else TOL["c64"]
+    for i, ref in enumerate(f["refs"]):
+        for r in range(3):
+            yr = ref.matvec(X[r][ptr[i]:ptr[i + 1]])
+            err = np.linalg.norm(Y[r][ptr[i]:ptr[i + 1]] - yr) / np.linalg.norm(yr)
+            print("%s body %d (N=%d, levels %d..%d) rhs %d: rel err %.2e"
+                  % (prec, i, ref.m.n, ref.t.l0, ref.t.L, r, err))
+            assert err <= tol, (i, r, err)

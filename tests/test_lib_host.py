@@ -117,3 +117,56 @@ def test_error_paths(nesa):
     with pytest.raises(nesa.NesaError) as e:
         nesa.assemble_translations(nesa.build_tree(*synth.icosphere(2, 1.0), 0.05))
     assert e.value.code == -4
+
+
+def _bodies():
+    return [synth.icosphere(6, 0.3), synth.box_mesh((0.5, 0.3, 0.4), 0.06),
+            synth.spheroid((0.6, 0.3, 0.3), 0.07), synth.capped_cylinder(0.2, 0.8, 0.07)]
+
+
+def test_forest_matches_per_body_trees(nesa):
+    """Forest of several meshes: body i keeps its own tree, shifted so that all
+    leaf levels align; RWGs and leaves numbered body by body."""
+    bodies = _bodies()
+    fr = nesa.build_forest(bodies, 0.25)
+    fi = fr.info()
+    trees = [nesa.build_tree(v, t, 0.25) for v, t in bodies]
+    infos = [tr.info() for tr in trees]
+    ptr = fr.bodies()
+    assert list(np.diff(ptr)) == [i["n_rwg"] for i in infos]
+    assert fi["L"] == max(i["L"] for i in infos)
+    assert fi["l0"] == min(i["l0"] + fi["L"] - i["L"] for i in infos)
+    for l in range(fi["l0"], fi["L"] + 1):
+        nb = 0
+        npairs = 0
+        for i in infos:
+            li = l - (fi["L"] - i["L"])
+            if li >= i["l0"]:
+                nb += i["n_box"][li - i["l0"]]
+                npairs += i["n_pairs"][li - i["l0"]]
+        assert fi["n_box"][l - fi["l0"]] == nb
+        assert fi["n_pairs"][l - fi["l0"]] == npairs
+    assert fi["near_entries"] == sum(i["near_entries"] for i in infos)
+    perm = np.concatenate([tr.perm() + ptr[i] for i, tr in enumerate(trees)])
+    assert np.array_equal(fr.perm(), perm)
+
+
+def test_forest_near_entries_match_oracle(nesa):
+    """Near-field entries of every body of a forest against the dense oracle
+    matrix of that body (bodies never couple)."""
+    bodies = _bodies()[:2]
+    fr = nesa.build_forest(bodies, 0.25)
+    nr = nesa.assemble_near(fr)
+    ptr = fr.bodies()
+    for i, (v, t) in enumerate(bodies):
+        m = efie.RWG(v, t)
+        ot = Octree(v, m.midpoints(), leaf=0.25)
+        Zd = efie.z_block(m, np.arange(m.n), np.arange(m.n))
+        for r in (0, m.n // 2, m.n - 1):
+            a = ot.rwg_leaf[r]
+            cols = np.concatenate([ot.leaf_rwgs[b] for b in ot.near[a]])
+            z = nesa.near_entries(fr, nr, [r + ptr[i]], cols + ptr[i])[0]
+            assert np.abs(z - Zd[r, cols]).max() <= 1e-13 * np.abs(Zd[r, cols]).max()
+        # no entry couples two bodies
+        other = ptr[1 - i] + np.arange(5)
+        assert np.all(nesa.near_entries(fr, nr, [ptr[i]], other)[0] == 0)
