@@ -47,6 +47,10 @@ def parse():
     p.add_argument("--precision", default="c64", choices=["c64", "c128", "split"])
     p.add_argument("--nrhs", type=int, default=8, help="right-hand sides of the batched product line")
     p.add_argument("--gmres-iters", type=int, default=1500)
+    p.add_argument("--only-product", action="store_true",
+                   help="time the product only (no GMRES, batched or CPU lines): the profiled command")
+    p.add_argument("--counters", action="store_true",
+                   help="run 5 products and a 512 MiB device copy for hardware-counter passes, then exit")
     p.add_argument("--bodies", type=int, default=32,
                    help="uneven bodies in the batched-forest line (256: the full batch; 0: skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -148,6 +152,28 @@ def cpu_baseline(v, t, sample_leaves, seed=0):
                        "means scaled to the full tree (extrapolated %.2f s per product; operators built "
                        "untimed in %.1f s)" % (len(leaves), nleaf, total, t_setup)),
             "stage_seconds": {k: round(v_, 3) for k, v_ in est.items()}}
+
+
+def profiled_traffic(kernel, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source has changed since the counters
+    were taken (or the summary does not cover this precision)."""
+    import hashlib
+    if precision != "c64" or kernel != "k_translate_gemm":
+        return None
+    prof = os.path.join(ROOT, "profiles", "k_translate_gemm_sphere201720_c64.md")
+    src = os.path.join(ROOT, "paper_1801_03589_amd", "csrc", "kernels.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if ("sha256 prefix `%s`" % sha) not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return int(line.split(":")[1])
+    return None
 
 
 def gmres_section(args, nesa, torch, op, info, x, stream):
@@ -310,6 +336,19 @@ def main():
     x = torch.from_numpy(synth.complex_normal(n, 0)).to(dt).cuda()
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    if args.counters:
+        # counter passes: five products, then a plain copy of known size whose
+        # FETCH_SIZE / WRITE_SIZE calibrate the counters (512 MiB read, 512 MiB written)
+        for _ in range(5):
+            nesa.matvec(op, x, y, stream=stream)
+        torch.cuda.synchronize()
+        log("products done")
+        big = torch.ones(64 * 2 ** 20, dtype=torch.complex64, device="cuda")
+        big2 = torch.empty_like(big)
+        big2.copy_(big)
+        torch.cuda.synchronize()
+        log("copy of 512 MiB done")
+        return
     for _ in range(args.warmup):
         nesa.matvec(op, x, y, stream=stream)
     torch.cuda.synchronize()
@@ -371,9 +410,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": kd["bytes"] / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
     roof["kernel"] = {"translate_gemm": "k_translate_gemm", "near_recv": "k_near_recv",
                       "upward_gemm": "k_transfer_gemm", "downward_gemm": "k_transfer_gemm"}.get(dom, dom)
+    roof["traffic"] = profiled_traffic(roof["kernel"], args.precision)
     roof["launches_per_product"] = kd["launches"]
     roof["avg_launch_ms"] = kd["ms"] / kd["launches"]
     kernels = {k: {"ms_per_product": round(v_["ms"], 4), "launches": v_["launches"],
@@ -385,13 +424,15 @@ def main():
         s_ = phase_ms[k] * 1e-3
         phases[k] = {"ms": phase_ms[k], "GB/s": round(alg[k]["bytes"] / s_ / 1e9, 1),
                      "TFLOP/s": round(alg[k]["flops"] / s_ / 1e12, 2)}
-    log("product: %.4f ms (%.1f Munknowns/s); GMRES section" % (ms, value))
-    gm = gmres_section(args, nesa, torch, op, info, x, stream)
-    log("GMRES done; batched right-hand sides")
-    batched = batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream)
-    del op
-    log("batch of %d bodies" % args.bodies)
-    bodies = bodies_section(args, nesa, torch, prec, dt, stream)
+    log("product: %.4f ms (%.1f Munknowns/s)" % (ms, value))
+    gm = batched = bodies = None
+    if not args.only_product:
+        gm = gmres_section(args, nesa, torch, op, info, x, stream)
+        log("GMRES done; batched right-hand sides")
+        batched = batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream)
+        del op
+        log("batch of %d bodies" % args.bodies)
+        bodies = bodies_section(args, nesa, torch, prec, dt, stream)
     out = {
         "metric": "NESA matvec Munknowns/s",
         "value": round(value, 3),
@@ -418,7 +459,7 @@ def main():
         "batched": batched,
         "bodies": bodies,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_product:
         log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(v, t, args.cpu_sample_leaves)
     print(json.dumps(out))
