@@ -84,6 +84,23 @@ def gmat(A, B, k=efie.K0):
     return efie.green(R, k)
 
 
+def leaf_radius_of(m, t):
+    """Leaf equivalent radius: 1.02 x the largest distance from a leaf centre to
+    a quadrature point of the leaf's RWGs."""
+    rmax = 0.0
+    for b, rw in enumerate(t.leaf_rwgs):
+        c = t.center(t.L, b)
+        pts = m.qp[m.tri[rw].ravel()].reshape(-1, 3)
+        rmax = max(rmax, float(np.linalg.norm(pts - c, axis=1).max()))
+    return 1.02 * rmax
+
+
+def leaf_radius(verts, tris, leaf=0.25):
+    """Leaf equivalent radius a body needs (the largest over a batch is shared)."""
+    m = efie.RWG(verts, tris)
+    return leaf_radius_of(m, Octree(verts, m.midpoints(), leaf=leaf))
+
+
 class NesaOracle:
     """NESA operator of a closed mesh, built from the mesh alone."""
 
@@ -97,13 +114,7 @@ class NesaOracle:
         self.levels = list(range(t.l0, t.L + 1))
         self.Q = {l: q_rule(t.side(l), d0, k) for l in self.levels}
         # radii
-        m = self.m
-        rmax = 0.0
-        for b, rw in enumerate(t.leaf_rwgs):
-            c = t.center(t.L, b)
-            pts = m.qp[m.tri[rw].ravel()].reshape(-1, 3)
-            rmax = max(rmax, float(np.linalg.norm(pts - c, axis=1).max()))
-        self.re = {t.L: 1.02 * rmax}
+        self.re = {t.L: leaf_radius_of(self.m, t)}
         if re_leaf is not None:
             # a batch of bodies shares the spheres of a level: the leaf radius
             # is the largest any body of the batch needs
@@ -180,12 +191,20 @@ class NesaOracle:
         t = self.t
         s = {l: [np.zeros((4, self.Q[l]), dtype=np.complex128) for _ in t.boxes[l]]
              for l in self.levels}
+        # a leaf (box) whose sources are all zero contributes exact zeros: it is
+        # skipped, so a vector supported on a few leaves needs only their V
+        live = set()
         for b, rw in enumerate(t.leaf_rwgs):
-            s[t.L][b] = self.V(b) @ x[rw]
+            if np.any(x[rw] != 0):
+                s[t.L][b] = self.V(b) @ x[rw]
+                live.add(b)
         for l in range(t.L, t.l0, -1):
-            for b in range(len(t.boxes[l])):
+            up = set()
+            for b in sorted(live):
                 p = t.parent[l][b]
                 s[l - 1][p] = s[l - 1][p] + (self.C(l, self.octant(l, b)) @ s[l][b].T).T
+                up.add(p)
+            live = up
         return s
 
     def translate(self, s, l, a):
@@ -194,6 +213,8 @@ class NesaOracle:
         ka = t.boxes[l][a]
         o = np.zeros((4, self.Q[l]), dtype=np.complex128)
         for b in t.il[l][a]:
+            if not np.any(s[l][b]):
+                continue                 # zero sources contribute exact zeros
             kb = t.boxes[l][b]
             off = (ka[0] - kb[0], ka[1] - kb[1], ka[2] - kb[2])
             o += (self.D(l, off) @ s[l][b].T).T

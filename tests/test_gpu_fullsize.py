@@ -1,0 +1,132 @@
+"""GPU parity at full workload sizes, in the launch configuration the benchmark
+times (complex64, canonical-order product through the C ABI), on outputs the
+oracle computes one by one.
+
+The input vectors are supported on a few random leaves: every stage of the
+product still runs over the whole tree (radiation, all upward levels, every
+translation, the downward pass, reception, near field), while the oracle needs
+radiation matrices only for those leaves and for the leaves of the sampled
+rows."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import nesa as onesa
+
+pytestmark = pytest.mark.gpu
+
+TOL_C64 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def nesa():
+    from paper_1801_03589_amd import nesa as n
+    n.lib()
+    return n
+
+
+def _sparse_x(ref, nleaves, seed):
+    rng = np.random.default_rng(seed)
+    t = ref.t
+    leaves = rng.choice(len(t.leaf_rwgs), size=nleaves, replace=False)
+    x = np.zeros(ref.m.n, dtype=np.complex128)
+    for a in leaves:
+        rw = np.asarray(t.leaf_rwgs[a])
+        x[rw] = synth.complex_normal(len(rw), seed + int(a))
+    return x, leaves
+
+
+def _rows(ref, src_leaves, nfar, seed):
+    """RWGs of leaves near the sources (near field and far field) and random RWGs."""
+    rng = np.random.default_rng(seed)
+    t = ref.t
+    near_rows = []
+    for a in src_leaves[:2]:
+        for b in t.near[a][:3]:
+            near_rows.append(int(t.leaf_rwgs[b][0]))
+    far_rows = rng.choice(ref.m.n, size=nfar, replace=False).tolist()
+    return np.array(sorted(set(near_rows + far_rows)))
+
+
+def _check(y, yr, tol, what):
+    err = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+    print("%s: %d sampled rows, rel err %.2e" % (what, len(yr), err))
+    assert err <= tol
+    assert np.abs(y - yr).max() <= 10 * tol * np.abs(yr).max()
+
+
+def test_bench_sphere_sampled_rows(torch_dev, nesa):
+    """201,720-unknown sphere, leaf 0.25, levels 2..5, d0 = 3: the benchmark
+    workload and launch configuration."""
+    torch = torch_dev
+    v, t = synth.icosphere(82, 4.0)
+    ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8)
+    tr = nesa.build_tree(v, t, 0.25)
+    op = nesa.op_create(tr, nesa.assemble_near(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8), nesa.C64)
+    x, src = _sparse_x(ref, 4, 60)
+    rows = _rows(ref, src, 40, 61)
+    xd = torch.from_numpy(x).to(torch.complex64).cuda()
+    yd = torch.empty_like(xd)
+    nesa.matvec(op, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy().astype(np.complex128)
+    _check(y[rows], ref.matvec_rows(x, rows), TOL_C64, "sphere N=%d" % ref.m.n)
+
+
+def test_aircraft_64_incidences_split_sampled_rows(torch_dev, nesa):
+    """Aircraft-like body (48,216 unknowns, levels 2..5), 64 right-hand sides in
+    one batched product with split-bf16x3 translations and transfers; three of
+    the right-hand sides are checked on sampled rows."""
+    torch = torch_dev
+    kw = dict(fuselage_radius=0.8, fuselage_length=6.0, span=2.5, chord_root=1.5, chord_tip=0.6,
+              thickness=0.3, wing_x=2.5, gap=0.1)
+    v, t = synth.aircraft_like(3, **kw)
+    ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8)
+    tr = nesa.build_tree(v, t, 0.25)
+    op = nesa.op_create(tr, nesa.assemble_near(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8),
+                        nesa.C64_SPLIT, max_nrhs=64)
+    X = synth.complex_normal((64, ref.m.n), 62)
+    checks = {}
+    for r in (0, 31, 63):
+        X[r], src = _sparse_x(ref, 3, 63 + r)
+        checks[r] = _rows(ref, src, 16, 64 + r)
+    Xd = torch.from_numpy(X).to(torch.complex64).cuda()
+    Yd = torch.empty_like(Xd)
+    nesa.matvec(op, Xd, Yd, 64)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().astype(np.complex128)
+    for r, rows in checks.items():
+        _check(Y[r][rows], ref.matvec_rows(X[r], rows), 1e-4, "aircraft N=%d split rhs %d" % (ref.m.n, r))
+
+
+def test_uneven_body_batch_8_incidences(torch_dev, nesa):
+    """The first 16 bodies of the seeded uneven family (spheroids, boxes,
+    cylinders) as one forest, 8 right-hand sides; the three smallest bodies are
+    checked in full against their oracle with the batch's shared leaf radius."""
+    torch = torch_dev
+    bodies = synth.body_family(16, seed=4)
+    sizes = [len(t) * 3 // 2 for _, t, _ in bodies]
+    re = max(onesa.leaf_radius(v, t, 0.25) for v, t, _ in bodies)
+    fr = nesa.build_forest([(v, t) for v, t, _ in bodies], 0.25)
+    op = nesa.op_create(fr, nesa.assemble_near(fr), nesa.assemble_translations(fr, d0=3, tau=1e-8),
+                        nesa.C64, max_nrhs=8)
+    ptr = fr.bodies()
+    X = synth.complex_normal((8, ptr[-1]), 70)
+    Xd = torch.from_numpy(X).to(torch.complex64).cuda()
+    Yd = torch.empty_like(Xd)
+    nesa.matvec(op, Xd, Yd, 8)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().astype(np.complex128)
+    for i in np.argsort(sizes)[:3]:
+        v, t, kind = bodies[i]
+        ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8, re_leaf=re)
+        for r in (0, 7):
+            yr = ref.matvec(X[r][ptr[i]:ptr[i + 1]])
+            _check(Y[r][ptr[i]:ptr[i + 1]], yr, TOL_C64, "batch body %d (%s, N=%d) rhs %d" % (i, kind, ref.m.n, r))
