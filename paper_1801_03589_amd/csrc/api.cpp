@@ -189,10 +189,11 @@ static void attach_split(nesa_op* op, nesa::GemmPlan& p, const std::vector<cd>& 
 }
 
 // Grouped pair lists of a GEMM plan (items in their given order inside a group);
-// the tiles for a number of right-hand sides are made by ensure_tiles.
+// the tiles for a number of right-hand sides are made by build_tiles.
 static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, int M, int K, int Mr, int nrt,
                                 int accumulate, const std::vector<int32_t>& group, int ngroups,
-                                const std::vector<int32_t>& src, const std::vector<int32_t>& dst) {
+                                const std::vector<int32_t>& src, const std::vector<int32_t>& dst,
+                                const std::vector<int8_t>& region) {
   nesa::GemmPlan p;
   p.A = A;
   p.a_stride = a_stride;
@@ -210,50 +211,60 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
   // neighbouring source vectors)
   for (auto& v : by) std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) { return src[x] < src[y]; });
   std::vector<int32_t> ps, pd, gs(1, 0);
+  std::vector<int8_t> pr;
   p.group_count.resize(ngroups);
   for (int u = 0; u < ngroups; ++u) {
     for (int32_t i : by[u]) {
       ps.push_back(src[i]);
       pd.push_back(dst[i]);
+      pr.push_back(region[i]);
     }
     p.group_count[u] = (int32_t)by[u].size();
     gs.push_back((int32_t)ps.size());
   }
   p.h_src = ps;
   p.h_dst = pd;
+  p.h_region = pr;
   p.by_nrhs.resize(op->max_nrhs + 1);
   return p;
 }
 
 // Tiles of up to 64 (pair, channel) columns of one group for nrhs right-hand
 // sides, with the source / destination offset of every column precomputed.
-static void ensure_tiles(nesa_op* op, nesa::GemmPlan& p, int nrhs) {
-  nesa::TileList& tl = p.by_nrhs[nrhs];
-  if (tl.tile_group) return;
+static nesa::TileList build_tiles(nesa_op* op, const nesa::GemmPlan& p, int nrhs, int regions) {
+  nesa::TileList tl;
   const int NC = 4 * nrhs;
   std::vector<int32_t> tg, tn;
   std::vector<int64_t> cs, cdst;
-  int64_t pstart = 0;
-  for (int u = 0; u < p.ngroups; ++u) {
-    const int64_t ncols = (int64_t)p.group_count[u] * NC;
-    for (int64_t c0 = 0; c0 < ncols; c0 += 64) {
-      const int64_t nc = std::min<int64_t>(64, ncols - c0);
-      tg.push_back(u);
-      tn.push_back((int32_t)nc);
-      for (int j = 0; j < 64; ++j) {
-        const int64_t gc = c0 + std::min<int64_t>(j, nc - 1);
-        const int64_t pi = pstart + gc / NC, c = gc % NC;
-        cs.push_back(((int64_t)p.h_src[pi] * NC + c) * p.K);
-        cdst.push_back(((int64_t)p.h_dst[pi] * NC + c) * p.M);
+  std::vector<int32_t> items;
+  for (int reg = 0; reg < regions; ++reg) {
+    int64_t pstart = 0;
+    for (int u = 0; u < p.ngroups; ++u) {
+      items.clear();
+      for (int64_t i = pstart; i < pstart + p.group_count[u]; ++i)
+        if (regions == 1 || p.h_region[i] == reg) items.push_back((int32_t)i);
+      pstart += p.group_count[u];
+      const int64_t ncols = (int64_t)items.size() * NC;
+      for (int64_t c0 = 0; c0 < ncols; c0 += 64) {
+        const int64_t nc = std::min<int64_t>(64, ncols - c0);
+        tg.push_back(u);
+        tn.push_back((int32_t)nc);
+        for (int j = 0; j < 64; ++j) {
+          const int64_t gc = c0 + std::min<int64_t>(j, nc - 1);
+          const int64_t pi = items[gc / NC], c = gc % NC;
+          cs.push_back(((int64_t)p.h_src[pi] * NC + c) * p.K);
+          cdst.push_back(((int64_t)p.h_dst[pi] * NC + c) * p.M);
+        }
       }
     }
-    pstart += p.group_count[u];
   }
+  tl.regions = regions;
   tl.ntiles = (int64_t)tg.size();
   tl.tile_group = upload(op, tg);
   tl.tile_ncols = upload(op, tn);
   tl.col_src = upload(op, cs);
   tl.col_dst = upload(op, cdst);
+  return tl;
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -271,13 +282,25 @@ struct TuneKey {
     return std::tie(kind, split, M, K, nrhs, ntiles) < std::tie(o.kind, o.split, o.M, o.K, o.nrhs, o.ntiles);
   }
 };
+struct TuneChoice {
+  int nrt, tpw, kt, regions;
+};
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune;
+static std::map<TuneKey, TuneChoice> g_tune;
 static bool g_tune_loaded = false;
 
-static bool autotune_enabled() {
+// NESA_AUTOTUNE: unset or "1" = all candidates, "0" = default blocking,
+// "chunked" / "resident" / "direct" = only that kernel family (the last two
+// where K <= 84, else chunked)
+static int autotune_mode() {
   const char* e = std::getenv("NESA_AUTOTUNE");
-  return !(e && std::string(e) == "0");
+  if (!e) return 1;
+  const std::string v(e);
+  if (v == "0") return 0;
+  if (v == "chunked") return 2;
+  if (v == "resident") return 3;
+  if (v == "direct") return 4;
+  return 1;
 }
 
 static void tune_load_locked() {
@@ -289,58 +312,119 @@ static void tune_load_locked() {
   if (!fp) return;
   TuneKey k;
   long long nt;
-  int nrt;
-  while (std::fscanf(fp, "%d %d %d %d %d %lld %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &nrt) == 7) {
+  TuneChoice c;
+  while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &c.nrt,
+                     &c.tpw, &c.kt, &c.regions) == 10) {
     k.ntiles = nt;
-    if (nrt >= 1 && nrt <= 8) g_tune[k] = nrt;
+    if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8))
+      g_tune[k] = c;
   }
   std::fclose(fp);
 }
 
-static void tune_store_locked(const TuneKey& k, int nrt) {
-  g_tune[k] = nrt;
+static void tune_store_locked(const TuneKey& k, const TuneChoice& c) {
+  g_tune[k] = c;
   const char* f = std::getenv("NESA_TUNE_FILE");
   if (!f) return;
   FILE* fp = std::fopen(f, "a");
   if (!fp) return;
-  std::fprintf(fp, "%d %d %d %d %d %lld %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles, nrt);
+  std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles, c.nrt,
+               c.tpw, c.kt, c.regions);
   std::fclose(fp);
 }
 
-static void set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, int nrt) {
-  tl.nrt = nrt;
-  tl.rblocks = ((p.M + 15) / 16 + nrt - 1) / nrt;
+// a choice is valid when its row blocks stay inside the allocated rows of A and
+// (resident kernel) K fits its LDS capacity
+// (tpw > 0: resident kernel; tpw = -13 / -21: direct kernel with that many k steps)
+static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice& c) {
+  const int blocks = ((p.M + 15) / 16 + c.nrt - 1) / c.nrt;
+  if (c.nrt < 1 || c.nrt > 8 || blocks * c.nrt * 16 > p.Mr) return false;
+  if (c.tpw > 0 && (p.A_split || (c.kt != 52 && c.kt != 84) || p.K > c.kt)) return false;
+  if (c.tpw < 0 && (p.A_split || (c.tpw != -13 && c.tpw != -21) || p.K > -4 * c.tpw ||
+                    (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
+    return false;
+  tl.nrt = c.nrt;
+  tl.rblocks = blocks;
+  tl.tpw = c.tpw;
+  tl.kt = c.tpw > 0 ? c.kt : 0;
+  return true;
 }
 
-static void tune_plan(nesa::GemmPlan& p, int nrhs, const void* src, void* dst, bool translation, hipStream_t st) {
-  nesa::TileList& tl = p.by_nrhs[nrhs];
-  if (tl.nrt > 0 || tl.ntiles == 0) return;
-  if (!autotune_enabled()) {
-    set_blocking(p, tl, p.nrt);
+// tile lists of both orderings are built on demand and kept per plan
+static nesa::TileList& tiles_for(nesa_op* op, nesa::GemmPlan& p, int nrhs, int regions,
+                                 std::vector<nesa::TileList>& made) {
+  for (auto& t : made)
+    if (t.regions == regions) return t;
+  made.push_back(build_tiles(op, p, nrhs, regions));
+  return made.back();
+}
+
+static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src, void* dst, bool translation,
+                      hipStream_t st) {
+  nesa::TileList& out = p.by_nrhs[nrhs];
+  if (out.tile_group) return;
+  std::vector<nesa::TileList> made;
+  made.reserve(2);
+  const int mode = autotune_mode();
+  const TuneChoice dflt{p.nrt, 0, 0, 1};
+  if (mode == 0) {
+    out = tiles_for(op, p, nrhs, 1, made);
+    set_blocking(p, out, dflt);
     return;
   }
-  const TuneKey key{translation ? 1 : (p.accumulate ? 3 : 2), p.A_split ? 1 : 0, p.M, p.K, nrhs, tl.ntiles};
+  const int64_t base_tiles = tiles_for(op, p, nrhs, 1, made).ntiles;
+  if (base_tiles == 0) {
+    out = made[0];
+    return;
+  }
+  const bool res_ok = !p.A_split && p.K <= 84;
+  // region ordering only pays when a group has many pairs per region
+  const bool reg_ok = p.ngroups > 0 && (int64_t)p.h_src.size() / p.ngroups >= 64;
+  const TuneKey key{(translation ? 1 : (p.accumulate ? 3 : 2)) + 10 * mode, p.A_split ? 1 : 0, p.M, p.K, nrhs,
+                    base_tiles};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load_locked();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
-      set_blocking(p, tl, it->second);
-      return;
+    if (it != g_tune.end() && (it->second.regions == 1 || reg_ok)) {
+      nesa::TileList tl = tiles_for(op, p, nrhs, it->second.regions, made);
+      if (set_blocking(p, tl, it->second)) {
+        out = tl;
+        return;
+      }
     }
   }
+  // candidates: chunked kernel with 1..8 row tiles (one per distinct row-block
+  // count), resident kernel with 1..8 row tiles and 4 or 16 tiles per
+  // workgroup; tiles in plain group order, and by region of the owner box
+  std::vector<TuneChoice> cand;
   const int tiles = (p.M + 15) / 16;
+  // the fewest row tiles per workgroup for every distinct number of row blocks
+  std::vector<int> nrts;
+  for (int blocks = 1; blocks <= tiles; ++blocks) {
+    const int nrt = (tiles + blocks - 1) / blocks;
+    if (nrt <= 8 && (nrts.empty() || nrts.back() != nrt)) nrts.push_back(nrt);
+  }
+  for (int regions : {1, 8}) {
+    if (regions == 8 && !reg_ok) continue;
+    for (int nrt : nrts) {
+      if ((mode != 3 && mode != 4) || !res_ok) cand.push_back({nrt, 0, 0, regions});
+      if (res_ok && (mode == 1 || mode == 3))
+        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions});
+    }
+    if (res_ok && (mode == 1 || mode == 4))
+      for (int nrt : {1, 2, 4})
+        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions});
+  }
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "hipEventCreate");
   hip_check(hipEventCreate(&e1), "hipEventCreate");
-  int best = p.nrt;
+  TuneChoice best = dflt;
   float best_ms = 1e30f;
-  int last_blocks = -1;
-  for (int nrt = 8; nrt >= 1; --nrt) {
-    const int blocks = (tiles + nrt - 1) / nrt;
-    if (blocks * nrt * 16 > p.Mr || blocks == last_blocks) continue;
-    last_blocks = blocks;
-    set_blocking(p, tl, nrt);
+  for (const TuneChoice& c : cand) {
+    nesa::TileList tl = tiles_for(op, p, nrhs, c.regions, made);
+    if (!set_blocking(p, tl, c)) continue;
+    p.by_nrhs[nrhs] = tl;
     nesa::launch_plan(p, nrhs, src, dst, st, translation);     // warm-up
     hip_check(hipEventRecord(e0, st), "hipEventRecord");
     for (int r = 0; r < 3; ++r) nesa::launch_plan(p, nrhs, src, dst, st, translation);
@@ -348,14 +432,23 @@ static void tune_plan(nesa::GemmPlan& p, int nrhs, const void* src, void* dst, b
     hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
     float ms = 0;
     hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (const char* lf = std::getenv("NESA_TUNE_LOG")) {     // candidate timings, for inspection
+      if (FILE* fp = std::fopen(lf, "a")) {
+        std::fprintf(fp, "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d : %.4f ms\n",
+                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, ms / 3);
+        std::fclose(fp);
+      }
+    }
     if (ms < best_ms) {
       best_ms = ms;
-      best = nrt;
+      best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  nesa::TileList tl = tiles_for(op, p, nrhs, best.regions, made);
   set_blocking(p, tl, best);
+  out = tl;
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_store_locked(key, best);
 }
@@ -369,15 +462,12 @@ static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs, hipStream
   for (size_t i = 0; i < d.lev.size(); ++i) {
     auto& dl = d.lev[i];
     if (dl.npairs > 0) {
-      ensure_tiles(op, dl.trans, nrhs);
-      tune_plan(dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
+      tune_plan(op, dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
     }
     if (i > 0) {
       auto& pl = d.lev[i - 1];
-      ensure_tiles(op, dl.up, nrhs);
-      tune_plan(dl.up, nrhs, s + dl.s_off * nrhs, dl.child_out, false, st);
-      ensure_tiles(op, dl.down, nrhs);
-      tune_plan(dl.down, nrhs, o + pl.s_off * nrhs, o + dl.s_off * nrhs, false, st);
+      tune_plan(op, dl.up, nrhs, s + dl.s_off * nrhs, dl.child_out, false, st);
+      tune_plan(op, dl.down, nrhs, o + pl.s_off * nrhs, o + dl.s_off * nrhs, false, st);
     }
   }
 }
@@ -449,7 +539,10 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       int nrt = 1, Qdef = 0;
       nesa::row_blocking(fl.Q, nrt, Qdef);
       const int Qr = nesa::row_alloc(fl.Q);
-      dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst);
+      std::vector<int8_t> reg(dl.npairs);
+      for (int64_t a = 0; a < lv.nbox; ++a)
+        for (int64_t k = lv.il_ptr[a]; k < lv.il_ptr[a + 1]; ++k) reg[k] = (int8_t)(a * 8 / lv.nbox);
+      dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst, reg);
       if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.trans, Dc, nused);
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * op->max_nrhs * fl.Q * 2 * sizeof(T));
     }
@@ -486,16 +579,20 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
             }
         // boxes with a parent (in a forest the top box of a body has none)
         std::vector<int32_t> grp, idx, par;
+        std::vector<int8_t> reg;
         for (int64_t b = 0; b < lv.nbox; ++b) {
           if (lv.parent[b] < 0) continue;
           grp.push_back(lv.octant[b]);
           idx.push_back((int32_t)b);
           par.push_back((int32_t)lv.parent[b]);
+          reg.push_back((int8_t)(b * 8 / lv.nbox));
         }
-        dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx);
+        dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx,
+                           reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
         dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * op->max_nrhs * Qp * 2 * sizeof(T));
-        dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx);
+        dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx,
+                             reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.down, ad, 8);
       }
     }
@@ -527,6 +624,15 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   });
   d.Minv = upload_complex<T>(op, minv);
   d.moff = upload(op, moff);
+  {
+    // launch order of the near-field workgroups: largest blocks first
+    std::vector<int32_t> ord(d.nleaf);
+    for (int64_t a = 0; a < d.nleaf; ++a) ord[a] = (int32_t)a;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+      return nr.off[x + 1] - nr.off[x] > nr.off[y + 1] - nr.off[y];
+    });
+    d.near_order = upload(op, ord);
+  }
   op->xl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
   op->yl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
   ensure_all_tiles<T>(op, d, 1);

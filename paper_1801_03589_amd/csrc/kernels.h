@@ -15,6 +15,8 @@ namespace nesa {
 // right-hand sides (channels = 4 x nrhs) and is built per nrhs on first use.
 struct TileList {
   int nrt = 0, rblocks = 0;       // row tiles per workgroup and row blocks chosen by the autotuner (0: plan default)
+  int tpw = 0, kt = 0;            // resident-A kernel: tiles per workgroup and its K capacity (0: chunked kernel)
+  int regions = 1;                // tiles ordered by (region, group) when 8: each XCD takes one region
   int64_t ntiles = 0;
   int32_t* tile_group = nullptr;
   int32_t* tile_ncols = nullptr;
@@ -32,7 +34,8 @@ struct GemmPlan {
   int accumulate = 0;
   int ngroups = 0;
   std::vector<int32_t> group_count;   // host: pairs per group
-  std::vector<int32_t> h_src, h_dst;  // host: pairs, group by group
+  std::vector<int32_t> h_src, h_dst;  // host: pairs, group by group (by source inside a group)
+  std::vector<int8_t> h_region;       // host: region (1/8 of the Morton order of the owner box) of every pair
   std::vector<TileList> by_nrhs;  // index nrhs
 };
 
@@ -74,6 +77,7 @@ struct DevOp {
   void* o = nullptr;             // equivalent potentials, all levels
   void* Minv = nullptr;          // block-diagonal preconditioner (inverse self blocks)
   int64_t* moff = nullptr;
+  int32_t* near_order = nullptr; // leaves by decreasing near-field work (launch order)
   int max_nrhs = 1;              // right-hand sides the work buffers hold
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;

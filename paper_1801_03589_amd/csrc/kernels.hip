@@ -509,6 +509,207 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm_bf16x3(GemmTiles g, const 
   cgemm_tiles_bf16x3_body<NRT>(g, As, Kp);
 }
 
+// Resident-A variant for small K (K <= KT): a workgroup takes a run of `tpw`
+// consecutive tiles, keeps the group matrix rows r0 .. r0 + 16 NRT for all K in
+// LDS (restaged only when the run crosses into another group), stages each
+// tile's 64 source columns for the whole K at once and loads the next tile's
+// columns into registers while the MFMAs of the current one run.  Suits the
+// fine levels, where a tile is only a few K steps and the chunked kernel's
+// per-workgroup latency dominates.
+template <int NRT, int KT>
+__device__ __forceinline__ void cgemm_resident_body(const GemmTiles& g, int tpw) {
+  constexpr int NBM = TR_COLS * KT / NT;          // max float2 of B per thread per tile
+  static_assert(TR_COLS * KT % NT == 0, "B tile must split evenly");
+  __shared__ float2 As[KT][NRT * 16];
+  __shared__ float2 Bs[TR_COLS][KT + 1];
+  __shared__ int64_t cdst[TR_COLS];
+  const int64_t nruns = (g.ntiles + tpw - 1) / tpw;
+  const int64_t run = xcd_tile(blockIdx.x, nruns);
+  if (run >= nruns) return;
+  const int64_t t_begin = run * tpw;
+  const int64_t t_end = min(g.ntiles, t_begin + tpw);
+  const int r0 = blockIdx.y * NRT * 16;
+  const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  const int K = g.K, M = g.M;
+  const int KP = (K + 3) / 4 * 4;
+  const int nb = TR_COLS * KP;                    // B elements of a tile
+  float2 rb[NBM];
+  auto load_b = [&](int64_t tile) {
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) {
+      const int e = t + i * NT;
+      const int col = min(e / KP, TR_COLS - 1), k = e % KP;
+      const int64_t off = g.col_src[tile * TR_COLS + col];
+      const float2 v = g.src[off + min(k, K - 1)];
+      const float f = (e < nb && k < K) ? 1.f : 0.f;
+      rb[i] = make_float2(v.x * f, v.y * f);
+    }
+  };
+  load_b(t_begin);
+  int group = -1;
+  for (int64_t tile = t_begin; tile < t_end; ++tile) {
+    const int grp = g.tile_group[tile];
+    const int cnt = g.tile_ncols[tile];
+    __syncthreads();                              // previous tile done with Bs (and As)
+    if (grp != group) {
+      const float2* A = g.A + (size_t)grp * g.a_stride + r0;
+      for (int e = t; e < KT * NRT * 16; e += NT) {
+        const int k = e / (NRT * 16), r = e % (NRT * 16);
+        const float2 v = A[(size_t)min(k, K - 1) * g.Mr + r];
+        const float f = k < K ? 1.f : 0.f;
+        As[k][r] = make_float2(v.x * f, v.y * f);
+      }
+      group = grp;
+    }
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) {
+      const int e = t + i * NT;
+      if (e < nb) Bs[e / KP][e % KP] = rb[i];
+    }
+    if (t < TR_COLS) cdst[t] = g.col_dst[tile * TR_COLS + t];
+    __syncthreads();
+    if (tile + 1 < t_end) load_b(tile + 1);       // next tile in flight during the MFMAs
+    if (16 * w < cnt) {
+      f32x4 cre[NRT], cim[NRT];
+#pragma unroll
+      for (int r = 0; r < NRT; ++r) {
+        cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+        cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      for (int ks = 0; ks < KP / 4; ++ks) {
+        const int kk = ks * 4 + lane / 16;
+        const float2 b = Bs[w * 16 + lane % 16][kk];
+        float2 a[NRT];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) a[r] = As[kk][r * 16 + lane % 16];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
+          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
+        }
+      }
+      const int col = w * 16 + lane % 16;
+      if (col < cnt) {
+        float2* out = g.dst + cdst[col];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+            if (row < M) {
+              float2 v = make_float2(cre[r][i], cim[r][i]);
+              if (g.accumulate) {
+                const float2 o = out[row];
+                v.x += o.x;
+                v.y += o.y;
+              }
+              out[row] = v;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Direct variant for small K (K <= 4 KS): no LDS and no barrier.  Wave w of a
+// workgroup owns column tile w of the tile; it loads its 16 source columns for
+// all K into registers at once (one memory latency per tile), reads the group
+// matrix rows from L1/L2 per k step, and runs its MFMA chain.  Occupancy is
+// bounded by registers only.
+template <int NRT, int KS>
+__device__ __forceinline__ void cgemm_direct_body(const GemmTiles& g) {
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
+  if (tile >= g.ntiles) return;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int cnt = g.tile_ncols[tile];
+  if (16 * w >= cnt) return;                      // whole wave idle (no barrier in this kernel)
+  const int K = g.K, M = g.M;
+  const int r0 = blockIdx.y * NRT * 16;
+  const int col = w * 16 + lane % 16;
+  const int kq = lane / 16;
+  const float2* bsrc = g.src + g.col_src[tile * TR_COLS + col];
+  float2 b[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 4 + kq;
+    const float2 v = bsrc[min(k, K - 1)];
+    const float f = k < K ? 1.f : 0.f;
+    b[ks] = make_float2(v.x * f, v.y * f);
+  }
+  const float2* A = g.A + (size_t)g.tile_group[tile] * g.a_stride + r0 + lane % 16;
+  f32x4 cre[NRT], cim[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) {
+    cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 4 + kq;
+    const float f = k < K ? 1.f : 0.f;
+    const float2* Ak = A + (size_t)min(k, K - 1) * g.Mr;
+    float2 a[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      const float2 v = Ak[r * 16];
+      a[r] = make_float2(v.x * f, v.y * f);
+    }
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b[ks].x, cre[r], 0, 0, 0);
+      cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b[ks].y, cim[r], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b[ks].y, cre[r], 0, 0, 0);
+      cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b[ks].x, cim[r], 0, 0, 0);
+    }
+  }
+  if (col < cnt) {
+    float2* out = g.dst + g.col_dst[tile * TR_COLS + col];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+        if (row < M) {
+          float2 v = make_float2(cre[r][i], cim[r][i]);
+          if (g.accumulate) {
+            const float2 o = out[row];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          out[row] = v;
+        }
+      }
+    }
+  }
+}
+
+template <int NRT, int KS>
+__global__ __launch_bounds__(NT) void k_translate_gemm_dir(GemmTiles g) {
+  cgemm_direct_body<NRT, KS>(g);
+}
+template <int NRT, int KS>
+__global__ __launch_bounds__(NT) void k_transfer_gemm_dir(GemmTiles g) {
+  cgemm_direct_body<NRT, KS>(g);
+}
+
+template <int NRT, int KT>
+__global__ __launch_bounds__(NT) void k_translate_gemm_res(GemmTiles g, int tpw) {
+  cgemm_resident_body<NRT, KT>(g, tpw);
+}
+template <int NRT, int KT>
+__global__ __launch_bounds__(NT) void k_transfer_gemm_res(GemmTiles g, int tpw) {
+  cgemm_resident_body<NRT, KT>(g, tpw);
+}
+
 // translations (groups = offset slots) and transfers (groups = octants) get
 // their own kernel names so that profiles separate them
 template <int NRT>
@@ -601,14 +802,15 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
                                                   const typename C2<T>::type* __restrict__ V,
                                                   const typename C2<T>::type* __restrict__ o,
                                                   typename C2<T>::type* __restrict__ y, int Q,
-                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d) {
+                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d,
+                                                  const int32_t* __restrict__ order) {
   using V2 = typename C2<T>::type;
   __shared__ V2 xs[NEAR_CW];
   __shared__ V2 red[NT];
   __shared__ int seg_col[MAX_NEAR + 1];
   __shared__ int seg_x[MAX_NEAR];
   __shared__ V2 ow[4 * MAX_QL];            // weighted o_a
-  const int a = blockIdx.x;
+  const int a = order[blockIdx.x];         // largest leaves first (shorter tail)
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
   if (threadIdx.x == 0) {
@@ -1021,6 +1223,52 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
   if (tl.ntiles == 0) return;
   const int nrt = tl.nrt > 0 ? tl.nrt : p.nrt;
   const int rblocks = tl.nrt > 0 ? tl.rblocks : p.rblocks;
+  if (tl.tpw < 0 && !p.A_split) {
+    // direct kernel: K <= 4 ks (ks = -tpw is 13 or 21), 1, 2 or 4 row tiles
+    dim3 gr((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
+#define NESA_DIR(N, KSV)                                                      \
+  if (translation)                                                            \
+    k_translate_gemm_dir<N, KSV><<<gr, NT, 0, st>>>(g);                       \
+  else                                                                        \
+    k_transfer_gemm_dir<N, KSV><<<gr, NT, 0, st>>>(g);                        \
+  return;
+#define NESA_DIR_K(N)                    \
+  if (-tl.tpw == 13) { NESA_DIR(N, 13) }  \
+  else { NESA_DIR(N, 21) }
+    switch (nrt) {
+      case 1: NESA_DIR_K(1)
+      case 2: NESA_DIR_K(2)
+      default: NESA_DIR_K(4)
+    }
+#undef NESA_DIR_K
+#undef NESA_DIR
+  }
+  if (tl.tpw > 0 && !p.A_split) {
+    // resident-A kernel: runs of tpw tiles, K <= kt
+    const int64_t nruns = (tl.ntiles + tl.tpw - 1) / tl.tpw;
+    dim3 gr((unsigned)((nruns + 7) / 8 * 8), (unsigned)rblocks);
+#define NESA_RES(N, KTV)                                                          \
+  if (translation)                                                                \
+    k_translate_gemm_res<N, KTV><<<gr, NT, 0, st>>>(g, tl.tpw);                   \
+  else                                                                            \
+    k_transfer_gemm_res<N, KTV><<<gr, NT, 0, st>>>(g, tl.tpw);                    \
+  return;
+#define NESA_RES_K(N)                    \
+  if (tl.kt == 52) { NESA_RES(N, 52) }    \
+  else { NESA_RES(N, 84) }
+    switch (nrt) {
+      case 1: NESA_RES_K(1)
+      case 2: NESA_RES_K(2)
+      case 3: NESA_RES_K(3)
+      case 4: NESA_RES_K(4)
+      case 5: NESA_RES_K(5)
+      case 6: NESA_RES_K(6)
+      case 7: NESA_RES_K(7)
+      default: NESA_RES_K(8)
+    }
+#undef NESA_RES_K
+#undef NESA_RES
+  }
   dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
 #define NESA_TILES(N)                                                                        \
   if (p.A_split) {                                                                           \
@@ -1127,7 +1375,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   if (R == 1) {
     k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
                                                      d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
-                                                     LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+                                                     LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3],
+                                                     d.near_order);
   } else {
     if constexpr (sizeof(T) == 4) {
       k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,

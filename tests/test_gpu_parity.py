@@ -281,3 +281,23 @@ def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
             print("%s body %d (N=%d, levels %d..%d) rhs %d: rel err %.2e"
                   % (prec, i, ref.m.n, ref.t.l0, ref.t.L, r, err))
             assert err <= tol, (i, r, err)
+
+
+@pytest.mark.parametrize("family", ["chunked", "resident", "direct"])
+@pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
+def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, name, family):
+    """The autotuner restricted to one kernel family (chunked-K tiles, resident
+    group matrices, or register-direct tiles; the last two for K <= 84) still
+    matches the oracle, for one and for five right-hand sides."""
+    monkeypatch.setenv("NESA_AUTOTUNE", family)
+    ref, tr, near, far = _case(nesa, name)
+    op = nesa.op_create(tr, near, far, nesa.C64, max_nrhs=5)
+    X = synth.complex_normal((5, ref.m.n), 80)
+    Y = _run(torch_dev, nesa, op, X, nrhs=5)
+    Y1 = _run(torch_dev, nesa, op, X[2])
+    for r in (0, 2, 4):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("%s %s rhs %d: rel err %.2e" % (name, family, r, err))
+        assert err <= TOL["c64"]
+    assert np.linalg.norm(Y1 - ref.matvec(X[2])) <= TOL["c64"] * np.linalg.norm(Y1)
