@@ -231,7 +231,7 @@ static nesa::GemmPlan make_plan(nesa_op* op, const void* A, int64_t a_stride, in
 
 // Tiles of up to 64 (pair, channel) columns of one group for nrhs right-hand
 // sides, with the source / destination offset of every column precomputed.
-static nesa::TileList build_tiles(nesa_op* op, const nesa::GemmPlan& p, int nrhs, int regions) {
+static nesa::TileList build_tiles(nesa_op* op, const nesa::GemmPlan& p, int nrhs, int regions, int width) {
   nesa::TileList tl;
   const int NC = 4 * nrhs;
   std::vector<int32_t> tg, tn;
@@ -245,11 +245,11 @@ static nesa::TileList build_tiles(nesa_op* op, const nesa::GemmPlan& p, int nrhs
         if (regions == 1 || p.h_region[i] == reg) items.push_back((int32_t)i);
       pstart += p.group_count[u];
       const int64_t ncols = (int64_t)items.size() * NC;
-      for (int64_t c0 = 0; c0 < ncols; c0 += 64) {
-        const int64_t nc = std::min<int64_t>(64, ncols - c0);
+      for (int64_t c0 = 0; c0 < ncols; c0 += width) {
+        const int64_t nc = std::min<int64_t>(width, ncols - c0);
         tg.push_back(u);
         tn.push_back((int32_t)nc);
-        for (int j = 0; j < 64; ++j) {
+        for (int j = 0; j < width; ++j) {
           const int64_t gc = c0 + std::min<int64_t>(j, nc - 1);
           const int64_t pi = items[gc / NC], c = gc % NC;
           cs.push_back(((int64_t)p.h_src[pi] * NC + c) * p.K);
@@ -259,6 +259,7 @@ static nesa::TileList build_tiles(nesa_op* op, const nesa::GemmPlan& p, int nrhs
     }
   }
   tl.regions = regions;
+  tl.width = width;
   tl.ntiles = (int64_t)tg.size();
   tl.tile_group = upload(op, tg);
   tl.tile_ncols = upload(op, tn);
@@ -283,15 +284,16 @@ struct TuneKey {
   }
 };
 struct TuneChoice {
-  int nrt, tpw, kt, regions;
+  int nrt, tpw, kt, regions, width;
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune;
 static bool g_tune_loaded = false;
 
 // NESA_AUTOTUNE: unset or "1" = all candidates, "0" = default blocking,
-// "chunked" / "resident" / "direct" = only that kernel family (the last two
-// where K <= 84, else chunked)
+// "chunked" / "resident" / "direct" / "narrow" = only that kernel family
+// (resident and direct where K <= 84, narrow = chunked with 32-column tiles
+// where the row tiles split over the waves; else the plain chunked kernel)
 static int autotune_mode() {
   const char* e = std::getenv("NESA_AUTOTUNE");
   if (!e) return 1;
@@ -300,6 +302,7 @@ static int autotune_mode() {
   if (v == "chunked") return 2;
   if (v == "resident") return 3;
   if (v == "direct") return 4;
+  if (v == "narrow") return 5;
   return 1;
 }
 
@@ -313,10 +316,11 @@ static void tune_load_locked() {
   TuneKey k;
   long long nt;
   TuneChoice c;
-  while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &c.nrt,
-                     &c.tpw, &c.kt, &c.regions) == 10) {
+  while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &c.nrt,
+                     &c.tpw, &c.kt, &c.regions, &c.width) == 11) {
     k.ntiles = nt;
-    if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8))
+    if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8) &&
+        (c.width == 32 || c.width == 64))
       g_tune[k] = c;
   }
   std::fclose(fp);
@@ -328,8 +332,8 @@ static void tune_store_locked(const TuneKey& k, const TuneChoice& c) {
   if (!f) return;
   FILE* fp = std::fopen(f, "a");
   if (!fp) return;
-  std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles, c.nrt,
-               c.tpw, c.kt, c.regions);
+  std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles,
+               c.nrt, c.tpw, c.kt, c.regions, c.width);
   std::fclose(fp);
 }
 
@@ -343,6 +347,7 @@ static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice
   if (c.tpw < 0 && (p.A_split || (c.tpw != -13 && c.tpw != -21) || p.K > -4 * c.tpw ||
                     (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
     return false;
+  if (c.width != (tl.width) || (c.width == 32 && (c.tpw != 0 || p.A_split || c.nrt % 2))) return false;
   tl.nrt = c.nrt;
   tl.rblocks = blocks;
   tl.tpw = c.tpw;
@@ -351,11 +356,11 @@ static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice
 }
 
 // tile lists of both orderings are built on demand and kept per plan
-static nesa::TileList& tiles_for(nesa_op* op, nesa::GemmPlan& p, int nrhs, int regions,
+static nesa::TileList& tiles_for(nesa_op* op, nesa::GemmPlan& p, int nrhs, int regions, int width,
                                  std::vector<nesa::TileList>& made) {
   for (auto& t : made)
-    if (t.regions == regions) return t;
-  made.push_back(build_tiles(op, p, nrhs, regions));
+    if (t.regions == regions && t.width == width) return t;
+  made.push_back(build_tiles(op, p, nrhs, regions, width));
   return made.back();
 }
 
@@ -364,15 +369,15 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   nesa::TileList& out = p.by_nrhs[nrhs];
   if (out.tile_group) return;
   std::vector<nesa::TileList> made;
-  made.reserve(2);
+  made.reserve(4);
   const int mode = autotune_mode();
-  const TuneChoice dflt{p.nrt, 0, 0, 1};
+  const TuneChoice dflt{p.nrt, 0, 0, 1, 64};
   if (mode == 0) {
-    out = tiles_for(op, p, nrhs, 1, made);
+    out = tiles_for(op, p, nrhs, 1, 64, made);
     set_blocking(p, out, dflt);
     return;
   }
-  const int64_t base_tiles = tiles_for(op, p, nrhs, 1, made).ntiles;
+  const int64_t base_tiles = tiles_for(op, p, nrhs, 1, 64, made).ntiles;
   if (base_tiles == 0) {
     out = made[0];
     return;
@@ -387,7 +392,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
     tune_load_locked();
     auto it = g_tune.find(key);
     if (it != g_tune.end() && (it->second.regions == 1 || reg_ok)) {
-      nesa::TileList tl = tiles_for(op, p, nrhs, it->second.regions, made);
+      nesa::TileList tl = tiles_for(op, p, nrhs, it->second.regions, it->second.width, made);
       if (set_blocking(p, tl, it->second)) {
         out = tl;
         return;
@@ -408,21 +413,25 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   for (int regions : {1, 8}) {
     if (regions == 8 && !reg_ok) continue;
     for (int nrt : nrts) {
-      if ((mode != 3 && mode != 4) || !res_ok) cand.push_back({nrt, 0, 0, regions});
+      if ((mode != 3 && mode != 4) || !res_ok) {
+        if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64});
+        if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32});
+      }
       if (res_ok && (mode == 1 || mode == 3))
-        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions});
+        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64});
     }
     if (res_ok && (mode == 1 || mode == 4))
       for (int nrt : {1, 2, 4})
-        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions});
+        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64});
   }
+  if (cand.empty()) cand.push_back(dflt);
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "hipEventCreate");
   hip_check(hipEventCreate(&e1), "hipEventCreate");
   TuneChoice best = dflt;
   float best_ms = 1e30f;
   for (const TuneChoice& c : cand) {
-    nesa::TileList tl = tiles_for(op, p, nrhs, c.regions, made);
+    nesa::TileList tl = tiles_for(op, p, nrhs, c.regions, c.width, made);
     if (!set_blocking(p, tl, c)) continue;
     p.by_nrhs[nrhs] = tl;
     nesa::launch_plan(p, nrhs, src, dst, st, translation);     // warm-up
@@ -434,8 +443,8 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
     hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
     if (const char* lf = std::getenv("NESA_TUNE_LOG")) {     // candidate timings, for inspection
       if (FILE* fp = std::fopen(lf, "a")) {
-        std::fprintf(fp, "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d : %.4f ms\n",
-                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, ms / 3);
+        std::fprintf(fp, "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d width %d : %.4f ms\n",
+                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, c.width, ms / 3);
         std::fclose(fp);
       }
     }
@@ -446,7 +455,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  nesa::TileList tl = tiles_for(op, p, nrhs, best.regions, made);
+  nesa::TileList tl = tiles_for(op, p, nrhs, best.regions, best.width, made);
   set_blocking(p, tl, best);
   out = tl;
   std::lock_guard<std::mutex> g(g_tune_mu);

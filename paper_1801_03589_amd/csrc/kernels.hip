@@ -217,36 +217,44 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
   return t;
 }
 
-template <int NRT>
+// CT = column tiles of 16 per workgroup (4: 64-column tiles, wave w owns
+// column tile w and all NRT row tiles; 2: 32-column tiles for groups with few
+// pairs, wave w owns column tile w % 2 and half of the row tiles).
+template <int NRT, int CT>
 __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   constexpr int NA = TR_KC * NRT * 8 / NT;        // float4 of A per thread per chunk (NRT*16 rows)
   constexpr int HALF = NRT * 8;                   // float4 per A column in a block
+  constexpr int COLS = 16 * CT;                   // columns of a tile
+  constexpr int NBT = TR_KC * COLS / NT;          // float2 of B per thread per chunk
+  constexpr int RPW = NRT * CT / 4;               // row tiles per wave
   static_assert(TR_KC * NRT * 8 % NT == 0, "A chunk must split evenly");
+  static_assert(NRT * CT % 4 == 0, "row tiles must split over the waves");
   __shared__ float4 As4[TR_KC][HALF];             // [k][row pair]
-  __shared__ float2 Bs[TR_COLS][TR_KC + 1];       // [column][k]
-  __shared__ int64_t col_src[TR_COLS];
-  __shared__ int64_t col_dst[TR_COLS];
+  __shared__ float2 Bs[COLS][TR_KC + 1];          // [column][k]
+  __shared__ int64_t col_src[COLS];
+  __shared__ int64_t col_dst[COLS];
   const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   if (tile >= g.ntiles) return;
   const int r0 = blockIdx.y * NRT * 16;
   const int cnt = g.tile_ncols[tile];              // valid columns
   const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  const int ct = w % CT, rt0 = (w / CT) * RPW;     // this wave's column tile and first row tile
   const int K = g.K, M = g.M;
-  if (t < TR_COLS) {
-    col_src[t] = g.col_src[tile * TR_COLS + t];
-    col_dst[t] = g.col_dst[tile * TR_COLS + t];
+  if (t < COLS) {
+    col_src[t] = g.col_src[tile * COLS + t];
+    col_dst[t] = g.col_dst[tile * COLS + t];
   }
   __syncthreads();
   const float4* A4 = reinterpret_cast<const float4*>(g.A + (size_t)g.tile_group[tile] * g.a_stride + r0);
-  const bool active = 16 * w < cnt;
-  f32x4 cre[NRT], cim[NRT];
+  const bool active = 16 * ct < cnt;
+  f32x4 cre[RPW], cim[RPW];
 #pragma unroll
-  for (int r = 0; r < NRT; ++r) {
+  for (int r = 0; r < RPW; ++r) {
     cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
     cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   float4 ra[NA];
-  float2 rb[TR_NB];
+  float2 rb[NBT];
   // per-thread staging addresses, fixed over the K loop; every load reads a
   // valid (clamped) address and invalid elements are zeroed by a 0/1 factor
   int a_k[NA], a_off[NA];
@@ -256,11 +264,11 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
     a_k[i] = e / HALF;
     a_off[i] = e % HALF;
   }
-  const float2* b_ptr[TR_NB];
-  int b_k[TR_NB];
-  float b_ok[TR_NB];
+  const float2* b_ptr[NBT];
+  int b_k[NBT];
+  float b_ok[NBT];
 #pragma unroll
-  for (int i = 0; i < TR_NB; ++i) {
+  for (int i = 0; i < NBT; ++i) {
     const int e = t + i * NT;
     const int col = e / TR_KC;
     b_k[i] = e % TR_KC;
@@ -277,7 +285,7 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       ra[i] = make_float4(v.x * f, v.y * f, v.z * f, v.w * f);
     }
 #pragma unroll
-    for (int i = 0; i < TR_NB; ++i) {
+    for (int i = 0; i < NBT; ++i) {
       const int k = k0 + b_k[i];
       const float2 v = b_ptr[i][min(k, K - 1)];
       const float f = k < K ? b_ok[i] : 0.f;
@@ -294,7 +302,7 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       As4[e / HALF][e % HALF] = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < TR_NB; ++i) {
+    for (int i = 0; i < NBT; ++i) {
       const int e = t + i * NT;
       Bs[e / TR_KC][e % TR_KC] = rb[i];
     }
@@ -305,17 +313,17 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       const int ksteps = (kc + 3) / 4;
       for (int ks = 0; ks < ksteps; ++ks) {
         const int kk = ks * 4 + lane / 16;
-        const float2 b = Bs[w * 16 + lane % 16][kk];
-        float2 a[NRT];
+        const float2 b = Bs[ct * 16 + lane % 16][kk];
+        float2 a[RPW];
 #pragma unroll
-        for (int r = 0; r < NRT; ++r) a[r] = As[kk * (NRT * 16) + r * 16 + lane % 16];
+        for (int r = 0; r < RPW; ++r) a[r] = As[kk * (NRT * 16) + (rt0 + r) * 16 + lane % 16];
 #pragma unroll
-        for (int r = 0; r < NRT; ++r) {
+        for (int r = 0; r < RPW; ++r) {
           cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
           cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < NRT; ++r) {
+        for (int r = 0; r < RPW; ++r) {
           cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
           cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
         }
@@ -323,14 +331,14 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
     }
   }
   // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
-  const int col = w * 16 + lane % 16;
+  const int col = ct * 16 + lane % 16;
   if (col < cnt) {
     float2* out = g.dst + col_dst[col];
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) {
+    for (int r = 0; r < RPW; ++r) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+        const int row = r0 + (rt0 + r) * 16 + 4 * (lane / 16) + i;
         if (row < M) {
           float2 v = make_float2(cre[r][i], cim[r][i]);
           if (g.accumulate) {
@@ -712,13 +720,13 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm_res(GemmTiles g, int tpw) 
 
 // translations (groups = offset slots) and transfers (groups = octants) get
 // their own kernel names so that profiles separate them
-template <int NRT>
+template <int NRT, int CT>
 __global__ __launch_bounds__(NT) void k_translate_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT>(g);
+  cgemm_tiles_body<NRT, CT>(g);
 }
-template <int NRT>
+template <int NRT, int CT>
 __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT>(g);
+  cgemm_tiles_body<NRT, CT>(g);
 }
 
 // dst_a = sum over [beg[a], end[a]) of the per-pair results, in order (deterministic)
@@ -1270,6 +1278,22 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
 #undef NESA_RES
   }
   dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
+  if (tl.width == 32 && !p.A_split) {
+    // 32-column tiles: waves split the rows (NRT even)
+#define NESA_TILES32(N)                                   \
+  if (translation)                                        \
+    k_translate_gemm<N, 2><<<grid, NT, 0, st>>>(g);       \
+  else                                                    \
+    k_transfer_gemm<N, 2><<<grid, NT, 0, st>>>(g);        \
+  return;
+    switch (nrt) {
+      case 2: NESA_TILES32(2)
+      case 4: NESA_TILES32(4)
+      case 6: NESA_TILES32(6)
+      default: NESA_TILES32(8)
+    }
+#undef NESA_TILES32
+  }
 #define NESA_TILES(N)                                                                        \
   if (p.A_split) {                                                                           \
     const unsigned short* As = static_cast<const unsigned short*>(p.A_split);                \
@@ -1278,9 +1302,9 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
     else                                                                                     \
       k_transfer_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                           \
   } else if (translation) {                                                                  \
-    k_translate_gemm<N><<<grid, NT, 0, st>>>(g);                                             \
+    k_translate_gemm<N, 4><<<grid, NT, 0, st>>>(g);                                          \
   } else {                                                                                   \
-    k_transfer_gemm<N><<<grid, NT, 0, st>>>(g);                                              \
+    k_transfer_gemm<N, 4><<<grid, NT, 0, st>>>(g);                                           \
   }                                                                                          \
   break;
   switch (nrt) {
