@@ -284,7 +284,7 @@ struct TuneKey {
   }
 };
 struct TuneChoice {
-  int nrt, tpw, kt, regions, width;
+  int nrt, tpw, kt, regions, width, kc;
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune;
@@ -316,11 +316,11 @@ static void tune_load_locked() {
   TuneKey k;
   long long nt;
   TuneChoice c;
-  while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt, &c.nrt,
-                     &c.tpw, &c.kt, &c.regions, &c.width) == 11) {
+  while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt,
+                     &c.nrt, &c.tpw, &c.kt, &c.regions, &c.width, &c.kc) == 12) {
     k.ntiles = nt;
     if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8) &&
-        (c.width == 32 || c.width == 64))
+        (c.width == 32 || c.width == 64) && (c.kc == 32 || c.kc == 64))
       g_tune[k] = c;
   }
   std::fclose(fp);
@@ -332,8 +332,8 @@ static void tune_store_locked(const TuneKey& k, const TuneChoice& c) {
   if (!f) return;
   FILE* fp = std::fopen(f, "a");
   if (!fp) return;
-  std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles,
-               c.nrt, c.tpw, c.kt, c.regions, c.width);
+  std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles,
+               c.nrt, c.tpw, c.kt, c.regions, c.width, c.kc);
   std::fclose(fp);
 }
 
@@ -348,7 +348,9 @@ static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice
                     (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
     return false;
   if (c.width != (tl.width) || (c.width == 32 && (c.tpw != 0 || p.A_split || c.nrt % 2))) return false;
+  if (c.kc != 32 && (c.kc != 64 || c.tpw != 0 || p.A_split)) return false;
   tl.nrt = c.nrt;
+  tl.kc = c.kc;
   tl.rblocks = blocks;
   tl.tpw = c.tpw;
   tl.kt = c.tpw > 0 ? c.kt : 0;
@@ -371,7 +373,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   std::vector<nesa::TileList> made;
   made.reserve(4);
   const int mode = autotune_mode();
-  const TuneChoice dflt{p.nrt, 0, 0, 1, 64};
+  const TuneChoice dflt{p.nrt, 0, 0, 1, 64, 32};
   if (mode == 0) {
     out = tiles_for(op, p, nrhs, 1, 64, made);
     set_blocking(p, out, dflt);
@@ -413,16 +415,19 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   for (int regions : {1, 8}) {
     if (regions == 8 && !reg_ok) continue;
     for (int nrt : nrts) {
-      if ((mode != 3 && mode != 4) || !res_ok) {
-        if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64});
-        if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32});
+      for (int kc : {32, 64}) {
+        if (kc == 64 && (p.A_split || p.K < 64)) continue;
+        if ((mode != 3 && mode != 4) || !res_ok) {
+          if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64, kc});
+          if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, kc});
+        }
       }
       if (res_ok && (mode == 1 || mode == 3))
-        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64});
+        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64, 32});
     }
     if (res_ok && (mode == 1 || mode == 4))
       for (int nrt : {1, 2, 4})
-        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64});
+        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64, 32});
   }
   if (cand.empty()) cand.push_back(dflt);
   hipEvent_t e0, e1;
@@ -443,8 +448,10 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
     hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
     if (const char* lf = std::getenv("NESA_TUNE_LOG")) {     // candidate timings, for inspection
       if (FILE* fp = std::fopen(lf, "a")) {
-        std::fprintf(fp, "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d width %d : %.4f ms\n",
-                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, c.width, ms / 3);
+        std::fprintf(fp,
+                     "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d width %d kc %d : %.4f ms\n",
+                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, c.width, c.kc,
+                     ms / 3);
         std::fclose(fp);
       }
     }

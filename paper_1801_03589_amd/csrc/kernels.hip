@@ -219,18 +219,24 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
 
 // CT = column tiles of 16 per workgroup (4: 64-column tiles, wave w owns
 // column tile w and all NRT row tiles; 2: 32-column tiles for groups with few
-// pairs, wave w owns column tile w % 2 and half of the row tiles).
-template <int NRT, int CT>
+// pairs, wave w owns column tile w % 2 and half of the row tiles); KC = K chunk
+// staged in LDS per barrier pair (32 or 64).
+template <int NRT, int CT, int KC>
 __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
-  constexpr int NA = TR_KC * NRT * 8 / NT;        // float4 of A per thread per chunk (NRT*16 rows)
+  constexpr int NA = KC * NRT * 8 / NT;        // float4 of A per thread per chunk (NRT*16 rows)
   constexpr int HALF = NRT * 8;                   // float4 per A column in a block
   constexpr int COLS = 16 * CT;                   // columns of a tile
-  constexpr int NBT = TR_KC * COLS / NT;          // float2 of B per thread per chunk
+  constexpr int NBT = KC * COLS / NT;          // float2 of B per thread per chunk
   constexpr int RPW = NRT * CT / 4;               // row tiles per wave
-  static_assert(TR_KC * NRT * 8 % NT == 0, "A chunk must split evenly");
+  static_assert(KC * NRT * 8 % NT == 0, "A chunk must split evenly");
   static_assert(NRT * CT % 4 == 0, "row tiles must split over the waves");
-  __shared__ float4 As4[TR_KC][HALF];             // [k][row pair]
-  __shared__ float2 Bs[COLS][TR_KC + 1];          // [column][k]
+  // LDS padding (64 banks of 4 bytes): the four k rows a wave reads at once sit
+  // 32 banks apart (A row stride = 32 x odd words), and the 16 columns of one k
+  // row and of the next fall in disjoint banks (B column stride = 4 banks mod 64)
+  constexpr int APAD = (NRT % 2 == 0) ? 4 : 0;    // float4
+  constexpr int AST = 2 * (HALF + APAD);          // A row stride in float2
+  __shared__ float4 As4[KC][HALF + APAD];      // [k][row pair]
+  __shared__ float2 Bs[COLS][KC + 2];          // [column][k]
   __shared__ int64_t col_src[COLS];
   __shared__ int64_t col_dst[COLS];
   const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
@@ -270,8 +276,8 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 #pragma unroll
   for (int i = 0; i < NBT; ++i) {
     const int e = t + i * NT;
-    const int col = e / TR_KC;
-    b_k[i] = e % TR_KC;
+    const int col = e / KC;
+    b_k[i] = e % KC;
     b_ptr[i] = g.src + col_src[col];
     b_ok[i] = col < cnt ? 1.f : 0.f;
   }
@@ -293,8 +299,8 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
     }
   };
   load(0);
-  for (int k0 = 0; k0 < K; k0 += TR_KC) {
-    const int kc = min(TR_KC, K - k0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const int kc = min(KC, K - k0);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -304,10 +310,10 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 #pragma unroll
     for (int i = 0; i < NBT; ++i) {
       const int e = t + i * NT;
-      Bs[e / TR_KC][e % TR_KC] = rb[i];
+      Bs[e / KC][e % KC] = rb[i];
     }
     __syncthreads();
-    if (k0 + TR_KC < K) load(k0 + TR_KC);     // next chunk in flight during the MFMAs
+    if (k0 + KC < K) load(k0 + KC);     // next chunk in flight during the MFMAs
     if (active) {
       const float2* As = reinterpret_cast<const float2*>(&As4[0][0]);
       const int ksteps = (kc + 3) / 4;
@@ -316,7 +322,7 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
         const float2 b = Bs[ct * 16 + lane % 16][kk];
         float2 a[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) a[r] = As[kk * (NRT * 16) + (rt0 + r) * 16 + lane % 16];
+        for (int r = 0; r < RPW; ++r) a[r] = As[kk * AST + (rt0 + r) * 16 + lane % 16];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
           cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
@@ -720,13 +726,13 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm_res(GemmTiles g, int tpw) 
 
 // translations (groups = offset slots) and transfers (groups = octants) get
 // their own kernel names so that profiles separate them
-template <int NRT, int CT>
+template <int NRT, int CT, int KC>
 __global__ __launch_bounds__(NT) void k_translate_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT, CT>(g);
+  cgemm_tiles_body<NRT, CT, KC>(g);
 }
-template <int NRT, int CT>
+template <int NRT, int CT, int KC>
 __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT, CT>(g);
+  cgemm_tiles_body<NRT, CT, KC>(g);
 }
 
 // dst_a = sum over [beg[a], end[a]) of the per-pair results, in order (deterministic)
@@ -1280,11 +1286,17 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
   dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
   if (tl.width == 32 && !p.A_split) {
     // 32-column tiles: waves split the rows (NRT even)
-#define NESA_TILES32(N)                                   \
-  if (translation)                                        \
-    k_translate_gemm<N, 2><<<grid, NT, 0, st>>>(g);       \
-  else                                                    \
-    k_transfer_gemm<N, 2><<<grid, NT, 0, st>>>(g);        \
+#define NESA_TILES32(N)                                                   \
+  if (tl.kc == 64) {                                                      \
+    if (translation)                                                      \
+      k_translate_gemm<N, 2, 64><<<grid, NT, 0, st>>>(g);                 \
+    else                                                                  \
+      k_transfer_gemm<N, 2, 64><<<grid, NT, 0, st>>>(g);                  \
+  } else if (translation) {                                               \
+    k_translate_gemm<N, 2, 32><<<grid, NT, 0, st>>>(g);                   \
+  } else {                                                                \
+    k_transfer_gemm<N, 2, 32><<<grid, NT, 0, st>>>(g);                    \
+  }                                                                       \
   return;
     switch (nrt) {
       case 2: NESA_TILES32(2)
@@ -1301,10 +1313,15 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
       k_translate_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                          \
     else                                                                                     \
       k_transfer_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                           \
+  } else if (tl.kc == 64) {                                                                  \
+    if (translation)                                                                         \
+      k_translate_gemm<N, 4, 64><<<grid, NT, 0, st>>>(g);                                    \
+    else                                                                                     \
+      k_transfer_gemm<N, 4, 64><<<grid, NT, 0, st>>>(g);                                     \
   } else if (translation) {                                                                  \
-    k_translate_gemm<N, 4><<<grid, NT, 0, st>>>(g);                                          \
+    k_translate_gemm<N, 4, 32><<<grid, NT, 0, st>>>(g);                                      \
   } else {                                                                                   \
-    k_transfer_gemm<N, 4><<<grid, NT, 0, st>>>(g);                                           \
+    k_transfer_gemm<N, 4, 32><<<grid, NT, 0, st>>>(g);                                       \
   }                                                                                          \
   break;
   switch (nrt) {
