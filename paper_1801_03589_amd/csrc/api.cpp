@@ -284,7 +284,7 @@ struct TuneKey {
   }
 };
 struct TuneChoice {
-  int nrt, tpw, kt, regions, width, kc;
+  int nrt, tpw, kt, regions, width, m3;
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune;
@@ -293,7 +293,8 @@ static bool g_tune_loaded = false;
 // NESA_AUTOTUNE: unset or "1" = all candidates, "0" = default blocking,
 // "chunked" / "resident" / "direct" / "narrow" = only that kernel family
 // (resident and direct where K <= 84, narrow = chunked with 32-column tiles
-// where the row tiles split over the waves; else the plain chunked kernel)
+// where the row tiles split over the waves, gauss = chunked with three real
+// MFMAs per complex product; else the plain chunked kernel)
 static int autotune_mode() {
   const char* e = std::getenv("NESA_AUTOTUNE");
   if (!e) return 1;
@@ -303,6 +304,7 @@ static int autotune_mode() {
   if (v == "resident") return 3;
   if (v == "direct") return 4;
   if (v == "narrow") return 5;
+  if (v == "gauss") return 6;
   return 1;
 }
 
@@ -317,10 +319,10 @@ static void tune_load_locked() {
   long long nt;
   TuneChoice c;
   while (std::fscanf(fp, "%d %d %d %d %d %lld %d %d %d %d %d %d", &k.kind, &k.split, &k.M, &k.K, &k.nrhs, &nt,
-                     &c.nrt, &c.tpw, &c.kt, &c.regions, &c.width, &c.kc) == 12) {
+                     &c.nrt, &c.tpw, &c.kt, &c.regions, &c.width, &c.m3) == 12) {
     k.ntiles = nt;
     if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8) &&
-        (c.width == 32 || c.width == 64) && (c.kc == 32 || c.kc == 64))
+        (c.width == 32 || c.width == 64) && (c.m3 == 0 || c.m3 == 1))
       g_tune[k] = c;
   }
   std::fclose(fp);
@@ -333,7 +335,7 @@ static void tune_store_locked(const TuneKey& k, const TuneChoice& c) {
   FILE* fp = std::fopen(f, "a");
   if (!fp) return;
   std::fprintf(fp, "%d %d %d %d %d %lld %d %d %d %d %d %d\n", k.kind, k.split, k.M, k.K, k.nrhs, (long long)k.ntiles,
-               c.nrt, c.tpw, c.kt, c.regions, c.width, c.kc);
+               c.nrt, c.tpw, c.kt, c.regions, c.width, c.m3);
   std::fclose(fp);
 }
 
@@ -348,9 +350,9 @@ static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice
                     (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
     return false;
   if (c.width != (tl.width) || (c.width == 32 && (c.tpw != 0 || p.A_split || c.nrt % 2))) return false;
-  if (c.kc != 32 && (c.kc != 64 || c.tpw != 0 || p.A_split)) return false;
+  if (c.m3 && (c.tpw != 0 || p.A_split)) return false;
   tl.nrt = c.nrt;
-  tl.kc = c.kc;
+  tl.m3 = c.m3;
   tl.rblocks = blocks;
   tl.tpw = c.tpw;
   tl.kt = c.tpw > 0 ? c.kt : 0;
@@ -415,12 +417,16 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   for (int regions : {1, 8}) {
     if (regions == 8 && !reg_ok) continue;
     for (int nrt : nrts) {
-      for (int kc : {32, 64}) {
-        if (kc == 64 && (p.A_split || p.K < 64)) continue;
-        if ((mode != 3 && mode != 4) || !res_ok) {
-          if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64, kc});
-          if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, kc});
-        }
+      for (int m3 : {0, 1}) {
+        bool use;
+        if (m3)
+          use = !p.A_split && (mode == 1 || mode == 6);
+        else
+          use = mode == 1 || mode == 2 || mode == 5 || ((mode == 3 || mode == 4) && !res_ok) ||
+                (mode == 6 && p.A_split);
+        if (!use) continue;
+        if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64, m3});
+        if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, m3});
       }
       if (res_ok && (mode == 1 || mode == 3))
         for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64, 32});
@@ -449,8 +455,8 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
     if (const char* lf = std::getenv("NESA_TUNE_LOG")) {     // candidate timings, for inspection
       if (FILE* fp = std::fopen(lf, "a")) {
         std::fprintf(fp,
-                     "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d width %d kc %d : %.4f ms\n",
-                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, c.width, c.kc,
+                     "kind %d M %d K %d nrhs %d tiles %lld : nrt %d tpw %d kt %d regions %d width %d m3 %d : %.4f ms\n",
+                     key.kind, p.M, p.K, nrhs, (long long)tl.ntiles, c.nrt, c.tpw, c.kt, c.regions, c.width, c.m3,
                      ms / 3);
         std::fclose(fp);
       }

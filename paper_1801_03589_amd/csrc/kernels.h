@@ -18,7 +18,7 @@ struct TileList {
   int tpw = 0, kt = 0;            // resident-A kernel: tiles per workgroup and its K capacity (0: chunked kernel)
   int regions = 1;                // tiles ordered by (region, group) when 8: each XCD takes one region
   int width = 64;                 // columns per tile (64; 32 for the chunked kernel on groups with few pairs)
-  int kc = 32;                    // K chunk of the chunked kernel (32 or 64)
+  int m3 = 0;                     // chunked kernel: complex products with three real MFMAs
   int64_t ntiles = 0;
   int32_t* tile_group = nullptr;
   int32_t* tile_ncols = nullptr;

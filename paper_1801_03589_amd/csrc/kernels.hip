@@ -219,10 +219,11 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
 
 // CT = column tiles of 16 per workgroup (4: 64-column tiles, wave w owns
 // column tile w and all NRT row tiles; 2: 32-column tiles for groups with few
-// pairs, wave w owns column tile w % 2 and half of the row tiles); KC = K chunk
-// staged in LDS per barrier pair (32 or 64).
-template <int NRT, int CT, int KC>
+// pairs, wave w owns column tile w % 2 and half of the row tiles); M3 = complex
+// products with three real MFMAs instead of four.
+template <int NRT, int CT, int M3>
 __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
+  constexpr int KC = TR_KC;
   constexpr int NA = KC * NRT * 8 / NT;        // float4 of A per thread per chunk (NRT*16 rows)
   constexpr int HALF = NRT * 8;                   // float4 per A column in a block
   constexpr int COLS = 16 * CT;                   // columns of a tile
@@ -253,11 +254,14 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   __syncthreads();
   const float4* A4 = reinterpret_cast<const float4*>(g.A + (size_t)g.tile_group[tile] * g.a_stride + r0);
   const bool active = 16 * ct < cnt;
-  f32x4 cre[RPW], cim[RPW];
+  // 4 real products per complex product, or (M3) three: P1 = Ar Br, P2 = Ai Bi,
+  // P3 = (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2 (25% fewer MFMAs)
+  f32x4 cre[RPW], cim[RPW], c3[M3 ? RPW : 1];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
     cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
     cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (M3) c3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   float4 ra[NA];
   float2 rb[NBT];
@@ -323,15 +327,25 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
         float2 a[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) a[r] = As[kk * AST + (rt0 + r) * 16 + lane % 16];
+        if (M3) {
+          const float bs = b.x + b.y;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
-          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
-        }
+          for (int r = 0; r < RPW; ++r) {
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, cim[r], 0, 0, 0);
+            c3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x + a[r].y, bs, c3[r], 0, 0, 0);
+          }
+        } else {
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
-          cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
+          for (int r = 0; r < RPW; ++r) {
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
+            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
+          }
         }
       }
     }
@@ -346,7 +360,8 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       for (int i = 0; i < 4; ++i) {
         const int row = r0 + (rt0 + r) * 16 + 4 * (lane / 16) + i;
         if (row < M) {
-          float2 v = make_float2(cre[r][i], cim[r][i]);
+          float2 v = M3 ? make_float2(cre[r][i] - cim[r][i], c3[r][i] - cre[r][i] - cim[r][i])
+                        : make_float2(cre[r][i], cim[r][i]);
           if (g.accumulate) {
             const float2 o = out[row];
             v.x += o.x;
@@ -726,13 +741,13 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm_res(GemmTiles g, int tpw) 
 
 // translations (groups = offset slots) and transfers (groups = octants) get
 // their own kernel names so that profiles separate them
-template <int NRT, int CT, int KC>
+template <int NRT, int CT, int M3>
 __global__ __launch_bounds__(NT) void k_translate_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT, CT, KC>(g);
+  cgemm_tiles_body<NRT, CT, M3>(g);
 }
-template <int NRT, int CT, int KC>
+template <int NRT, int CT, int M3>
 __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
-  cgemm_tiles_body<NRT, CT, KC>(g);
+  cgemm_tiles_body<NRT, CT, M3>(g);
 }
 
 // dst_a = sum over [beg[a], end[a]) of the per-pair results, in order (deterministic)
@@ -1287,15 +1302,15 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
   if (tl.width == 32 && !p.A_split) {
     // 32-column tiles: waves split the rows (NRT even)
 #define NESA_TILES32(N)                                                   \
-  if (tl.kc == 64) {                                                      \
+  if (tl.m3) {                                                            \
     if (translation)                                                      \
-      k_translate_gemm<N, 2, 64><<<grid, NT, 0, st>>>(g);                 \
+      k_translate_gemm<N, 2, 1><<<grid, NT, 0, st>>>(g);                  \
     else                                                                  \
-      k_transfer_gemm<N, 2, 64><<<grid, NT, 0, st>>>(g);                  \
+      k_transfer_gemm<N, 2, 1><<<grid, NT, 0, st>>>(g);                   \
   } else if (translation) {                                               \
-    k_translate_gemm<N, 2, 32><<<grid, NT, 0, st>>>(g);                   \
+    k_translate_gemm<N, 2, 0><<<grid, NT, 0, st>>>(g);                    \
   } else {                                                                \
-    k_transfer_gemm<N, 2, 32><<<grid, NT, 0, st>>>(g);                    \
+    k_transfer_gemm<N, 2, 0><<<grid, NT, 0, st>>>(g);                     \
   }                                                                       \
   return;
     switch (nrt) {
@@ -1313,15 +1328,15 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
       k_translate_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                          \
     else                                                                                     \
       k_transfer_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                           \
-  } else if (tl.kc == 64) {                                                                  \
+  } else if (tl.m3) {                                                                       \
     if (translation)                                                                         \
-      k_translate_gemm<N, 4, 64><<<grid, NT, 0, st>>>(g);                                    \
+      k_translate_gemm<N, 4, 1><<<grid, NT, 0, st>>>(g);                                     \
     else                                                                                     \
-      k_transfer_gemm<N, 4, 64><<<grid, NT, 0, st>>>(g);                                     \
+      k_transfer_gemm<N, 4, 1><<<grid, NT, 0, st>>>(g);                                      \
   } else if (translation) {                                                                  \
-    k_translate_gemm<N, 4, 32><<<grid, NT, 0, st>>>(g);                                      \
+    k_translate_gemm<N, 4, 0><<<grid, NT, 0, st>>>(g);                                       \
   } else {                                                                                   \
-    k_transfer_gemm<N, 4, 32><<<grid, NT, 0, st>>>(g);                                       \
+    k_transfer_gemm<N, 4, 0><<<grid, NT, 0, st>>>(g);                                        \
   }                                                                                          \
   break;
   switch (nrt) {

@@ -283,12 +283,13 @@ def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
             assert err <= tol, (i, r, err)
 
 
-@pytest.mark.parametrize("family", ["chunked", "resident", "direct", "narrow"])
+@pytest.mark.parametrize("family", ["chunked", "resident", "direct", "narrow", "gauss"])
 @pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
 def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, name, family):
     """The autotuner restricted to one kernel family (chunked-K tiles, resident
-    group matrices, register-direct tiles, or 32-column chunked tiles) still
-    matches the oracle, for one and for five right-hand sides."""
+    group matrices, register-direct tiles, 32-column chunked tiles, or three
+    real products per complex product) still matches the oracle, for one and
+    for five right-hand sides."""
     monkeypatch.setenv("NESA_AUTOTUNE", family)
     ref, tr, near, far = _case(nesa, name)
     op = nesa.op_create(tr, near, far, nesa.C64, max_nrhs=5)
