@@ -657,6 +657,23 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   }
   op->xl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
   op->yl = dev_alloc(op, (size_t)d.n * op->max_nrhs * 2 * sizeof(T));
+  // side stream (default priority, non-blocking so that it never serialises
+  // with the legacy default stream) and the fork / join events of the product
+  hip_check(hipStreamCreateWithFlags(&d.side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  {
+    // persistent near-field grid: one workgroup per CU (measured best beside the
+    // far-field stages; NESA_NEAR_WGS overrides)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    }
+    d.near_wgs = cus;
+    if (const char* e = std::getenv("NESA_NEAR_WGS")) d.near_wgs = std::max(1, std::atoi(e));
+  }
+  hip_check(hipEventCreateWithFlags(&d.ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+  hip_check(hipEventCreateWithFlags(&d.ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
   ensure_all_tiles<T>(op, d, 1);
 }
 
@@ -694,6 +711,11 @@ struct nesa_mlp {
 
 nesa_op::~nesa_op() {
   for (nesa_mlp* m : nets) m->op = nullptr;
+  (void)hipDeviceSynchronize();
+  for (auto* dv : {&f.side, &d.side})
+    if (*dv) (void)hipStreamDestroy(*dv);
+  for (auto* ev : {&f.ev_fork, &f.ev_join, &d.ev_fork, &d.ev_join})
+    if (*ev) (void)hipEventDestroy(*ev);
   for (void* p : allocs) (void)hipFree(p);
 }
 

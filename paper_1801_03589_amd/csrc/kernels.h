@@ -80,6 +80,9 @@ struct DevOp {
   void* Minv = nullptr;          // block-diagonal preconditioner (inverse self blocks)
   int64_t* moff = nullptr;
   int32_t* near_order = nullptr; // leaves by decreasing near-field work (launch order)
+  hipStream_t side = nullptr;    // non-blocking stream of the near field (untimed products)
+  int near_wgs = 0;              // workgroups of the persistent near-field grid (0: 256)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int max_nrhs = 1;              // right-hand sides the work buffers hold
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;

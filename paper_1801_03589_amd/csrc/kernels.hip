@@ -12,6 +12,8 @@
 // Complex numbers are interleaved (re, im) pairs of T = float or double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace nesa {
@@ -42,6 +44,10 @@ __device__ __forceinline__ V cmul(const V a, const V b) {
   r.y = a.x * b.y + a.y * b.x;
   return r;
 }
+
+// stream / event calls inside the launchers: failures surface at the next
+// synchronising call of the caller, as launch failures do
+static inline void hip_ok(hipError_t e) { (void)e; }
 
 constexpr int NT = 256;     // threads per workgroup
 constexpr int WAVE = 64;
@@ -750,14 +756,15 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
   cgemm_tiles_body<NRT, CT, M3>(g);
 }
 
-// dst_a = sum over [beg[a], end[a]) of the per-pair results, in order (deterministic)
+// dst_a = sum over [beg[a], end[a]) of the per-pair results, in order
+// (deterministic); workgroup (a, y) takes elements y*NT, y*NT + gridDim.y*NT, ...
 template <typename V>
 __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
                                                    const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
                                                    int J) {
   const int a = blockIdx.x;
   const int k0 = beg[a], k1 = end[a];
-  for (int j = threadIdx.x; j < J; j += NT) {
+  for (int j = blockIdx.y * NT + threadIdx.x; j < J; j += gridDim.y * NT) {
     V acc;
     acc.x = 0;
     acc.y = 0;
@@ -821,8 +828,9 @@ constexpr int NEAR_CW = 1024;   // x columns staged in LDS per pass
 constexpr int MAX_NEAR = 128;   // near-list entries per leaf
 constexpr int MAX_QL = 256;     // equivalent sources per leaf
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __restrict__ Z,
+template <typename T, bool RECV>
+__device__ __forceinline__ void near_leaf(const int a, typename C2<T>::type* xs, typename C2<T>::type* red, int* seg_col, int* seg_x, typename C2<T>::type* ow,
+                                          const typename C2<T>::type* __restrict__ Z,
                                                   const int64_t* __restrict__ zoff,
                                                   const int32_t* __restrict__ leaf_ptr,
                                                   const int32_t* __restrict__ near_ptr,
@@ -834,12 +842,7 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
                                                   T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d,
                                                   const int32_t* __restrict__ order) {
   using V2 = typename C2<T>::type;
-  __shared__ V2 xs[NEAR_CW];
-  __shared__ V2 red[NT];
-  __shared__ int seg_col[MAX_NEAR + 1];
-  __shared__ int seg_x[MAX_NEAR];
-  __shared__ V2 ow[4 * MAX_QL];            // weighted o_a
-  const int a = order[blockIdx.x];         // largest leaves first (shorter tail)
+  (void)order;
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
   if (threadIdx.x == 0) {
@@ -879,10 +882,12 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
   // weighted equivalent potentials of the leaf (channel weights of the
   // mixed-potential split: w_xyz = -i eta k, w_div = +i eta / k)
   const int J = 4 * Q;
-  for (int j = t; j < J; j += NT) {
-    const V2 ov = o[(size_t)a * J + j];
-    const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
-    ow[j] = cmul(ov, wv);
+  if (RECV) {
+    for (int j = t; j < J; j += NT) {
+      const V2 ov = o[(size_t)a * J + j];
+      const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
+      ow[j] = cmul(ov, wv);
+    }
   }
   __syncthreads();
   // reduce the column groups (fixed order) -> near result of row r in red[r]
@@ -895,6 +900,10 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
     }
   }
   __syncthreads();
+  if (!RECV) {                            // near field only (reception added later)
+    if (t < S) y[p0 + t] = yn;
+    return;
+  }
   if (t < S) red[t] = yn;
   __syncthreads();
   // reception: one wave per row
@@ -913,6 +922,90 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
       out.y += s.y;
       y[p0 + row] = out;
     }
+  }
+}
+
+template <typename T, bool RECV>
+__global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __restrict__ Z,
+                                                  const int64_t* __restrict__ zoff,
+                                                  const int32_t* __restrict__ leaf_ptr,
+                                                  const int32_t* __restrict__ near_ptr,
+                                                  const int32_t* __restrict__ near_idx,
+                                                  const typename C2<T>::type* __restrict__ x,
+                                                  const typename C2<T>::type* __restrict__ V,
+                                                  const typename C2<T>::type* __restrict__ o,
+                                                  typename C2<T>::type* __restrict__ y, int Q,
+                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d,
+                                                  const int32_t* __restrict__ order) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 xs[NEAR_CW];
+  __shared__ V2 red[NT];
+  __shared__ int seg_col[MAX_NEAR + 1];
+  __shared__ int seg_x[MAX_NEAR];
+  __shared__ V2 ow[4 * MAX_QL];            // weighted o_a
+  // largest leaves first (shorter tail)
+  near_leaf<T, RECV>(order[blockIdx.x], xs, red, seg_col, seg_x, ow, Z, zoff, leaf_ptr, near_ptr, near_idx, x, V, o,
+                     y, Q, w_re_xyz, w_im_xyz, w_re_d, w_im_d, order);
+}
+
+// reception of one right-hand side (Eq. 14), added to y: one workgroup per
+// leaf, the weighted potentials in LDS, one wave per row
+template <typename T>
+__global__ __launch_bounds__(NT) void k_recv1(const typename C2<T>::type* __restrict__ V,
+                                              const typename C2<T>::type* __restrict__ o,
+                                              const int32_t* __restrict__ leaf_ptr,
+                                              typename C2<T>::type* __restrict__ y, int Q, T w_re_xyz,
+                                              T w_im_xyz, T w_re_d, T w_im_d) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 ow[4 * MAX_QL];
+  const int a = blockIdx.x;
+  const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
+  const int J = 4 * Q, t = threadIdx.x;
+  for (int j = t; j < J; j += NT) {
+    const V2 ov = o[(size_t)a * J + j];
+    const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
+    ow[j] = cmul(ov, wv);
+  }
+  __syncthreads();
+  const int lane = t % WAVE, wv = t / WAVE;
+  for (int row = wv; row < S; row += NT / WAVE) {
+    const V2* Vr = V + (size_t)(p0 + row) * J;
+    V2 s = cmk<T>(0, 0);
+    for (int j = lane; j < J; j += WAVE) cfma(s, Vr[j], ow[j]);
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+      s.x += __shfl_xor(s.x, off);
+      s.y += __shfl_xor(s.y, off);
+    }
+    if (lane == 0) {
+      V2 out = y[p0 + row];
+      out.x += s.x;
+      out.y += s.y;
+      y[p0 + row] = out;
+    }
+  }
+}
+
+// near field only, as a persistent grid of a few workgroups per CU that walk
+// the leaves (largest first): run beside the far-field stages, it leaves most of
+// every CU to them
+template <typename T>
+__global__ __launch_bounds__(NT) void k_near_persist(const typename C2<T>::type* __restrict__ Z,
+                                                     const int64_t* __restrict__ zoff,
+                                                     const int32_t* __restrict__ leaf_ptr,
+                                                     const int32_t* __restrict__ near_ptr,
+                                                     const int32_t* __restrict__ near_idx,
+                                                     const typename C2<T>::type* __restrict__ x,
+                                                     typename C2<T>::type* __restrict__ y, int64_t nleaf,
+                                                     const int32_t* __restrict__ order) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 xs[NEAR_CW];
+  __shared__ V2 red[NT];
+  __shared__ int seg_col[MAX_NEAR + 1];
+  __shared__ int seg_x[MAX_NEAR];
+  for (int64_t i = blockIdx.x; i < nleaf; i += gridDim.x) {
+    near_leaf<T, false>(order[i], xs, red, seg_col, seg_x, nullptr, Z, zoff, leaf_ptr, near_ptr, near_idx, x,
+                        nullptr, nullptr, y, 0, T(0), T(0), T(0), T(0), order);
+    __syncthreads();                       // shared arrays reused by the next leaf
   }
 }
 
@@ -1356,6 +1449,15 @@ void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStr
   launch_tiles(p, nrhs, src, dst, st, translation);
 }
 
+// grid of an ordered per-box sum: enough workgroups to fill the chip when
+// there are few boxes (each takes a share of the box's elements)
+static dim3 csr_grid(int64_t nbox, int J) {
+  const int chunks = (J + NT - 1) / NT;
+  int y = 1;
+  while (y < chunks && nbox * y < 2048) ++y;
+  return dim3((unsigned)nbox, (unsigned)y);
+}
+
 template <typename T>
 void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hipStream_t st, PhaseTimer* tm) {
   using V2 = typename C2<T>::type;
@@ -1369,6 +1471,25 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   const int NC = 4 * R;
   const unsigned rblk = (unsigned)((R + RB - 1) / RB);
   if (!mfma && R != 1) return;   // the complex128 path takes one right-hand side at a time
+  // untimed products run the near field (HBM-bound) on a side stream while
+  // this stream runs the far-field stages (matrix-core bound); the timed form
+  // keeps every stage on one stream so that stage times stay separate
+  const bool overlap = !tm && d.side != nullptr && (R == 1 || mfma);
+  auto fork_near = [&]() {
+    hip_ok(hipEventRecord(d.ev_fork, st));
+    hip_ok(hipStreamWaitEvent(d.side, d.ev_fork, 0));
+    if (R == 1) {
+      const unsigned nwg = (unsigned)std::min<int64_t>(d.nleaf, d.near_wgs > 0 ? d.near_wgs : 256);
+      k_near_persist<T><<<nwg, NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
+                                               d.near_idx, xl, yl, d.nleaf, d.near_order);
+    } else {
+      if constexpr (sizeof(T) == 4)
+        k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff,
+                                                                          d.leaf_ptr, d.near_ptr, d.near_idx, xl,
+                                                                          yl, R, d.n);
+    }
+    hip_ok(hipEventRecord(d.ev_join, d.side));
+  };
   if (tm) tm->mark(st, 0, -1, 0);
   if (R == 1) {
     k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr, s + LL.s_off, LL.Q);
@@ -1378,14 +1499,18 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                                        s + LL.s_off * R, LL.Q, R, d.n);
   }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
+  // the near field starts once radiation (also HBM-bound) is done, and runs
+  // beside the transfers and translations
+  if (overlap) fork_near();
   for (int l = L; l > l0; --l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
     if (mfma) {
       launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
-      k_csr_reduce<V2><<<(unsigned)p.nbox, NT, 0, st>>>(static_cast<const V2*>(c.child_out), s + p.s_off * R,
-                                                        p.child_ptr, p.child_end, NC * p.Q);
+      k_csr_reduce<V2><<<csr_grid(p.nbox, NC * p.Q), NT, 0, st>>>(static_cast<const V2*>(c.child_out),
+                                                                   s + p.s_off * R, p.child_ptr, p.child_end,
+                                                                   NC * p.Q);
       if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
     } else {
       dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
@@ -1400,8 +1525,9 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     if (mfma && lv.npairs > 0) {
       launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, st, true);
       if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
-      k_csr_reduce<V2><<<(unsigned)lv.nbox, NT, 0, st>>>(static_cast<const V2*>(lv.pair_out), o + lv.s_off * R,
-                                                         lv.il_ptr, lv.il_ptr + 1, NC * lv.Q);
+      k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, st>>>(static_cast<const V2*>(lv.pair_out),
+                                                                    o + lv.s_off * R, lv.il_ptr, lv.il_ptr + 1,
+                                                                    NC * lv.Q);
       if (tm) tm->mark(st, -1, l, K_TRANS_REDUCE);
     } else if (mfma) {
       const int64_t cnt = lv.nbox * NC * lv.Q;
@@ -1428,11 +1554,21 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     }
   }
   if (tm) tm->mark(st, 4, -1, 0);
-  if (R == 1) {
-    k_near_recv<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
-                                                     d.near_idx, xl, static_cast<const V2*>(d.V), o + LL.s_off, yl,
-                                                     LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3],
-                                                     d.near_order);
+  if (overlap) {
+    // the near field ran on the side stream: join, then add the reception
+    hip_ok(hipStreamWaitEvent(st, d.ev_join, 0));
+    if (R == 1)
+      k_recv1<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off, d.leaf_ptr, yl, LL.Q,
+                                                   (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+    else
+      k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V),
+                                                                   o + LL.s_off * R, d.leaf_ptr, yl, LL.Q, R, d.n,
+                                                                   (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+  } else if (R == 1) {
+    k_near_recv<T, true><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr,
+                                                           d.near_ptr, d.near_idx, xl, static_cast<const V2*>(d.V),
+                                                           o + LL.s_off, yl, LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2],
+                                                           (T)d.w[3], d.near_order);
   } else {
     if constexpr (sizeof(T) == 4) {
       k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,
