@@ -71,6 +71,9 @@ def algorithmic(info, Q, esize):
                        "flops": 8 * info["near_entries"] + 8 * 4 * QL * n}
     ph["radiate"] = {"bytes": n * 4 * QL * esize + n * esize + nleaf * 4 * QL * esize,
                      "flops": 8 * 4 * QL * n}
+    # reception alone (the overlapped product adds it after the side-stream near field)
+    ph["receive"] = {"bytes": n * 4 * QL * esize + 2 * n * esize + nleaf * 4 * QL * esize,
+                     "flops": 8 * 4 * QL * n}
     up = 0
     for i in range(1, nl):
         up += info["n_box"][i] * 8 * 4 * Q[i - 1] * Q[i]
@@ -397,6 +400,9 @@ def main():
         elif kind == "radiate":
             e["bytes"] += alg["radiate"]["bytes"]
             e["flops"] += alg["radiate"]["flops"]
+        elif kind == "receive":
+            e["bytes"] += alg["receive"]["bytes"]
+            e["flops"] += alg["receive"]["flops"]
         elif kind in ("translate_sum",):
             e["bytes"] += 2 * info["n_pairs"][i] * 4 * Q[i] * esize
         elif kind in ("upward_sum",):

@@ -1234,6 +1234,7 @@ int nesa_matvec_launch_times(nesa_op* op, const void* x_dev, void* y_dev, void* 
   return guarded([&]() {
     if (!op || !x_dev || !y_dev || !ms || !kind || !level || !count) return fail(NESA_EINVAL, "null argument");
     nesa::PhaseTimer tm;
+    tm.overlap = true;       // the launches as the untimed product runs them
     timed_matvec(op, x_dev, y_dev, static_cast<hipStream_t>(stream), tm);
     int c = 0;
     for (int i = 1; i < tm.n && c < max_launches; ++i) {

@@ -109,7 +109,7 @@ inline int row_alloc(int M) {
 
 // kernel kinds of the per-launch timing
 enum { K_RADIATE = 1, K_UP_GEMM, K_UP_REDUCE, K_UP_VALU, K_TRANS_GEMM, K_TRANS_REDUCE, K_TRANS_VALU,
-       K_DOWN_GEMM, K_DOWN_VALU, K_NEAR_RECV };
+       K_DOWN_GEMM, K_DOWN_VALU, K_NEAR_RECV, K_RECV };
 
 // hipEvent markers between the matvec stages (phase >= 0) and after every
 // launch (kind > 0); events are recorded on the launch stream.
@@ -120,6 +120,7 @@ struct PhaseTimer {
   int phase_ev[NMARK];
   int kind[MAXEV], level[MAXEV];
   int n = 0;
+  bool overlap = false;   // time the launches of the overlapped form (near field on the side stream, untimed)
   void mark(hipStream_t st, int phase, int lev, int k) {
     if (n >= MAXEV) return;
     (void)hipEventRecord(ev[n], st);

@@ -1474,7 +1474,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   // untimed products run the near field (HBM-bound) on a side stream while
   // this stream runs the far-field stages (matrix-core bound); the timed form
   // keeps every stage on one stream so that stage times stay separate
-  const bool overlap = !tm && d.side != nullptr && (R == 1 || mfma);
+  const bool overlap = (!tm || tm->overlap) && d.side != nullptr && (R == 1 || mfma);
   auto fork_near = [&]() {
     hip_ok(hipEventRecord(d.ev_fork, st));
     hip_ok(hipStreamWaitEvent(d.side, d.ev_fork, 0));
@@ -1579,7 +1579,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                                    (T)d.w[1], (T)d.w[2], (T)d.w[3]);
     }
   }
-  if (tm) tm->mark(st, 5, L, K_NEAR_RECV);
+  if (tm) tm->mark(st, 5, L, overlap ? K_RECV : K_NEAR_RECV);
 }
 
 template <typename T>

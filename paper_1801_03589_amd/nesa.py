@@ -272,7 +272,7 @@ def matvec_phase_times(op, x, y, stream=None):
 
 KIND_NAMES = {1: "radiate", 2: "upward_gemm", 3: "upward_sum", 4: "upward_fp64", 5: "translate_gemm",
               6: "translate_sum", 7: "translate_fp64", 8: "downward_gemm", 9: "downward_fp64",
-              10: "near_recv"}
+              10: "near_recv", 11: "receive"}
 
 
 def matvec_launch_times(op, x, y, stream=None, max_launches=128):
