@@ -302,3 +302,38 @@ def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, name, family):
         print("%s %s rhs %d: rel err %.2e" % (name, family, r, err))
         assert err <= TOL["c64"]
     assert np.linalg.norm(Y1 - ref.matvec(X[2])) <= TOL["c64"] * np.linalg.norm(Y1)
+
+
+def test_product_on_user_stream_and_in_hip_graph(torch_dev, nesa):
+    """The product on a caller's (non-default) stream equals the default-stream
+    result bit for bit, and a HIP graph captured from it (side-stream fork and
+    join included) replays to the same bits, three times, with eager work and
+    synchronisations between the replays.  The plan's tiles are tuned by an
+    eager product before capture."""
+    torch = torch_dev
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    op = nesa.op_create(tr, near, far, nesa.C64)
+    x = torch.from_numpy(synth.complex_normal(ref.m.n, 90)).to(torch.complex64).cuda()
+    y0 = torch.empty_like(x)
+    nesa.matvec(op, x, y0)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    y1 = torch.empty_like(x)
+    with torch.cuda.stream(s):
+        nesa.matvec(op, x, y1, stream=s)
+    s.synchronize()
+    assert torch.equal(y0, y1)
+    xg = x.clone()
+    yg = torch.zeros_like(x)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        nesa.matvec(op, xg, yg, stream=s)
+    for rep in range(3):
+        yg.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(yg, y0), rep
+        z = torch.empty_like(x)
+        nesa.matvec(op, x, z)                  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(z, y0)
