@@ -366,6 +366,18 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / args.steps
     value = n / (ms * 1e-3) / 1e6
+    # five further blocks of the same length: median (spread of the timing)
+    blocks = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            nesa.matvec(op, x, y, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        blocks.append(e0.elapsed_time(e1) / args.steps)
+    repeat_ms = sorted(blocks)
     # per-stage and per-launch durations (hipEvents on the launch stream), averaged
     xl = torch.empty_like(x)
     yl = torch.empty_like(x)
@@ -425,6 +437,10 @@ def main():
                    "TFLOP/s": round(v_["flops"] / (v_["ms"] * 1e-3) / 1e12, 2) if v_["flops"] else None,
                    "GB/s": round(v_["bytes"] / (v_["ms"] * 1e-3) / 1e9, 1) if v_["bytes"] else None}
                for k, v_ in kern.items()}
+    # whole-product roofline: sum over stages of max(bytes / HBM peak, flops / FP32 peak)
+    peak_f = PEAK_FP32 if prec != nesa.C128 else 78.6e12
+    t_roof = sum(max(alg[k]["bytes"] / PEAK_HBM, alg[k]["flops"] / peak_f)
+                 for k in ("near_recv", "radiate", "upward", "downward", "translate"))
     phases = {}
     for k in names:
         s_ = phase_ms[k] * 1e-3
@@ -457,6 +473,11 @@ def main():
                    "Q": Q, "boxes": info["n_box"], "pairs": info["n_pairs"],
                    "near_entries": info["near_entries"], "parallelism": "single_gpu"},
         "roofline": roof,
+        "product_roofline": {"t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof * 1e3 / ms, 4),
+                             "definition": "sum over stages of max(algorithmic bytes / 8 TB/s, "
+                                           "algorithmic flops / matrix-core peak)"},
+        "repeat_ms_per_step": {"median": round(repeat_ms[2], 4), "min": round(repeat_ms[0], 4),
+                               "max": round(repeat_ms[4], 4), "blocks": 5},
         "phases": phases,
         "kernels": kernels,
         "wall_s_timed": round(wall, 4),

@@ -98,3 +98,31 @@ def test_near_schwarz_chain_matches_restricted_inverse():
     cols0 = np.arange(7)
     assert np.allclose(z[leaf_rwgs[0]], (np.linalg.inv(Z[np.ix_(cols0, cols0)]) @ r[cols0])[leaf_rwgs[0]],
                        atol=1e-12)
+
+
+def test_arnoldi_relation_of_the_gmres_basis():
+    """A V_m = V_{m+1} H_m to round-off for the oracle's Arnoldi process (the
+    Hessenberg matrix rebuilt from the same modified Gram-Schmidt steps)."""
+    rng = np.random.default_rng(12)
+    n, m = 40, 12
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    V = [b / np.linalg.norm(b)]
+    H = np.zeros((m + 1, m), dtype=complex)
+    for j in range(m):
+        w = A @ V[j]
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w)
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j])
+    Vm, Vm1 = np.array(V[:m]).T, np.array(V).T
+    assert np.linalg.norm(A @ Vm - Vm1 @ H) <= 1e-12 * np.linalg.norm(A) * np.sqrt(m)
+    assert np.linalg.norm(Vm1.conj().T @ Vm1 - np.eye(m + 1)) <= 1e-12
+    # the oracle's GMRES after m steps reaches the least-squares minimum over the
+    # same Krylov space
+    x, info = krylov.gmres(lambda v: A @ v, b, m=m, tol=1e-30, max_iters=m)
+    e1 = np.zeros(m + 1, dtype=complex)
+    e1[0] = np.linalg.norm(b)
+    y = np.linalg.lstsq(H, e1, rcond=None)[0]
+    assert np.linalg.norm(x - Vm @ y) <= 1e-10 * np.linalg.norm(x)
