@@ -41,7 +41,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--nu", type=int, default=82, help="icosphere frequency (82: 201,720 unknowns)")
     p.add_argument("--radius", type=float, default=4.0)
     p.add_argument("--precision", default="c64", choices=["c64", "c128", "split"])

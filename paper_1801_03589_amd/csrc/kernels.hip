@@ -282,78 +282,84 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   }
   const float2* b_ptr[NBT];
   int b_k[NBT];
-  float b_ok[NBT];
+  bool b_ok[NBT];
 #pragma unroll
   for (int i = 0; i < NBT; ++i) {
     const int e = t + i * NT;
     const int col = e / KC;
     b_k[i] = e % KC;
     b_ptr[i] = g.src + col_src[col];
-    b_ok[i] = col < cnt ? 1.f : 0.f;
+    b_ok[i] = col < cnt;
   }
   const int mr2 = g.Mr / 2;
+  // raw loads; the zero mask of k >= K and of empty columns is applied when the
+  // chunk is written to LDS, so the loads stay in flight during the MFMAs
   auto load = [&](int k0) {
 #pragma unroll
+    for (int i = 0; i < NA; ++i) ra[i] = A4[(size_t)min(k0 + a_k[i], K - 1) * mr2 + a_off[i]];
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
+  };
+  // chunk of kc <= KC steps of k into LDS; k past the chunk and empty columns are zeroed
+  auto stage = [&](int kc) {
+    __syncthreads();
+#pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int k = k0 + a_k[i];
-      const float4 v = A4[(size_t)min(k, K - 1) * mr2 + a_off[i]];
-      const float f = k < K ? 1.f : 0.f;
-      ra[i] = make_float4(v.x * f, v.y * f, v.z * f, v.w * f);
+      const int e = t + i * NT;
+      As4[e / HALF][e % HALF] = a_k[i] < kc ? ra[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < NBT; ++i) {
-      const int k = k0 + b_k[i];
-      const float2 v = b_ptr[i][min(k, K - 1)];
-      const float f = k < K ? b_ok[i] : 0.f;
-      rb[i] = make_float2(v.x * f, v.y * f);
+      const int e = t + i * NT;
+      Bs[e / KC][e % KC] = (b_k[i] < kc && b_ok[i]) ? rb[i] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+  };
+  const float2* As = reinterpret_cast<const float2*>(&As4[0][0]);
+  auto step = [&](int ks) {
+    const int kk = ks * 4 + lane / 16;
+    const float2 b = Bs[ct * 16 + lane % 16][kk];
+    float2 a[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) a[r] = As[kk * AST + (rt0 + r) * 16 + lane % 16];
+    if (M3) {
+      const float bs = b.x + b.y;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, cim[r], 0, 0, 0);
+        c3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x + a[r].y, bs, c3[r], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
+      }
     }
   };
+  // the partial chunk (K mod KC steps of k) goes first, so every later chunk is
+  // full and its step loop is unrolled: the LDS reads of later steps are issued
+  // ahead of the MFMAs of earlier ones
+  const int kc0 = (K % KC) ? K % KC : KC;
   load(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    const int kc = min(KC, K - k0);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = t + i * NT;
-      As4[e / HALF][e % HALF] = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NBT; ++i) {
-      const int e = t + i * NT;
-      Bs[e / KC][e % KC] = rb[i];
-    }
-    __syncthreads();
-    if (k0 + KC < K) load(k0 + KC);     // next chunk in flight during the MFMAs
+  stage(kc0);
+  if (kc0 < K) load(kc0);               // next chunk in flight during the MFMAs
+  if (active) {
+    const int ksteps = (kc0 + 3) / 4;
+    for (int ks = 0; ks < ksteps; ++ks) step(ks);
+  }
+  for (int k0 = kc0; k0 < K; k0 += KC) {
+    stage(KC);
+    if (k0 + KC < K) load(k0 + KC);
     if (active) {
-      const float2* As = reinterpret_cast<const float2*>(&As4[0][0]);
-      const int ksteps = (kc + 3) / 4;
-      for (int ks = 0; ks < ksteps; ++ks) {
-        const int kk = ks * 4 + lane / 16;
-        const float2 b = Bs[ct * 16 + lane % 16][kk];
-        float2 a[RPW];
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) a[r] = As[kk * AST + (rt0 + r) * 16 + lane % 16];
-        if (M3) {
-          const float bs = b.x + b.y;
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
-            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.y, cim[r], 0, 0, 0);
-            c3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x + a[r].y, bs, c3[r], 0, 0, 0);
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.x, cre[r], 0, 0, 0);
-            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, b.y, cim[r], 0, 0, 0);
-          }
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            cre[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r].y, b.y, cre[r], 0, 0, 0);
-            cim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, b.x, cim[r], 0, 0, 0);
-          }
-        }
-      }
+      for (int ks = 0; ks < KC / 4; ++ks) step(ks);
     }
   }
   // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
@@ -828,6 +834,40 @@ constexpr int NEAR_CW = 1024;   // x columns staged in LDS per pass
 constexpr int MAX_NEAR = 128;   // near-list entries per leaf
 constexpr int MAX_QL = 256;     // equivalent sources per leaf
 
+// Reception of one leaf (Eq. 14): y[p0 + r] = base_r + sum_j V[p0 + r][j] ow[j]
+// for the S rows of the leaf, with base_r = red[r] (near-field result staged in
+// LDS) or, when red is null, the value already in y.  16 lanes per row and 4
+// rows per wave: each row is read in 16-element runs, the j loop keeps several
+// loads in flight, and the row sum takes 4 shuffle steps.
+template <typename T>
+__device__ __forceinline__ void recv_rows(const typename C2<T>::type* __restrict__ V,
+                                          const typename C2<T>::type* ow, const typename C2<T>::type* red,
+                                          typename C2<T>::type* __restrict__ y, int p0, int S, int J) {
+  using V2 = typename C2<T>::type;
+  constexpr int LR = 16;
+  const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
+  const int c = lane % LR, sub = lane / LR;
+  for (int row0 = wv * (WAVE / LR); row0 < S; row0 += (NT / WAVE) * (WAVE / LR)) {
+    const int row = row0 + sub;
+    V2 s = cmk<T>(0, 0);
+    if (row < S) {
+      const V2* Vr = V + (size_t)(p0 + row) * J;
+#pragma unroll 4
+      for (int j = c; j < J; j += LR) cfma(s, Vr[j], ow[j]);
+    }
+    for (int off = LR / 2; off > 0; off >>= 1) {
+      s.x += __shfl_xor(s.x, off);
+      s.y += __shfl_xor(s.y, off);
+    }
+    if (c == 0 && row < S) {
+      V2 out = red ? red[row] : y[p0 + row];
+      out.x += s.x;
+      out.y += s.y;
+      y[p0 + row] = out;
+    }
+  }
+}
+
 template <typename T, bool RECV>
 __device__ __forceinline__ void near_leaf(const int a, typename C2<T>::type* xs, typename C2<T>::type* red, int* seg_col, int* seg_x, typename C2<T>::type* ow,
                                           const typename C2<T>::type* __restrict__ Z,
@@ -906,23 +946,7 @@ __device__ __forceinline__ void near_leaf(const int a, typename C2<T>::type* xs,
   }
   if (t < S) red[t] = yn;
   __syncthreads();
-  // reception: one wave per row
-  const int lane = t % WAVE, wv = t / WAVE;
-  for (int row = wv; row < S; row += NT / WAVE) {
-    const V2* Vr = V + (size_t)(p0 + row) * J;
-    V2 s = cmk<T>(0, 0);
-    for (int j = lane; j < J; j += WAVE) cfma(s, Vr[j], ow[j]);
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-      s.x += __shfl_xor(s.x, off);
-      s.y += __shfl_xor(s.y, off);
-    }
-    if (lane == 0) {
-      V2 out = red[row];
-      out.x += s.x;
-      out.y += s.y;
-      y[p0 + row] = out;
-    }
-  }
+  recv_rows<T>(V, ow, red, y, p0, S, J);
 }
 
 template <typename T, bool RECV>
@@ -967,22 +991,7 @@ __global__ __launch_bounds__(NT) void k_recv1(const typename C2<T>::type* __rest
     ow[j] = cmul(ov, wv);
   }
   __syncthreads();
-  const int lane = t % WAVE, wv = t / WAVE;
-  for (int row = wv; row < S; row += NT / WAVE) {
-    const V2* Vr = V + (size_t)(p0 + row) * J;
-    V2 s = cmk<T>(0, 0);
-    for (int j = lane; j < J; j += WAVE) cfma(s, Vr[j], ow[j]);
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-      s.x += __shfl_xor(s.x, off);
-      s.y += __shfl_xor(s.y, off);
-    }
-    if (lane == 0) {
-      V2 out = y[p0 + row];
-      out.x += s.x;
-      out.y += s.y;
-      y[p0 + row] = out;
-    }
-  }
+  recv_rows<T>(V, ow, nullptr, y, p0, S, J);
 }
 
 // near field only, as a persistent grid of a few workgroups per CU that walk
