@@ -480,6 +480,7 @@ def main():
                                "max": round(repeat_ms[4], 4), "blocks": 5},
         "phases": phases,
         "kernels": kernels,
+        "launches": [[k, lev, round(m, 4)] for k, lev, m in launches],
         "wall_s_timed": round(wall, 4),
         "setup_s": {k: round(v_, 2) for k, v_ in setup.items()},
         "gmres": gm,

@@ -770,17 +770,62 @@ __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_ou
                                                    int J) {
   const int a = blockIdx.x;
   const int k0 = beg[a], k1 = end[a];
-  for (int j = blockIdx.y * NT + threadIdx.x; j < J; j += gridDim.y * NT) {
-    V acc;
-    acc.x = 0;
-    acc.y = 0;
+  if constexpr (sizeof(V) == 8) {
+    // complex64: two values per 16-byte load (J is even: 4 channels per right-hand
+    // side); a row of at most 128 such pairs leaves half of the workgroup free,
+    // which then sums the odd-numbered partials (combined in a fixed order)
+    __shared__ float4 half1[NT / 2];
+    const int J2 = J / 2;
+    const float4* src = reinterpret_cast<const float4*>(pair_out);
+    float4* dst = reinterpret_cast<float4*>(o);
+    const bool split = J2 <= NT / 2 && gridDim.y == 1;     // uniform over the workgroup
+    const int t = threadIdx.x;
+    if (split) {
+      const int j = t % (NT / 2), ks = t / (NT / 2);
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j < J2) {
 #pragma unroll 8
-    for (int k = k0; k < k1; ++k) {
-      const V v = pair_out[(size_t)k * J + j];
-      acc.x += v.x;
-      acc.y += v.y;
+        for (int k = k0 + ks; k < k1; k += 2) {
+          const float4 v = src[(size_t)k * J2 + j];
+          acc.x += v.x;
+          acc.y += v.y;
+          acc.z += v.z;
+          acc.w += v.w;
+        }
+        if (ks == 1) half1[j] = acc;
+      }
+      __syncthreads();
+      if (ks == 0 && j < J2) {
+        const float4 b = half1[j];
+        dst[(size_t)a * J2 + j] = make_float4(acc.x + b.x, acc.y + b.y, acc.z + b.z, acc.w + b.w);
+      }
+    } else {
+      for (int j = blockIdx.y * NT + t; j < J2; j += gridDim.y * NT) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+        for (int k = k0; k < k1; ++k) {
+          const float4 v = src[(size_t)k * J2 + j];
+          acc.x += v.x;
+          acc.y += v.y;
+          acc.z += v.z;
+          acc.w += v.w;
+        }
+        dst[(size_t)a * J2 + j] = acc;
+      }
     }
-    o[(size_t)a * J + j] = acc;
+  } else {
+    for (int j = blockIdx.y * NT + threadIdx.x; j < J; j += gridDim.y * NT) {
+      V acc;
+      acc.x = 0;
+      acc.y = 0;
+#pragma unroll 8
+      for (int k = k0; k < k1; ++k) {
+        const V v = pair_out[(size_t)k * J + j];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      o[(size_t)a * J + j] = acc;
+    }
   }
 }
 
@@ -1460,8 +1505,9 @@ void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStr
 
 // grid of an ordered per-box sum: enough workgroups to fill the chip when
 // there are few boxes (each takes a share of the box's elements)
+// grid of k_csr_reduce for J complex64 values per row (two per thread)
 static dim3 csr_grid(int64_t nbox, int J) {
-  const int chunks = (J + NT - 1) / NT;
+  const int chunks = (J / 2 + NT - 1) / NT;
   int y = 1;
   while (y < chunks && nbox * y < 2048) ++y;
   return dim3((unsigned)nbox, (unsigned)y);
@@ -1566,6 +1612,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   if (overlap) {
     // the near field ran on the side stream: join, then add the reception
     hip_ok(hipStreamWaitEvent(st, d.ev_join, 0));
+    if (tm) tm->mark(st, -1, L, 0);     // the reception's time starts after the join
     if (R == 1)
       k_recv1<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off, d.leaf_ptr, yl, LL.Q,
                                                    (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
