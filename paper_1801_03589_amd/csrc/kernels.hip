@@ -66,6 +66,8 @@ __global__ void k_scatter(const V* __restrict__ yl, V* __restrict__ y, const int
 
 // ------------------------------------------------------------------ radiation (Eq. 10)
 // V in leaf order: row p (one RWG) holds its 4*Q coefficients contiguously.
+constexpr int MAX_QL = 256;     // equivalent sources per leaf
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_radiate(const typename C2<T>::type* __restrict__ V,
                                                 const typename C2<T>::type* __restrict__ x,
@@ -76,6 +78,64 @@ __global__ __launch_bounds__(NT) void k_radiate(const typename C2<T>::type* __re
   const int b = blockIdx.x;
   const int p0 = leaf_ptr[b], S = leaf_ptr[b + 1] - p0;
   const int J = 4 * Q;
+  if constexpr (sizeof(T) == 4) {
+    // complex64: two values of a row per 16-byte load; the even and the odd
+    // rows go to the two halves of the workgroup (summed in that order at the
+    // end), which keeps two rows of loads in flight per step
+    __shared__ float4 part[NT / 2][MAX_QL * 4 / 2 / (NT / 2)];
+    constexpr int H = NT / 2, MJ = MAX_QL * 4 / 2 / H;        // float4 per thread per row (J / 2 <= H MJ)
+    const int J2 = J / 2, t = threadIdx.x, h = t / H, c = t % H;
+    const float4* V4 = reinterpret_cast<const float4*>(V);
+    float4 acc4[MJ];
+#pragma unroll
+    for (int m = 0; m < MJ; ++m) acc4[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i0 = 0; i0 < S; i0 += NT) {
+      const int ni = min(NT, S - i0);
+      __syncthreads();
+      if (t < ni) xs[t] = x[p0 + i0 + t];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < MJ; ++m) {
+        const int j2 = c + m * H;
+        if (j2 < J2) {
+          const float4* Vp = V4 + (size_t)(p0 + i0) * J2 + j2;
+          float4 a = acc4[m];
+#pragma unroll 4
+          for (int i = h; i < ni; i += 2) {
+            const float4 v = Vp[(size_t)i * J2];
+            const V2 xv = xs[i];
+            a.x = fma(v.x, xv.x, a.x);
+            a.x = fma(-v.y, xv.y, a.x);
+            a.y = fma(v.x, xv.y, a.y);
+            a.y = fma(v.y, xv.x, a.y);
+            a.z = fma(v.z, xv.x, a.z);
+            a.z = fma(-v.w, xv.y, a.z);
+            a.w = fma(v.z, xv.y, a.w);
+            a.w = fma(v.w, xv.x, a.w);
+          }
+          acc4[m] = a;
+        }
+      }
+    }
+    __syncthreads();
+    if (h == 1) {
+#pragma unroll
+      for (int m = 0; m < MJ; ++m) part[c][m] = acc4[m];
+    }
+    __syncthreads();
+    if (h == 0) {
+      float4* s4 = reinterpret_cast<float4*>(s) + (size_t)b * J2;
+#pragma unroll
+      for (int m = 0; m < MJ; ++m) {
+        const int j2 = c + m * H;
+        if (j2 < J2) {
+          const float4 o = part[c][m];
+          s4[j2] = make_float4(acc4[m].x + o.x, acc4[m].y + o.y, acc4[m].z + o.z, acc4[m].w + o.w);
+        }
+      }
+    }
+    return;
+  }
   V2 acc[2];
   acc[0] = cmk<T>(0, 0);
   acc[1] = cmk<T>(0, 0);
@@ -271,47 +331,68 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   }
   float4 ra[NA];
   float2 rb[NBT];
-  // per-thread staging addresses, fixed over the K loop; every load reads a
-  // valid (clamped) address and invalid elements are zeroed by a 0/1 factor
-  int a_k[NA], a_off[NA];
+  // per-thread staging: element e = t + i NT of a chunk is A row pair e % HALF at
+  // k offset e / HALF, and B column e / KC at k offset e % KC.  The partial chunk
+  // (kc0 = K mod KC steps of k, or KC) goes first, so every later chunk lies
+  // inside [0, K): its loads advance plain pointers by KC steps, with no clamp
+  // and no mask of k
+  const int mr2 = g.Mr / 2;
+  const int kc0 = (K % KC) ? K % KC : KC;
+  const float4* pa[NA];
+  const float2* pb[NBT];
+  bool b_ok[NBT];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int e = t + i * NT;
-    a_k[i] = e / HALF;
-    a_off[i] = e % HALF;
+    pa[i] = A4 + (size_t)(kc0 + e / HALF) * mr2 + e % HALF;    // chunk 1
   }
-  const float2* b_ptr[NBT];
-  int b_k[NBT];
-  bool b_ok[NBT];
 #pragma unroll
   for (int i = 0; i < NBT; ++i) {
     const int e = t + i * NT;
     const int col = e / KC;
-    b_k[i] = e % KC;
-    b_ptr[i] = g.src + col_src[col];
+    pb[i] = g.src + col_src[col] + kc0 + e % KC;                 // chunk 1
     b_ok[i] = col < cnt;
   }
-  const int mr2 = g.Mr / 2;
-  // raw loads; the zero mask of k >= K and of empty columns is applied when the
-  // chunk is written to LDS, so the loads stay in flight during the MFMAs
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) ra[i] = A4[(size_t)min(k0 + a_k[i], K - 1) * mr2 + a_off[i]];
-#pragma unroll
-    for (int i = 0; i < NBT; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
-  };
-  // chunk of kc <= KC steps of k into LDS; k past the chunk and empty columns are zeroed
-  auto stage = [&](int kc) {
-    __syncthreads();
+  // chunk 0: clamped addresses (K may be below KC), zero mask at the LDS store
+  auto load_first = [&]() {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = t + i * NT;
-      As4[e / HALF][e % HALF] = a_k[i] < kc ? ra[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra[i] = A4[(size_t)min(e / HALF, K - 1) * mr2 + e % HALF];
     }
 #pragma unroll
     for (int i = 0; i < NBT; ++i) {
       const int e = t + i * NT;
-      Bs[e / KC][e % KC] = (b_k[i] < kc && b_ok[i]) ? rb[i] : make_float2(0.f, 0.f);
+      rb[i] = g.src[col_src[e / KC] + min(e % KC, K - 1)];
+    }
+  };
+  const int64_t a_step = (int64_t)KC * mr2;
+  auto load_next = [&]() {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      ra[i] = *pa[i];
+      pa[i] += a_step;
+    }
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+      rb[i] = *pb[i];
+      pb[i] += KC;
+    }
+  };
+  // the loads stay in flight during the MFMAs: their values are first used
+  // here, when the chunk (kc steps of k) is written to LDS; k past the chunk
+  // (first chunk only) and empty columns are zeroed
+  auto stage = [&](int kc, bool first) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = t + i * NT;
+      As4[e / HALF][e % HALF] = (!first || e / HALF < kc) ? ra[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+      const int e = t + i * NT;
+      Bs[e / KC][e % KC] = ((!first || e % KC < kc) && b_ok[i]) ? rb[i] : make_float2(0.f, 0.f);
     }
     __syncthreads();
   };
@@ -343,20 +424,18 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       }
     }
   };
-  // the partial chunk (K mod KC steps of k) goes first, so every later chunk is
-  // full and its step loop is unrolled: the LDS reads of later steps are issued
-  // ahead of the MFMAs of earlier ones
-  const int kc0 = (K % KC) ? K % KC : KC;
-  load(0);
-  stage(kc0);
-  if (kc0 < K) load(kc0);               // next chunk in flight during the MFMAs
+  // full chunks run their step loop unrolled: the LDS reads of later steps are
+  // issued ahead of the MFMAs of earlier ones
+  load_first();
+  stage(kc0, true);
+  if (kc0 < K) load_next();             // next chunk in flight during the MFMAs
   if (active) {
     const int ksteps = (kc0 + 3) / 4;
     for (int ks = 0; ks < ksteps; ++ks) step(ks);
   }
   for (int k0 = kc0; k0 < K; k0 += KC) {
-    stage(KC);
-    if (k0 + KC < K) load(k0 + KC);
+    stage(KC, false);
+    if (k0 + KC < K) load_next();
     if (active) {
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) step(ks);
@@ -877,28 +956,42 @@ __global__ __launch_bounds__(NT) void k_downward(const typename C2<T>::type* __r
 // groups; each thread reads Z contiguously (address k*G*S + tid).
 constexpr int NEAR_CW = 1024;   // x columns staged in LDS per pass
 constexpr int MAX_NEAR = 128;   // near-list entries per leaf
-constexpr int MAX_QL = 256;     // equivalent sources per leaf
 
 // Reception of one leaf (Eq. 14): y[p0 + r] = base_r + sum_j V[p0 + r][j] ow[j]
 // for the S rows of the leaf, with base_r = red[r] (near-field result staged in
-// LDS) or, when red is null, the value already in y.  16 lanes per row and 4
-// rows per wave: each row is read in 16-element runs, the j loop keeps several
-// loads in flight, and the row sum takes 4 shuffle steps.
+// LDS) or, when red is null, the value already in y.  8 lanes per row and 8
+// rows per wave: each lane keeps several loads of its row in flight, and the
+// row sum takes 3 shuffle steps.
 template <typename T>
 __device__ __forceinline__ void recv_rows(const typename C2<T>::type* __restrict__ V,
                                           const typename C2<T>::type* ow, const typename C2<T>::type* red,
                                           typename C2<T>::type* __restrict__ y, int p0, int S, int J) {
   using V2 = typename C2<T>::type;
-  constexpr int LR = 16;
+  constexpr int LR = 8;
   const int t = threadIdx.x, lane = t % WAVE, wv = t / WAVE;
   const int c = lane % LR, sub = lane / LR;
   for (int row0 = wv * (WAVE / LR); row0 < S; row0 += (NT / WAVE) * (WAVE / LR)) {
     const int row = row0 + sub;
     V2 s = cmk<T>(0, 0);
     if (row < S) {
-      const V2* Vr = V + (size_t)(p0 + row) * J;
+      if constexpr (sizeof(T) == 4) {
+        // complex64: two values per 16-byte load (J is even)
+        const float4* Vr = reinterpret_cast<const float4*>(V + (size_t)(p0 + row) * J);
+        const float4* ow4 = reinterpret_cast<const float4*>(ow);
+        V2 s2 = cmk<T>(0, 0);
 #pragma unroll 4
-      for (int j = c; j < J; j += LR) cfma(s, Vr[j], ow[j]);
+        for (int j = c; j < J / 2; j += LR) {
+          const float4 v = Vr[j], w = ow4[j];
+          cfma(s, make_float2(v.x, v.y), make_float2(w.x, w.y));
+          cfma(s2, make_float2(v.z, v.w), make_float2(w.z, w.w));
+        }
+        s.x += s2.x;
+        s.y += s2.y;
+      } else {
+        const V2* Vr = V + (size_t)(p0 + row) * J;
+#pragma unroll 4
+        for (int j = c; j < J; j += LR) cfma(s, Vr[j], ow[j]);
+      }
     }
     for (int off = LR / 2; off > 0; off >>= 1) {
       s.x += __shfl_xor(s.x, off);
@@ -1011,7 +1104,7 @@ __global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __
   __shared__ V2 red[NT];
   __shared__ int seg_col[MAX_NEAR + 1];
   __shared__ int seg_x[MAX_NEAR];
-  __shared__ V2 ow[4 * MAX_QL];            // weighted o_a
+  __shared__ __align__(16) V2 ow[4 * MAX_QL];            // weighted o_a
   // largest leaves first (shorter tail)
   near_leaf<T, RECV>(order[blockIdx.x], xs, red, seg_col, seg_x, ow, Z, zoff, leaf_ptr, near_ptr, near_idx, x, V, o,
                      y, Q, w_re_xyz, w_im_xyz, w_re_d, w_im_d, order);
@@ -1026,7 +1119,7 @@ __global__ __launch_bounds__(NT) void k_recv1(const typename C2<T>::type* __rest
                                               typename C2<T>::type* __restrict__ y, int Q, T w_re_xyz,
                                               T w_im_xyz, T w_re_d, T w_im_d) {
   using V2 = typename C2<T>::type;
-  __shared__ V2 ow[4 * MAX_QL];
+  __shared__ __align__(16) V2 ow[4 * MAX_QL];
   const int a = blockIdx.x;
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int J = 4 * Q, t = threadIdx.x;
