@@ -67,6 +67,11 @@ static int fail(int code, const std::string& msg) {
   return code;
 }
 
+namespace nesa {
+// error path shared with the 2D model module (sets nesa_last_error())
+int report_failure(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace nesa
+
 template <class F>
 static int guarded(F&& fn) {
   try {

@@ -61,6 +61,19 @@ class AdamParams(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
 
+class Model2DParams(C.Structure):
+    _fields_ = [("P", C.c_int), ("Q", C.c_int), ("tau", C.c_double)]
+
+
+MODEL2D_MAX_LEVELS = 24
+
+
+class Model2DInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("l0", C.c_int), ("L", C.c_int), ("Q", C.c_int),
+                ("n_box", C.c_int64 * MODEL2D_MAX_LEVELS), ("n_far", C.c_int64 * MODEL2D_MAX_LEVELS),
+                ("near_pairs", C.c_int64), ("max_leaf", C.c_int64)]
+
+
 _P = C.c_void_p
 _SIGS = {
     "nesa_build_tree": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(TreeParams), C.POINTER(_P)]),
@@ -100,6 +113,11 @@ _SIGS = {
     "nesa_op_set_mlp": (C.c_int, [_P, _P]),
     "nesa_residual_error": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "nesa_last_error": (C.c_char_p, []),
+    "nesa2d_create": (C.c_int, [_P, C.c_int64, C.POINTER(Model2DParams), C.POINTER(_P)]),
+    "nesa2d_info_get": (C.c_int, [_P, C.POINTER(Model2DInfo)]),
+    "nesa2d_perm": (C.c_int, [_P, _P]),
+    "nesa2d_matvec": (C.c_int, [_P, _P, _P, _P]),
+    "nesa2d_free": (C.c_int, [_P]),
 }
 
 _lib = None
@@ -409,3 +427,39 @@ def solve_pairs(op, b, xs, iters, restart, precond):
             gmres_solve(op, b, x, restart=restart, max_iters=k, tol=1e-12, precond=precond, check=False)
         residual_error(op, b, xs, x, R[i], E[i])
     return R, E
+
+
+class Model2D:
+    """NESA operator of the 2D potential problem phi = K q, k_ij = -log|x_i - x_j|
+    (real FP64; tree, matrices and conventions in include/nesa2d.h)."""
+
+    def __init__(self, xy, P, Q, tau=1e-12):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        if xy.ndim != 2 or xy.shape[1] != 2:
+            raise NesaError(-1, "xy must be an (n, 2) array")
+        h = _P()
+        prm = Model2DParams(int(P), int(Q), float(tau))
+        _check(lib().nesa2d_create(_ptr(xy), len(xy), C.byref(prm), C.byref(h)))
+        self.h = h
+
+    def info(self):
+        inf = Model2DInfo()
+        _check(lib().nesa2d_info_get(self.h, C.byref(inf)))
+        nl = inf.L - inf.l0 + 1
+        return {"n": inf.n, "l0": inf.l0, "L": inf.L, "Q": inf.Q, "n_box": list(inf.n_box[:nl]),
+                "n_far": list(inf.n_far[:nl]), "near_pairs": inf.near_pairs, "max_leaf": inf.max_leaf}
+
+    def perm(self):
+        out = np.zeros(self.info()["n"], dtype=np.int32)
+        _check(lib().nesa2d_perm(self.h, _ptr(out)))
+        return out
+
+    def matvec(self, q, phi, stream=None):
+        """phi = K_NESA q for float64 device tensors of n entries."""
+        _check(lib().nesa2d_matvec(self.h, _dptr(q), _dptr(phi), _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.nesa2d_free(h)
+            self.h = None

@@ -23,9 +23,12 @@ def nesa():
 
 
 def test_every_declared_symbol_is_exported(nesa):
-    hdr = open(os.path.join(ROOT, "include", "nesa.h")).read()
-    names = set(re.findall(r"\b(nesa_[a-z0-9_]+)\s*\(", hdr))
+    import glob
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        names |= set(re.findall(r"\b(nesa2?d?_[a-z0-9_]+)\s*\(", open(h).read()))
     assert len(names) > 15
+    assert {"nesa2d_create", "nesa2d_matvec", "nesa2d_free"} <= names
     so = ctypes.CDLL(nesa.LIB_PATH)
     for name in sorted(names):
         assert hasattr(so, name), name
