@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--bodies", type=int, default=32,
                    help="uneven bodies in the batched-forest line (256: the full batch; 0: skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--only-model2d", action="store_true",
+                   help="time only the 2D model problem (paper's own workload) and print its section")
     p.add_argument("--cpu-sample-leaves", type=int, default=24)
     return p.parse_args()
 
@@ -262,6 +264,50 @@ def batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream):
             "Munknowns_matvec_per_s": round(n * args.nrhs / (ms * 1e-3) / 1e6, 2)}
 
 
+# The paper's own timed workload (2D model problem, N = 100 000, real FP64):
+# best complete-product times it prints, with their hardware (context only)
+PAPER_2D = {(50, 10): (100.0, "64 Xeon E5-4650 cores, SuperGlue"),
+            (300, 100): (127.0, "64 Xeon E5-4650 cores, SuperGlue"),
+            (400, 100): (None, "no complete-product time printed")}
+
+
+def model2d_section(args, nesa, torch, stream):
+    """The 2D potential problem at the paper's size and (P, Q) settings: one NESA
+    product per step (near field + five far-field stages), charges resident on
+    the GPU; the seeded curve stands in for the paper's (unpublished) one."""
+    import synth
+    n = 100000
+    xy = synth.smooth_curve(n, 23)
+    q = torch.from_numpy(synth.real_normal(n, 24)).cuda()
+    phi = torch.empty_like(q)
+    out = []
+    for P, Q in ((50, 10), (300, 100), (400, 100)):
+        t0 = time.perf_counter()
+        op = nesa.Model2D(xy, P, Q)
+        build = time.perf_counter() - t0
+        info = op.info()
+        for _ in range(5):
+            op.matvec(q, phi, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            op.matvec(q, phi, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        paper_ms, hw = PAPER_2D[(P, Q)]
+        out.append({"P": P, "Q": Q, "levels": [info["l0"], info["L"]], "boxes": info["n_box"],
+                    "near_pairs": info["near_pairs"], "ms_per_product": round(ms, 4),
+                    "Munknowns_per_s": round(n / (ms * 1e-3) / 1e6, 2),
+                    "near_Gpairs_per_s": round(info["near_pairs"] / (ms * 1e-3) / 1e9, 1),
+                    "build_s": round(build, 2), "paper_best_ms": paper_ms, "paper_hardware": hw})
+        log("2D model P %d Q %d: %.4f ms per product" % (P, Q, ms))
+        del op
+    return {"n": n, "dtype": "f64", "runs": out}
+
+
 def bodies_section(args, nesa, torch, prec, dt, stream):
     """A batch of uneven seeded bodies (spheroids, boxes, capped cylinders with
     2k to 50k unknowns, log-uniform) in one forest operator: every stage is one
@@ -315,6 +361,9 @@ def main():
     import synth
     from paper_1801_03589_amd import nesa
 
+    if args.only_model2d:
+        print(json.dumps({"model2d": model2d_section(args, nesa, torch, torch.cuda.current_stream())}))
+        return
     prec = {"c64": nesa.C64, "c128": nesa.C128, "split": nesa.C64_SPLIT}[args.precision]
     esize = 16 if prec == nesa.C128 else 8
     dt = torch.complex128 if prec == nesa.C128 else torch.complex64
@@ -447,7 +496,7 @@ def main():
         phases[k] = {"ms": phase_ms[k], "GB/s": round(alg[k]["bytes"] / s_ / 1e9, 1),
                      "TFLOP/s": round(alg[k]["flops"] / s_ / 1e12, 2)}
     log("product: %.4f ms (%.1f Munknowns/s)" % (ms, value))
-    gm = batched = bodies = None
+    gm = batched = bodies = model2d = None
     if not args.only_product:
         gm = gmres_section(args, nesa, torch, op, info, x, stream)
         log("GMRES done; batched right-hand sides")
@@ -455,6 +504,8 @@ def main():
         del op
         log("batch of %d bodies" % args.bodies)
         bodies = bodies_section(args, nesa, torch, prec, dt, stream)
+        log("2D model problem")
+        model2d = model2d_section(args, nesa, torch, stream)
     out = {
         "metric": "NESA matvec Munknowns/s",
         "value": round(value, 3),
@@ -486,6 +537,7 @@ def main():
         "gmres": gm,
         "batched": batched,
         "bodies": bodies,
+        "model2d": model2d,
     }
     if not args.no_cpu_baseline and not args.only_product:
         log("CPU oracle sample")

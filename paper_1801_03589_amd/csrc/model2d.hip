@@ -263,130 +263,218 @@ Mat tikhonov(const Mat& G, int M, int Q, double tau) {
 }
 
 // ------------------------------------------------------------------ device kernels
-// near field (Eq. algnf): one workgroup per finest-level group; the points and
-// charges of each near group are staged in LDS; k_ii = 0 by point identity
-__global__ __launch_bounds__(NT2) void k2_near(const double2* __restrict__ xy, const double* __restrict__ q,
-                                               const int32_t* __restrict__ leaf_ptr,
-                                               const int32_t* __restrict__ near_ptr,
-                                               const int32_t* __restrict__ near_idx, double* __restrict__ phi) {
-  __shared__ double2 sx[NT2];
-  __shared__ double sq[NT2];
+// near blocks (Eq. algnf), assembled once on the device: leaf a holds one
+// column-major block of n_a rows and W_a = sum of its near groups' sizes
+// columns (near groups in list order); k_ii = 0 by point identity
+__global__ __launch_bounds__(NT2) void k2_near_fill(const double2* __restrict__ xy,
+                                                    const int32_t* __restrict__ leaf_ptr,
+                                                    const int32_t* __restrict__ near_ptr,
+                                                    const int32_t* __restrict__ near_idx,
+                                                    const int64_t* __restrict__ zoff, double* __restrict__ Z) {
+  __shared__ int seg_col[10], seg_pt[10];
   const int a = blockIdx.x, t = threadIdx.x;
   const int p0 = leaf_ptr[a], na = leaf_ptr[a + 1] - p0;
-  for (int i0 = 0; i0 < na; i0 += NT2) {
-    const int i = i0 + t;
-    const bool act = i < na;
-    const double2 xi = act ? xy[p0 + i] : make_double2(0.0, 0.0);
-    double acc = 0.0;
-    for (int k = near_ptr[a]; k < near_ptr[a + 1]; ++k) {
-      const int b = near_idx[k];
-      const int s0 = leaf_ptr[b], nb = leaf_ptr[b + 1] - s0;
-      for (int j0 = 0; j0 < nb; j0 += NT2) {
-        const int cnt = min(NT2, nb - j0);
-        __syncthreads();
-        if (t < cnt) {
-          sx[t] = xy[s0 + j0 + t];
-          sq[t] = q[s0 + j0 + t];
-        }
-        __syncthreads();
-        if (act) {
-          const int self = (b == a) ? i - j0 : -1;     // local index of the target itself, if staged
-          for (int j = 0; j < cnt; ++j) {
-            const double dx = xi.x - sx[j].x, dy = xi.y - sx[j].y;
-            const double r2 = (j == self) ? 1.0 : dx * dx + dy * dy;
-            acc += sq[j] * (-0.5 * log(r2));
-          }
-        }
-      }
+  const int k0 = near_ptr[a], nn = near_ptr[a + 1] - k0;      // nn <= 9
+  if (t == 0) {
+    int c = 0;
+    for (int k = 0; k < nn; ++k) {
+      const int b = near_idx[k0 + k];
+      seg_col[k] = c;
+      seg_pt[k] = leaf_ptr[b];
+      c += leaf_ptr[b + 1] - leaf_ptr[b];
     }
-    if (act) phi[p0 + i] = acc;
+    seg_col[nn] = c;
+  }
+  __syncthreads();
+  const int W = seg_col[nn];
+  double* Za = Z + zoff[a];
+  for (int64_t e = t; e < (int64_t)na * W; e += NT2) {
+    const int col = (int)(e / na), i = (int)(e % na);
+    int k = 0;
+    while (seg_col[k + 1] <= col) ++k;
+    const int j = seg_pt[k] + (col - seg_col[k]);             // source point (group order)
+    const double2 xi = xy[p0 + i], xj = xy[j];
+    const double dx = xi.x - xj.x, dy = xi.y - xj.y;
+    Za[e] = (p0 + i == j) ? 0.0 : -0.5 * log(dx * dx + dy * dy);
+  }
+}
+
+// near-field product (Eq. algnf): phi_a = Z_a [q of the near groups].  A
+// workgroup takes up to 64 rows of one group (grid y = row chunks); thread
+// (row i, column group g) sums the columns g, g + G, ...; the G partial sums
+// are added in a fixed order
+constexpr int NEAR_CW = 1024;      // columns of q staged in LDS at a time
+constexpr int NEAR_RW = 64;        // rows per workgroup
+__global__ __launch_bounds__(NT2) void k2_near(const double* __restrict__ Z, const int64_t* __restrict__ zoff,
+                                               const int32_t* __restrict__ leaf_ptr,
+                                               const int32_t* __restrict__ near_ptr,
+                                               const int32_t* __restrict__ near_idx, const double* __restrict__ q,
+                                               double* __restrict__ phi) {
+  __shared__ double qs[NEAR_CW];
+  __shared__ double red[NT2];
+  __shared__ int seg_col[10], seg_pt[10];
+  const int a = blockIdx.x, t = threadIdx.x;
+  const int p0 = leaf_ptr[a], na = leaf_ptr[a + 1] - p0;
+  const int r0 = blockIdx.y * NEAR_RW;
+  if (r0 >= na) return;                                        // whole workgroup
+  const int nr = min(NEAR_RW, na - r0);
+  const int G = NT2 / nr;                                      // column groups
+  const int k0 = near_ptr[a], nn = near_ptr[a + 1] - k0;
+  if (t == 0) {
+    int c = 0;
+    for (int k = 0; k < nn; ++k) {
+      const int b = near_idx[k0 + k];
+      seg_col[k] = c;
+      seg_pt[k] = leaf_ptr[b];
+      c += leaf_ptr[b + 1] - leaf_ptr[b];
+    }
+    seg_col[nn] = c;
+  }
+  __syncthreads();
+  const int W = seg_col[nn];
+  const int i = r0 + t % nr, g = t / nr;
+  const double* Za = Z + zoff[a];
+  double acc = 0.0;
+  for (int c0 = 0; c0 < W; c0 += NEAR_CW) {
+    const int cw = min(NEAR_CW, W - c0);
+    __syncthreads();
+    for (int c = t; c < cw; c += NT2) {
+      const int col = c0 + c;
+      int k = 0;
+      while (seg_col[k + 1] <= col) ++k;
+      qs[c] = q[seg_pt[k] + (col - seg_col[k])];
+    }
+    __syncthreads();
+    if (g < G) {
+      const double* Zc = Za + (size_t)c0 * na + i;
+#pragma unroll 8
+      for (int c = g; c < cw; c += G) acc += Zc[(size_t)c * na] * qs[c];
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < nr) {
+    double y = red[t];
+    for (int gg = 1; gg < G; ++gg) y += red[gg * nr + t];
+    phi[p0 + r0 + t] = y;
+  }
+}
+
+// The far-field kernels below take one box per workgroup of NT2 threads:
+// thread t owns output row t % Q and reduction slice g = t / Q of G = NT2 / Q
+// slices (every G-th term of the sum); the G partial sums of a row are added in
+// slice order, so results do not depend on timing.
+template <int NT = NT2>
+__device__ __forceinline__ void slice_sum_store(double acc, double* red, double* out, int Q, bool add) {
+  const int t = threadIdx.x, G = NT / Q;
+  red[t] = acc;
+  __syncthreads();
+  if (t < Q) {
+    double y = red[t];
+    for (int g = 1; g < G; ++g) y += red[g * Q + t];
+    out[t] = add ? out[t] + y : y;
   }
 }
 
 // radiation (Eq. algrad): s_b[k] = sum_j V_b[j][k] q_j (V stored point-major)
-__global__ __launch_bounds__(QMAX) void k2_radiate(const double* __restrict__ V, const int64_t* __restrict__ voff,
-                                                   const int32_t* __restrict__ leaf_ptr,
-                                                   const double* __restrict__ q, double* __restrict__ s, int Q) {
-  const int b = blockIdx.x, k = threadIdx.x;
-  if (k >= Q) return;
+__global__ __launch_bounds__(NT2) void k2_radiate(const double* __restrict__ V, const int64_t* __restrict__ voff,
+                                                  const int32_t* __restrict__ leaf_ptr,
+                                                  const double* __restrict__ q, double* __restrict__ s, int Q) {
+  __shared__ double red[NT2];
+  const int b = blockIdx.x, t = threadIdx.x, G = NT2 / Q, k = t % Q, g = t / Q;
   const int p0 = leaf_ptr[b], nb = leaf_ptr[b + 1] - p0;
   const double* Vb = V + voff[b];
   double acc = 0.0;
-  for (int j = 0; j < nb; ++j) acc += Vb[(size_t)j * Q + k] * q[p0 + j];
-  s[(size_t)b * Q + k] = acc;
+  if (g < G) {
+#pragma unroll 4
+    for (int j = g; j < nb; j += G) acc += Vb[(size_t)j * Q + k] * q[p0 + j];
+  }
+  slice_sum_store(acc, red, s + (size_t)b * Q, Q, false);
 }
 
-// source transfer (Eq. algsou), one parent per workgroup, children in quadrant
-// order: s_P[p] = sum_c sum_r C_quad[p][r] s_c[r] (C stored column-major)
-__global__ __launch_bounds__(QMAX) void k2_upward(const double* __restrict__ Ccm, const int32_t* __restrict__ child,
-                                                  const double* __restrict__ s_child, double* __restrict__ s_par,
-                                                  int Q) {
-  const int P = blockIdx.x, p = threadIdx.x;
-  if (p >= Q) return;
+// source transfer (Eq. algsou), one parent per workgroup, terms (child quadrant,
+// r): s_P[p] = sum_c sum_r C_quad[p][r] s_c[r] (C stored column-major)
+__global__ __launch_bounds__(NT2) void k2_upward(const double* __restrict__ Ccm, const int32_t* __restrict__ child,
+                                                 const double* __restrict__ s_child, double* __restrict__ s_par,
+                                                 int Q) {
+  __shared__ double red[NT2];
+  const int P = blockIdx.x, t = threadIdx.x, G = NT2 / Q, p = t % Q, g = t / Q;
   double acc = 0.0;
-  for (int c = 0; c < 4; ++c) {
-    const int ch = child[4 * P + c];
-    if (ch < 0) continue;
-    const double* C = Ccm + (size_t)c * Q * Q;
-    const double* sc = s_child + (size_t)ch * Q;
-    for (int r = 0; r < Q; ++r) acc += C[(size_t)r * Q + p] * sc[r];
+  if (g < G) {
+    for (int c = 0; c < 4; ++c) {
+      const int ch = child[4 * P + c];
+      if (ch < 0) continue;
+      const double* C = Ccm + (size_t)c * Q * Q;
+      const double* sc = s_child + (size_t)ch * Q;
+#pragma unroll 4
+      for (int r = g; r < Q; r += G) acc += C[(size_t)r * Q + p] * sc[r];
+    }
   }
-  s_par[(size_t)P * Q + p] = acc;
+  slice_sum_store(acc, red, s_par + (size_t)P * Q, Q, false);
 }
 
 // translation (Eq. algtrans): o_a[p] = sum_{b in far(a)} sum_r D_off[p][r] s_b[r]
-// (D stored column-major per offset slot)
-__global__ __launch_bounds__(QMAX) void k2_translate(const double* __restrict__ Dcm,
-                                                     const int32_t* __restrict__ il_ptr,
-                                                     const int32_t* __restrict__ il_src,
-                                                     const int32_t* __restrict__ il_off,
-                                                     const double* __restrict__ s, double* __restrict__ o, int Q) {
-  const int a = blockIdx.x, p = threadIdx.x;
-  if (p >= Q) return;
+// (D stored column-major per offset slot); 1024 threads per box, so that every
+// thread's chain of terms stays short
+constexpr int NT_TR = 1024;
+__global__ __launch_bounds__(NT_TR) void k2_translate(const double* __restrict__ Dcm,
+                                                      const int32_t* __restrict__ il_ptr,
+                                                      const int32_t* __restrict__ il_src,
+                                                      const int32_t* __restrict__ il_off,
+                                                      const double* __restrict__ s, double* __restrict__ o, int Q) {
+  __shared__ double red[NT_TR];
+  const int a = blockIdx.x, t = threadIdx.x, G = NT_TR / Q, p = t % Q, g = t / Q;
   double acc = 0.0;
-  for (int k = il_ptr[a]; k < il_ptr[a + 1]; ++k) {
-    const double* D = Dcm + (size_t)il_off[k] * Q * Q;
-    const double* sb = s + (size_t)il_src[k] * Q;
-    for (int r = 0; r < Q; ++r) acc += D[(size_t)r * Q + p] * sb[r];
+  if (g < G) {
+    for (int k = il_ptr[a]; k < il_ptr[a + 1]; ++k) {
+      const double* D = Dcm + (size_t)il_off[k] * Q * Q;
+      const double* sb = s + (size_t)il_src[k] * Q;
+#pragma unroll 4
+      for (int r = g; r < Q; r += G) acc += D[(size_t)r * Q + p] * sb[r];
+    }
   }
-  o[(size_t)a * Q + p] = acc;
+  slice_sum_store<NT_TR>(acc, red, o + (size_t)a * Q, Q, false);
 }
 
 // potential transfer (Eq. algpot): o_c[p] += sum_r B_quad[p][r] o_P[r], B = C^T
 // (stored column-major, i.e. C row-major)
-__global__ __launch_bounds__(QMAX) void k2_downward(const double* __restrict__ Bcm, const int32_t* __restrict__ parent,
-                                                    const int32_t* __restrict__ quad,
-                                                    const double* __restrict__ o_par, double* __restrict__ o_child,
-                                                    int Q) {
-  const int c = blockIdx.x, p = threadIdx.x;
-  if (p >= Q) return;
-  const double* B = Bcm + (size_t)quad[c] * Q * Q;
-  const double* op = o_par + (size_t)parent[c] * Q;
-  double acc = o_child[(size_t)c * Q + p];
-  for (int r = 0; r < Q; ++r) acc += B[(size_t)r * Q + p] * op[r];
-  o_child[(size_t)c * Q + p] = acc;
+__global__ __launch_bounds__(NT2) void k2_downward(const double* __restrict__ Bcm, const int32_t* __restrict__ parent,
+                                                   const int32_t* __restrict__ quad,
+                                                   const double* __restrict__ o_par, double* __restrict__ o_child,
+                                                   int Q) {
+  __shared__ double red[NT2];
+  const int c = blockIdx.x, t = threadIdx.x, G = NT2 / Q, p = t % Q, g = t / Q;
+  double acc = 0.0;
+  if (g < G) {
+    const double* B = Bcm + (size_t)quad[c] * Q * Q;
+    const double* op = o_par + (size_t)parent[c] * Q;
+#pragma unroll 4
+    for (int r = g; r < Q; r += G) acc += B[(size_t)r * Q + p] * op[r];
+  }
+  slice_sum_store(acc, red, o_child + (size_t)c * Q, Q, true);
 }
 
-// reception (Eq. algrec): phi_j += sum_k V_b[j][k] o_b[k], U = V^T; 16 lanes per point
+// reception (Eq. algrec): phi_j += sum_k V_b[j][k] o_b[k], U = V^T; 16 lanes
+// per point, 16 points per workgroup (grid y = chunks of points)
 __global__ __launch_bounds__(NT2) void k2_receive(const double* __restrict__ V, const int64_t* __restrict__ voff,
                                                   const int32_t* __restrict__ leaf_ptr,
                                                   const double* __restrict__ o, double* __restrict__ phi, int Q) {
   __shared__ double ob[QMAX];
+  constexpr int LP = 16;
   const int b = blockIdx.x, t = threadIdx.x;
+  const int p0 = leaf_ptr[b], nb = leaf_ptr[b + 1] - p0;
+  const int j = blockIdx.y * (NT2 / LP) + t / LP, c = t % LP;
+  if ((int)blockIdx.y * (NT2 / LP) >= nb) return;              // whole workgroup
   if (t < Q) ob[t] = o[(size_t)b * Q + t];
   __syncthreads();
-  const int p0 = leaf_ptr[b], nb = leaf_ptr[b + 1] - p0;
   const double* Vb = V + voff[b];
-  constexpr int LP = 16;
-  const int c = t % LP, sub = t / LP;
-  for (int j0 = 0; j0 < nb; j0 += NT2 / LP) {
-    const int j = j0 + sub;
-    double acc = 0.0;
-    if (j < nb)
-      for (int k = c; k < Q; k += LP) acc += Vb[(size_t)j * Q + k] * ob[k];
-    for (int off = LP / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (c == 0 && j < nb) phi[p0 + j] += acc;
+  double acc = 0.0;
+  if (j < nb) {
+#pragma unroll 4
+    for (int k = c; k < Q; k += LP) acc += Vb[(size_t)j * Q + k] * ob[k];
   }
+  for (int off = LP / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (c == 0 && j < nb) phi[p0 + j] += acc;
 }
 
 __global__ void k2_gather(const double* __restrict__ x, double* __restrict__ xl, const int32_t* __restrict__ perm,
@@ -423,6 +511,8 @@ struct nesa2d {
   double* V = nullptr;
   int64_t* voff = nullptr;
   int32_t *perm = nullptr, *leaf_ptr = nullptr, *near_ptr = nullptr, *near_idx = nullptr;
+  double* Z = nullptr;            // near blocks
+  int64_t* zoff = nullptr;        // [nleaf] block offsets
   ~nesa2d() {
     (void)hipDeviceSynchronize();
     for (void* p : allocs) (void)hipFree(p);
@@ -526,6 +616,22 @@ extern "C" nesa_status nesa2d_create(const double* xy, int64_t n, const nesa2d_p
     h->near_idx = h->upload(t.near_idx);
     h->ql = h->alloc<double>(n);
     h->phil = h->alloc<double>(n);
+    {
+      std::vector<int64_t> zoff(nleaf);
+      int64_t tot = 0;
+      for (int64_t a = 0; a < nleaf; ++a) {
+        zoff[a] = tot;
+        int64_t W = 0;
+        for (int k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k)
+          W += t.leaf_ptr[t.near_idx[k] + 1] - t.leaf_ptr[t.near_idx[k]];
+        tot += (int64_t)(t.leaf_ptr[a + 1] - t.leaf_ptr[a]) * W;
+      }
+      h->zoff = h->upload(zoff);
+      h->Z = h->alloc<double>((size_t)tot);
+      k2_near_fill<<<(unsigned)nleaf, NT2>>>(h->xy, h->leaf_ptr, h->near_ptr, h->near_idx, h->zoff, h->Z);
+      hip_ok2(hipGetLastError(), "near block assembly");
+      hip_ok2(hipDeviceSynchronize(), "near block assembly");
+    }
     h->lev.resize(nl);
     for (int i = 0; i < nl; ++i) {
       const Level2& lv = t.lev[i];
@@ -625,18 +731,21 @@ extern "C" nesa_status nesa2d_matvec(nesa2d* h, const double* q, double* phi, vo
     const unsigned nleaf = (unsigned)(t.leaf_ptr.size() - 1);
     const unsigned gb = (unsigned)((n + 255) / 256);
     k2_gather<<<gb, 256, 0, st>>>(q, h->ql, h->perm, n);
-    k2_near<<<nleaf, NT2, 0, st>>>(h->xy, h->ql, h->leaf_ptr, h->near_ptr, h->near_idx, h->phil);
-    k2_radiate<<<nleaf, QMAX, 0, st>>>(h->V, h->voff, h->leaf_ptr, h->ql, h->lev[nl - 1].s, Q);
+    const unsigned rchunks = (unsigned)((h->info.max_leaf + NEAR_RW - 1) / NEAR_RW);
+    k2_near<<<dim3(nleaf, rchunks), NT2, 0, st>>>(h->Z, h->zoff, h->leaf_ptr, h->near_ptr, h->near_idx, h->ql,
+                                                  h->phil);
+    k2_radiate<<<nleaf, NT2, 0, st>>>(h->V, h->voff, h->leaf_ptr, h->ql, h->lev[nl - 1].s, Q);
     for (int i = nl - 1; i > 0; --i)
-      k2_upward<<<(unsigned)h->lev[i - 1].nbox, QMAX, 0, st>>>(h->lev[i].Ccm, h->lev[i - 1].child, h->lev[i].s,
+      k2_upward<<<(unsigned)h->lev[i - 1].nbox, NT2, 0, st>>>(h->lev[i].Ccm, h->lev[i - 1].child, h->lev[i].s,
                                                                h->lev[i - 1].s, Q);
     for (int i = 0; i < nl; ++i)
-      k2_translate<<<(unsigned)h->lev[i].nbox, QMAX, 0, st>>>(h->lev[i].Dcm, h->lev[i].il_ptr, h->lev[i].il_src,
+      k2_translate<<<(unsigned)h->lev[i].nbox, NT_TR, 0, st>>>(h->lev[i].Dcm, h->lev[i].il_ptr, h->lev[i].il_src,
                                                               h->lev[i].il_off, h->lev[i].s, h->lev[i].o, Q);
     for (int i = 1; i < nl; ++i)
-      k2_downward<<<(unsigned)h->lev[i].nbox, QMAX, 0, st>>>(h->lev[i].Bcm, h->lev[i].parent, h->lev[i].quad,
+      k2_downward<<<(unsigned)h->lev[i].nbox, NT2, 0, st>>>(h->lev[i].Bcm, h->lev[i].parent, h->lev[i].quad,
                                                              h->lev[i - 1].o, h->lev[i].o, Q);
-    k2_receive<<<nleaf, NT2, 0, st>>>(h->V, h->voff, h->leaf_ptr, h->lev[nl - 1].o, h->phil, Q);
+    k2_receive<<<dim3(nleaf, (unsigned)((h->info.max_leaf + 15) / 16)), NT2, 0, st>>>(h->V, h->voff, h->leaf_ptr,
+                                                                                     h->lev[nl - 1].o, h->phil, Q);
     k2_scatter<<<gb, 256, 0, st>>>(h->phil, phi, h->perm, n);
     hip_ok2(hipGetLastError(), "kernel launch");
     return NESA_OK;
