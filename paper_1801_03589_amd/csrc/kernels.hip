@@ -441,26 +441,43 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
       for (int ks = 0; ks < KC / 4; ++ks) step(ks);
     }
   }
-  // accumulator layout: lane -> column lane % 16 of the wave's tile, rows 4 * (lane / 16) + i
-  const int col = ct * 16 + lane % 16;
-  if (col < cnt) {
-    float2* out = g.dst + col_dst[col];
+  // Output through LDS: the accumulators (lane -> column lane % 16 of the
+  // wave's tile, rows 4 (lane / 16) + i) go to a [column][row] tile in the A
+  // chunk buffer (row stride ROWS + 2), then the workgroup writes runs of
+  // consecutive rows of each column, so a store instruction fills whole cache
+  // lines instead of 32 bytes of 16 lines.  Columns go in passes of PC.
+  constexpr int ROWS = NRT * 16;
+  constexpr int RS = ROWS + 2;                                   // float2
+  constexpr int ACAP = KC * (HALF + APAD) * 2;                   // float2 in As4
+  constexpr int PC = (ACAP / RS) >= COLS ? COLS : (ACAP / RS) / 16 * 16;
+  static_assert(PC >= 16, "the LDS tile must hold one column tile");
+  float2* otile = reinterpret_cast<float2*>(&As4[0][0]);
+  const int mloc = min(ROWS, M - r0);
+  for (int c0 = 0; c0 < COLS; c0 += PC) {
+    __syncthreads();                                             // LDS no longer read
+    if (ct * 16 >= c0 && ct * 16 < c0 + PC) {
+      const int lc = ct * 16 - c0 + lane % 16;
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
+      for (int r = 0; r < RPW; ++r) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = r0 + (rt0 + r) * 16 + 4 * (lane / 16) + i;
-        if (row < M) {
-          float2 v = M3 ? make_float2(cre[r][i] - cim[r][i], c3[r][i] - cre[r][i] - cim[r][i])
-                        : make_float2(cre[r][i], cim[r][i]);
-          if (g.accumulate) {
-            const float2 o = out[row];
-            v.x += o.x;
-            v.y += o.y;
-          }
-          out[row] = v;
-        }
+        for (int i = 0; i < 4; ++i)
+          otile[lc * RS + (rt0 + r) * 16 + 4 * (lane / 16) + i] =
+              M3 ? make_float2(cre[r][i] - cim[r][i], c3[r][i] - cre[r][i] - cim[r][i])
+                 : make_float2(cre[r][i], cim[r][i]);
       }
+    }
+    __syncthreads();
+    const int ncols = min(PC, cnt - c0);
+    for (int e = t; e < ncols * mloc; e += NT) {
+      const int lc = e / mloc, row = e % mloc;
+      float2 v = otile[lc * RS + row];
+      float2* out = g.dst + col_dst[c0 + lc] + r0 + row;
+      if (g.accumulate) {
+        const float2 o = *out;
+        v.x += o.x;
+        v.y += o.y;
+      }
+      *out = v;
     }
   }
 }
