@@ -414,26 +414,40 @@ __global__ __launch_bounds__(NT2) void k2_upward(const double* __restrict__ Ccm,
 }
 
 // translation (Eq. algtrans): o_a[p] = sum_{b in far(a)} sum_r D_off[p][r] s_b[r]
-// (D stored column-major per offset slot); 1024 threads per box, so that every
-// thread's chain of terms stays short
+// (D stored column-major per offset slot); one launch for every level (the
+// levels are independent): workgroup = box of the concatenated level ranges;
+// 1024 threads per box, so that every thread's chain of terms stays short
 constexpr int NT_TR = 1024;
-__global__ __launch_bounds__(NT_TR) void k2_translate(const double* __restrict__ Dcm,
-                                                      const int32_t* __restrict__ il_ptr,
-                                                      const int32_t* __restrict__ il_src,
-                                                      const int32_t* __restrict__ il_off,
-                                                      const double* __restrict__ s, double* __restrict__ o, int Q) {
+struct TransLevels {
+  int n;                                         // levels
+  int64_t box0[NESA2D_MAX_LEVELS + 1];           // first box of each level in the grid
+  const double* Dcm[NESA2D_MAX_LEVELS];
+  const int32_t* il_ptr[NESA2D_MAX_LEVELS];
+  const int32_t* il_src[NESA2D_MAX_LEVELS];
+  const int32_t* il_off[NESA2D_MAX_LEVELS];
+  const double* s[NESA2D_MAX_LEVELS];
+  double* o[NESA2D_MAX_LEVELS];
+};
+__global__ __launch_bounds__(NT_TR) void k2_translate(TransLevels tl, int Q) {
   __shared__ double red[NT_TR];
-  const int a = blockIdx.x, t = threadIdx.x, G = NT_TR / Q, p = t % Q, g = t / Q;
+  int lv = 0;
+  while (lv + 1 < tl.n && (int64_t)blockIdx.x >= tl.box0[lv + 1]) ++lv;
+  const int a = (int)((int64_t)blockIdx.x - tl.box0[lv]);
+  const int t = threadIdx.x, G = NT_TR / Q, p = t % Q, g = t / Q;
+  const double* Dcm = tl.Dcm[lv];
+  const double* s = tl.s[lv];
+  const int32_t* il_src = tl.il_src[lv];
+  const int32_t* il_off = tl.il_off[lv];
   double acc = 0.0;
   if (g < G) {
-    for (int k = il_ptr[a]; k < il_ptr[a + 1]; ++k) {
+    for (int k = tl.il_ptr[lv][a]; k < tl.il_ptr[lv][a + 1]; ++k) {
       const double* D = Dcm + (size_t)il_off[k] * Q * Q;
       const double* sb = s + (size_t)il_src[k] * Q;
 #pragma unroll 4
       for (int r = g; r < Q; r += G) acc += D[(size_t)r * Q + p] * sb[r];
     }
   }
-  slice_sum_store<NT_TR>(acc, red, o + (size_t)a * Q, Q, false);
+  slice_sum_store<NT_TR>(acc, red, tl.o[lv] + (size_t)a * Q, Q, false);
 }
 
 // potential transfer (Eq. algpot): o_c[p] += sum_r B_quad[p][r] o_P[r], B = C^T
@@ -738,9 +752,21 @@ extern "C" nesa_status nesa2d_matvec(nesa2d* h, const double* q, double* phi, vo
     for (int i = nl - 1; i > 0; --i)
       k2_upward<<<(unsigned)h->lev[i - 1].nbox, NT2, 0, st>>>(h->lev[i].Ccm, h->lev[i - 1].child, h->lev[i].s,
                                                                h->lev[i - 1].s, Q);
-    for (int i = 0; i < nl; ++i)
-      k2_translate<<<(unsigned)h->lev[i].nbox, NT_TR, 0, st>>>(h->lev[i].Dcm, h->lev[i].il_ptr, h->lev[i].il_src,
-                                                              h->lev[i].il_off, h->lev[i].s, h->lev[i].o, Q);
+    {
+      TransLevels tl{};
+      tl.n = nl;
+      tl.box0[0] = 0;
+      for (int i = 0; i < nl; ++i) {
+        tl.box0[i + 1] = tl.box0[i] + h->lev[i].nbox;
+        tl.Dcm[i] = h->lev[i].Dcm;
+        tl.il_ptr[i] = h->lev[i].il_ptr;
+        tl.il_src[i] = h->lev[i].il_src;
+        tl.il_off[i] = h->lev[i].il_off;
+        tl.s[i] = h->lev[i].s;
+        tl.o[i] = h->lev[i].o;
+      }
+      k2_translate<<<(unsigned)tl.box0[nl], NT_TR, 0, st>>>(tl, Q);
+    }
     for (int i = 1; i < nl; ++i)
       k2_downward<<<(unsigned)h->lev[i].nbox, NT2, 0, st>>>(h->lev[i].Bcm, h->lev[i].parent, h->lev[i].quad,
                                                              h->lev[i - 1].o, h->lev[i].o, Q);
