@@ -319,10 +319,15 @@ def bodies_section(args, nesa, torch, prec, dt, stream):
     t0 = time.perf_counter()
     bodies = synth.body_family(args.bodies, seed=4)
     tree = nesa.build_forest([(v, t) for v, t, _ in bodies], 0.25)
+    log("bodies: forest of %d unknowns built" % tree.info()["n_rwg"])
     near = nesa.assemble_near(tree)
+    log("bodies: near field assembled")
     far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
+    log("bodies: far-field operators assembled")
     R = max(1, args.nrhs)
     op = nesa.op_create(tree, near, far, prec, max_nrhs=R)
+    del near, far
+    log("bodies: operator on the GPU")
     setup = time.perf_counter() - t0
     info = tree.info()
     n = info["n_rwg"]
