@@ -470,7 +470,9 @@ def main():
             e["bytes"] += alg["receive"]["bytes"]
             e["flops"] += alg["receive"]["flops"]
         elif kind in ("translate_sum",):
-            e["bytes"] += 2 * info["n_pairs"][i] * 4 * Q[i] * esize
+            # level -1: one launch for the sums of every level
+            lv_range = range(len(Q)) if lev < 0 else [i]
+            e["bytes"] += sum(2 * info["n_pairs"][j] * 4 * Q[j] * esize for j in lv_range)
         elif kind in ("upward_sum",):
             e["bytes"] += 2 * info["n_box"][i] * 4 * Q[i - 1] * esize
     dom = max(kern, key=lambda k: kern[k]["ms"])

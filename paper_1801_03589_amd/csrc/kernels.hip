@@ -860,11 +860,12 @@ __global__ __launch_bounds__(NT) void k_transfer_gemm(GemmTiles g) {
 
 // dst_a = sum over [beg[a], end[a]) of the per-pair results, in order
 // (deterministic); workgroup (a, y) takes elements y*NT, y*NT + gridDim.y*NT, ...
+// o[a] = sum of the partial rows beg[a] .. end[a] - 1 (fixed order); this
+// workgroup takes chunk `yb` of `ny` chunks of the J values of row a
 template <typename V>
-__global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
-                                                   const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
-                                                   int J) {
-  const int a = blockIdx.x;
+__device__ __forceinline__ void csr_reduce_row(const V* __restrict__ pair_out, V* __restrict__ o,
+                                               const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
+                                               int J, int a, int yb, int ny) {
   const int k0 = beg[a], k1 = end[a];
   if constexpr (sizeof(V) == 8) {
     // complex64: two values per 16-byte load (J is even: 4 channels per right-hand
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_ou
     const int J2 = J / 2;
     const float4* src = reinterpret_cast<const float4*>(pair_out);
     float4* dst = reinterpret_cast<float4*>(o);
-    const bool split = J2 <= NT / 2 && gridDim.y == 1;     // uniform over the workgroup
+    const bool split = J2 <= NT / 2 && ny == 1;                 // uniform over the workgroup
     const int t = threadIdx.x;
     if (split) {
       const int j = t % (NT / 2), ks = t / (NT / 2);
@@ -896,7 +897,7 @@ __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_ou
         dst[(size_t)a * J2 + j] = make_float4(acc.x + b.x, acc.y + b.y, acc.z + b.z, acc.w + b.w);
       }
     } else {
-      for (int j = blockIdx.y * NT + t; j < J2; j += gridDim.y * NT) {
+      for (int j = yb * NT + t; j < J2; j += ny * NT) {
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 8
         for (int k = k0; k < k1; ++k) {
@@ -910,7 +911,7 @@ __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_ou
       }
     }
   } else {
-    for (int j = blockIdx.y * NT + threadIdx.x; j < J; j += gridDim.y * NT) {
+    for (int j = yb * NT + threadIdx.x; j < J; j += ny * NT) {
       V acc;
       acc.x = 0;
       acc.y = 0;
@@ -923,6 +924,13 @@ __global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_ou
       o[(size_t)a * J + j] = acc;
     }
   }
+}
+
+template <typename V>
+__global__ __launch_bounds__(NT) void k_csr_reduce(const V* __restrict__ pair_out, V* __restrict__ o,
+                                                   const int32_t* __restrict__ beg, const int32_t* __restrict__ end,
+                                                   int J) {
+  csr_reduce_row<V>(pair_out, o, beg, end, J, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 // ------------------------------------------------------------------ potential transfer (Eq. 13)
@@ -1688,6 +1696,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   for (int l = l0; l <= L; ++l) {
     const auto& lv = d.lev[l - l0];
     if (mfma && lv.npairs > 0) {
+      // each level's sums right after its GEMM, while its per-pair outputs are
+      // still in the last-level cache (one launch for all levels measured slower)
       launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, st, true);
       if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
       k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, st>>>(static_cast<const V2*>(lv.pair_out),
