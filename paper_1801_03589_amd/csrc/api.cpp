@@ -548,7 +548,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       compact[s] = nused++;
       // column-major; for complex64 the rows are padded for the row blocking
       const cd* Ds = &fl.D[(size_t)s * fl.Q * fl.Q];
-      int nrt_d = 1, Qr = fl.Q;
+      int Qr = fl.Q;
       if (sizeof(T) == 4) Qr = nesa::row_alloc(fl.Q);
       for (int q = 0; q < fl.Q; ++q)
         for (int p = 0; p < Qr; ++p) Dc.push_back(p < fl.Q ? Ds[(size_t)p * fl.Q + q] : cd(0, 0));
