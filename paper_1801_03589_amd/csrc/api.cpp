@@ -380,7 +380,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   std::vector<nesa::TileList> made;
   made.reserve(4);
   const int mode = autotune_mode();
-  const TuneChoice dflt{p.nrt, 0, 0, 1, 64, 32};
+  const TuneChoice dflt{p.nrt, 0, 0, 1, 64, 0};
   if (mode == 0) {
     out = tiles_for(op, p, nrhs, 1, 64, made);
     set_blocking(p, out, dflt);
@@ -434,11 +434,11 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
         if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, m3});
       }
       if (res_ok && (mode == 1 || mode == 3))
-        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64, 32});
+        for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64, 0});
     }
     if (res_ok && (mode == 1 || mode == 4))
       for (int nrt : {1, 2, 4})
-        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64, 32});
+        if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64, 0});
   }
   if (cand.empty()) cand.push_back(dflt);
   hipEvent_t e0, e1;

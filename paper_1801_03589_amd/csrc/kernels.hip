@@ -671,15 +671,15 @@ __device__ __forceinline__ void cgemm_resident_body(const GemmTiles& g, int tpw)
   const int KP = (K + 3) / 4 * 4;
   const int nb = TR_COLS * KP;                    // B elements of a tile
   float2 rb[NBM];
+  // raw loads; k >= K is zeroed at the LDS store, so the loads of the next tile
+  // stay in flight during the MFMAs
   auto load_b = [&](int64_t tile) {
 #pragma unroll
     for (int i = 0; i < NBM; ++i) {
       const int e = t + i * NT;
       const int col = min(e / KP, TR_COLS - 1), k = e % KP;
       const int64_t off = g.col_src[tile * TR_COLS + col];
-      const float2 v = g.src[off + min(k, K - 1)];
-      const float f = (e < nb && k < K) ? 1.f : 0.f;
-      rb[i] = make_float2(v.x * f, v.y * f);
+      rb[i] = g.src[off + min(k, K - 1)];
     }
   };
   load_b(t_begin);
@@ -701,7 +701,7 @@ __device__ __forceinline__ void cgemm_resident_body(const GemmTiles& g, int tpw)
 #pragma unroll
     for (int i = 0; i < NBM; ++i) {
       const int e = t + i * NT;
-      if (e < nb) Bs[e / KP][e % KP] = rb[i];
+      if (e < nb) Bs[e / KP][e % KP] = (e % KP < K) ? rb[i] : make_float2(0.f, 0.f);
     }
     if (t < TR_COLS) cdst[t] = g.col_dst[tile * TR_COLS + t];
     __syncthreads();

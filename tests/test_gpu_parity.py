@@ -287,12 +287,15 @@ def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
 
 @pytest.mark.parametrize("family", ["chunked", "resident", "direct", "narrow", "gauss"])
 @pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
-def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, name, family):
+def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, tmp_path, name, family):
     """The autotuner restricted to one kernel family (chunked-K tiles, resident
     group matrices, register-direct tiles, 32-column chunked tiles, or three
     real products per complex product) still matches the oracle, for one and
-    for five right-hand sides."""
+    for five right-hand sides; the blockings it records show that the family
+    was the one launched."""
     monkeypatch.setenv("NESA_AUTOTUNE", family)
+    tune_file = tmp_path / "tune.txt"
+    monkeypatch.setenv("NESA_TUNE_FILE", str(tune_file))
     ref, tr, near, far = _case(nesa, name)
     op = nesa.op_create(tr, near, far, nesa.C64, max_nrhs=5)
     X = synth.complex_normal((5, ref.m.n), 80)
@@ -304,6 +307,22 @@ def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, name, family):
         print("%s %s rhs %d: rel err %.2e" % (name, family, r, err))
         assert err <= TOL["c64"]
     assert np.linalg.norm(Y1 - ref.matvec(X[2])) <= TOL["c64"] * np.linalg.norm(Y1)
+    # recorded choices: kind split M K nrhs tiles | nrt tpw kt regions width m3
+    rows = [list(map(int, ln.split())) for ln in tune_file.read_text().splitlines() if ln.strip()]
+    assert rows, "no blocking was tuned"
+    tpw = [r[7] for r in rows]
+    width = [r[10] for r in rows]
+    m3 = [r[11] for r in rows]
+    if family == "resident":
+        assert any(v > 0 for v in tpw)
+    elif family == "direct":
+        assert any(v < 0 for v in tpw)
+    elif family == "narrow":
+        assert any(v == 32 for v in width) and all(v == 0 for v in tpw)
+    elif family == "gauss":
+        assert all(v == 1 for v in m3) and all(v == 0 for v in tpw)
+    else:
+        assert all(v == 0 for v in tpw) and all(v == 0 for v in m3)
 
 
 def test_product_on_user_stream_and_in_hip_graph(torch_dev, nesa):
