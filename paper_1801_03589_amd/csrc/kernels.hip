@@ -541,25 +541,22 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   float2 rb[TR_NB];
   const float2* b_ptr[TR_NB];
   int b_k[TR_NB];
-  float b_ok[TR_NB];
+  bool b_ok[TR_NB];
 #pragma unroll
   for (int i = 0; i < TR_NB; ++i) {
     const int e = t + i * NT;
     const int col = e / TR_KC;
     b_k[i] = e % TR_KC;
     b_ptr[i] = g.src + col_src[col];
-    b_ok[i] = col < cnt ? 1.f : 0.f;
+    b_ok[i] = col < cnt;
   }
+  // raw loads; the zero mask of k >= K and of empty columns is applied at the
+  // LDS store, so the loads stay in flight during the MFMAs
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NRT; ++i) ra[i] = a_ptr[i][k0 / 8];
 #pragma unroll
-    for (int i = 0; i < TR_NB; ++i) {
-      const int k = k0 + b_k[i];
-      const float2 v = b_ptr[i][min(k, K - 1)];
-      const float f = k < K ? b_ok[i] : 0.f;
-      rb[i] = make_float2(v.x * f, v.y * f);
-    }
+    for (int i = 0; i < TR_NB; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
   };
   load(0);
   for (int k0 = 0; k0 < K; k0 += TR_KC) {
@@ -572,7 +569,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) {
       const int e = t + i * NT;
-      Bs[e / TR_KC][e % TR_KC] = rb[i];
+      Bs[e / TR_KC][e % TR_KC] = (k0 + b_k[i] < K && b_ok[i]) ? rb[i] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     if (k0 + TR_KC < K) load(k0 + TR_KC);
