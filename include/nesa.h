@@ -247,6 +247,10 @@ typedef struct {
 
 /* Solve Z_NESA x = b for nrhs right-hand sides (each its own Krylov space).
  * b_dev, x_dev: canonical order, RHS-major; x_dev holds x0 on entry.
+ * Complex64 operators with nrhs > 1 run the right-hand sides in lock step: each
+ * iteration every unconverged one takes one Arnoldi step of its own restart
+ * cycle and their vectors go through one multi-RHS product (report.seconds is
+ * then the wall time of the whole batch); complex128 solves them one by one.
  * history (host, nullable): estimated relative residual after each iteration
  * of RHS 0, up to history_len values.  Blocks until the solve ends. */
 int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,

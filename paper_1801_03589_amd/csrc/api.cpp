@@ -960,6 +960,329 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   return NESA_OK;
 }
 
+// Several right-hand sides in lock step (complex64).  Every right-hand side
+// runs its own restarted (F)GMRES as in gmres_one, but each iteration all the
+// unconverged ones take one Arnoldi step (each at its own position in its own
+// restart cycle), their new vectors go through one multi-RHS product, and one
+// host synchronisation serves all their Gram-Schmidt coefficients.  The true
+// residuals that close the cycles are batched the same way.
+static int gmres_batch(nesa_op* op, nesa::DevOp<float>& d, const void* b_c, void* x_c, int R,
+                       const nesa_gmres_params& prm, nesa_gmres_report* rep, double* history, int64_t hist_len,
+                       hipStream_t st) {
+  using T = float;
+  const int64_t n = d.n;
+  const int m = prm.restart;
+  const size_t es = 2 * sizeof(T);
+  auto t0 = std::chrono::steady_clock::now();
+  const bool flex = prm.precond != NESA_PRECOND_NONE;
+  std::vector<void*> mine;
+  auto alloc = [&](size_t bytes) {
+    void* p = nullptr;
+    hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
+    mine.push_back(p);
+    return p;
+  };
+  const int HS = 2 * (m + 2) + 2;                      // double2 slots per right-hand side
+  double2* hh = nullptr;
+  struct Free {
+    std::vector<void*>& v;
+    double2*& host;
+    ~Free() {
+      for (void* p : v) (void)hipFree(p);
+      if (host) (void)hipHostFree(host);
+    }
+  } guard{mine, hh};
+  hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * HS * R), "hipHostMalloc");
+  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  double2* hd = static_cast<double2*>(alloc(sizeof(double2) * HS * R));
+  double2* partial = static_cast<double2*>(alloc(sizeof(double2) * nblocks * (m + 2)));
+  // product input / output and preconditioned vectors, one slot per RHS; the
+  // products always run R wide (slots of finished right-hand sides are ignored),
+  // so the multi-RHS blockings are tuned once
+  char* Xb = static_cast<char*>(alloc((size_t)R * n * es));
+  char* Yb = static_cast<char*>(alloc((size_t)R * n * es));
+  char* Pb = flex ? static_cast<char*>(alloc((size_t)R * n * es)) : nullptr;
+  hip_check(hipMemsetAsync(Xb, 0, (size_t)R * n * es, st), "hipMemsetAsync");
+  if (Pb) hip_check(hipMemsetAsync(Pb, 0, (size_t)R * n * es, st), "hipMemsetAsync");
+  ensure_all_tiles<T>(op, d, R, st);
+  struct Rhs {
+    char *V, *Z;
+    void *bl, *xl, *ax;                                             // b, x, A x (leaf order)
+    double nb = 0, beta = 0, beta_prev = 0;
+    int j = 0, iters = 0, active = 0;
+    bool done = false, in_cycle = false, discard = false;
+    std::vector<cd> H, g, sn;
+    std::vector<double> cs;
+  };
+  std::vector<Rhs> rh(R);
+  for (int r = 0; r < R; ++r) {
+    Rhs& q = rh[r];
+    q.V = static_cast<char*>(alloc((size_t)(m + 1) * n * es));
+    q.Z = flex ? static_cast<char*>(alloc((size_t)m * n * es)) : nullptr;
+    q.bl = alloc(n * es);
+    q.xl = alloc(n * es);
+    q.ax = alloc(n * es);
+    q.H.assign((size_t)(m + 1) * m, cd(0, 0));
+    q.g.assign(m + 1, cd(0, 0));
+    q.sn.assign(m, cd(0, 0));
+    q.cs.assign(m, 0.0);
+    q.active = prm.precond;
+    rep[r] = nesa_gmres_report{0, 0, 0.0, 0.0, 0};
+  }
+  auto vec = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
+  auto slot = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
+  auto hslot = [&](int r) { return hd + (size_t)r * HS; };
+  auto fetch = [&]() {
+    hip_check(hipMemcpyAsync(hh, hd, sizeof(double2) * HS * R, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  };
+  auto precond = [&](Rhs& q, const void* r, void* z) {
+    if (q.active == NESA_PRECOND_LEARNED)
+      learned_apply<T>(op->mlp, d, r, z, st);
+    else if (q.active == NESA_PRECOND_SCHWARZ || q.active == NESA_PRECOND_BLOCKDIAG)
+      base_apply<T>(op, d, q.active, r, z, st);
+    else
+      hip_check(hipMemcpyAsync(z, r, n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+  };
+  // y = A x for the listed right-hand sides' vectors in one product (R wide)
+  auto batched_matvec = [&](const std::vector<const void*>& src, const std::vector<void*>& dst) {
+    const int ra = (int)src.size();
+    if (ra == 0) return;
+    for (int i = 0; i < ra; ++i)
+      if (src[i] != slot(Xb, i))
+        hip_check(hipMemcpyAsync(slot(Xb, i), src[i], n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+    nesa::launch_matvec_leaf<T>(d, Xb, Yb, R, st, nullptr);
+    for (int i = 0; i < ra; ++i)
+      if (dst[i] != slot(Yb, i))
+        hip_check(hipMemcpyAsync(dst[i], slot(Yb, i), n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+  };
+  // true residuals of the listed right-hand sides: ax = A x, V0 = b - ax, beta
+  auto residuals = [&](const std::vector<int>& list) {
+    std::vector<const void*> src;
+    std::vector<void*> dst;
+    for (int r : list) {
+      src.push_back(rh[r].xl);
+      dst.push_back(rh[r].ax);
+    }
+    batched_matvec(src, dst);
+    for (int r : list) {
+      nesa::launch_sub<T>(rh[r].bl, rh[r].ax, vec(rh[r].V, 0), n, st);
+      nesa::launch_multidot<T>(vec(rh[r].V, 0), n, 1, vec(rh[r].V, 0), n, partial, nblocks, hslot(r), 0, st);
+    }
+    fetch();
+    for (int r : list) {
+      rh[r].beta_prev = rh[r].beta;
+      rh[r].beta = std::sqrt(std::max(0.0, hh[(size_t)r * HS].x));
+    }
+  };
+  auto start_cycle = [&](int r) {
+    Rhs& q = rh[r];
+    nesa::launch_scale<T>(vec(q.V, 0), vec(q.V, 0), n, 1.0 / q.beta, st);
+    std::fill(q.H.begin(), q.H.end(), cd(0, 0));
+    std::fill(q.g.begin(), q.g.end(), cd(0, 0));
+    q.g[0] = q.beta;
+    q.j = 0;
+    q.in_cycle = true;
+    q.discard = false;
+    rep[r].restarts++;
+  };
+  int64_t nh = 0;
+  // right-hand side norms and initial residuals
+  std::vector<int> all;
+  for (int r = 0; r < R; ++r) {
+    all.push_back(r);
+    const char* br = static_cast<const char*>(b_c) + (size_t)r * n * es;
+    char* xr = static_cast<char*>(x_c) + (size_t)r * n * es;
+    nesa::launch_gather<T>(br, rh[r].bl, d.perm, n, st);
+    nesa::launch_gather<T>(xr, rh[r].xl, d.perm, n, st);
+    nesa::launch_multidot<T>(rh[r].bl, n, 1, rh[r].bl, n, partial, nblocks, hslot(r), 0, st);
+  }
+  fetch();
+  std::vector<int> live;
+  for (int r = 0; r < R; ++r) {
+    rh[r].nb = std::sqrt(std::max(0.0, hh[(size_t)r * HS].x));
+    if (rh[r].nb == 0) {
+      rh[r].done = true;
+      hip_check(hipMemsetAsync(static_cast<char*>(x_c) + (size_t)r * n * es, 0, n * es, st), "hipMemsetAsync");
+    } else {
+      live.push_back(r);
+    }
+  }
+  residuals(live);
+  if (!live.empty() && live[0] == 0 && history && nh < hist_len) history[nh] = rh[0].beta / rh[0].nb;
+  if (!live.empty() && live[0] == 0) ++nh;
+  for (int r : live) {
+    if (rh[r].beta / rh[r].nb <= prm.tol || prm.max_iters <= 0)
+      rh[r].done = true;
+    else
+      start_cycle(r);
+  }
+  int status = NESA_OK;
+  for (;;) {
+    std::vector<int> act;
+    for (int r = 0; r < R; ++r)
+      if (!rh[r].done) act.push_back(r);
+    if (act.empty()) break;
+    // one Arnoldi step for every active right-hand side: the basis vectors
+    // (preconditioned together when every active one uses the Schwarz base)
+    // go through one product
+    std::vector<const void*> src;
+    std::vector<void*> dst;
+    bool all_schwarz = flex;
+    for (int r : act) all_schwarz = all_schwarz && rh[r].active == NESA_PRECOND_SCHWARZ;
+    for (size_t i = 0; i < act.size(); ++i) {
+      Rhs& q = rh[act[i]];
+      const void* v = vec(q.V, q.j);
+      if (flex && !all_schwarz) {
+        precond(q, v, vec(q.Z, q.j));
+        v = vec(q.Z, q.j);
+      }
+      hip_check(hipMemcpyAsync(slot(Xb, (int)i), v, n * es, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+      src.push_back(slot(Xb, (int)i));
+      dst.push_back(slot(Yb, (int)i));
+    }
+    if (all_schwarz) {
+      nesa::launch_near_apply<T>(d, op->schwarz, Xb, Pb, st, R);
+      for (size_t i = 0; i < act.size(); ++i) {
+        Rhs& q = rh[act[i]];
+        hip_check(hipMemcpyAsync(vec(q.Z, q.j), slot(Pb, (int)i), n * es, hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(slot(Xb, (int)i), slot(Pb, (int)i), n * es, hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync");
+      }
+    }
+    batched_matvec(src, dst);
+    for (size_t i = 0; i < act.size(); ++i) {
+      Rhs& q = rh[act[i]];
+      void* w = slot(Yb, (int)i);
+      double2* h = hslot(act[i]);
+      // two passes of classical Gram-Schmidt, FP64 dot products
+      nesa::launch_multidot<T>(q.V, n, q.j + 1, w, n, partial, nblocks, h, 0, st);
+      nesa::launch_combine<T>(q.V, n, q.j + 1, h, w, n, -1.0, st);
+      nesa::launch_multidot<T>(q.V, n, q.j + 1, w, n, partial, nblocks, h + (m + 2), 0, st);
+      nesa::launch_combine<T>(q.V, n, q.j + 1, h + (m + 2), w, n, -1.0, st);
+      nesa::launch_multidot<T>(w, n, 1, w, n, partial, nblocks, h + 2 * (m + 2), 0, st);
+    }
+    fetch();
+    std::vector<int> ended;
+    for (size_t i = 0; i < act.size(); ++i) {
+      const int r = act[i];
+      Rhs& q = rh[r];
+      const double2* hr = hh + (size_t)r * HS;
+      const int j = q.j;
+      cd* Hj = &q.H[(size_t)j * (m + 1)];
+      for (int k = 0; k <= j; ++k) Hj[k] = cd(hr[k].x + hr[m + 2 + k].x, hr[k].y + hr[m + 2 + k].y);
+      const double hn = std::sqrt(std::max(0.0, hr[2 * (m + 2)].x));
+      bool finite = std::isfinite(hn);
+      for (int k = 0; k <= j && finite; ++k) finite = std::isfinite(std::abs(Hj[k]));
+      if (!finite) {
+        if (q.active == NESA_PRECOND_LEARNED) {
+          q.active = op->mlp->base;
+          rep[r].fell_back = 1;
+          q.discard = true;
+          ended.push_back(r);
+          continue;
+        }
+        status = fail(NESA_EBREAKDOWN, "non-finite value in GMRES");
+        q.done = true;
+        continue;
+      }
+      Hj[j + 1] = hn;
+      for (int k = 0; k < j; ++k) {
+        cd t0v = q.cs[k] * Hj[k] + q.sn[k] * Hj[k + 1];
+        Hj[k + 1] = -std::conj(q.sn[k]) * Hj[k] + q.cs[k] * Hj[k + 1];
+        Hj[k] = t0v;
+      }
+      cd a = Hj[j], bb = Hj[j + 1];
+      double c;
+      cd sv, rr;
+      if (bb == cd(0, 0)) {
+        c = 1;
+        sv = 0;
+        rr = a;
+      } else if (a == cd(0, 0)) {
+        c = 0;
+        sv = 1;
+        rr = bb;
+      } else {
+        const double rho = std::hypot(std::abs(a), std::abs(bb));
+        c = std::abs(a) / rho;
+        sv = a * std::conj(bb) / (std::abs(a) * rho);
+        rr = a * rho / std::abs(a);
+      }
+      q.cs[j] = c;
+      q.sn[j] = sv;
+      Hj[j] = rr;
+      Hj[j + 1] = 0;
+      q.g[j + 1] = -std::conj(sv) * q.g[j];
+      q.g[j] = c * q.g[j];
+      ++q.iters;
+      if (r == 0) {
+        if (history && nh < hist_len) history[nh] = std::abs(q.g[j + 1]) / q.nb;
+        ++nh;
+      }
+      q.j = j + 1;
+      if (std::abs(q.g[j + 1]) / q.nb <= prm.tol || q.iters >= prm.max_iters || hn == 0 || q.j == m) {
+        ended.push_back(r);
+      } else {
+        nesa::launch_scale<T>(slot(Yb, (int)i), vec(q.V, q.j), n, 1.0 / hn, st);
+      }
+    }
+    if (status != NESA_OK) break;
+    if (ended.empty()) continue;
+    // close the cycles: x += Z y (or V y), then the true residuals in one product
+    std::vector<int> upd;
+    for (int r : ended) {
+      Rhs& q = rh[r];
+      if (q.discard) continue;
+      const int k = q.j;
+      std::vector<cd> y(k);
+      for (int i2 = k - 1; i2 >= 0; --i2) {
+        cd acc = q.g[i2];
+        for (int c2 = i2 + 1; c2 < k; ++c2) acc -= q.H[(size_t)c2 * (m + 1) + i2] * y[c2];
+        y[i2] = acc / q.H[(size_t)i2 * (m + 1) + i2];
+      }
+      double2* yh = hh + (size_t)r * HS;
+      for (int i2 = 0; i2 < k; ++i2) yh[i2] = make_double2(y[i2].real(), y[i2].imag());
+      hip_check(hipMemcpyAsync(hslot(r), yh, sizeof(double2) * k, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+      nesa::launch_combine<T>(flex ? q.Z : q.V, n, k, hslot(r), q.xl, n, +1.0, st);
+      upd.push_back(r);
+    }
+    residuals(upd);
+    for (int r : ended) {
+      Rhs& q = rh[r];
+      if (q.discard) {                        // restart from the same x with the base preconditioner
+        nesa::launch_sub<T>(q.bl, q.ax, vec(q.V, 0), n, st);
+        start_cycle(r);
+        continue;
+      }
+      const double ratio = prm.fallback_ratio > 0 ? prm.fallback_ratio : 1.0;
+      if (q.active == NESA_PRECOND_LEARNED && !(q.beta < ratio * q.beta_prev)) {
+        q.active = op->mlp->base;
+        rep[r].fell_back = 1;
+      }
+      if (q.beta / q.nb <= prm.tol || q.iters >= prm.max_iters)
+        q.done = true;
+      else
+        start_cycle(r);
+    }
+  }
+  int worst = status;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < R; ++r) {
+    char* xr = static_cast<char*>(x_c) + (size_t)r * n * es;
+    if (rh[r].nb != 0) nesa::launch_scatter<T>(rh[r].xl, xr, d.perm, n, st);
+    rep[r].iters = rh[r].iters;
+    rep[r].true_rel_residual = rh[r].nb != 0 ? rh[r].beta / rh[r].nb : 0.0;
+    rep[r].seconds = secs;
+    if (worst == NESA_OK && rh[r].nb != 0 && rep[r].true_rel_residual > prm.tol)
+      worst = fail(NESA_ENOCONV, "GMRES reached max_iters above tolerance");
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  for (int r = 0; r < R; ++r) rep[r].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return worst;
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -1335,6 +1658,8 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
       return fail(NESA_EINVAL, "no network attached for the learned preconditioner");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = op->geo.rwg.n;
+    if (op->precision != NESA_C128 && nrhs > 1)
+      return gmres_batch(op, op->f, b_dev, x_dev, (int)nrhs, *params, report, history, history_len, st);
     int worst = NESA_OK;
     for (int64_t r = 0; r < nrhs; ++r) {
       const char* br = static_cast<const char*>(b_dev) + (size_t)r * n * op->esize;

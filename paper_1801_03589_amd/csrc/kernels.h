@@ -155,6 +155,6 @@ void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st)
 void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st, bool translation);
 // y = arena x with an arena in the near-block layout (leaf order, one RHS)
 template <typename T>
-void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st);
+void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st, int nrhs = 1);
 
 }  // namespace nesa

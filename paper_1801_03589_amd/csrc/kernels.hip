@@ -1791,11 +1791,12 @@ void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st
   k_sub<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(a), static_cast<const V2*>(b), static_cast<V2*>(y), n);
 }
 template <typename T>
-void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st) {
+void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st, int nrhs) {
   using V2 = typename C2<T>::type;
-  k_near_multi<V2><<<dim3((unsigned)d.nleaf, 1), NT, 0, st>>>(static_cast<const V2*>(arena), d.zoff, d.leaf_ptr,
-                                                             d.near_ptr, d.near_idx, static_cast<const V2*>(x),
-                                                             static_cast<V2*>(y), 1, d.n);
+  const unsigned rblk = (unsigned)((nrhs + RB - 1) / RB);
+  k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(arena), d.zoff, d.leaf_ptr,
+                                                                d.near_ptr, d.near_idx, static_cast<const V2*>(x),
+                                                                static_cast<V2*>(y), nrhs, d.n);
 }
 
 template <typename T>
@@ -1816,7 +1817,7 @@ void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st)
   template void launch_scale<T>(const void*, void*, int64_t, double, hipStream_t);                           \
   template void launch_sub<T>(const void*, const void*, void*, int64_t, hipStream_t);                       \
   template void launch_blockdiag<T>(const DevOp<T>&, const void*, void*, hipStream_t);                      \
-  template void launch_near_apply<T>(const DevOp<T>&, const void*, const void*, void*, hipStream_t);
+  template void launch_near_apply<T>(const DevOp<T>&, const void*, const void*, void*, hipStream_t, int);
 NESA_INST(float)
 NESA_INST(double)
 

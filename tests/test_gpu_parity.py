@@ -143,6 +143,45 @@ def test_gmres_matches_oracle(torch_dev, nesa):
     assert np.allclose(h[:30], ho[:30], rtol=1e-6, atol=1e-12)
 
 
+@pytest.mark.parametrize("precond", ["none", "schwarz"])
+def test_batched_gmres_matches_sequential(torch_dev, nesa, precond):
+    """Four incidences solved in lock step (one multi-RHS product per iteration)
+    against the same four solved one at a time: every one converges, with the
+    same iteration counts to within a few and solutions that agree to the
+    tolerance; the oracle's residual of each batched solution is at the tolerance;
+    a zero right-hand side in the batch gives x = 0."""
+    torch = torch_dev
+    ref, tr, near, far = _case(nesa, "sphere1")
+    op = nesa.op_create(tr, near, far, nesa.C64, max_nrhs=5)
+    pc = {"none": nesa.PRECOND_NONE, "schwarz": nesa.PRECOND_SCHWARZ}[precond]
+    dirs = [([0, 0, 1], [1, 0, 0]), ([1, 0, 0], [0, 1, 0]), ([0, 1, 0], [0, 0, 1]),
+            ([0.6, 0, 0.8], [0, 1, 0])]
+    n = ref.m.n
+    B = torch.zeros(5, n, dtype=torch.complex64, device="cuda")
+    for r, (k, e) in enumerate(dirs):
+        nesa.rhs_plane_wave(op, k, e, B[r])
+    tol = 1e-4
+    X = torch.zeros_like(B)
+    rc, rep, _ = nesa.gmres_solve(op, B, X, nrhs=5, restart=30, max_iters=1000, tol=tol, precond=pc)
+    assert rc == 0
+    assert not torch.any(X[4])
+    Xb = X.cpu().numpy().astype(np.complex128)
+    for r in range(4):
+        x1 = torch.zeros(n, dtype=torch.complex64, device="cuda")
+        rc1, rep1, _ = nesa.gmres_solve(op, B[r].clone(), x1, restart=30, max_iters=1000, tol=tol, precond=pc)
+        assert rc1 == 0
+        xs = x1.cpu().numpy().astype(np.complex128)
+        b = B[r].cpu().numpy().astype(np.complex128)
+        res = np.linalg.norm(b - ref.matvec(Xb[r])) / np.linalg.norm(b)
+        print("%s rhs %d: batched %d iters, alone %d; residual %.2e; solutions differ %.2e"
+              % (precond, r, rep[r]["iters"], rep1[0]["iters"], res,
+                 np.linalg.norm(Xb[r] - xs) / np.linalg.norm(xs)))
+        assert rep[r]["true_rel_residual"] <= tol
+        assert abs(rep[r]["iters"] - rep1[0]["iters"]) <= 3
+        assert np.linalg.norm(Xb[r] - xs) <= 10 * tol * np.linalg.norm(xs)
+        assert res <= 2 * tol
+
+
 def test_blockdiag_preconditioned_fgmres(torch_dev, nesa):
     """Flexible GMRES with the near-field block-diagonal preconditioner against
     the oracle's FGMRES with the per-leaf inverses of the same self blocks.
