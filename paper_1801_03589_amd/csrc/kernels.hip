@@ -1307,46 +1307,54 @@ __global__ __launch_bounds__(NT) void k_recv_multi(const typename C2<T>::type* _
                                                    typename C2<T>::type* __restrict__ y, int Q, int R, int64_t n,
                                                    T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d) {
   using V2 = typename C2<T>::type;
-  __shared__ V2 ow[RB][4 * MAX_QL / 2];
+  __shared__ __align__(16) V2 ow[RB][4 * MAX_QL / 2];
   const int a = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int J = 4 * Q;
   for (int e = threadIdx.x; e < RB * J; e += NT) {
     const int r = e / J, j = e % J;
+    const int c = j / Q, q = j % Q;
+    V2 v = cmk<T>(0, 0);
     if (r < nr) {
-      const int c = j / Q, q = j % Q;
       const V2 ov = o[((size_t)a * 4 * R + c * R + r0 + r) * Q + q];
       const V2 wv = (c < 3) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
-      ow[r][j] = cmul(ov, wv);
+      v = cmul(ov, wv);
     }
+    ow[r][j] = v;
   }
   __syncthreads();
+  // 8 lanes per row and 8 rows per wave: every lane keeps the partial sums of
+  // all RB right-hand sides, so one row of V is read once and each sum takes 3
+  // shuffle steps
+  constexpr int LR = 8;
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-  constexpr int PL = 4 * MAX_QL / 2 / WAVE;      // V values per lane
-  for (int row = wv; row < S; row += NT / WAVE) {
-    const V2* Vr = V + (size_t)(p0 + row) * J;
-    V2 vv[PL];
+  const int c = lane % LR, sub = lane / LR;
+  for (int row0 = wv * (WAVE / LR); row0 < S; row0 += (NT / WAVE) * (WAVE / LR)) {
+    const int row = row0 + sub;
+    V2 acc[RB];
 #pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int j = lane + k * WAVE;
-      vv[k] = (j < J) ? Vr[j] : cmk<T>(0, 0);
+    for (int r = 0; r < RB; ++r) acc[r] = cmk<T>(0, 0);
+    if (row < S) {
+      const V2* Vr = V + (size_t)(p0 + row) * J;
+#pragma unroll 2
+      for (int j = c; j < J; j += LR) {
+        const V2 v = Vr[j];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cfma(acc[r], v, ow[r][j]);
+      }
     }
-    for (int r = 0; r < nr; ++r) {
-      V2 sum = cmk<T>(0, 0);
 #pragma unroll
-      for (int k = 0; k < PL; ++k) {
-        const int j = lane + k * WAVE;
-        if (j < J) cfma(sum, vv[k], ow[r][j]);
+    for (int r = 0; r < RB; ++r)
+      for (int off = LR / 2; off > 0; off >>= 1) {
+        acc[r].x += __shfl_xor(acc[r].x, off);
+        acc[r].y += __shfl_xor(acc[r].y, off);
       }
-      for (int off = WAVE / 2; off > 0; off >>= 1) {
-        sum.x += __shfl_xor(sum.x, off);
-        sum.y += __shfl_xor(sum.y, off);
-      }
-      if (lane == 0) {
+    if (c == 0 && row < S) {
+      for (int r = 0; r < nr; ++r) {
         V2* yp = y + (size_t)(r0 + r) * n + p0 + row;
         V2 out = *yp;
-        out.x += sum.x;
-        out.y += sum.y;
+        out.x += acc[r].x;
+        out.y += acc[r].y;
         *yp = out;
       }
     }
