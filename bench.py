@@ -67,14 +67,19 @@ def algorithmic(info, Q, esize):
     QL = Q[-1]
     nleaf = info["n_box"][-1]
     ph = {}
-    # near field + reception (fused kernel): near blocks, V read once, x read, y written, o read
-    ph["near_recv"] = {"bytes": info["near_entries"] * esize + n * 4 * QL * esize + 2 * n * esize
-                       + nleaf * 4 * QL * esize,
+    # near field (reciprocity half storage: blocks Z_ab with b >= a, read once;
+    # the outputs Z_ab^T x_a written and read back) + reception: V read once,
+    # x read, y written, o read; flops: one complex MAC per entry of the full
+    # near field (each stored off-diagonal entry serves two)
+    nt = info["near_transposed"]
+    ph["near_recv"] = {"bytes": info["near_entries_half"] * esize + 2 * nt * esize + n * 4 * QL * esize
+                       + 2 * n * esize + nleaf * 4 * QL * esize,
                        "flops": 8 * info["near_entries"] + 8 * 4 * QL * n}
     ph["radiate"] = {"bytes": n * 4 * QL * esize + n * esize + nleaf * 4 * QL * esize,
                      "flops": 8 * 4 * QL * n}
-    # reception alone (the overlapped product adds it after the side-stream near field)
-    ph["receive"] = {"bytes": n * 4 * QL * esize + 2 * n * esize + nleaf * 4 * QL * esize,
+    # reception alone (the overlapped product adds it, with the transposed
+    # near-field outputs, after the side-stream near field)
+    ph["receive"] = {"bytes": n * 4 * QL * esize + 3 * n * esize + nleaf * 4 * QL * esize + nt * esize,
                      "flops": 8 * 4 * QL * n}
     up = 0
     for i in range(1, nl):
@@ -530,7 +535,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": kd["bytes"] / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"translate_gemm": "k_translate_gemm", "near_recv": "k_near_recv",
+    roof["kernel"] = {"translate_gemm": "k_translate_gemm", "near_recv": "k_near_half",
                       "upward_gemm": "k_transfer_gemm", "downward_gemm": "k_transfer_gemm"}.get(dom, dom)
     roof["traffic"] = profiled_traffic(roof["kernel"], args.precision)
     roof["launches_per_product"] = kd["launches"]
@@ -575,7 +580,8 @@ def main():
         "config": {"workload": "pec_sphere_r%gl_icosphere%d_%drwg" % (args.radius, args.nu, n),
                    "n_unknowns": n, "nrhs": 1, "leaf_lambda": 0.25, "levels": [info["l0"], info["L"]],
                    "Q": Q, "boxes": info["n_box"], "pairs": info["n_pairs"],
-                   "near_entries": info["near_entries"], "parallelism": "single_gpu"},
+                   "near_entries": info["near_entries"], "near_entries_half": info["near_entries_half"],
+                   "parallelism": "single_gpu"},
         "roofline": roof,
         "product_roofline": {"t_roof_ms": round(t_roof * 1e3, 4), "frac": round(t_roof * 1e3 / ms, 4),
                              "definition": "sum over stages of max(algorithmic bytes / 8 TB/s, "

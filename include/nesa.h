@@ -114,6 +114,11 @@ typedef struct {
   int Q[32];             /* equivalent sources per box at level l0 + i
                             (0 until nesa_assemble_translations) */
   int64_t max_leaf;      /* RWGs of the largest leaf */
+  int64_t near_entries_half;  /* entries of the blocks Z_ab with b >= a (leaf order):
+                                 what the single-RHS product stores and reads,
+                                 Z_ba = Z_ab^T being the Galerkin EFIE's reciprocity */
+  int64_t near_transposed;    /* outputs Z_ab^T x_a (b > a) that the single-RHS
+                                 product writes and reads back per product */
 } nesa_tree_info;
 
 /* Build the RWG basis and the oct-tree of a closed triangle mesh.

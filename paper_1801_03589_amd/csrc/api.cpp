@@ -522,7 +522,58 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   d.near_ptr = upload(op, to_i32(t.near_ptr));
   d.near_idx = upload(op, to_i32(t.near_idx));
   d.zoff = upload(op, nr.off);
-  d.Z = upload_complex<T>(op, nr.z);
+  // the full blocks serve the products of several right-hand sides only
+  if (op->max_nrhs > 1 && sizeof(T) == 4) d.Z = upload_complex<T>(op, nr.z);
+  std::vector<int64_t> zh_off(d.nleaf + 1, 0);
+  {
+    // reciprocity half storage: leaf a keeps the columns of its near leaves
+    // b >= a, i.e. the tail of its full block from its own columns on
+    const int64_t nleaf = d.nleaf;
+    std::vector<int32_t> nh(nleaf), tsrc(t.near_idx.size(), -1);
+    std::vector<int64_t> col0(nleaf), toff(nleaf + 1, 0);
+    for (int64_t a = 0; a < nleaf; ++a) {
+      const int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+      int64_t k = t.near_ptr[a], c = 0;
+      while (k < t.near_ptr[a + 1] && t.near_idx[k] < a) {
+        c += t.leaf_ptr[t.near_idx[k] + 1] - t.leaf_ptr[t.near_idx[k]];
+        ++k;
+      }
+      if (k == t.near_ptr[a + 1] || t.near_idx[k] != a) throw Error(NESA_EINVAL, "leaf missing from its near list");
+      const int64_t W = (nr.off[a + 1] - nr.off[a]) / S;
+      nh[a] = (int32_t)k;
+      col0[a] = c;
+      zh_off[a + 1] = zh_off[a] + S * (W - c);
+      toff[a + 1] = toff[a] + (W - c - S);
+    }
+    if (toff[nleaf] >= INT32_MAX) throw Error(NESA_EINVAL, "near field too large for 32-bit slot offsets");
+    for (int64_t a = 0; a < nleaf; ++a) {
+      const int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+      int64_t col = S;
+      for (int64_t k = nh[a] + 1; k < t.near_ptr[a + 1]; ++k) {
+        const int64_t b = t.near_idx[k];
+        const auto lo = t.near_idx.begin() + t.near_ptr[b], hi = t.near_idx.begin() + t.near_ptr[b + 1];
+        const auto it = std::lower_bound(lo, hi, a);
+        if (it == hi || *it != a) throw Error(NESA_EINVAL, "near lists are not symmetric");
+        tsrc[it - t.near_idx.begin()] = (int32_t)(toff[a] + col - S);
+        col += t.leaf_ptr[b + 1] - t.leaf_ptr[b];
+      }
+    }
+    for (int64_t b = 0; b < nleaf; ++b)
+      for (int64_t k = t.near_ptr[b]; k < nh[b]; ++k)
+        if (tsrc[k] < 0) throw Error(NESA_EINVAL, "transposed near block without a slot");
+    std::vector<cd> zh(zh_off[nleaf]);
+    nesa::parallel_for(nleaf, [&](int64_t a) {
+      const int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+      std::copy(nr.z.begin() + nr.off[a] + col0[a] * S, nr.z.begin() + nr.off[a + 1], zh.begin() + zh_off[a]);
+    });
+    d.nh_ptr = upload(op, nh);
+    d.zh_off = upload(op, zh_off);
+    d.Zh = upload_complex<T>(op, zh);
+    std::vector<int32_t> to32(toff.begin(), toff.end() - 1);
+    d.toff = upload(op, to32);
+    d.tsrc = upload(op, tsrc);
+    d.tpart = dev_alloc(op, (size_t)std::max<int64_t>(toff[nleaf], 1) * 2 * sizeof(T));
+  }
   d.V = upload_complex<T>(op, fr.V);
   d.w[0] = 0.0;
   d.w[1] = -fr.eta * fr.k;
@@ -656,7 +707,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     std::vector<int32_t> ord(d.nleaf);
     for (int64_t a = 0; a < d.nleaf; ++a) ord[a] = (int32_t)a;
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
-      return nr.off[x + 1] - nr.off[x] > nr.off[y + 1] - nr.off[y];
+      return zh_off[x + 1] - zh_off[x] > zh_off[y + 1] - zh_off[y];
     });
     d.near_order = upload(op, ord);
   }
@@ -1334,15 +1385,22 @@ int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info) {
     info->n_tri = t.rwg.nt;
     info->L = t.L;
     info->l0 = t.l0;
-    int64_t ne = 0;
+    int64_t ne = 0, nh = 0, nt = 0;
     const auto& LL = t.level(t.L);
     for (int64_t a = 0; a < LL.nbox; ++a) {
-      int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a], W = 0;
-      for (int64_t j = t.near_ptr[a]; j < t.near_ptr[a + 1]; ++j)
-        W += t.leaf_ptr[t.near_idx[j] + 1] - t.leaf_ptr[t.near_idx[j]];
+      int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a], W = 0, Wh = 0;
+      for (int64_t j = t.near_ptr[a]; j < t.near_ptr[a + 1]; ++j) {
+        const int64_t b = t.near_idx[j], Sb = t.leaf_ptr[b + 1] - t.leaf_ptr[b];
+        W += Sb;
+        if (b >= a) Wh += Sb;
+      }
       ne += S * W;
+      nh += S * Wh;
+      nt += Wh - S;
     }
     info->near_entries = ne;
+    info->near_entries_half = nh;
+    info->near_transposed = nt;
     info->max_leaf = max_leaf(t);
     for (int l = t.l0; l <= t.L && l - t.l0 < 32; ++l) {
       info->n_box[l - t.l0] = t.level(l).nbox;

@@ -73,13 +73,21 @@ struct DevOp {
   int32_t* near_ptr = nullptr;
   int32_t* near_idx = nullptr;
   int64_t* zoff = nullptr;       // [nleaf + 1]
-  void* Z = nullptr;             // near blocks
+  void* Z = nullptr;             // near blocks, full (products of several right-hand sides)
+  // near blocks in reciprocity half storage (products of one right-hand side):
+  // leaf a keeps the blocks Z_ab of the near leaves b >= a, itself first
+  int32_t* nh_ptr = nullptr;     // [nleaf] near-list entry of the leaf itself
+  int64_t* zh_off = nullptr;     // [nleaf + 1]
+  void* Zh = nullptr;
+  int32_t* toff = nullptr;       // [nleaf] first slot of leaf a's outputs Z_ab^T x_a (b > a)
+  int32_t* tsrc = nullptr;       // [near entries] entry (a, b < a): slot of Z_ba^T x_b
+  void* tpart = nullptr;         // those outputs
   void* V = nullptr;             // [n][4][Q_L]
   void* s = nullptr;             // equivalent sources, all levels
   void* o = nullptr;             // equivalent potentials, all levels
   void* Minv = nullptr;          // block-diagonal preconditioner (inverse self blocks)
   int64_t* moff = nullptr;
-  int32_t* near_order = nullptr; // leaves by decreasing near-field work (launch order)
+  int32_t* near_order = nullptr; // leaves by decreasing half-storage near-field work (launch order)
   hipStream_t side = nullptr;    // non-blocking stream of the near field (untimed products)
   int near_wgs = 0;              // workgroups of the persistent near-field grid (0: 256)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

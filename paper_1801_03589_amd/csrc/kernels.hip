@@ -1028,23 +1028,38 @@ __device__ __forceinline__ void recv_rows(const typename C2<T>::type* __restrict
   }
 }
 
-template <typename T, bool RECV>
-__device__ __forceinline__ void near_leaf(const int a, typename C2<T>::type* xs, typename C2<T>::type* red, int* seg_col, int* seg_x, typename C2<T>::type* ow,
-                                          const typename C2<T>::type* __restrict__ Z,
-                                                  const int64_t* __restrict__ zoff,
-                                                  const int32_t* __restrict__ leaf_ptr,
-                                                  const int32_t* __restrict__ near_ptr,
-                                                  const int32_t* __restrict__ near_idx,
-                                                  const typename C2<T>::type* __restrict__ x,
-                                                  const typename C2<T>::type* __restrict__ V,
-                                                  const typename C2<T>::type* __restrict__ o,
-                                                  typename C2<T>::type* __restrict__ y, int Q,
-                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d,
-                                                  const int32_t* __restrict__ order) {
+// ------------------------------------------------------------------ near field, reciprocity half storage
+// The Galerkin EFIE matrix is symmetric (Z_mn = Z_nm: testing and basis
+// functions are the same RWGs), so of every pair of neighbouring leaves only
+// the blocks Z_ab with b >= a (leaf order) are stored: leaf a's columns are the
+// RWGs of the leaves b >= a of its near list (itself first), column-major
+// S_a x W_a.  One pass over them gives both Z_ab x_b (summed into y_a) and,
+// for b > a, Z_ab^T x_a, written to its own slot of `tpart`; the reception
+// kernel adds the slots of every leaf in increasing a (a fixed order).
+constexpr int NEAR_HCW = 512;                 // x columns staged in LDS per sub-chunk (<= 2 NT)
+constexpr int NEAR_TP_BYTES = 36 * 1024;      // LDS of the transposed products of a sub-chunk
+
+// Sub-chunks of CT columns; each thread holds at most U of a sub-chunk's near
+// entries, loaded into registers while the previous sub-chunk is computed and
+// reduced (the loads' latency hides behind that work and the barriers).
+template <typename T>
+__device__ __forceinline__ void near_half_leaf(const int a, typename C2<T>::type* xs, typename C2<T>::type* red,
+                                               typename C2<T>::type* tp, int* seg_col, int* seg_x,
+                                               const typename C2<T>::type* __restrict__ Z,
+                                               const int64_t* __restrict__ zoff,
+                                               const int32_t* __restrict__ leaf_ptr,
+                                               const int32_t* __restrict__ nh_ptr,
+                                               const int32_t* __restrict__ near_ptr,
+                                               const int32_t* __restrict__ near_idx,
+                                               const int32_t* __restrict__ toff,
+                                               const typename C2<T>::type* __restrict__ x,
+                                               typename C2<T>::type* __restrict__ y,
+                                               typename C2<T>::type* __restrict__ tpart) {
   using V2 = typename C2<T>::type;
-  (void)order;
+  constexpr int TP_N = NEAR_TP_BYTES / (int)sizeof(V2);
+  constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
-  const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
+  const int n0 = nh_ptr[a], nn = near_ptr[a + 1] - n0;
   if (threadIdx.x == 0) {
     int c = 0;
     for (int k = 0; k < nn; ++k) {
@@ -1058,90 +1073,150 @@ __device__ __forceinline__ void near_leaf(const int a, typename C2<T>::type* xs,
   __syncthreads();
   const int W = seg_col[nn];
   const V2* Za = Z + zoff[a];
-  const int G = NT / S;                 // column groups (S <= NT checked on the host)
-  const int t = threadIdx.x;
-  const int g = t / S;
+  const int G = NT / S;                    // column groups of S threads (S <= NT checked on the host)
+  const int t = threadIdx.x, g = t / S, i = t - g * S;
+  const bool row_ok = g < G;
+  const V2 xa = row_ok ? x[p0 + i] : cmk<T>(0, 0);
+  const int SP = S | 1;                    // odd LDS stride of a column of products
+  const int CT = min(min(NEAR_HCW, TP_N / SP), U * G);   // columns per sub-chunk
+  V2* ta = tpart + toff[a] - S;            // Z_ab^T x_a of column col >= S goes to ta[col]
+  V2 zr[U], xr[2];
+  // loads of the sub-chunk at column c0 into registers
+  auto fetch = [&](int c0) {
+    const int cw = min(CT, W - c0);
+    const V2* Zp = Za + (size_t)c0 * S + t;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = g + u * G;
+      if (row_ok && j < cw) zr[u] = Zp[(size_t)(u * G) * S];
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int j = t + e * NT;
+      if (j < cw) {
+        const int col = c0 + j;
+        int k = 0;
+        while (seg_col[k + 1] <= col) ++k;
+        xr[e] = x[seg_x[k] + (col - seg_col[k])];
+      }
+    }
+  };
   V2 acc = cmk<T>(0, 0);
-  for (int c0 = 0; c0 < W; c0 += NEAR_CW) {
-    const int cw = min(NEAR_CW, W - c0);
+  if (W > 0) fetch(0);
+  for (int c0 = 0; c0 < W; c0 += CT) {
+    const int cw = min(CT, W - c0);
+    __syncthreads();                       // xs and tp of the previous sub-chunk consumed
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (t + e * NT < cw) xs[t + e * NT] = xr[e];
     __syncthreads();
-    for (int j = t; j < cw; j += NT) {
-      const int col = c0 + j;
-      int k = 0;
-      while (seg_col[k + 1] <= col) ++k;
-      xs[j] = x[seg_x[k] + (col - seg_col[k])];
+    V2 zc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) zc[u] = zr[u];
+    if (c0 + CT < W) fetch(c0 + CT);
+    if (row_ok) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = g + u * G;
+        if (j < cw) {
+          cfma(acc, zc[u], xs[j]);
+          tp[j * SP + i] = cmul(zc[u], xa);
+        }
+      }
     }
     __syncthreads();
-    if (g < G) {
-      const V2* Zp = Za + (size_t)c0 * S + t;
-#pragma unroll 8
-      for (int j = g; j < cw; j += G) cfma(acc, Zp[(size_t)(j - g) * S], xs[j]);
+    // column sums of the products of the off-diagonal columns (fixed order:
+    // rows strided by TPC per thread, then a butterfly over the TPC lanes)
+    const int jlo = max(0, S - c0), nc = cw - jlo;
+    if (nc > 0) {
+      int TPC = 1;
+      while (TPC < WAVE && TPC * 2 * nc <= NT) TPC *= 2;
+      if (TPC == 1) {
+        for (int jj = t; jj < nc; jj += NT) {
+          const V2* col = tp + (jlo + jj) * SP;
+          V2 sum = cmk<T>(0, 0);
+          for (int r = 0; r < S; ++r) {
+            sum.x += col[r].x;
+            sum.y += col[r].y;
+          }
+          ta[c0 + jlo + jj] = sum;
+        }
+      } else {
+        const int jj = t / TPC, part = t % TPC;
+        V2 sum = cmk<T>(0, 0);
+        if (jj < nc) {
+          const V2* col = tp + (jlo + jj) * SP;
+          for (int r = part; r < S; r += TPC) {
+            sum.x += col[r].x;
+            sum.y += col[r].y;
+          }
+        }
+        for (int m = 1; m < TPC; m <<= 1) {
+          sum.x += __shfl_xor(sum.x, m);
+          sum.y += __shfl_xor(sum.y, m);
+        }
+        if (jj < nc && part == 0) ta[c0 + jlo + jj] = sum;
+      }
     }
   }
   red[t] = acc;
-  // weighted equivalent potentials of the leaf (channel weights of the
-  // mixed-potential split: w_xyz = -i eta k, w_div = +i eta / k)
-  const int J = 4 * Q;
-  if (RECV) {
-    for (int j = t; j < J; j += NT) {
-      const V2 ov = o[(size_t)a * J + j];
-      const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
-      ow[j] = cmul(ov, wv);
-    }
-  }
   __syncthreads();
-  // reduce the column groups (fixed order) -> near result of row r in red[r]
-  V2 yn = cmk<T>(0, 0);
+  // reduce the column groups (fixed order): Z_ab x_b summed over b >= a
   if (t < S) {
-    yn = red[t];
+    V2 yn = red[t];
     for (int gg = 1; gg < G; ++gg) {
       yn.x += red[gg * S + t].x;
       yn.y += red[gg * S + t].y;
     }
+    y[p0 + t] = yn;
   }
-  __syncthreads();
-  if (!RECV) {                            // near field only (reception added later)
-    if (t < S) y[p0 + t] = yn;
-    return;
-  }
-  if (t < S) red[t] = yn;
-  __syncthreads();
-  recv_rows<T>(V, ow, red, y, p0, S, J);
 }
 
-template <typename T, bool RECV>
-__global__ __launch_bounds__(NT) void k_near_recv(const typename C2<T>::type* __restrict__ Z,
+// near field of one right-hand side as a persistent grid that walks the leaves
+// (largest blocks first): beside the far-field stages it holds one workgroup
+// slot per CU and leaves the rest of every CU to them; with one workgroup per
+// leaf it is the near field of the serial form
+template <typename T>
+__global__ __launch_bounds__(NT) void k_near_half(const typename C2<T>::type* __restrict__ Z,
                                                   const int64_t* __restrict__ zoff,
                                                   const int32_t* __restrict__ leaf_ptr,
+                                                  const int32_t* __restrict__ nh_ptr,
                                                   const int32_t* __restrict__ near_ptr,
                                                   const int32_t* __restrict__ near_idx,
+                                                  const int32_t* __restrict__ toff,
                                                   const typename C2<T>::type* __restrict__ x,
-                                                  const typename C2<T>::type* __restrict__ V,
-                                                  const typename C2<T>::type* __restrict__ o,
-                                                  typename C2<T>::type* __restrict__ y, int Q,
-                                                  T w_re_xyz, T w_im_xyz, T w_re_d, T w_im_d,
+                                                  typename C2<T>::type* __restrict__ y,
+                                                  typename C2<T>::type* __restrict__ tpart, int64_t nleaf,
                                                   const int32_t* __restrict__ order) {
   using V2 = typename C2<T>::type;
-  __shared__ V2 xs[NEAR_CW];
+  __shared__ V2 xs[NEAR_HCW];
   __shared__ V2 red[NT];
+  __shared__ V2 tp[NEAR_TP_BYTES / sizeof(V2)];
   __shared__ int seg_col[MAX_NEAR + 1];
   __shared__ int seg_x[MAX_NEAR];
-  __shared__ __align__(16) V2 ow[4 * MAX_QL];            // weighted o_a
-  // largest leaves first (shorter tail)
-  near_leaf<T, RECV>(order[blockIdx.x], xs, red, seg_col, seg_x, ow, Z, zoff, leaf_ptr, near_ptr, near_idx, x, V, o,
-                     y, Q, w_re_xyz, w_im_xyz, w_re_d, w_im_d, order);
+  for (int64_t k = blockIdx.x; k < nleaf; k += gridDim.x) {
+    near_half_leaf<T>(order[k], xs, red, tp, seg_col, seg_x, Z, zoff, leaf_ptr, nh_ptr, near_ptr, near_idx, toff,
+                      x, y, tpart);
+    __syncthreads();                       // shared arrays reused by the next leaf
+  }
 }
 
-// reception of one right-hand side (Eq. 14), added to y: one workgroup per
-// leaf, the weighted potentials in LDS, one wave per row
+// reception of one right-hand side (Eq. 14) after the half-storage near field:
+// y_a += sum over near leaves b < a (increasing b) of Z_ba^T x_b, then the
+// received field; one workgroup per leaf, the weighted potentials in LDS
 template <typename T>
-__global__ __launch_bounds__(NT) void k_recv1(const typename C2<T>::type* __restrict__ V,
-                                              const typename C2<T>::type* __restrict__ o,
-                                              const int32_t* __restrict__ leaf_ptr,
-                                              typename C2<T>::type* __restrict__ y, int Q, T w_re_xyz,
-                                              T w_im_xyz, T w_re_d, T w_im_d) {
+__global__ __launch_bounds__(NT) void k_recv1h(const typename C2<T>::type* __restrict__ V,
+                                               const typename C2<T>::type* __restrict__ o,
+                                               const int32_t* __restrict__ leaf_ptr,
+                                               const int32_t* __restrict__ near_ptr,
+                                               const int32_t* __restrict__ nh_ptr,
+                                               const int32_t* __restrict__ tsrc,
+                                               const typename C2<T>::type* __restrict__ tpart,
+                                               typename C2<T>::type* __restrict__ y, int Q, T w_re_xyz,
+                                               T w_im_xyz, T w_re_d, T w_im_d) {
   using V2 = typename C2<T>::type;
   __shared__ __align__(16) V2 ow[4 * MAX_QL];
+  __shared__ V2 red[NT];
   const int a = blockIdx.x;
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int J = 4 * Q, t = threadIdx.x;
@@ -1150,32 +1225,18 @@ __global__ __launch_bounds__(NT) void k_recv1(const typename C2<T>::type* __rest
     const V2 wv = (j < 3 * Q) ? cmk<T>(w_re_xyz, w_im_xyz) : cmk<T>(w_re_d, w_im_d);
     ow[j] = cmul(ov, wv);
   }
-  __syncthreads();
-  recv_rows<T>(V, ow, nullptr, y, p0, S, J);
-}
-
-// near field only, as a persistent grid of a few workgroups per CU that walk
-// the leaves (largest first): run beside the far-field stages, it leaves most of
-// every CU to them
-template <typename T>
-__global__ __launch_bounds__(NT) void k_near_persist(const typename C2<T>::type* __restrict__ Z,
-                                                     const int64_t* __restrict__ zoff,
-                                                     const int32_t* __restrict__ leaf_ptr,
-                                                     const int32_t* __restrict__ near_ptr,
-                                                     const int32_t* __restrict__ near_idx,
-                                                     const typename C2<T>::type* __restrict__ x,
-                                                     typename C2<T>::type* __restrict__ y, int64_t nleaf,
-                                                     const int32_t* __restrict__ order) {
-  using V2 = typename C2<T>::type;
-  __shared__ V2 xs[NEAR_CW];
-  __shared__ V2 red[NT];
-  __shared__ int seg_col[MAX_NEAR + 1];
-  __shared__ int seg_x[MAX_NEAR];
-  for (int64_t i = blockIdx.x; i < nleaf; i += gridDim.x) {
-    near_leaf<T, false>(order[i], xs, red, seg_col, seg_x, nullptr, Z, zoff, leaf_ptr, near_ptr, near_idx, x,
-                        nullptr, nullptr, y, 0, T(0), T(0), T(0), T(0), order);
-    __syncthreads();                       // shared arrays reused by the next leaf
+  const int k0 = near_ptr[a], k1 = nh_ptr[a];
+  if (t < S) {
+    V2 v = y[p0 + t];
+    for (int k = k0; k < k1; ++k) {
+      const V2 u = tpart[tsrc[k] + t];
+      v.x += u.x;
+      v.y += u.y;
+    }
+    red[t] = v;
   }
+  __syncthreads();
+  recv_rows<T>(V, ow, red, y, p0, S, J);
 }
 
 template <typename V>
@@ -1658,8 +1719,9 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     hip_ok(hipStreamWaitEvent(d.side, d.ev_fork, 0));
     if (R == 1) {
       const unsigned nwg = (unsigned)std::min<int64_t>(d.nleaf, d.near_wgs > 0 ? d.near_wgs : 256);
-      k_near_persist<T><<<nwg, NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr,
-                                               d.near_idx, xl, yl, d.nleaf, d.near_order);
+      k_near_half<T><<<nwg, NT, 0, d.side>>>(static_cast<const V2*>(d.Zh), d.zh_off, d.leaf_ptr, d.nh_ptr,
+                                            d.near_ptr, d.near_idx, d.toff, xl, yl, static_cast<V2*>(d.tpart),
+                                            d.nleaf, d.near_order);
     } else {
       if constexpr (sizeof(T) == 4)
         k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff,
@@ -1739,17 +1801,21 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     hip_ok(hipStreamWaitEvent(st, d.ev_join, 0));
     if (tm) tm->mark(st, -1, L, 0);     // the reception's time starts after the join
     if (R == 1)
-      k_recv1<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off, d.leaf_ptr, yl, LL.Q,
-                                                   (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+      k_recv1h<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off, d.leaf_ptr,
+                                                    d.near_ptr, d.nh_ptr, d.tsrc,
+                                                    static_cast<const V2*>(d.tpart), yl, LL.Q, (T)d.w[0],
+                                                    (T)d.w[1], (T)d.w[2], (T)d.w[3]);
     else
       k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V),
                                                                    o + LL.s_off * R, d.leaf_ptr, yl, LL.Q, R, d.n,
                                                                    (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
   } else if (R == 1) {
-    k_near_recv<T, true><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff, d.leaf_ptr,
-                                                           d.near_ptr, d.near_idx, xl, static_cast<const V2*>(d.V),
-                                                           o + LL.s_off, yl, LL.Q, (T)d.w[0], (T)d.w[1], (T)d.w[2],
-                                                           (T)d.w[3], d.near_order);
+    k_near_half<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Zh), d.zh_off, d.leaf_ptr, d.nh_ptr,
+                                                    d.near_ptr, d.near_idx, d.toff, xl, yl,
+                                                    static_cast<V2*>(d.tpart), d.nleaf, d.near_order);
+    k_recv1h<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off, d.leaf_ptr, d.near_ptr,
+                                                  d.nh_ptr, d.tsrc, static_cast<const V2*>(d.tpart), yl, LL.Q,
+                                                  (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
   } else {
     if constexpr (sizeof(T) == 4) {
       k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,

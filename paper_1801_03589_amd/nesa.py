@@ -40,7 +40,8 @@ class FarParams(C.Structure):
 class TreeInfo(C.Structure):
     _fields_ = [("n_rwg", C.c_int64), ("n_tri", C.c_int64), ("L", C.c_int), ("l0", C.c_int),
                 ("n_box", C.c_int64 * 32), ("near_entries", C.c_int64),
-                ("n_pairs", C.c_int64 * 32), ("Q", C.c_int * 32), ("max_leaf", C.c_int64)]
+                ("n_pairs", C.c_int64 * 32), ("Q", C.c_int * 32), ("max_leaf", C.c_int64),
+                ("near_entries_half", C.c_int64), ("near_transposed", C.c_int64)]
 
 
 class GmresParams(C.Structure):
@@ -184,7 +185,8 @@ class Tree(_Handle):
         nl = i.L - i.l0 + 1
         return {"n_rwg": i.n_rwg, "n_tri": i.n_tri, "L": i.L, "l0": i.l0,
                 "n_box": list(i.n_box[:nl]), "n_pairs": list(i.n_pairs[:nl]),
-                "near_entries": i.near_entries, "max_leaf": i.max_leaf}
+                "near_entries": i.near_entries, "max_leaf": i.max_leaf,
+                "near_entries_half": i.near_entries_half, "near_transposed": i.near_transposed}
 
     def bodies(self):
         """Canonical RWG range of every body: array [nbodies + 1]."""

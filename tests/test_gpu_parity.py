@@ -95,6 +95,25 @@ def test_matvec_several_rhs_leaf_order_and_repeatable(torch_dev, nesa):
     assert np.array_equal(Y, Y2)
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_serial_form_matches_overlapped(torch_dev, nesa, prec):
+    """The stage-timed product (half-storage near field with one workgroup per
+    leaf, every stage on one stream) and the overlapped one (persistent
+    near-field grid on a side stream, transposed near blocks added after the
+    join) do the same arithmetic per leaf in the same order: identical output."""
+    ref, tr, near, far = _case(nesa, "box")
+    op = nesa.op_create(tr, near, far, nesa.C128 if prec == "c128" else nesa.C64)
+    dt = torch_dev.complex128 if prec == "c128" else torch_dev.complex64
+    x = synth.complex_normal(ref.m.n, 5)[tr.perm()]
+    y = _run(torch_dev, nesa, op, x, leaf=True)
+    xd = torch_dev.from_numpy(np.ascontiguousarray(x)).to(dt).cuda()
+    yd = torch_dev.empty_like(xd)
+    ms = nesa.matvec_phase_times(op, xd, yd)
+    torch_dev.cuda.synchronize()
+    assert np.all(ms >= 0)
+    assert np.array_equal(yd.cpu().numpy().astype(np.complex128), y)
+
+
 def test_matvec_edge_cases(torch_dev, nesa):
     # tiny body: a single level with no far pairs (product = near field only)
     v, t = synth.icosphere(3, 0.2)

@@ -80,6 +80,31 @@ def test_near_entries_match_oracle(nesa, sphere1, dense1):
         assert np.abs(z - dense1[r, cols]).max() <= 1e-13 * np.abs(dense1[r, cols]).max()
 
 
+@pytest.mark.parametrize("leaf", [0.25, 0.125])
+def test_half_storage_counts_match_oracle(nesa, sphere1, leaf):
+    """Reciprocity half storage keeps, per leaf a, the blocks Z_ab of its near
+    leaves b >= a in leaf order (Morton order of the leaf keys): sum_a S_a^2
+    plus S_a S_b once per neighbouring pair, and Z_ab^T x_a yields S_b outputs
+    per pair a < b.  Counted here on the oracle's own tree."""
+    v, t = sphere1
+    info = nesa.build_tree(v, t, leaf).info()
+    m = efie.RWG(v, t)
+    ot = Octree(v, m.midpoints(), leaf=leaf)
+
+    def morton(k):
+        return sum(((int(k[d]) >> b) & 1) << (3 * b + d) for b in range(21) for d in range(3))
+    nleaf = len(ot.boxes[ot.L])
+    rank = {a: r for r, a in enumerate(sorted(range(nleaf), key=lambda a: morton(ot.boxes[ot.L][a])))}
+    S = [len(ot.leaf_rwgs[a]) for a in range(nleaf)]
+    full = sum(S[a] * sum(S[b] for b in ot.near[a]) for a in range(nleaf))
+    half = sum(S[a] * sum(S[b] for b in ot.near[a] if rank[b] >= rank[a]) for a in range(nleaf))
+    trans = sum(S[b] for a in range(nleaf) for b in ot.near[a] if rank[b] > rank[a])
+    diag = sum(s * s for s in S)
+    assert 2 * half - diag == full          # every off-diagonal block once
+    assert (info["near_entries"], info["near_entries_half"], info["near_transposed"]) == (full, half, trans)
+    assert half < 0.6 * full
+
+
 def test_rhs_matches_oracle(nesa, sphere1, rwg1):
     tr = nesa.build_tree(*sphere1, 0.25)
     kh = np.array([[0, 0, 1.0], [0.6, 0, 0.8]])
