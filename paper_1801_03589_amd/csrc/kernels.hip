@@ -1042,7 +1042,9 @@ constexpr int NEAR_TP_BYTES = 36 * 1024;      // LDS of the transposed products 
 // Sub-chunks of CT columns; each thread holds at most U of a sub-chunk's near
 // entries, loaded into registers while the previous sub-chunk is computed and
 // reduced (the loads' latency hides behind that work and the barriers).
-template <typename T>
+// HALF = false: the plain product of one leaf's full block (columns: the whole
+// near list), no transposed outputs; `tp`, `nh_ptr`, `toff`, `tpart` unused.
+template <typename T, bool HALF>
 __device__ __forceinline__ void near_half_leaf(const int a, typename C2<T>::type* xs, typename C2<T>::type* red,
                                                typename C2<T>::type* tp, int* seg_col, int* seg_x,
                                                const typename C2<T>::type* __restrict__ Z,
@@ -1059,7 +1061,7 @@ __device__ __forceinline__ void near_half_leaf(const int a, typename C2<T>::type
   constexpr int TP_N = NEAR_TP_BYTES / (int)sizeof(V2);
   constexpr int U = sizeof(T) == 4 ? 16 : 8;
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
-  const int n0 = nh_ptr[a], nn = near_ptr[a + 1] - n0;
+  const int n0 = HALF ? nh_ptr[a] : near_ptr[a], nn = near_ptr[a + 1] - n0;
   if (threadIdx.x == 0) {
     int c = 0;
     for (int k = 0; k < nn; ++k) {
@@ -1076,10 +1078,10 @@ __device__ __forceinline__ void near_half_leaf(const int a, typename C2<T>::type
   const int G = NT / S;                    // column groups of S threads (S <= NT checked on the host)
   const int t = threadIdx.x, g = t / S, i = t - g * S;
   const bool row_ok = g < G;
-  const V2 xa = row_ok ? x[p0 + i] : cmk<T>(0, 0);
+  const V2 xa = HALF && row_ok ? x[p0 + i] : cmk<T>(0, 0);
   const int SP = S | 1;                    // odd LDS stride of a column of products
-  const int CT = min(min(NEAR_HCW, TP_N / SP), U * G);   // columns per sub-chunk
-  V2* ta = tpart + toff[a] - S;            // Z_ab^T x_a of column col >= S goes to ta[col]
+  const int CT = HALF ? min(min(NEAR_HCW, TP_N / SP), U * G) : min(NEAR_HCW, U * G);   // columns per sub-chunk
+  V2* ta = HALF ? tpart + toff[a] - S : nullptr;   // Z_ab^T x_a of column col >= S goes to ta[col]
   V2 zr[U], xr[2];
   // loads of the sub-chunk at column c0 into registers
   auto fetch = [&](int c0) {
@@ -1120,10 +1122,11 @@ __device__ __forceinline__ void near_half_leaf(const int a, typename C2<T>::type
         const int j = g + u * G;
         if (j < cw) {
           cfma(acc, zc[u], xs[j]);
-          tp[j * SP + i] = cmul(zc[u], xa);
+          if constexpr (HALF) tp[j * SP + i] = cmul(zc[u], xa);
         }
       }
     }
+    if constexpr (!HALF) continue;
     __syncthreads();
     // column sums of the products of the off-diagonal columns (fixed order:
     // rows strided by TPC per thread, then a butterfly over the TPC lanes)
@@ -1195,10 +1198,29 @@ __global__ __launch_bounds__(NT) void k_near_half(const typename C2<T>::type* __
   __shared__ int seg_col[MAX_NEAR + 1];
   __shared__ int seg_x[MAX_NEAR];
   for (int64_t k = blockIdx.x; k < nleaf; k += gridDim.x) {
-    near_half_leaf<T>(order[k], xs, red, tp, seg_col, seg_x, Z, zoff, leaf_ptr, nh_ptr, near_ptr, near_idx, toff,
-                      x, y, tpart);
+    near_half_leaf<T, true>(order[k], xs, red, tp, seg_col, seg_x, Z, zoff, leaf_ptr, nh_ptr, near_ptr, near_idx,
+                            toff, x, y, tpart);
     __syncthreads();                       // shared arrays reused by the next leaf
   }
+}
+
+// y = A x for one right-hand side with an arena A in the full near-block layout
+// (the Schwarz preconditioner): one workgroup per leaf
+template <typename T>
+__global__ __launch_bounds__(NT) void k_near_full1(const typename C2<T>::type* __restrict__ Z,
+                                                   const int64_t* __restrict__ zoff,
+                                                   const int32_t* __restrict__ leaf_ptr,
+                                                   const int32_t* __restrict__ near_ptr,
+                                                   const int32_t* __restrict__ near_idx,
+                                                   const typename C2<T>::type* __restrict__ x,
+                                                   typename C2<T>::type* __restrict__ y) {
+  using V2 = typename C2<T>::type;
+  __shared__ V2 xs[NEAR_HCW];
+  __shared__ V2 red[NT];
+  __shared__ int seg_col[MAX_NEAR + 1];
+  __shared__ int seg_x[MAX_NEAR];
+  near_half_leaf<T, false>(blockIdx.x, xs, red, nullptr, seg_col, seg_x, Z, zoff, leaf_ptr, nullptr, near_ptr,
+                           near_idx, nullptr, x, y, nullptr);
 }
 
 // reception of one right-hand side (Eq. 14) after the half-storage near field:
@@ -1867,6 +1889,11 @@ void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st
 template <typename T>
 void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void* y, hipStream_t st, int nrhs) {
   using V2 = typename C2<T>::type;
+  if (nrhs == 1) {
+    k_near_full1<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(arena), d.zoff, d.leaf_ptr, d.near_ptr,
+                                                      d.near_idx, static_cast<const V2*>(x), static_cast<V2*>(y));
+    return;
+  }
   const unsigned rblk = (unsigned)((nrhs + RB - 1) / RB);
   k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(arena), d.zoff, d.leaf_ptr,
                                                                 d.near_ptr, d.near_idx, static_cast<const V2*>(x),
