@@ -730,6 +730,9 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   }
   hip_check(hipEventCreateWithFlags(&d.ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
   hip_check(hipEventCreateWithFlags(&d.ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+  hip_check(hipStreamCreateWithFlags(&d.side2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  hip_check(hipEventCreateWithFlags(&d.ev_fork2, hipEventDisableTiming), "hipEventCreateWithFlags");
+  hip_check(hipEventCreateWithFlags(&d.ev_join2, hipEventDisableTiming), "hipEventCreateWithFlags");
   ensure_all_tiles<T>(op, d, 1);
 }
 
@@ -768,9 +771,10 @@ struct nesa_mlp {
 nesa_op::~nesa_op() {
   for (nesa_mlp* m : nets) m->op = nullptr;
   (void)hipDeviceSynchronize();
-  for (auto* dv : {&f.side, &d.side})
+  for (auto* dv : {&f.side, &d.side, &f.side2, &d.side2})
     if (*dv) (void)hipStreamDestroy(*dv);
-  for (auto* ev : {&f.ev_fork, &f.ev_join, &d.ev_fork, &d.ev_join})
+  for (auto* ev : {&f.ev_fork, &f.ev_join, &d.ev_fork, &d.ev_join, &f.ev_fork2, &f.ev_join2, &d.ev_fork2,
+                   &d.ev_join2})
     if (*ev) (void)hipEventDestroy(*ev);
   for (void* p : allocs) (void)hipFree(p);
 }

@@ -91,6 +91,8 @@ struct DevOp {
   hipStream_t side = nullptr;    // non-blocking stream of the near field (untimed products)
   int near_wgs = 0;              // workgroups of the persistent near-field grid (0: 256)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side2 = nullptr;   // second side stream: the finest level's translations (untimed products)
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
   int max_nrhs = 1;              // right-hand sides the work buffers hold
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;

@@ -1764,6 +1764,26 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   // the near field starts once radiation (also HBM-bound) is done, and runs
   // beside the transfers and translations
   if (overlap) fork_near();
+  // the finest level's translations (the largest launch) need only the
+  // radiated sources: on a second side stream they run beside the upward pass
+  // (small, latency-bound launches) and the coarser levels' translations; the
+  // downward step into the finest level waits for them.  (Moving the next
+  // level there as well, after the first upward step, measured slower: it then
+  // competes with the coarse levels' translations.)
+  auto side_ok = [&](int l) {
+    return overlap && !tm && mfma && d.side2 != nullptr && l > l0 && l == L && d.lev[l - l0].npairs > 0;
+  };
+  auto fork_trans = [&](int l, hipEvent_t fork, hipEvent_t join) {
+    const auto& lv = d.lev[l - l0];
+    hip_ok(hipEventRecord(fork, st));
+    hip_ok(hipStreamWaitEvent(d.side2, fork, 0));
+    launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, d.side2, true);
+    k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, d.side2>>>(static_cast<const V2*>(lv.pair_out),
+                                                                        o + lv.s_off * R, lv.il_ptr,
+                                                                        lv.il_ptr + 1, NC * lv.Q);
+    hip_ok(hipEventRecord(join, d.side2));
+  };
+  if (side_ok(L)) fork_trans(L, d.ev_fork2, d.ev_join2);
   for (int l = L; l > l0; --l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
@@ -1784,6 +1804,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   if (tm) tm->mark(st, 2, -1, 0);
   for (int l = l0; l <= L; ++l) {
     const auto& lv = d.lev[l - l0];
+    if (side_ok(l)) continue;
     if (mfma && lv.npairs > 0) {
       // each level's sums right after its GEMM, while its per-pair outputs are
       // still in the last-level cache (one launch for all levels measured slower)
@@ -1807,6 +1828,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   for (int l = l0 + 1; l <= L; ++l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
+    if (side_ok(l)) hip_ok(hipStreamWaitEvent(st, d.ev_join2, 0));
     if (mfma) {
       launch_tiles(c.down, R, o + p.s_off * R, o + c.s_off * R, st, false);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
