@@ -1317,17 +1317,25 @@ __global__ __launch_bounds__(NT) void k_radiate_multi(const V2* __restrict__ V, 
   }
 }
 
+// near field of several right-hand sides (RB per workgroup) with an arena in
+// the full near-block layout: sub-chunks of CT columns, each thread holding at
+// most U near entries of a sub-chunk and RB x CW / NT x values, loaded into
+// registers while the previous sub-chunk is computed; x staged in LDS as
+// [column][right-hand side] so that one entry meets its RB values in a few
+// wide LDS reads
 template <typename V2>
 __global__ __launch_bounds__(NT) void k_near_multi(const V2* __restrict__ Z, const int64_t* __restrict__ zoff,
                                                    const int32_t* __restrict__ leaf_ptr,
                                                    const int32_t* __restrict__ near_ptr,
                                                    const int32_t* __restrict__ near_idx, const V2* __restrict__ x,
                                                    V2* __restrict__ y, int R, int64_t n) {
-  constexpr int CW = 256;
-  __shared__ V2 xs[RB][CW];
-  __shared__ V2 red[RB][NT];
+  constexpr int CW = 256;              // most columns per sub-chunk
+  constexpr int U = 8;                 // near entries per thread per sub-chunk
+  constexpr int XE = CW * RB / NT;     // x values per thread per sub-chunk
+  __shared__ V2 xs[CW * RB];           // [column][rhs]; then the column groups' sums [rhs][NT]
   __shared__ int seg_col[MAX_NEAR + 1];
   __shared__ int seg_x[MAX_NEAR];
+  static_assert(CW * RB == RB * NT, "the group sums reuse the staging array");
   const int a = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
   const int p0 = leaf_ptr[a], S = leaf_ptr[a + 1] - p0;
   const int n0 = near_ptr[a], nn = near_ptr[a + 1] - n0;
@@ -1346,38 +1354,68 @@ __global__ __launch_bounds__(NT) void k_near_multi(const V2* __restrict__ Z, con
   const V2* Za = Z + zoff[a];
   const int G = NT / S;
   const int t = threadIdx.x, g = t / S;
-  V2 acc[RB];
-  for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = 0;
-  for (int c0 = 0; c0 < W; c0 += CW) {
-    const int cw = min(CW, W - c0);
-    __syncthreads();
-    for (int e = t; e < RB * CW; e += NT) {
-      const int r = e / CW, j = e % CW;
+  const bool row_ok = g < G;
+  const int CT = min(CW, U * G);
+  V2 zr[U], xr[XE];
+  auto fetch = [&](int c0) {
+    const int cw = min(CT, W - c0);
+    const V2* Zp = Za + (size_t)c0 * S + t;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = g + u * G;
+      if (row_ok && j < cw) zr[u] = Zp[(size_t)(u * G) * S];
+    }
+#pragma unroll
+    for (int e = 0; e < XE; ++e) {
+      const int idx = t + e * NT, r = idx / CT, j = idx - r * CT;
       if (r < nr && j < cw) {
         const int col = c0 + j;
         int k = 0;
         while (seg_col[k + 1] <= col) ++k;
-        xs[r][j] = x[(size_t)(r0 + r) * n + seg_x[k] + (col - seg_col[k])];
+        xr[e] = x[(size_t)(r0 + r) * n + seg_x[k] + (col - seg_col[k])];
       }
     }
-    __syncthreads();
-    if (g < G) {
-      const V2* Zp = Za + (size_t)c0 * S + t;
-      for (int j = g; j < cw; j += G) {
-        const V2 zv = Zp[(size_t)(j - g) * S];
+  };
+  V2 acc[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) cfma(acc[r], zv, xs[r][j]);
+  for (int r = 0; r < RB; ++r) acc[r].x = acc[r].y = 0;
+  if (W > 0) fetch(0);
+  for (int c0 = 0; c0 < W; c0 += CT) {
+    const int cw = min(CT, W - c0);
+    __syncthreads();                   // the previous sub-chunk's x consumed
+#pragma unroll
+    for (int e = 0; e < XE; ++e) {
+      const int idx = t + e * NT, r = idx / CT, j = idx - r * CT;
+      if (r < nr && j < cw) xs[j * RB + r] = xr[e];
+    }
+    __syncthreads();
+    V2 zc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) zc[u] = zr[u];
+    if (c0 + CT < W) fetch(c0 + CT);
+    if (row_ok) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = g + u * G;
+        if (j < cw) {
+          const V2* xj = xs + j * RB;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) cfma(acc[r], zc[u], xj[r]);
+        }
       }
     }
   }
-  for (int r = 0; r < RB; ++r) red[r][t] = acc[r];
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RB; ++r) xs[r * NT + t] = acc[r];
+  __syncthreads();
+  // reduce the column groups (fixed order)
   for (int e = t; e < nr * S; e += NT) {
     const int r = e / S, m = e % S;
-    V2 v = red[r][m];
+    V2 v = xs[r * NT + m];
     for (int gg = 1; gg < G; ++gg) {
-      v.x += red[r][gg * S + m].x;
-      v.y += red[r][gg * S + m].y;
+      v.x += xs[r * NT + gg * S + m].x;
+      v.y += xs[r * NT + gg * S + m].y;
     }
     y[(size_t)(r0 + r) * n + p0 + m] = v;
   }
