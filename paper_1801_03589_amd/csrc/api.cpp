@@ -590,21 +590,46 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     dl.s_off = soff;
     soff += lv.nbox * 4 * fl.Q;
     dl.npairs = (int64_t)lv.il_src.size();
-    // compact translation table
-    std::vector<int32_t> compact(t.nslot(), -1);
-    std::vector<cd> Dc;
+    // compact translation table of the offset slots that occur, assembled on
+    // the device: column-major, for complex64 the rows padded for the row blocking
+    std::vector<int32_t> compact(t.nslot(), -1), offs;
     int nused = 0;
+    const int SW = t.slot_w(), SH = SW / 2;
     for (int s = 0; s < t.nslot(); ++s) {
       if (!fl.slot_used[s]) continue;
       compact[s] = nused++;
-      // column-major; for complex64 the rows are padded for the row blocking
-      const cd* Ds = &fl.D[(size_t)s * fl.Q * fl.Q];
-      int Qr = fl.Q;
-      if (sizeof(T) == 4) Qr = nesa::row_alloc(fl.Q);
-      for (int q = 0; q < fl.Q; ++q)
-        for (int p = 0; p < Qr; ++p) Dc.push_back(p < fl.Q ? Ds[(size_t)p * fl.Q + q] : cd(0, 0));
+      offs.push_back(s / (SW * SW) - SH);
+      offs.push_back((s / SW) % SW - SH);
+      offs.push_back(s % SW - SH);
     }
-    dl.D = upload_complex<T>(op, Dc);
+    const int Qr = sizeof(T) == 4 ? nesa::row_alloc(fl.Q) : fl.Q;
+    std::vector<cd> Dc;   // host copy (split precision: its bf16 planes are made on the host)
+    {
+      std::vector<double> Eh(2 * fl.E.size());
+      for (size_t i = 0; i < fl.E.size(); ++i) {
+        Eh[2 * i] = fl.E[i].real();
+        Eh[2 * i + 1] = fl.E[i].imag();
+      }
+      const double* Ed = upload(op, Eh);
+      const int32_t* offd = offs.empty() ? nullptr : upload(op, offs);
+      const size_t cnt = (size_t)nused * fl.Q * Qr;
+      if (op->precision == NESA_C64_SPLIT) {
+        void* tmp = nullptr;
+        if (cnt > 0) {
+          hip_check(hipMalloc(&tmp, cnt * sizeof(cd)), "hipMalloc");
+          nesa::launch_fill_translation(Ed, offd, nused, fl.Q, Qr, lv.side, fr.k, tmp, true, nullptr);
+          hip_check(hipGetLastError(), "kernel launch");
+          Dc.resize(cnt);
+          hip_check(hipMemcpy(Dc.data(), tmp, cnt * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");
+          hip_check(hipFree(tmp), "hipFree");
+        }
+        dl.D = upload_complex<T>(op, Dc);
+      } else {
+        dl.D = dev_alloc(op, std::max<size_t>(cnt, 1) * 2 * sizeof(T));
+        nesa::launch_fill_translation(Ed, offd, nused, fl.Q, Qr, lv.side, fr.k, dl.D, sizeof(T) == 8, nullptr);
+        hip_check(hipGetLastError(), "kernel launch");
+      }
+    }
     std::vector<int32_t> slot(lv.il_slot.size());
     for (size_t i = 0; i < slot.size(); ++i) slot[i] = compact[lv.il_slot[i]];
     dl.il_slot = upload(op, slot);

@@ -15,8 +15,8 @@
 // sphere of radius r_e and 4Q check points on radius r_c = max(box side, 1.05 r_e)
 // (golden-angle spirals); the fitting operator R = argmin ||G(X,E) R - I||^2 +
 // lambda^2 ||R||^2 (lambda = tau * sigma_max) is computed by Householder QR of
-// [G; lambda I]; V = R G_src, C = R_parent G(X_parent, E_child + delta),
-// D_ab = G(E_a, E_b).
+// [G; lambda I]; V = R G_src, C = R_parent G(X_parent, E_child + delta).
+// D_ab = G(E_a, E_b) is assembled on the device (kernel k_fill_translation).
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -505,22 +505,13 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
         }
     });
   }
-  // translation matrices D per offset slot actually used
-  const int W = t.slot_w(), H = W / 2;
+  // translation matrices D: only the offset slots that occur are recorded here;
+  // their entries D_d[p][q] = g(E_p + d - E_q) are computed on the device when
+  // an operator is created
   for (int l = t.l0; l <= t.L; ++l) {
     FarLevel& fl = F->lev[l - t.l0];
-    const Level& lv = t.level(l);
     fl.slot_used.assign(t.nslot(), 0);
-    for (int32_t s : lv.il_slot) fl.slot_used[s] = 1;
-    fl.D.assign((size_t)t.nslot() * fl.Q * fl.Q, cd(0, 0));
-    parallel_for(t.nslot(), [&](int64_t s) {
-      if (!fl.slot_used[s]) return;
-      int dx = (int)(s / (W * W)) - H, dy = (int)((s / W) % W) - H, dz = (int)(s % W) - H;
-      P3 d = {dx * lv.side, dy * lv.side, dz * lv.side};
-      CMat G = gmat(fl.E, d, fl.E, k);
-      for (int p = 0; p < fl.Q; ++p)
-        for (int q = 0; q < fl.Q; ++q) fl.D[((size_t)s * fl.Q + p) * fl.Q + q] = G(p, q);
-    });
+    for (int32_t s : t.level(l).il_slot) fl.slot_used[s] = 1;
   }
   return F.release();
 }

@@ -161,6 +161,12 @@ template <typename T>
 void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st);
 template <typename T>
 void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st);
+// D_u[p][q] = g(E_p + off_u side - E_q) for the nused offsets off [nused][3]
+// (cells) and the level's equivalent points E [Q][3] complex (re, im pairs),
+// column-major [u][q][Qr] with zero rows p >= Q; FP64 math, stored as complex128
+// (fp64) or complex64.  All pointers are device pointers.
+void launch_fill_translation(const double* E, const int32_t* off, int nused, int Q, int Qr, double side, double k,
+                             void* D, bool fp64, hipStream_t st);
 // one grouped GEMM plan for nrhs right-hand sides (autotuner timing)
 void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st, bool translation);
 // y = arena x with an arena in the near-block layout (leaf order, one RHS)

@@ -1261,6 +1261,52 @@ __global__ __launch_bounds__(NT) void k_recv1h(const typename C2<T>::type* __res
   recv_rows<T>(V, ow, red, y, p0, S, J);
 }
 
+// ------------------------------------------------------------------ translation operators
+// D_u[p][q] = g(E_p + d_u - E_q), g = exp(-i k R) / (4 pi R), R the principal
+// square root of the summed squared coordinate differences (Sec. 2, Eq. 6; the
+// equivalent points E are complex).  Computed in FP64; stored column-major
+// [u][q][Qr], rows p >= Q zero (padding of the row blocking).
+template <typename V2>
+__global__ void k_fill_translation(const double* __restrict__ E, const int32_t* __restrict__ off, double side,
+                                   double k, int Q, int Qr, int64_t total, V2* __restrict__ D) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= total) return;
+  const int p = (int)(i % Qr);
+  const int64_t rest = i / Qr;
+  const int q = (int)(rest % Q);
+  const int64_t u = rest / Q;
+  V2 out;
+  out.x = 0;
+  out.y = 0;
+  if (p < Q) {
+    double zr = 0, zi = 0;                 // sum_d (E_pd + off_d side - E_qd)^2
+    for (int dd = 0; dd < 3; ++dd) {
+      const double er = E[(3 * p + dd) * 2] + off[3 * u + dd] * side - E[(3 * q + dd) * 2];
+      const double ei = E[(3 * p + dd) * 2 + 1] - E[(3 * q + dd) * 2 + 1];
+      zr += er * er - ei * ei;
+      zi += 2.0 * er * ei;
+    }
+    // principal square root, the cancellation-free branch of each half plane
+    const double m = hypot(zr, zi);
+    double a, b;
+    if (zr >= 0) {
+      a = sqrt(0.5 * (m + zr));
+      b = a > 0 ? zi / (2.0 * a) : 0.0;
+    } else {
+      b = copysign(sqrt(0.5 * (m - zr)), zi);
+      a = zi / (2.0 * b);
+    }
+    // exp(-i k R) / (4 pi R), R = a + i b
+    double sn, cs;
+    sincos(k * a, &sn, &cs);
+    const double e = exp(k * b) / (4.0 * 3.14159265358979323846 * (a * a + b * b));
+    const double nr = e * cs, ni = -e * sn;   // exp(-ikR) |R|^-2 / (4 pi) ...
+    out.x = nr * a + ni * b;                  // ... times conj(R)
+    out.y = ni * a - nr * b;
+  }
+  D[i] = out;
+}
+
 template <typename V>
 __global__ void k_fill_zero(V* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -1958,6 +2004,17 @@ void launch_near_apply(const DevOp<T>& d, const void* arena, const void* x, void
   k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(arena), d.zoff, d.leaf_ptr,
                                                                 d.near_ptr, d.near_idx, static_cast<const V2*>(x),
                                                                 static_cast<V2*>(y), nrhs, d.n);
+}
+
+void launch_fill_translation(const double* E, const int32_t* off, int nused, int Q, int Qr, double side, double k,
+                             void* D, bool fp64, hipStream_t st) {
+  const int64_t total = (int64_t)nused * Q * Qr;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)((total + NT - 1) / NT);
+  if (fp64)
+    k_fill_translation<double2><<<grid, NT, 0, st>>>(E, off, side, k, Q, Qr, total, static_cast<double2*>(D));
+  else
+    k_fill_translation<float2><<<grid, NT, 0, st>>>(E, off, side, k, Q, Qr, total, static_cast<float2*>(D));
 }
 
 template <typename T>

@@ -91,8 +91,7 @@ struct FarLevel {
   double re = 0, rc = 0;
   std::vector<cd> E, X;             // [Q][3] on the complex radius re (1 + i eps), [M][3] on rc
   std::vector<cd> Cup;              // [8][Q_{l-1}][Q_l] row-major (l > l0)
-  std::vector<cd> D;                // [nslot][Q][Q] row-major, D[p][q] = g(E_p + d - E_q)
-  std::vector<uint8_t> slot_used;
+  std::vector<uint8_t> slot_used;   // offset slots of the level's translations (D assembled on the device)
 };
 
 struct Far {
