@@ -574,7 +574,40 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     d.tsrc = upload(op, tsrc);
     d.tpart = dev_alloc(op, (size_t)std::max<int64_t>(toff[nleaf], 1) * 2 * sizeof(T));
   }
-  d.V = upload_complex<T>(op, fr.V);
+  {
+    // radiation matrices V = R_L G_src, assembled on the device
+    const nesa::FarLevel& fl = fr.lev[t.L - t.l0];
+    const nesa::Rwg& rw = t.rwg;
+    nesa::RadGeo g;
+    g.perm = d.perm;
+    g.leaf_ptr = d.leaf_ptr;
+    g.tri = upload(op, to_i32(rw.tri));
+    g.freev = upload(op, to_i32(rw.freev));
+    g.len = upload(op, rw.len);
+    g.area = upload(op, rw.area);
+    g.qp = upload(op, rw.qp);
+    g.v = upload(op, rw.v);
+    std::vector<double> cen(3 * d.nleaf), X(3 * fl.M), Rt(2 * fr.RLt.size());
+    for (int64_t b = 0; b < d.nleaf; ++b) {
+      const auto c = t.center(t.L, b);
+      for (int e = 0; e < 3; ++e) cen[3 * b + e] = c[e];
+    }
+    for (int j = 0; j < 3 * fl.M; ++j) X[j] = fl.X[j].real();
+    for (size_t i = 0; i < fr.RLt.size(); ++i) {
+      Rt[2 * i] = fr.RLt[i].real();
+      Rt[2 * i + 1] = fr.RLt[i].imag();
+    }
+    g.centre = upload(op, cen);
+    g.X = upload(op, X);
+    g.Rt = reinterpret_cast<const double2*>(upload(op, Rt));
+    g.k = fr.k;
+    g.Q = fl.Q;
+    g.M = fl.M;
+    if ((int64_t)fr.RLt.size() != (int64_t)fl.Q * fl.M) throw Error(NESA_EINVAL, "fitting operator size mismatch");
+    d.V = dev_alloc(op, (size_t)d.n * 4 * fl.Q * 2 * sizeof(T));
+    nesa::launch_fill_radiation(g, d.nleaf, d.V, sizeof(T) == 8, nullptr);
+    hip_check(hipGetLastError(), "kernel launch");
+  }
   d.w[0] = 0.0;
   d.w[1] = -fr.eta * fr.k;
   d.w[2] = 0.0;

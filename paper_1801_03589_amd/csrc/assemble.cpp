@@ -15,8 +15,9 @@
 // sphere of radius r_e and 4Q check points on radius r_c = max(box side, 1.05 r_e)
 // (golden-angle spirals); the fitting operator R = argmin ||G(X,E) R - I||^2 +
 // lambda^2 ||R||^2 (lambda = tau * sigma_max) is computed by Householder QR of
-// [G; lambda I]; V = R G_src, C = R_parent G(X_parent, E_child + delta).
-// D_ab = G(E_a, E_b) is assembled on the device (kernel k_fill_translation).
+// [G; lambda I]; C = R_parent G(X_parent, E_child + delta).  V = R_L G_src and
+// D_ab = G(E_a, E_b) are assembled on the device (kernels k_fill_radiation,
+// k_fill_translation).
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -441,51 +442,9 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
     fibonacci(fl.M, cd(fl.rc, 0.0), fl.X);
     R[l - t.l0] = tikhonov_fit(gmat(fl.X, {0, 0, 0}, fl.E, k), tau);
   }
-  // radiation matrices V: [pos][4][Q_L]
-  {
-    const FarLevel& fl = F->lev[nl - 1];
-    const CMat& RL = R[nl - 1];
-    const int Q = fl.Q, M = fl.M;
-    F->V.assign((size_t)r.n * 4 * Q, cd(0, 0));
-    parallel_for(LL.nbox, [&](int64_t b) {
-      auto c = t.center(t.L, b);
-      const int64_t p0 = t.leaf_ptr[b], S = t.leaf_ptr[b + 1] - p0;
-      // G_src[ch][j][i] for check point j, RWG i of the leaf
-      std::vector<cd> Gs((size_t)4 * M * S, cd(0, 0));
-      for (int64_t i = 0; i < S; ++i) {
-        const int64_t n = t.perm[p0 + i];
-        for (int s = 0; s < 2; ++s) {
-          const int64_t T = r.tri[2 * n + s];
-          const double sg = (s == 0 ? 1.0 : -1.0);
-          const int64_t fv = r.freev[2 * n + s];
-          P3 pv = {r.v[3 * fv], r.v[3 * fv + 1], r.v[3 * fv + 2]};
-          const double cv = sg * r.len[n] / (2.0 * r.area[T]);
-          const double cdv = sg * r.len[n] / r.area[T];
-          const double w = r.area[T] / 3.0;
-          for (int q = 0; q < 3; ++q) {
-            P3 rq = {r.qp[9 * T + 3 * q], r.qp[9 * T + 3 * q + 1], r.qp[9 * T + 3 * q + 2]};
-            P3 ph = mul(sub(rq, pv), cv);
-            for (int j = 0; j < M; ++j) {
-              P3 x = {c[0] + fl.X[3 * j].real(), c[1] + fl.X[3 * j + 1].real(),
-                      c[2] + fl.X[3 * j + 2].real()};
-              cd g = green(norm(sub(x, rq)), k) * w;
-              Gs[((size_t)0 * M + j) * S + i] += g * ph.x;
-              Gs[((size_t)1 * M + j) * S + i] += g * ph.y;
-              Gs[((size_t)2 * M + j) * S + i] += g * ph.z;
-              Gs[((size_t)3 * M + j) * S + i] += g * cdv;
-            }
-          }
-        }
-      }
-      for (int ch = 0; ch < 4; ++ch)
-        for (int qq = 0; qq < Q; ++qq)
-          for (int64_t i = 0; i < S; ++i) {
-            cd s = 0;
-            for (int j = 0; j < M; ++j) s += RL(qq, j) * Gs[((size_t)ch * M + j) * S + i];
-            F->V[((size_t)(p0 + i) * 4 + ch) * Q + qq] = s;
-          }
-    });
-  }
+  // radiation matrices V = R_L G_src are assembled on the device (kernel
+  // k_fill_radiation) from the finest level's fitting operator and check points
+  F->RLt = R[nl - 1].a;
   // transfer matrices C (child level l, octant o): Q_{l-1} x Q_l row-major
   for (int l = t.l0 + 1; l <= t.L; ++l) {
     FarLevel& fc = F->lev[l - t.l0];

@@ -167,6 +167,27 @@ void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st)
 // (fp64) or complex64.  All pointers are device pointers.
 void launch_fill_translation(const double* E, const int32_t* off, int nused, int Q, int Qr, double side, double k,
                              void* D, bool fp64, hipStream_t st);
+// Geometry of the radiation matrices (device pointers): RWGs in leaf order via
+// perm, their triangles (T+, T-), free vertices, edge lengths; triangle areas and
+// 3-point quadrature points [nt][3][3]; vertices [nv][3]; leaf centres
+// [nleaf][3]; check points X [M][3] around the origin; R_L^T [M][Q].
+struct RadGeo {
+  const int32_t* perm = nullptr;
+  const int32_t* leaf_ptr = nullptr;
+  const int32_t* tri = nullptr;
+  const int32_t* freev = nullptr;
+  const double* len = nullptr;
+  const double* area = nullptr;
+  const double* qp = nullptr;
+  const double* v = nullptr;
+  const double* centre = nullptr;
+  const double* X = nullptr;
+  const double2* Rt = nullptr;
+  double k = 0;
+  int Q = 0, M = 0;
+};
+// V [n leaf order][4][Q] (complex128 if fp64, else complex64) on `st`.
+void launch_fill_radiation(const RadGeo& g, int64_t nleaf, void* V, bool fp64, hipStream_t st);
 // one grouped GEMM plan for nrhs right-hand sides (autotuner timing)
 void launch_plan(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st, bool translation);
 // y = arena x with an arena in the near-block layout (leaf order, one RHS)

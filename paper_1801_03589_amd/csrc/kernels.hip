@@ -1307,6 +1307,73 @@ __global__ void k_fill_translation(const double* __restrict__ E, const int32_t* 
   D[i] = out;
 }
 
+// ------------------------------------------------------------------ radiation operators
+// V[pos][ch][q] = sum_j R_L[q][j] G_src[ch][j] (Sec. 2, Eq. 4-5): G_src holds
+// the four channels of the RWG at leaf position pos -- phi_x, phi_y, phi_z
+// (half-edge-weighted (r - free vertex) on each triangle) and div phi -- times
+// g(|x_j - r|), integrated over its two triangles with the 3-point rule, x_j =
+// check point j + leaf centre.  FP64 math; one workgroup per leaf, as many RWGs
+// at a time as the LDS holds.
+template <typename V2>
+__global__ __launch_bounds__(NT) void k_fill_radiation(RadGeo g, V2* __restrict__ V) {
+  constexpr int GS = 3072;                 // complex128 entries of the G_src tile
+  __shared__ double2 Gs[GS];
+  const int b = blockIdx.x;
+  const int p0 = g.leaf_ptr[b], S = g.leaf_ptr[b + 1] - p0;
+  const int M = g.M, Q = g.Q;
+  const int nrw = max(1, GS / (4 * M));
+  const double cx = g.centre[3 * b], cy = g.centre[3 * b + 1], cz = g.centre[3 * b + 2];
+  const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+  for (int i0 = 0; i0 < S; i0 += nrw) {
+    const int nr = min(nrw, S - i0);
+    __syncthreads();                       // the previous tile consumed
+    for (int e = threadIdx.x; e < nr * M; e += NT) {
+      const int r = e / M, j = e - r * M;
+      const int n = g.perm[p0 + i0 + r];
+      const double xx = cx + g.X[3 * j], xy = cy + g.X[3 * j + 1], xz = cz + g.X[3 * j + 2];
+      double2 acc[4];
+      for (int c = 0; c < 4; ++c) acc[c].x = acc[c].y = 0;
+      for (int sd = 0; sd < 2; ++sd) {
+        const int T = g.tri[2 * n + sd], fv = g.freev[2 * n + sd];
+        const double sg = sd == 0 ? 1.0 : -1.0;
+        const double cv = sg * g.len[n] / (2.0 * g.area[T]);
+        const double cdv = sg * g.len[n] / g.area[T];
+        const double w = g.area[T] / 3.0;
+        for (int qd = 0; qd < 3; ++qd) {
+          const double rx = g.qp[9 * T + 3 * qd], ry = g.qp[9 * T + 3 * qd + 1], rz = g.qp[9 * T + 3 * qd + 2];
+          const double ph[4] = {(rx - g.v[3 * fv]) * cv, (ry - g.v[3 * fv + 1]) * cv, (rz - g.v[3 * fv + 2]) * cv,
+                                cdv};
+          const double dx = xx - rx, dy = xy - ry, dz = xz - rz;
+          const double R = sqrt(dx * dx + dy * dy + dz * dz);
+          double sn, cs;
+          sincos(g.k * R, &sn, &cs);
+          const double gr = cs * inv4pi / R * w, gi = -sn * inv4pi / R * w;
+          for (int c = 0; c < 4; ++c) {
+            acc[c].x += gr * ph[c];
+            acc[c].y += gi * ph[c];
+          }
+        }
+      }
+      for (int c = 0; c < 4; ++c) Gs[(r * 4 + c) * M + j] = acc[c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * 4 * Q; e += NT) {
+      const int rc = e / Q, q = e - rc * Q;  // rc = 4 r + channel
+      const double2* gs = Gs + rc * M;
+      double sr = 0, si = 0;
+      for (int j = 0; j < M; ++j) {
+        const double2 rr = g.Rt[(size_t)j * Q + q], gv = gs[j];
+        sr += rr.x * gv.x - rr.y * gv.y;
+        si += rr.x * gv.y + rr.y * gv.x;
+      }
+      V2 out;
+      out.x = sr;
+      out.y = si;
+      V[((size_t)(p0 + i0 + rc / 4) * 4 + rc % 4) * Q + q] = out;
+    }
+  }
+}
+
 template <typename V>
 __global__ void k_fill_zero(V* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -2015,6 +2082,14 @@ void launch_fill_translation(const double* E, const int32_t* off, int nused, int
     k_fill_translation<double2><<<grid, NT, 0, st>>>(E, off, side, k, Q, Qr, total, static_cast<double2*>(D));
   else
     k_fill_translation<float2><<<grid, NT, 0, st>>>(E, off, side, k, Q, Qr, total, static_cast<float2*>(D));
+}
+
+void launch_fill_radiation(const RadGeo& g, int64_t nleaf, void* V, bool fp64, hipStream_t st) {
+  if (nleaf == 0) return;
+  if (fp64)
+    k_fill_radiation<double2><<<(unsigned)nleaf, NT, 0, st>>>(g, static_cast<double2*>(V));
+  else
+    k_fill_radiation<float2><<<(unsigned)nleaf, NT, 0, st>>>(g, static_cast<float2*>(V));
 }
 
 template <typename T>

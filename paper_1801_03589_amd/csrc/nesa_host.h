@@ -100,7 +100,7 @@ struct Far {
   double tau = 1e-8;
   double eps = 0.1;
   std::vector<FarLevel> lev;        // lev[l - l0]
-  std::vector<cd> V;                // [N leaf order][4][Q_L]
+  std::vector<cd> RLt;              // finest level's fitting operator R_L (Q_L x M), column-major
 };
 
 // thread pool helper: fn(i) for i in [0, n)
