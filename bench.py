@@ -430,7 +430,7 @@ def main():
     info = tree.info()
     setup["tree_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    near = nesa.assemble_near(tree)
+    near = nesa.assemble_near_device(tree)      # near-field blocks assembled on the GPU
     setup["near_s"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     far = nesa.assemble_translations(tree, d0=3, tau=1e-8)

@@ -152,6 +152,14 @@ void nesa_tree_free(nesa_tree* tree);
  * closed-form static singular integrals for triangle pairs that share a
  * vertex (mean of both integration orders, so Z = Z^T).  Host-only. */
 int nesa_assemble_near(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out);
+/* The same blocks computed on the current device: one thread per entry, FP64,
+ * the same integration rules and summation order (entries agree with
+ * nesa_assemble_near up to the rounding of the device's math functions), copied
+ * back into a host handle that every consumer of nesa_assemble_near's accepts.
+ * Device memory: 16 bytes per entry plus the mesh, freed before returning.
+ * Errors: NESA_EINVAL (null pointer, k or eta not positive, a near list longer
+ * than 128), NESA_EHIP. */
+int nesa_assemble_near_device(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out);
 /* Copy the entries Z[rows[i]][cols[j]] (canonical indices, both RWGs in near
  * leaves) into host out[i * ncols + j] (complex128); missing entries -> 0. */
 int nesa_near_entries(const nesa_tree* tree, const nesa_near* near, const int64_t* rows,

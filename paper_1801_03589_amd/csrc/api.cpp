@@ -1493,6 +1493,17 @@ int nesa_assemble_near(const nesa_tree* tree, const nesa_em_params* em, nesa_nea
   });
 }
 
+int nesa_assemble_near_device(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out) {
+  return guarded([&]() {
+    if (!tree || !em || !out) return fail(NESA_EINVAL, "null argument");
+    if (!(em->k > 0) || !(em->eta > 0)) return fail(NESA_EINVAL, "k and eta must be positive");
+    std::unique_ptr<nesa_near> h(new nesa_near());
+    h->n.reset(nesa::assemble_near_device(*tree->t, em->k, em->eta));
+    *out = h.release();
+    return (int)NESA_OK;
+  });
+}
+
 int nesa_near_entries(const nesa_tree* tree, const nesa_near* near, const int64_t* rows, int64_t nrows,
                       const int64_t* cols, int64_t ncols, double* out) {
   return guarded([&]() {

@@ -114,6 +114,8 @@ Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t n
 Tree* build_forest(int nbodies, const double* const* verts, const int64_t* nv, const int32_t* const* tris,
                    const int64_t* nt, double leaf, int l0_max, int buffer);
 Near* assemble_near(const Tree& t, double k, double eta);
+// the same blocks computed on the current device (FP64) and copied back
+Near* assemble_near_device(const Tree& t, double k, double eta);
 Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau, double eps);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);

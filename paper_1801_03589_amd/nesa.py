@@ -84,6 +84,7 @@ _SIGS = {
     "nesa_tree_perm": (C.c_int, [_P, _P]),
     "nesa_tree_free": (None, [_P]),
     "nesa_assemble_near": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
+    "nesa_assemble_near_device": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
     "nesa_near_entries": (C.c_int, [_P, _P, _P, C.c_int64, _P, C.c_int64, _P]),
     "nesa_near_free": (None, [_P]),
     "nesa_assemble_translations": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(FarParams), C.POINTER(_P)]),
@@ -249,6 +250,13 @@ def build_tree(verts, tris, leaf_size=0.25, l0_max=2, buffer=1):
 def assemble_near(tree, k=K0, eta=ETA0):
     h = C.c_void_p()
     _check(lib().nesa_assemble_near(tree.h, C.byref(EmParams(k, eta)), C.byref(h)))
+    return Near(h)
+
+
+def assemble_near_device(tree, k=K0, eta=ETA0):
+    """Near-field blocks computed on the current GPU, returned as a host handle."""
+    h = C.c_void_p()
+    _check(lib().nesa_assemble_near_device(tree.h, C.byref(EmParams(k, eta)), C.byref(h)))
     return Near(h)
 
 

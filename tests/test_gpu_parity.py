@@ -114,6 +114,35 @@ def test_serial_form_matches_overlapped(torch_dev, nesa, prec):
     assert np.array_equal(yd.cpu().numpy().astype(np.complex128), y)
 
 
+def test_near_assembled_on_device_matches_oracle(torch_dev, nesa):
+    """Near-field blocks computed on the GPU (one thread per entry, FP64):
+    sampled rows against the oracle's dense EFIE matrix, every entry against the
+    host assembly, and a complex128 operator built from them against the
+    oracle's product."""
+    from oracle.tree import Octree
+    ref, tr, near, far = _case(nesa, "sphere1")
+    v, t = synth.icosphere(10, 0.5)
+    nd = nesa.assemble_near_device(tr)
+    m = ref.m
+    ot = Octree(v, m.midpoints(), leaf=0.25)
+    Z = efie.dense_z(m)
+    for r in (0, 5, 100, 1500, 2999):
+        a = ot.rwg_leaf[r]
+        cols = np.concatenate([ot.leaf_rwgs[b] for b in ot.near[a]])
+        zd = nesa.near_entries(tr, nd, [r], cols)[0]
+        assert np.abs(zd - Z[r, cols]).max() <= 1e-12 * np.abs(Z[r, cols]).max()
+    allr = np.arange(m.n)
+    Ed = nesa.near_entries(tr, nd, allr, allr)
+    Eh = nesa.near_entries(tr, near, allr, allr)
+    assert np.count_nonzero(Eh) > 0.1 * m.n * m.n
+    assert np.abs(Ed - Eh).max() <= 1e-13 * np.abs(Eh).max()
+    op = nesa.op_create(tr, nd, far, nesa.C128)
+    x = synth.complex_normal(m.n, 9)
+    y = _run(torch_dev, nesa, op, x)
+    yr = ref.matvec(x)
+    assert np.linalg.norm(y - yr) / np.linalg.norm(yr) <= TOL["c128"]
+
+
 def test_matvec_edge_cases(torch_dev, nesa):
     # tiny body: a single level with no far pairs (product = near field only)
     v, t = synth.icosphere(3, 0.2)
