@@ -334,7 +334,7 @@ static double sigma_max(const CMat& G) {
     double nu = 0;
     for (auto& x : u) nu += std::norm(x);
     lam = std::sqrt(nu);
-    if (it > 20 && std::fabs(lam - prev) <= 1e-15 * lam) break;
+    if (it > 20 && std::fabs(lam - prev) <= 1e-12 * lam) break;
     prev = lam;
   }
   return lam;
@@ -375,20 +375,26 @@ static CMat tikhonov_fit(const CMat& G, double tau) {
     });
     vs[j] = std::move(v);
   }
-  // Y = Q^H [I_M; 0], then solve R_qr X = Y[0:Q]
+  // Y = Q^H [I_M; 0]: column col of Y is the conjugate of row col of the thin
+  // factor Q[:, 0:Q] = H_1 ... H_Q [I_Q; 0] (accumulated backwards, m Q^2
+  // operations instead of M m Q for the reflectors applied to every e_col);
+  // then solve R_qr X = Y
+  CMat Qt(m, Q);
+  for (int64_t j = 0; j < Q; ++j) Qt(j, j) = 1.0;
+  for (int64_t j = Q - 1; j >= 0; --j) {
+    const auto& v = vs[j];
+    parallel_for(Q - j, [&](int64_t cc) {
+      const int64_t c = j + cc;      // columns left of j are still zero in rows >= j
+      cd s = 0;
+      for (int64_t i = j; i < m; ++i) s += std::conj(v[i - j]) * Qt(i, c);
+      s *= 2.0;
+      for (int64_t i = j; i < m; ++i) Qt(i, c) -= v[i - j] * s;
+    });
+  }
   CMat X(Q, M);
   parallel_for(M, [&](int64_t col) {
-    std::vector<cd> b(m, cd(0, 0));
-    b[col] = 1.0;
-    for (int64_t j = 0; j < Q; ++j) {
-      const auto& v = vs[j];
-      cd s = 0;
-      for (int64_t i = j; i < m; ++i) s += std::conj(v[i - j]) * b[i];
-      s *= 2.0;
-      for (int64_t i = j; i < m; ++i) b[i] -= v[i - j] * s;
-    }
     for (int64_t i = Q - 1; i >= 0; --i) {
-      cd s = b[i];
+      cd s = std::conj(Qt(col, i));
       for (int64_t c = i + 1; c < Q; ++c) s -= A(i, c) * X(c, col);
       X(i, col) = s / A(i, i);
     }
@@ -452,16 +458,26 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
     const CMat& Rp = R[l - 1 - t.l0];
     const double a = t.level(l).side;
     fc.Cup.assign((size_t)8 * fp.Q * fc.Q, cd(0, 0));
+    // G(X_p, E_c + delta) = g(|X_p - delta - E_c|) per octant (column-major, so
+    // that column q is contiguous over the check points j)
+    std::vector<CMat> G(8);
     parallel_for(8, [&](int64_t o) {
       P3 delta = {((o & 1) - 0.5) * a, (((o >> 1) & 1) - 0.5) * a, (((o >> 2) & 1) - 0.5) * a};
-      // G(X_p, E_c + delta) = g(|X_p - delta - E_c|)
-      CMat G = gmat(fp.X, mul(delta, -1.0), fc.E, k);
-      for (int p = 0; p < fp.Q; ++p)
-        for (int q = 0; q < fc.Q; ++q) {
-          cd s = 0;
-          for (int j = 0; j < fp.M; ++j) s += Rp(p, j) * G(j, q);
-          fc.Cup[((size_t)o * fp.Q + p) * fc.Q + q] = s;
-        }
+      G[o] = gmat(fp.X, mul(delta, -1.0), fc.E, k);
+    });
+    // rows of R_parent contiguous over j
+    std::vector<cd> Rrow((size_t)fp.Q * fp.M);
+    for (int j = 0; j < fp.M; ++j)
+      for (int p = 0; p < fp.Q; ++p) Rrow[(size_t)p * fp.M + j] = Rp(p, j);
+    parallel_for((int64_t)8 * fp.Q, [&](int64_t op) {
+      const int o = (int)(op / fp.Q), p = (int)(op % fp.Q);
+      const cd* rp = &Rrow[(size_t)p * fp.M];
+      for (int q = 0; q < fc.Q; ++q) {
+        const cd* gq = &G[o].a[(size_t)q * fp.M];
+        cd s = 0;
+        for (int j = 0; j < fp.M; ++j) s += rp[j] * gq[j];
+        fc.Cup[((size_t)o * fp.Q + p) * fc.Q + q] = s;
+      }
     });
   }
   // translation matrices D: only the offset slots that occur are recorded here;
