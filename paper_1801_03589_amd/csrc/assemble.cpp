@@ -14,7 +14,7 @@
 // (phi_x, phi_y, phi_z, div phi) share g; per level Q equivalent points on a
 // sphere of radius r_e and 4Q check points on radius r_c = max(box side, 1.05 r_e)
 // (golden-angle spirals); the fitting operator R = argmin ||G(X,E) R - I||^2 +
-// lambda^2 ||R||^2 (lambda = tau * sigma_max) is computed by Householder QR of
+// lambda^2 ||R||^2 (lambda = tau * sigma_max, sigma_max by Lanczos) is computed by Householder QR of
 // [G; lambda I]; C = R_parent G(X_parent, E_child + delta).  V = R_L G_src and
 // D_ab = G(E_a, E_b) are assembled on the device (kernels k_fill_radiation,
 // k_fill_translation).
@@ -315,29 +315,79 @@ static CMat gmat(const std::vector<cd>& A, P3 shift, const std::vector<cd>& B, d
   return G;
 }
 
-static double sigma_max(const CMat& G) {
-  std::vector<cd> v(G.n, cd(1.0, 0.0)), u(G.m);
-  double lam = 0, prev = -1;
-  for (int it = 0; it < 2000; ++it) {
-    double nv = 0;
-    for (auto& x : v) nv += std::norm(x);
-    nv = std::sqrt(nv);
-    for (auto& x : v) x /= nv;
-    for (int64_t i = 0; i < G.m; ++i) u[i] = 0;
-    for (int64_t j = 0; j < G.n; ++j)
-      for (int64_t i = 0; i < G.m; ++i) u[i] += G(i, j) * v[j];
-    for (int64_t j = 0; j < G.n; ++j) {
-      cd s = 0;
-      for (int64_t i = 0; i < G.m; ++i) s += std::conj(G(i, j)) * u[i];
-      v[j] = s;
-    }
-    double nu = 0;
-    for (auto& x : u) nu += std::norm(x);
-    lam = std::sqrt(nu);
-    if (it > 20 && std::fabs(lam - prev) <= 1e-12 * lam) break;
-    prev = lam;
+// largest eigenvalue of the symmetric tridiagonal matrix (a, b) by bisection
+// on the Sturm count (number of eigenvalues below x)
+static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const size_t k = a.size();
+  double lo = a[0], hi = a[0];
+  for (size_t i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
   }
-  return lam;
+  auto below = [&](double x) {
+    size_t c = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < k; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-16 * std::max(std::fabs(hi), std::fabs(lo)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) == k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+// largest singular value of G: Lanczos on G^H G with full reorthogonalisation
+// (the largest Ritz value approaches the largest eigenvalue from below, much
+// faster than power iteration when the top singular values are clustered)
+static double sigma_max(const CMat& G) {
+  const int64_t M = G.m, Q = G.n;
+  const int kmax = (int)std::min<int64_t>(Q, 300);
+  std::vector<std::vector<cd>> qs;
+  std::vector<double> al, be;
+  std::vector<cd> q(Q, cd(1.0 / std::sqrt((double)Q), 0.0)), u(M), w(Q);
+  double est = 0;
+  for (int j = 0; j < kmax; ++j) {
+    qs.push_back(q);
+    for (int64_t i = 0; i < M; ++i) u[i] = 0;
+    for (int64_t c = 0; c < Q; ++c)
+      for (int64_t i = 0; i < M; ++i) u[i] += G(i, c) * q[c];
+    for (int64_t c = 0; c < Q; ++c) {
+      cd s = 0;
+      for (int64_t i = 0; i < M; ++i) s += std::conj(G(i, c)) * u[i];
+      w[c] = s;
+    }
+    cd aj = 0;
+    for (int64_t c = 0; c < Q; ++c) aj += std::conj(q[c]) * w[c];
+    al.push_back(aj.real());
+    // w -= sum_i q_i (q_i^H w), twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& qi : qs) {
+        cd h = 0;
+        for (int64_t c = 0; c < Q; ++c) h += std::conj(qi[c]) * w[c];
+        for (int64_t c = 0; c < Q; ++c) w[c] -= h * qi[c];
+      }
+    double nb = 0;
+    for (const auto& x : w) nb += std::norm(x);
+    nb = std::sqrt(nb);
+    const bool last = j + 1 == kmax || nb <= 1e-14 * std::sqrt(std::fabs(al[0]) + 1e-300);
+    if (last || (j + 1) % 10 == 0) {
+      const double e = tridiag_max_eig(al, be);
+      if (last || (est > 0 && std::fabs(e - est) <= 1e-14 * e)) return std::sqrt(std::max(e, 0.0));
+      est = e;
+    }
+    be.push_back(nb);
+    for (int64_t c = 0; c < Q; ++c) q[c] = w[c] / nb;
+  }
+  return std::sqrt(std::max(est, 0.0));
 }
 
 // R = argmin ||G R - I_M||_F^2 + lambda^2 ||R||_F^2  (Q x M), via Householder QR
