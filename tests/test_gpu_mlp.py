@@ -223,7 +223,7 @@ def test_trained_network_gain_reported(torch_dev, setup):
     base preconditioner alone is printed, not required: a leaf-local network
     sees none of the global error components that dominate these pairs.  What
     is required: training lowers the loss and every solve reaches the
-    tolerance (the run-time judge hands a cycle that does not halve the true
+    tolerance (the run-time check hands a cycle that does not halve the true
     residual over to the base)."""
     torch = torch_dev
     nesa, ref, tr, _, perm, leaf_ptr = setup
