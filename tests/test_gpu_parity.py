@@ -143,6 +143,27 @@ def test_near_assembled_on_device_matches_oracle(torch_dev, nesa):
     assert np.linalg.norm(y - yr) / np.linalg.norm(yr) <= TOL["c128"]
 
 
+def test_large_leaves_match_oracle(torch_dev, nesa):
+    """Leaves near the 256-RWG limit (up to 213 RWGs, 26 leaves, one far level):
+    one or two column groups per workgroup and the shortest sub-chunks of the
+    half-storage near-field kernel (16 columns, 8 lanes per column sum; 8 and 16
+    in complex128) and of the several-right-hand-side kernel (8 columns)."""
+    v, t = synth.icosphere(12, 0.75)
+    ref = onesa.NesaOracle(v, t, leaf=0.5, d0=3, tau=1e-8)
+    tr = nesa.build_tree(v, t, 0.5)
+    assert 128 < tr.info()["max_leaf"] <= 256
+    near = nesa.assemble_near(tr)
+    far = nesa.assemble_translations(tr, d0=3, tau=1e-8)
+    X = synth.complex_normal((2, ref.m.n), 11)
+    Y = [ref.matvec(X[r]) for r in range(2)]
+    for prec, R in (("c128", 1), ("c64", 1), ("c64", 2)):
+        op = nesa.op_create(tr, near, far, nesa.C128 if prec == "c128" else nesa.C64, max_nrhs=R)
+        Yg = _run(torch_dev, nesa, op, X[:R] if R > 1 else X[0], nrhs=R).reshape(R, -1)
+        for r in range(R):
+            err = np.linalg.norm(Yg[r] - Y[r]) / np.linalg.norm(Y[r])
+            assert err <= TOL[prec], (prec, R, r, err)
+
+
 def test_matvec_edge_cases(torch_dev, nesa):
     # tiny body: a single level with no far pairs (product = near field only)
     v, t = synth.icosphere(3, 0.2)
