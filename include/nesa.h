@@ -166,23 +166,34 @@ int nesa_near_entries(const nesa_tree* tree, const nesa_near* near, const int64_
                       int64_t nrows, const int64_t* cols, int64_t ncols, double* out);
 void nesa_near_free(nesa_near* near);
 
-/* Radiation V, transfer C (and B = C^T), translation D (Sec. 2, Eq. 4-7;
- * U = V^T).  Host-only. */
+/* Far-field operators (Sec. 2, Eq. 4-7): per level the equivalent and check
+ * points and the Tikhonov fitting operator, and the transfer matrices C (and
+ * B = C^T), computed on the host; the radiation matrices V (U = V^T) and the
+ * translation matrices D are assembled on the device by nesa_op_create from
+ * what this call records (the finest level's fitting operator, the points, the
+ * offsets that occur).  Host-only. */
 int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em,
                                const nesa_far_params* params, nesa_far** out);
 /* Q of every level l0..L into Q[0 .. nmax-1]. */
 int nesa_far_get_q(const nesa_far* far, int* Q, int nmax);
 void nesa_far_free(nesa_far* far);
 
-/* Upload near and far operators to the current device in the given precision
- * and allocate work buffers for up to max_nrhs right-hand sides. */
+/* Upload near and far operators to the current device in the given precision,
+ * assemble V and D there, and allocate work buffers for up to max_nrhs
+ * right-hand sides.  Products of one right-hand side read the near field in
+ * reciprocity half storage (the blocks Z_ab of near leaves b >= a, Z_ba =
+ * Z_ab^T); the full blocks are uploaded as well when max_nrhs > 1. */
 int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far* far,
                    int precision, int max_nrhs, nesa_op** out);
 void nesa_op_free(nesa_op* op);
 
 /* y = Z_NESA x for nrhs right-hand sides (1 <= nrhs <= max_nrhs), x and y in
  * canonical order, RHS-major.  Applies the near-field product (Eq. 9) and the
- * five far-field stages (Eq. 10-14) with GPU kernels on `stream`. */
+ * five far-field stages (Eq. 10-14) with GPU kernels on `stream`; the near field
+ * and the finest level's translations run on two streams of the operator forked
+ * from `stream` and joined back into it, so the call is ordered on `stream` as
+ * a whole (also under HIP graph capture).  Products on one operator share its
+ * work buffers: calls that overlap in time race. */
 int nesa_matvec(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream);
 
 /* Same product in leaf order (no permutation), for callers that keep their
