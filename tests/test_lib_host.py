@@ -141,6 +141,14 @@ def test_error_paths(nesa):
     tr = nesa.build_tree(v, t, 0.25)
     with pytest.raises(nesa.NesaError):
         nesa.assemble_translations(tr, d0=0)
+    # the device near-field assembly checks its arguments before touching a GPU
+    assert lib.nesa_assemble_near_device(None, None, None) == -1
+    with pytest.raises(nesa.NesaError) as e:
+        nesa.assemble_near_device(tr, k=-1.0)
+    assert e.value.code == -1
+    with pytest.raises(nesa.NesaError) as e:
+        nesa.assemble_near_device(tr, eta=0.0)
+    assert e.value.code == -1
     # a mesh far too coarse for the leaf: equivalent sphere outside the check sphere
     with pytest.raises(nesa.NesaError) as e:
         nesa.assemble_translations(nesa.build_tree(*synth.icosphere(2, 1.0), 0.05))
