@@ -31,17 +31,17 @@ inline Cx<R> cdiv(Cx<R> a, Cx<R> b) {
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-// In-place LU with partial pivoting of an n x n column-major matrix; piv[k] is
-// the row swapped with row k at step k.
+// In-place LU with partial pivoting of an n x n column-major complex matrix
+// held as separate real and imaginary parts (so that the column updates
+// vectorise); piv[k] is the row swapped with row k at step k.
 template <typename R>
-void lu(Cx<R>* A, int n, std::vector<int>& piv) {
+void lu(R* Ar, R* Ai, int n, std::vector<int>& piv) {
   piv.resize(n);
   for (int k = 0; k < n; ++k) {
     int p = k;
     R best = -1;
     for (int i = k; i < n; ++i) {
-      const Cx<R> v = A[(size_t)k * n + i];
-      const R m = std::fabs(v.re) + std::fabs(v.im);
+      const R m = std::fabs(Ar[(size_t)k * n + i]) + std::fabs(Ai[(size_t)k * n + i]);
       if (m > best) {
         best = m;
         p = i;
@@ -50,17 +50,26 @@ void lu(Cx<R>* A, int n, std::vector<int>& piv) {
     piv[k] = p;
     if (!(best > 0)) throw Error(-1, "singular near-field matrix in the Schwarz preconditioner");
     if (p != k)
-      for (int j = 0; j < n; ++j) std::swap(A[(size_t)j * n + k], A[(size_t)j * n + p]);
-    const Cx<R> d = A[(size_t)k * n + k];
-    for (int i = k + 1; i < n; ++i) A[(size_t)k * n + i] = cdiv(A[(size_t)k * n + i], d);
+      for (int j = 0; j < n; ++j) {
+        std::swap(Ar[(size_t)j * n + k], Ar[(size_t)j * n + p]);
+        std::swap(Ai[(size_t)j * n + k], Ai[(size_t)j * n + p]);
+      }
+    const Cx<R> d = {Ar[(size_t)k * n + k], Ai[(size_t)k * n + k]};
+    R* __restrict__ kr = Ar + (size_t)k * n;
+    R* __restrict__ ki = Ai + (size_t)k * n;
+    for (int i = k + 1; i < n; ++i) {
+      const Cx<R> q = cdiv(Cx<R>{kr[i], ki[i]}, d);
+      kr[i] = q.re;
+      ki[i] = q.im;
+    }
     for (int j = k + 1; j < n; ++j) {
-      const Cx<R> f = A[(size_t)j * n + k];
-      if (f.re == 0 && f.im == 0) continue;
-      Cx<R>* cj = A + (size_t)j * n;
-      const Cx<R>* ck = A + (size_t)k * n;
+      R* __restrict__ jr = Ar + (size_t)j * n;
+      R* __restrict__ ji = Ai + (size_t)j * n;
+      const R fr = jr[k], fi = ji[k];
+      if (fr == 0 && fi == 0) continue;
       for (int i = k + 1; i < n; ++i) {
-        cj[i].re -= ck[i].re * f.re - ck[i].im * f.im;
-        cj[i].im -= ck[i].re * f.im + ck[i].im * f.re;
+        jr[i] -= kr[i] * fr - ki[i] * fi;
+        ji[i] -= kr[i] * fi + ki[i] * fr;
       }
     }
   }
@@ -68,22 +77,22 @@ void lu(Cx<R>* A, int n, std::vector<int>& piv) {
 
 // Solve (LU) x = b in place for one right-hand side.
 template <typename R>
-void lu_solve(const Cx<R>* A, int n, const std::vector<int>& piv, Cx<R>* b) {
+void lu_solve(const R* Ar, const R* Ai, int n, const std::vector<int>& piv, Cx<R>* b) {
   for (int k = 0; k < n; ++k)
     if (piv[k] != k) std::swap(b[k], b[piv[k]]);
   for (int j = 0; j < n; ++j) {
     const Cx<R> bj = b[j];
     for (int i = j + 1; i < n; ++i) {
-      const Cx<R> l = A[(size_t)j * n + i];
+      const Cx<R> l = {Ar[(size_t)j * n + i], Ai[(size_t)j * n + i]};
       b[i].re -= l.re * bj.re - l.im * bj.im;
       b[i].im -= l.re * bj.im + l.im * bj.re;
     }
   }
   for (int j = n - 1; j >= 0; --j) {
-    b[j] = cdiv(b[j], A[(size_t)j * n + j]);
+    b[j] = cdiv(b[j], Cx<R>{Ar[(size_t)j * n + j], Ai[(size_t)j * n + j]});
     const Cx<R> bj = b[j];
     for (int i = 0; i < j; ++i) {
-      const Cx<R> u = A[(size_t)j * n + i];
+      const Cx<R> u = {Ar[(size_t)j * n + i], Ai[(size_t)j * n + i]};
       b[i].re -= u.re * bj.re - u.im * bj.im;
       b[i].im -= u.re * bj.im + u.im * bj.re;
     }
@@ -99,8 +108,8 @@ void schwarz_leaf(const Tree& t, const Near& nr, int64_t a, std::vector<cd>& out
     off[i + 1] = off[i] + (t.leaf_ptr[nb[i] + 1] - t.leaf_ptr[nb[i]]);
   }
   const int W = (int)off[na];
-  // T = Z_N^T, column-major: T[i][j] = Z_N[j][i]
-  std::vector<Cx<R>> T((size_t)W * W, Cx<R>{0, 0});
+  // T = Z_N^T, column-major: T[i][j] = Z_N[j][i] (real and imaginary parts apart)
+  std::vector<R> Tr((size_t)W * W, R(0)), Ti((size_t)W * W, R(0));
   for (int64_t i = 0; i < na; ++i) {
     const int64_t b = nb[i];
     const int64_t Sb = t.leaf_ptr[b + 1] - t.leaf_ptr[b];
@@ -116,14 +125,15 @@ void schwarz_leaf(const Tree& t, const Near& nr, int64_t a, std::vector<cd>& out
         for (int64_t cc = 0; cc < Sc; ++cc)
           for (int64_t rr = 0; rr < Sb; ++rr) {
             const cd v = Zb[(cb + cc) * Sb + rr];          // Z_N[off_i + rr][off_j + cc]
-            T[(size_t)(off[i] + rr) * W + off[j] + cc] = {(R)v.real(), (R)v.imag()};
+            Tr[(size_t)(off[i] + rr) * W + off[j] + cc] = (R)v.real();
+            Ti[(size_t)(off[i] + rr) * W + off[j] + cc] = (R)v.imag();
           }
       }
       cb += Sc;
     }
   }
   std::vector<int> piv;
-  lu(T.data(), W, piv);
+  lu(Tr.data(), Ti.data(), W, piv);
   // rows of Z_N^-1 for leaf a: solve Z_N^T y = e_r for every RWG r of a
   const int64_t ia = std::find(nb.begin(), nb.end(), a) - nb.begin();
   const int64_t Sa = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
@@ -132,7 +142,7 @@ void schwarz_leaf(const Tree& t, const Near& nr, int64_t a, std::vector<cd>& out
   for (int64_t r = 0; r < Sa; ++r) {
     std::fill(y.begin(), y.end(), Cx<R>{0, 0});
     y[off[ia] + r] = {1, 0};
-    lu_solve(T.data(), W, piv, y.data());
+    lu_solve(Tr.data(), Ti.data(), W, piv, y.data());
     for (int j = 0; j < W; ++j) out[(size_t)j * Sa + r] = cd(y[j].re, y[j].im);   // column-major S_a x W
   }
 }
