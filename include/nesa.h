@@ -12,7 +12,7 @@
  *   Sec. 3, Eq. (9)       near-field product
  *   Sec. 3, Eq. (10)-(14) radiation, source transfer, translation,
  *                         potential transfer, reception
- *   Sec. 2 / Sec. 4       the product is applied many times inside an
+ *   Sec. 2 / Sec. 5       the product is applied many times inside an
  *                         iterative solver while the structure is built once
  *
  * Conventions

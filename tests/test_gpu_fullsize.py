@@ -69,7 +69,9 @@ def test_bench_sphere_sampled_rows(torch_dev, nesa):
     v, t = synth.icosphere(82, 4.0)
     ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8)
     tr = nesa.build_tree(v, t, 0.25)
-    op = nesa.op_create(tr, nesa.assemble_near(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8), nesa.C64)
+    # near field assembled on the device, as the benchmark builds it
+    op = nesa.op_create(tr, nesa.assemble_near_device(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8),
+                        nesa.C64)
     x, src = _sparse_x(ref, 4, 60)
     rows = _rows(ref, src, 40, 61)
     xd = torch.from_numpy(x).to(torch.complex64).cuda()

@@ -38,9 +38,12 @@ def _case(nesa, name):
         elif name == "sphere1_nested":  # 3000 RWGs, two levels (leaf 0.125)
             v, t = synth.icosphere(10, 0.5)
             leaf, d0 = 0.125, 3
-        elif name == "sphere_3lev":     # 12000 RWGs, three levels
+        elif name == "sphere_2lev":     # 12000 RWGs, two levels (leaf 0.25)
             v, t = synth.icosphere(20, 1.0)
             leaf, d0 = 0.25, 3
+        elif name == "sphere_3lev":     # 12000 RWGs, three levels (leaf 0.125)
+            v, t = synth.icosphere(20, 1.0)
+            leaf, d0 = 0.125, 3
         elif name == "box":             # flat faces, ragged leaves
             v, t = synth.box_mesh((0.9, 0.6, 0.5), 0.05)
             leaf, d0 = 0.25, 3
@@ -61,7 +64,7 @@ def _run(torch, nesa, op, x, nrhs=1, leaf=False):
     return yd.cpu().numpy().astype(np.complex128)
 
 
-@pytest.mark.parametrize("name", ["sphere1", "sphere1_nested", "box", "sphere_3lev"])
+@pytest.mark.parametrize("name", ["sphere1", "sphere1_nested", "box", "sphere_2lev", "sphere_3lev"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_matvec_matches_oracle(torch_dev, nesa, name, prec):
     ref, tr, near, far = _case(nesa, name)
