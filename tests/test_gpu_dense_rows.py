@@ -25,7 +25,9 @@ import make_dense_rows as golden  # noqa: E402
 # ||(Z_NESA x)[rows] - (Z x)[rows]|| / ||(Z x)[rows]||, d0 = 3, leaf 0.25,
 # complex64 on the GPU
 ERR_SPHERE201720 = 3e-3        # measured 2.05e-3 (levels 2..5, Q = 441/196/81/49)
-ERR_BODY4 = 3e-3               # bodies 0-3 of the uneven family, measured below 1.6e-3
+# bodies 0-3 of the uneven family in one forest (shared leaf radius 0.263):
+# the oracle's errors on these rows are 4.18e-3, 2.63e-3, 3.65e-3, 1.17e-3
+ERR_BODY4 = [5e-3, 3e-3, 4e-3, 1.5e-3]
 
 
 @pytest.fixture(scope="module")
@@ -89,4 +91,4 @@ def test_uneven_bodies_vs_dense_rows(torch_dev, nesa):
     for i, (rows, yd) in enumerate(fx):
         e = _err(y[ptr[i]:ptr[i + 1]][rows], yd)
         print("body %d (N=%d): %d dense rows, NESA truncation error %.3e" % (i, ptr[i + 1] - ptr[i], len(rows), e))
-        assert e <= ERR_BODY4
+        assert e <= ERR_BODY4[i]
