@@ -56,7 +56,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only-model2d", action="store_true",
                    help="time only the 2D model problem (paper's own workload) and print its section")
-    p.add_argument("--cpu-sample-leaves", type=int, default=24)
+    p.add_argument("--aircraft-nrhs", type=int, default=64,
+                   help="incidences of the aircraft-like body's batched product (0: skip that line)")
+    p.add_argument("--aircraft-fp32", action="store_true",
+                   help="also time the aircraft's batched product with FP32 translations")
+    p.add_argument("--only-aircraft", action="store_true", help="time only the aircraft-like body's line")
     return p.parse_args()
 
 
@@ -92,76 +96,54 @@ def algorithmic(info, Q, esize):
     return ph
 
 
-def cpu_baseline(v, t, sample_leaves, seed=0):
-    """Time the FP64 oracle's stages on a bounded sample of the same workload and
-    extrapolate to one full product.  Sample: `sample_leaves` random leaves for the
-    near field, radiation and reception; 32 random boxes per level for the
-    translations and the transfers (operators built untimed)."""
-    from threadpoolctl import threadpool_limits
-    from oracle import nesa as onesa
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
-    with threadpool_limits(limits=1):
-        t_setup = time.perf_counter()
-        ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8)
-        tr = ref.t
-        rng = np.random.default_rng(seed)
-        L, l0 = tr.L, tr.l0
-        nleaf = len(tr.boxes[L])
-        leaves = rng.choice(nleaf, size=min(sample_leaves, nleaf), replace=False)
-        x = np.asarray(rng.standard_normal(ref.m.n) + 1j * rng.standard_normal(ref.m.n))
-        for a in leaves:
-            ref.near_block(a)
-            ref.V(a)
-        s = {l: [rng.standard_normal((4, ref.Q[l])) + 0j for _ in tr.boxes[l]] for l in ref.levels}
-        for l in ref.levels:
-            for off in {(tuple(np.subtract(tr.boxes[l][a], tr.boxes[l][b]))) for a in range(len(tr.boxes[l]))
-                        for b in tr.il[l][a]}:
-                ref.D(l, off)
-        for l in range(l0 + 1, L + 1):
-            for o in range(8):
-                ref.C(l, o)
-        t_setup = time.perf_counter() - t_setup
-        est = {}
-        # near field (Eq. 9) and radiation / reception (Eq. 10, 14) per leaf
-        t0 = time.perf_counter()
-        for a in leaves:
-            rows, cols, Z = ref.near_block(a)
-            _ = Z @ x[cols]
-        est["near"] = (time.perf_counter() - t0) / len(leaves) * nleaf
-        t0 = time.perf_counter()
-        for a in leaves:
-            _ = ref.V(a) @ x[tr.leaf_rwgs[a]]
-            _ = np.einsum("c,cqn,cq->n", ref.w, ref.V(a), s[L][0])
-        est["radiate_receive"] = (time.perf_counter() - t0) / len(leaves) * nleaf
-        # translations (Eq. 12) per level
-        tt = 0.0
-        for l in ref.levels:
-            nb = len(tr.boxes[l])
-            boxes = rng.choice(nb, size=min(32, nb), replace=False)
+
+def cpu_baseline(v, t, seed=0):
+    """The FP64 oracle's whole product on the host: the NumPy oracle builds the
+    tree, point sets and fitting operators; its C loop form (oracle/nesa_c.c,
+    pinned against it) assembles the near blocks and radiation matrices
+    (untimed) and runs the full product (near field and the five far-field
+    stages), timed on every core this process may use and on one core.  The
+    same 201,720-unknown operator (d0 = 3) as the GPU line."""
+    from oracle import nesa as onesa
+    from oracle import nesa_c
+
+    t0 = time.perf_counter()
+    ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    nesa_c.set_threads(cores)
+    c = nesa_c.NesaC(ref)
+    setup = time.perf_counter() - t0
+    x = np.asarray(np.random.default_rng(seed).standard_normal(ref.m.n)
+                   + 1j * np.random.default_rng(seed + 1).standard_normal(ref.m.n))
+    times = {}
+    for th in (cores, 1):
+        nesa_c.set_threads(th)
+        reps = 2 if th > 1 else 1
+        best = None
+        for _ in range(reps):
             t0 = time.perf_counter()
-            for a in boxes:
-                ref.translate(s, l, a)
-            tt += (time.perf_counter() - t0) / len(boxes) * nb
-        est["translate"] = tt
-        # transfers (Eq. 11, 13)
-        tt = 0.0
-        for l in range(l0 + 1, L + 1):
-            nb = len(tr.boxes[l])
-            boxes = rng.choice(nb, size=min(32, nb), replace=False)
-            t0 = time.perf_counter()
-            for b in boxes:
-                C = ref.C(l, ref.octant(l, b))
-                _ = (C @ s[l][b].T).T
-                _ = (C.T @ s[l - 1][tr.parent[l][b]].T).T
-            tt += (time.perf_counter() - t0) / len(boxes) * nb
-        est["transfer"] = tt
-    total = sum(est.values())
-    return {"value": ref.m.n / total / 1e6, "unit": "Munknowns*matvec/s", "cores": 1, "kind": "oracle",
-            "sample": ("FP64 NumPy oracle, one thread: near field and radiation/reception timed on %d random "
-                       "leaves of %d, translations and transfers on 32 random boxes per level; per-stage "
-                       "means scaled to the full tree (extrapolated %.2f s per product; operators built "
-                       "untimed in %.1f s)" % (len(leaves), nleaf, total, t_setup)),
-            "stage_seconds": {k: round(v_, 3) for k, v_ in est.items()}}
+            c.matvec(x)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        times[th] = best
+        log("CPU oracle product on %d thread(s): %.2f s" % (th, best))
+    n = ref.m.n
+    return {"value": n / times[cores] / 1e6, "unit": "Munknowns*matvec/s", "cores": cores, "kind": "oracle",
+            "sample": ("whole FP64 product (near field + five far-field stages) of the same 201,720-unknown "
+                       "operator by the oracle's C loops with OpenMP, %d threads: %.2f s (best of 2); "
+                       "operators assembled untimed in %.1f s" % (cores, times[cores], setup)),
+            "one_core": {"value": n / times[1] / 1e6, "seconds": round(times[1], 2), "cores": 1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def profiled_traffic(kernel, precision):
@@ -184,6 +166,56 @@ def profiled_traffic(kernel, precision):
         if line.startswith("traffic_bytes_per_launch:"):
             return int(line.split(":")[1])
     return None
+
+
+def dense_rows_error(nesa, torch, op, n, stream):
+    """||(Z_NESA x)[rows] - (Z x)[rows]|| / ||(Z x)[rows]|| on the stored dense
+    rows of the bench sphere (x = synth.complex_normal(n, 0); the rows and values
+    come from the oracle alone, tests/golden/make_dense_rows.py)."""
+    import synth
+    path = os.path.join(ROOT, "tests", "golden", "dense_rows_sphere201720.json")
+    with open(path) as f:
+        g = json.load(f)
+    if g["n"] != n:
+        return None
+    rows = np.array(g["rows"])
+    yd = np.array(g["y_re"]) + 1j * np.array(g["y_im"])
+    x = torch.from_numpy(synth.complex_normal(n, 0)).to(torch.complex64).cuda()
+    y = torch.empty_like(x)
+    nesa.matvec(op, x, y, stream=stream)
+    torch.cuda.synchronize()
+    yr = y.cpu().numpy().astype(np.complex128)[rows]
+    return {"dense_rows": int(len(rows)), "rel_err": float(np.linalg.norm(yr - yd) / np.linalg.norm(yd))}
+
+
+def accurate_section(args, nesa, torch, tree, near, n, stream):
+    """The bench sphere with d0 = 5 equivalent sources per box (Q = 576, 256,
+    144, 81): the setting whose truncation error against the dense matrix is
+    below 1e-3; product time and that error."""
+    t0 = time.perf_counter()
+    far5 = nesa.assemble_translations(tree, d0=5, tau=1e-8)
+    op5 = nesa.op_create(tree, near, far5, nesa.C64)
+    setup = time.perf_counter() - t0
+    info = tree.info()
+    Q = [int(q) for q in far5.q(info["L"] - info["l0"] + 1)]
+    x = torch.from_numpy(np.ones(n, dtype=np.complex64)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(5):
+        nesa.matvec(op5, x, y, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        nesa.matvec(op5, x, y, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {"d0": 5, "Q": Q, "ms_per_product": round(ms, 4),
+           "Munknowns_matvec_per_s": round(n / (ms * 1e-3) / 1e6, 2), "setup_s": round(setup, 2),
+           "truncation_error": dense_rows_error(nesa, torch, op5, n, stream)}
+    del op5, far5
+    return out
 
 
 def gmres_section(args, nesa, torch, op, info, x, stream):
@@ -315,6 +347,90 @@ def batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream):
             "Munknowns_matvec_per_s": round(n * args.nrhs / (ms * 1e-3) / 1e6, 2)}
 
 
+def aircraft_section(args, nesa, torch, stream):
+    """Aircraft-like body (seed 3: 959,364 unknowns, 50-wavelength fuselage, two
+    swept wings), leaf 0.25, far field from the 4-wavelength level (l0 = 4:
+    Q = 1156, 441, 196, 81, 49), 64 plane-wave incidences in one batched
+    product with split-bf16x3 translations and transfers (FP32 accumulation).
+    Munknowns * matvec / s counted over all right-hand sides; the translation
+    stage's roofline against the bf16 matrix-core peak (the dtype its products
+    run in), its algorithmic flops 8 x 4 nrhs x Q^2 per pair."""
+    import synth
+    R = args.aircraft_nrhs
+    if R <= 0:
+        return None
+    setup = {}
+    t0 = time.perf_counter()
+    v, t = synth.aircraft_like(3)
+    tree = nesa.build_tree(v, t, 0.25, l0_max=4)
+    info = tree.info()
+    setup["tree_s"] = time.perf_counter() - t0
+    log("aircraft: tree of %d unknowns, levels %d..%d" % (info["n_rwg"], info["l0"], info["L"]))
+    t0 = time.perf_counter()
+    near = nesa.assemble_near_device(tree)
+    setup["near_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
+    setup["far_s"] = time.perf_counter() - t0
+    nl = info["L"] - info["l0"] + 1
+    Q = [int(q) for q in far.q(nl)]
+    log("aircraft: far-field operators (Q %s)" % Q)
+    out = {"workload": "aircraft_like_seed3_%drwg" % info["n_rwg"], "n_unknowns": info["n_rwg"], "nrhs": R,
+           "leaf_lambda": 0.25, "levels": [info["l0"], info["L"]], "Q": Q, "boxes": info["n_box"],
+           "pairs": info["n_pairs"], "near_entries": info["near_entries"]}
+    n = info["n_rwg"]
+    precs = [("split", nesa.C64_SPLIT)] + ([("c64", nesa.C64)] if args.aircraft_fp32 else [])
+    for name, prec in precs:
+        t0 = time.perf_counter()
+        op = nesa.op_create(tree, near, far, prec, max_nrhs=R)
+        setup["op_%s_s" % name] = time.perf_counter() - t0
+        X = torch.from_numpy(synth.complex_normal((R, n), 5)).to(torch.complex64).cuda()
+        Y = torch.empty_like(X)
+        t0 = time.perf_counter()
+        nesa.matvec(op, X, Y, R, stream=stream)          # first product: tile tuning
+        torch.cuda.synchronize()
+        setup["first_product_%s_s" % name] = time.perf_counter() - t0
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            nesa.matvec(op, X, Y, R, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        lt = nesa.matvec_launch_times(op, X, Y, stream=stream, nrhs=R)
+        kern = {}
+        for kind, lev, m in lt:
+            e = kern.setdefault(kind, {"ms": 0.0, "launches": 0, "flops": 0.0})
+            e["ms"] += m
+            e["launches"] += 1
+            i = lev - info["l0"]
+            if kind == "translate_gemm":
+                e["flops"] += 8 * 4 * R * info["n_pairs"][i] * Q[i] * Q[i]
+            elif kind in ("upward_gemm", "downward_gemm"):
+                e["flops"] += info["n_box"][i] * 8 * 4 * R * Q[i - 1] * Q[i]
+        tr_ = kern.get("translate_gemm")
+        peak = PEAK_BF16 if prec == nesa.C64_SPLIT else PEAK_FP32
+        sec = {"ms_per_product": round(ms, 3),
+               "Munknowns_matvec_per_s": round(n * R / (ms * 1e-3) / 1e6, 1),
+               "kernels": {k: {"ms_per_product": round(v_["ms"], 3), "launches": v_["launches"],
+                               "TFLOP/s": round(v_["flops"] / (v_["ms"] * 1e-3) / 1e12, 1) if v_["flops"] else None}
+                           for k, v_ in kern.items()}}
+        if tr_:
+            ach = tr_["flops"] / (tr_["ms"] * 1e-3)
+            sec["translate_roofline"] = {"bound": "mfma", "achieved": round(ach / 1e12, 1),
+                                         "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                                         "kernel": "k_translate_tm_split" if prec == nesa.C64_SPLIT
+                                         else "k_translate_tm"}
+        out[name] = sec
+        log("aircraft %s: %d right-hand sides, %.2f ms per product" % (name, R, ms))
+        del op, X, Y
+        torch.cuda.empty_cache()
+    out["setup_s"] = {k: round(v_, 2) for k, v_ in setup.items()}
+    return out
+
+
 # The paper's own timed workload (2D model problem, N = 100 000, real FP64):
 # best complete-product times it prints, with their hardware (context only)
 PAPER_2D = {(50, 10): (100.0, "64 Xeon E5-4650 cores, SuperGlue"),
@@ -419,6 +535,9 @@ def main():
 
     if args.only_model2d:
         print(json.dumps({"model2d": model2d_section(args, nesa, torch, torch.cuda.current_stream())}))
+        return
+    if args.only_aircraft:
+        print(json.dumps({"aircraft": aircraft_section(args, nesa, torch, torch.cuda.current_stream())}))
         return
     prec = {"c64": nesa.C64, "c128": nesa.C128, "split": nesa.C64_SPLIT}[args.precision]
     esize = 16 if prec == nesa.C128 else 8
@@ -554,8 +673,13 @@ def main():
         phases[k] = {"ms": phase_ms[k], "GB/s": round(alg[k]["bytes"] / s_ / 1e9, 1),
                      "TFLOP/s": round(alg[k]["flops"] / s_ / 1e12, 2)}
     log("product: %.4f ms (%.1f Munknowns/s)" % (ms, value))
-    gm = batched = bodies = model2d = None
+    gm = batched = bodies = model2d = accurate = aircraft = trunc = None
     if not args.only_product:
+        trunc = dense_rows_error(nesa, torch, op, n, stream)
+        trunc["bound"] = 3e-3
+        log("truncation error on the dense rows: %.3e" % trunc["rel_err"])
+        accurate = accurate_section(args, nesa, torch, tree, near, n, stream)
+        log("d0 = 5: %.4f ms per product" % accurate["ms_per_product"])
         gm = gmres_section(args, nesa, torch, op, info, x, stream)
         log("GMRES done; batched right-hand sides")
         batched = batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream)
@@ -564,6 +688,7 @@ def main():
         bodies = bodies_section(args, nesa, torch, prec, dt, stream)
         log("2D model problem")
         model2d = model2d_section(args, nesa, torch, stream)
+        aircraft = aircraft_section(args, nesa, torch, stream)
     out = {
         "metric": "NESA matvec Munknowns/s",
         "value": round(value, 3),
@@ -593,14 +718,17 @@ def main():
         "launches": [[k, lev, round(m, 4)] for k, lev, m in launches],
         "wall_s_timed": round(wall, 4),
         "setup_s": {k: round(v_, 2) for k, v_ in setup.items()},
+        "truncation_error": trunc,
+        "accurate": accurate,
         "gmres": gm,
         "batched": batched,
         "bodies": bodies,
         "model2d": model2d,
+        "aircraft": aircraft,
     }
     if not args.no_cpu_baseline and not args.only_product:
         log("CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(v, t, args.cpu_sample_leaves)
+        out["cpu_baseline"] = cpu_baseline(v, t)
     print(json.dumps(out))
 
 

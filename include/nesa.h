@@ -69,7 +69,9 @@ typedef struct nesa_op nesa_op;
  *     bounding-box side / leaf_size)), root cube anchored 1e-9 below the
  *     vertex bounding-box minimum.
  *   l0_max: coarsest far level is min(l0_max, L) (2 = four boxes along the
- *     root side).
+ *     root side, the rule of Sec. 3; larger values start the far field at
+ *     finer boxes, which bounds the equivalent sources per box on bodies many
+ *     wavelengths long; at most 6).
  *   buffer: near boxes are those at Chebyshev index distance <= buffer
  *     (1 = adjacent boxes including diagonal ones and the box itself). */
 typedef struct {
@@ -215,6 +217,11 @@ int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* s
  * reception) and the tree level[i] it works on. */
 int nesa_matvec_launch_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms,
                              int32_t* kind, int32_t* level, int32_t max_launches, int32_t* count);
+/* The same for nrhs right-hand sides in leaf order (RHS-major; complex64 and
+ * split operators; nrhs = 1 is nesa_matvec_launch_times). */
+int nesa_matvec_launch_times_nrhs(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream,
+                                  float* ms, int32_t* kind, int32_t* level, int32_t max_launches,
+                                  int32_t* count);
 
 /* Plane-wave right-hand sides b_m = -<e_inc, phi_m> (Sec. 2, Eq. 2),
  * e_inc = pol exp(-i k khat.r); khat, pol: host [nrhs][3].  Writes device b
@@ -324,6 +331,14 @@ int nesa_residual_error(nesa_op* op, const void* b_dev, const void* xs_dev, cons
 /* Replace the parameters (host FP32) and reset the optimiser state. */
 int nesa_mlp_set_params(nesa_mlp* net, const float* theta);
 int nesa_mlp_get_params(const nesa_mlp* net, float* theta);
+/* Save the network's parameters (FP32), s_max, hidden and base to a file;
+ * nesa_mlp_load creates a network for `op` from such a file (as
+ * nesa_mlp_create with those values).  Layout: the 8 bytes "NESAMLP1", int32
+ * s_max, hidden, base, int64 parameter count, the FP32 parameters (host byte
+ * order).  Errors: NESA_EINVAL (null argument, file not writable / readable,
+ * not such a file, sizes that nesa_mlp_create rejects). */
+int nesa_mlp_save(const nesa_mlp* net, const char* path);
+int nesa_mlp_load(nesa_op* op, const char* path, nesa_mlp** out);
 /* Training set: nsamples pairs (r, e), device, canonical order, sample-major
  * [nsamples][n_rwg], in the op's vector precision.  The base preconditioner is
  * applied to every r here; features and targets stay on the device. */

@@ -175,20 +175,22 @@ static float bf16_to_float(uint16_t h) {
 static void attach_split(nesa_op* op, nesa::GemmPlan& p, const std::vector<cd>& Acm, int ngroups) {
   const int Kp = (p.K + 31) / 32 * 32;
   const size_t plane = (size_t)p.Mr * Kp;
-  std::vector<uint16_t> As((size_t)ngroups * 4 * plane, 0);
-  for (int gi = 0; gi < ngroups; ++gi)
+  std::vector<uint16_t> As((size_t)ngroups * 6 * plane, 0);
+  nesa::parallel_for(ngroups, [&](int64_t gi) {
     for (int k = 0; k < p.K; ++k)
       for (int m = 0; m < p.Mr; ++m) {
         const cd v = Acm[((size_t)gi * p.K + k) * p.Mr + m];
-        const float re = (float)v.real(), im = (float)v.imag();
-        const uint16_t rh = bf16_rne_host(re), ih = bf16_rne_host(im);
-        const uint16_t rl = bf16_rne_host(re - bf16_to_float(rh)), il = bf16_rne_host(im - bf16_to_float(ih));
-        const size_t base = (size_t)gi * 4 * plane + (size_t)m * Kp + k;
+        const float re = (float)v.real(), im = (float)v.imag(), sm = re + im;
+        const uint16_t rh = bf16_rne_host(re), ih = bf16_rne_host(im), sh = bf16_rne_host(sm);
+        const size_t base = (size_t)gi * 6 * plane + (size_t)m * Kp + k;
         As[base] = rh;
-        As[base + plane] = rl;
+        As[base + plane] = bf16_rne_host(re - bf16_to_float(rh));
         As[base + 2 * plane] = ih;
-        As[base + 3 * plane] = il;
+        As[base + 3 * plane] = bf16_rne_host(im - bf16_to_float(ih));
+        As[base + 4 * plane] = sh;
+        As[base + 5 * plane] = bf16_rne_host(sm - bf16_to_float(sh));
       }
+  });
   p.A_split = upload(op, As);
   p.Kp = Kp;
 }
@@ -488,7 +490,9 @@ static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs, hipStream
   V2* o = static_cast<V2*>(d.o);
   for (size_t i = 0; i < d.lev.size(); ++i) {
     auto& dl = d.lev[i];
-    if (dl.npairs > 0) {
+    // from TM_MIN_NRHS right-hand sides the translations run target-major
+    // (no tiles, no per-pair outputs)
+    if (dl.npairs > 0 && nrhs < nesa::TM_MIN_NRHS) {
       tune_plan(op, dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
     }
     if (i > 0) {
@@ -514,7 +518,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   if (smax > 256) throw Error(NESA_EINVAL, "a leaf holds more than 256 RWGs; use a smaller leaf size");
   if (QL > 128) throw Error(NESA_EINVAL, "more than 128 equivalent sources per leaf");
   for (const auto& fl : fr.lev)
-    if (fl.Q > 512) throw Error(NESA_EINVAL, "more than 512 equivalent sources per box");
+    if (fl.Q > 4096) throw Error(NESA_EINVAL, "more than 4096 equivalent sources per box");
   for (int64_t b = 0; b < d.nleaf; ++b)
     if (t.near_ptr[b + 1] - t.near_ptr[b] > 128) throw Error(NESA_EINVAL, "near list longer than 128");
   d.perm = upload(op, to_i32(t.perm));
@@ -636,7 +640,8 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       offs.push_back(s % SW - SH);
     }
     const int Qr = sizeof(T) == 4 ? nesa::row_alloc(fl.Q) : fl.Q;
-    std::vector<cd> Dc;   // host copy (split precision: its bf16 planes are made on the host)
+    void* d_split = nullptr;   // split precision: bf16 planes of D made on the device
+    int d_split_kp = 0;
     {
       std::vector<double> Eh(2 * fl.E.size());
       for (size_t i = 0; i < fl.E.size(); ++i) {
@@ -647,16 +652,21 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       const int32_t* offd = offs.empty() ? nullptr : upload(op, offs);
       const size_t cnt = (size_t)nused * fl.Q * Qr;
       if (op->precision == NESA_C64_SPLIT) {
-        void* tmp = nullptr;
+        // FP64 on the device, then its complex64 copy and the bf16 planes of
+        // the split products (no host round trip: the coarsest level of a
+        // long body holds gigabytes)
+        dl.D = dev_alloc(op, std::max<size_t>(cnt, 1) * 2 * sizeof(T));
+        d_split_kp = (fl.Q + 31) / 32 * 32;
+        d_split = dev_alloc(op, std::max<size_t>((size_t)nused * 6 * Qr * d_split_kp, 1) * sizeof(uint16_t));
         if (cnt > 0) {
+          void* tmp = nullptr;
           hip_check(hipMalloc(&tmp, cnt * sizeof(cd)), "hipMalloc");
           nesa::launch_fill_translation(Ed, offd, nused, fl.Q, Qr, lv.side, fr.k, tmp, true, nullptr);
+          nesa::launch_split_planes(tmp, nused, fl.Q, Qr, d_split_kp, dl.D, d_split, nullptr);
           hip_check(hipGetLastError(), "kernel launch");
-          Dc.resize(cnt);
-          hip_check(hipMemcpy(Dc.data(), tmp, cnt * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");
+          hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
           hip_check(hipFree(tmp), "hipFree");
         }
-        dl.D = upload_complex<T>(op, Dc);
       } else {
         dl.D = dev_alloc(op, std::max<size_t>(cnt, 1) * 2 * sizeof(T));
         nesa::launch_fill_translation(Ed, offd, nused, fl.Q, Qr, lv.side, fr.k, dl.D, sizeof(T) == 8, nullptr);
@@ -679,8 +689,13 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       for (int64_t a = 0; a < lv.nbox; ++a)
         for (int64_t k = lv.il_ptr[a]; k < lv.il_ptr[a + 1]; ++k) reg[k] = (int8_t)(a * 8 / lv.nbox);
       dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst, reg);
-      if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.trans, Dc, nused);
-      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * op->max_nrhs * fl.Q * 2 * sizeof(T));
+      if (op->precision == NESA_C64_SPLIT) {
+        dl.trans.A_split = d_split;
+        dl.trans.Kp = d_split_kp;
+      }
+      // per-pair outputs serve the offset-major form only (below TM_MIN_NRHS)
+      const int nr_pair = std::min(op->max_nrhs, nesa::TM_MIN_NRHS - 1);
+      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * nr_pair * fl.Q * 2 * sizeof(T));
     }
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
@@ -1665,12 +1680,13 @@ int nesa_residual_error(nesa_op* op, const void* b_dev, const void* xs_dev, cons
   });
 }
 
-static void timed_matvec(nesa_op* op, const void* x_dev, void* y_dev, hipStream_t st, nesa::PhaseTimer& tm) {
+static void timed_matvec(nesa_op* op, const void* x_dev, void* y_dev, hipStream_t st, nesa::PhaseTimer& tm,
+                         int nrhs = 1) {
   for (auto& e : tm.ev) hip_check(hipEventCreate(&e), "hipEventCreate");
   if (op->precision == NESA_C128)
     nesa::launch_matvec_leaf<double>(op->d, x_dev, y_dev, 1, st, &tm);
   else
-    nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, 1, st, &tm);
+    nesa::launch_matvec_leaf<float>(op->f, x_dev, y_dev, nrhs, st, &tm);
   hip_check(hipGetLastError(), "kernel launch");
   hip_check(hipEventSynchronize(tm.ev[tm.n - 1]), "hipEventSynchronize");
 }
@@ -1690,11 +1706,19 @@ int nesa_matvec_phase_times(nesa_op* op, const void* x_dev, void* y_dev, void* s
 
 int nesa_matvec_launch_times(nesa_op* op, const void* x_dev, void* y_dev, void* stream, float* ms,
                              int32_t* kind, int32_t* level, int32_t max_launches, int32_t* count) {
+  return nesa_matvec_launch_times_nrhs(op, x_dev, y_dev, 1, stream, ms, kind, level, max_launches, count);
+}
+
+int nesa_matvec_launch_times_nrhs(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream,
+                                  float* ms, int32_t* kind, int32_t* level, int32_t max_launches, int32_t* count) {
   return guarded([&]() {
     if (!op || !x_dev || !y_dev || !ms || !kind || !level || !count) return fail(NESA_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
+    if (nrhs > 1 && op->precision == NESA_C128) return fail(NESA_EINVAL, "complex128 products take one right-hand side");
+    if (op->precision != NESA_C128 && nrhs > 1) ensure_all_tiles<float>(op, op->f, (int)nrhs, static_cast<hipStream_t>(stream));
     nesa::PhaseTimer tm;
     tm.overlap = true;       // the launches as the untimed product runs them
-    timed_matvec(op, x_dev, y_dev, static_cast<hipStream_t>(stream), tm);
+    timed_matvec(op, x_dev, y_dev, static_cast<hipStream_t>(stream), tm, (int)nrhs);
     int c = 0;
     for (int i = 1; i < tm.n && c < max_launches; ++i) {
       if (tm.kind[i] == 0) continue;
@@ -1957,6 +1981,52 @@ int nesa_mlp_get_params(const nesa_mlp* net, float* theta) {
     if (!net || !theta) return fail(NESA_EINVAL, "null argument");
     hip_check(hipMemcpy(theta, net->net.theta, net->net.np * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
     return (int)NESA_OK;
+  });
+}
+
+// file layout: 8-byte tag "NESAMLP1", int32 s_max, hidden, base, int64 count,
+// then count FP32 parameters (host byte order)
+int nesa_mlp_save(const nesa_mlp* net, const char* path) {
+  return guarded([&]() {
+    if (!net || !path) return fail(NESA_EINVAL, "null argument");
+    std::vector<float> th(net->net.np);
+    hip_check(hipMemcpy(th.data(), net->net.theta, th.size() * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(NESA_EINVAL, std::string("cannot open for writing: ") + path);
+    const int32_t hdr[3] = {net->net.S, net->net.H, net->base};
+    const int64_t cnt = net->net.np;
+    bool ok = std::fwrite("NESAMLP1", 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1 &&
+              std::fwrite(&cnt, sizeof(cnt), 1, fp) == 1 &&
+              std::fwrite(th.data(), sizeof(float), th.size(), fp) == th.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(NESA_EINVAL, std::string("write failed: ") + path);
+    return (int)NESA_OK;
+  });
+}
+
+int nesa_mlp_load(nesa_op* op, const char* path, nesa_mlp** out) {
+  return guarded([&]() {
+    if (!op || !path || !out) return fail(NESA_EINVAL, "null argument");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(NESA_EINVAL, std::string("cannot open for reading: ") + path);
+    char tag[8];
+    int32_t hdr[3];
+    int64_t cnt = 0;
+    bool ok = std::fread(tag, 1, 8, fp) == 8 && std::memcmp(tag, "NESAMLP1", 8) == 0 &&
+              std::fread(hdr, sizeof(hdr), 1, fp) == 1 && std::fread(&cnt, sizeof(cnt), 1, fp) == 1;
+    nesa_mlp_params prm{hdr[0], hdr[1], hdr[2]};
+    std::vector<float> th;
+    if (ok) {
+      check_mlp_params(&prm);
+      ok = cnt == nesa::mlp_nparams(prm.s_max, prm.hidden);
+      if (ok) {
+        th.resize(cnt);
+        ok = std::fread(th.data(), sizeof(float), th.size(), fp) == th.size();
+      }
+    }
+    std::fclose(fp);
+    if (!ok) return fail(NESA_EINVAL, std::string("not a network file of this library: ") + path);
+    return nesa_mlp_create(op, &prm, th.data(), out);
   });
 }
 

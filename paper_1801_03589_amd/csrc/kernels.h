@@ -27,7 +27,8 @@ struct TileList {
 };
 struct GemmPlan {
   const void* A = nullptr;       // [groups][K][Mr] column-major, rows padded with zeros
-  const void* A_split = nullptr; // split precision: [groups][4 planes][Mr][Kp] bf16 (re hi, re lo, im hi, im lo)
+  const void* A_split = nullptr; // split precision: [groups][6 planes][Mr][Kp] bf16 (re hi, re lo, im hi, im lo,
+                                 // (re + im) hi, (re + im) lo)
   int Kp = 0;                    // K rounded up to 32
   int64_t a_stride = 0;
   int M = 0, K = 0, Mr = 0;      // Mr = rows of A allocated (row_alloc), >= rblocks x nrt x 16
@@ -116,6 +117,37 @@ inline int row_alloc(int M) {
   const int tiles = (M + 15) / 16;
   return 16 * ((tiles + 7) / 8 * 8);
 }
+
+// Target-major translations (translate_tm.hip): o_a = sum over the
+// interaction list of D_{a-b} s_b for the 4 nrhs channel columns of every box,
+// one workgroup per (box, tile of up to 64 columns, row block).  FP32 three-MFMA
+// complex products, or split bf16x3 products when Asplit is set.
+struct TmArgs {
+  const float2* D = nullptr;              // [slot][K][Mr] column-major (FP32 form)
+  const unsigned short* Asplit = nullptr; // [slot][6][Mr][Kp] bf16 planes (split form)
+  int64_t a_stride = 0;                   // K * Mr
+  int M = 0, K = 0, Mr = 0, Kp = 0;
+  const float2* s = nullptr;              // this level's sources [box][NC][K]
+  float2* o = nullptr;                    // this level's potentials [box][NC][M] (overwritten)
+  const int32_t* il_ptr = nullptr;        // [nbox + 1]
+  const int32_t* il_src = nullptr;
+  const int32_t* il_slot = nullptr;       // compact slot of every pair
+  int64_t nbox = 0;
+  int NC = 0;                             // 4 x nrhs
+  int nct = 0;                            // column tiles per box
+};
+// right-hand sides from which the translations run target-major
+constexpr int TM_MIN_NRHS = 8;
+// row tiles per workgroup, row blocks and column tiles of 16 (4 or 2) for M
+// rows inside Mr allocated rows and NC columns; nrt = 0 if none fits
+void tm_blocking(int M, int Mr, int NC, int& nrt, int& rblocks, int& ct);
+void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStream_t st);
+// Split planes of a grouped GEMM's A on the device (the host's rounding):
+// complex128 [ngroups][K][Mr] -> bf16 [ngroups][6][Mr][Kp] (re hi, re lo, im
+// hi, im lo, (re + im) hi, (re + im) lo; zero for k >= K) and, if D32 is not
+// null, its complex64 copy [ngroups][K][Mr].
+void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes,
+                         hipStream_t st);
 
 // kernel kinds of the per-launch timing
 enum { K_RADIATE = 1, K_UP_GEMM, K_UP_REDUCE, K_UP_VALU, K_TRANS_GEMM, K_TRANS_REDUCE, K_TRANS_VALU,

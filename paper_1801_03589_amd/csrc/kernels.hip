@@ -485,7 +485,8 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 // Split-precision variant (complex64 vectors, bf16x3 products): every FP32
 // value v is split as hi = bf16(v), lo = bf16(v - hi); a real product is
 // hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMAs with FP32 accumulation.  A is
-// pre-split on the host into four planes (re hi, re lo, im hi, im lo), each
+// pre-split on the host into planes (re hi, re lo, im hi, im lo, and the two of
+// re + im that the target-major kernel uses), each
 // [Mr][Kp] with k contiguous (Kp = K rounded up to 32, zero padded); B is split
 // in the kernel from the FP32 tile in LDS.  Fragment layout of the 16x16x32
 // instruction: lane l holds rows/columns l % 16 and k = 8 (l / 16) .. +7.
@@ -504,7 +505,7 @@ template <int NRT>
 __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, const unsigned short* __restrict__ As,
                                                         int Kp) {
   static_assert(TR_KC == 32, "one bf16 MFMA k-step per chunk");
-  __shared__ uint4 Al[4][NRT * 16][4];                        // [plane][row][8 k], split planes of A
+  __shared__ uint4 Al[6][NRT * 16][4];                        // [plane][row][8 k], split planes of A
   __shared__ float2 Bs[TR_COLS][TR_KC + 1];                   // [column][k] FP32 B, split in place
   __shared__ int64_t col_src[TR_COLS];
   __shared__ int64_t col_dst[TR_COLS];
@@ -521,20 +522,28 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   __syncthreads();
   const bool active = 16 * w < cnt;
   const size_t plane = (size_t)g.Mr * Kp;
-  const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 4 * plane + (size_t)r0 * Kp;
-  f32x4 cre[NRT], cim[NRT];
+  const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 6 * plane + (size_t)r0 * Kp;
+  // three real products per complex one (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)
+  // (Br + Bi)), each as bf16 hi hi + hi lo + lo hi: nine MFMAs per k step
+  f32x4 c1[NRT], c2[NRT], c3[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) {
-    cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-    cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    c1[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    c2[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    c3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  // A staging: NRT x 16 B per thread per chunk (4 planes x NRT*16 rows x 4 quarters of 8 k)
-  uint4 ra[NRT];
-  const uint4* a_ptr[NRT];
+  // A staging: 6 planes x NRT*16 rows x 4 quarters of 8 k (uint4) per chunk
+  constexpr int NAQ = 6 * NRT * 16 * 4;
+  constexpr int NAT = (NAQ + NT - 1) / NT;
+  uint4 ra[NAT];
+  const uint4* a_ptr[NAT];
+  bool a_ok[NAT];
 #pragma unroll
-  for (int i = 0; i < NRT; ++i) {
+  for (int i = 0; i < NAT; ++i) {
     const int e = t + i * NT;
-    const int pl = e / (NRT * 16 * 4), row = (e / 4) % (NRT * 16), qu = e % 4;
+    a_ok[i] = e < NAQ;
+    const int ee = a_ok[i] ? e : 0;
+    const int pl = ee / (NRT * 16 * 4), row = (ee / 4) % (NRT * 16), qu = ee % 4;
     a_ptr[i] = reinterpret_cast<const uint4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
   }
   // B staging: TR_NB float2 per thread per chunk
@@ -554,7 +563,8 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   // LDS store, so the loads stay in flight during the MFMAs
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < NRT; ++i) ra[i] = a_ptr[i][k0 / 8];
+    for (int i = 0; i < NAT; ++i)
+      if (a_ok[i]) ra[i] = a_ptr[i][k0 / 8];
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
   };
@@ -562,9 +572,9 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   for (int k0 = 0; k0 < K; k0 += TR_KC) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NRT; ++i) {
+    for (int i = 0; i < NAT; ++i) {
       const int e = t + i * NT;
-      Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
+      if (a_ok[i]) Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) {
@@ -574,8 +584,9 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
     __syncthreads();
     if (k0 + TR_KC < K) load(k0 + TR_KC);
     if (active) {
-      // B fragments of this wave's column tile as bf16 hi / lo planes
-      bf16x8 brh, brl, bih, bil, nbih, nbil;
+      // B fragments of this wave's column tile as bf16 hi / lo planes of the
+      // real part, the imaginary part and their sum
+      bf16x8 brh, brl, bih, bil, bsh, bsl;
       const float2* bcol = &Bs[w * 16 + lane % 16][8 * (lane / 16)];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -587,8 +598,9 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         split_bf16(v.y, h, l);
         bih[j] = __builtin_bit_cast(__bf16, h);
         bil[j] = __builtin_bit_cast(__bf16, l);
-        nbih[j] = __builtin_bit_cast(__bf16, (unsigned short)(h ^ 0x8000u));
-        nbil[j] = __builtin_bit_cast(__bf16, (unsigned short)(l ^ 0x8000u));
+        split_bf16(v.x + v.y, h, l);
+        bsh[j] = __builtin_bit_cast(__bf16, h);
+        bsl[j] = __builtin_bit_cast(__bf16, l);
       }
 #pragma unroll
       for (int r = 0; r < NRT; ++r) {
@@ -597,18 +609,17 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         const bf16x8 arl = __builtin_bit_cast(bf16x8, Al[1][row][qu]);
         const bf16x8 aih = __builtin_bit_cast(bf16x8, Al[2][row][qu]);
         const bf16x8 ail = __builtin_bit_cast(bf16x8, Al[3][row][qu]);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbih, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbil, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nbih, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, cim[r], 0, 0, 0);
+        const bf16x8 ash = __builtin_bit_cast(bf16x8, Al[4][row][qu]);
+        const bf16x8 asl = __builtin_bit_cast(bf16x8, Al[5][row][qu]);
+        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, c1[r], 0, 0, 0);
+        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bih, c2[r], 0, 0, 0);
+        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsh, c3[r], 0, 0, 0);
+        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, c1[r], 0, 0, 0);
+        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bil, c2[r], 0, 0, 0);
+        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsl, c3[r], 0, 0, 0);
+        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, c1[r], 0, 0, 0);
+        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bih, c2[r], 0, 0, 0);
+        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asl, bsh, c3[r], 0, 0, 0);
       }
     }
   }
@@ -621,7 +632,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
       for (int i = 0; i < 4; ++i) {
         const int row = r0 + r * 16 + 4 * (lane / 16) + i;
         if (row < M) {
-          float2 v = make_float2(cre[r][i], cim[r][i]);
+          float2 v = make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
           if (g.accumulate) {
             const float2 o = out[row];
             v.x += o.x;
@@ -1924,14 +1935,46 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   auto side_ok = [&](int l) {
     return overlap && !tm && mfma && d.side2 != nullptr && l > l0 && l == L && d.lev[l - l0].npairs > 0;
   };
+  // translations of one level (complex64): target-major from TM_MIN_NRHS
+  // right-hand sides, else offset-major tiles and the ordered per-target sums
+  auto translate = [&](const DevLevel& lv, hipStream_t ss, int l) {
+    if constexpr (sizeof(T) == 4) {
+      if (R >= TM_MIN_NRHS) {
+        TmArgs g;
+        g.D = static_cast<const float2*>(lv.trans.A);
+        g.Asplit = static_cast<const unsigned short*>(lv.trans.A_split);
+        g.a_stride = lv.trans.a_stride;
+        g.M = lv.Q;
+        g.K = lv.Q;
+        g.Mr = lv.trans.Mr;
+        g.Kp = lv.trans.Kp;
+        g.s = reinterpret_cast<const float2*>(s + lv.s_off * R);
+        g.o = reinterpret_cast<float2*>(o + lv.s_off * R);
+        g.il_ptr = lv.il_ptr;
+        g.il_src = lv.il_src;
+        g.il_slot = lv.il_slot;
+        g.nbox = lv.nbox;
+        g.NC = NC;
+        int nrt = 0, rblocks = 0, ct = 0;
+        tm_blocking(lv.Q, lv.trans.Mr, NC, nrt, rblocks, ct);
+        g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
+        launch_translate_tm(g, nrt, rblocks, ct, ss);
+        if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
+        return;
+      }
+    }
+    launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, ss, true);
+    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
+    k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, ss>>>(static_cast<const V2*>(lv.pair_out),
+                                                                  o + lv.s_off * R, lv.il_ptr, lv.il_ptr + 1,
+                                                                  NC * lv.Q);
+    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_REDUCE);
+  };
   auto fork_trans = [&](int l, hipEvent_t fork, hipEvent_t join) {
     const auto& lv = d.lev[l - l0];
     hip_ok(hipEventRecord(fork, st));
     hip_ok(hipStreamWaitEvent(d.side2, fork, 0));
-    launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, d.side2, true);
-    k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, d.side2>>>(static_cast<const V2*>(lv.pair_out),
-                                                                        o + lv.s_off * R, lv.il_ptr,
-                                                                        lv.il_ptr + 1, NC * lv.Q);
+    translate(lv, d.side2, l);
     hip_ok(hipEventRecord(join, d.side2));
   };
   if (side_ok(L)) fork_trans(L, d.ev_fork2, d.ev_join2);
@@ -1959,12 +2002,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     if (mfma && lv.npairs > 0) {
       // each level's sums right after its GEMM, while its per-pair outputs are
       // still in the last-level cache (one launch for all levels measured slower)
-      launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, st, true);
-      if (tm) tm->mark(st, -1, l, K_TRANS_GEMM);
-      k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, st>>>(static_cast<const V2*>(lv.pair_out),
-                                                                    o + lv.s_off * R, lv.il_ptr, lv.il_ptr + 1,
-                                                                    NC * lv.Q);
-      if (tm) tm->mark(st, -1, l, K_TRANS_REDUCE);
+      translate(lv, st, l);
     } else if (mfma) {
       const int64_t cnt = lv.nbox * NC * lv.Q;
       k_fill_zero<V2><<<(unsigned)((cnt + NT - 1) / NT), NT, 0, st>>>(o + lv.s_off * R, cnt);

@@ -65,7 +65,11 @@ struct Tree {
   // (empty for a single mesh); levels are aligned at the leaves
   std::vector<std::array<double, 3>> body_lo;
   std::vector<int64_t> body_rwg;    // [nbodies + 1]
-  int slot_w() const { return 4 * buffer + 3; }   // offsets in [-(2b+1), 2b+1] per axis
+  // offset slots of the translation tables: offsets in [-(W-1)/2, (W-1)/2] per
+  // axis, W = max(4 buffer + 3, 2^(l0 + 1) - 1): the interaction lists below l0
+  // reach 2 buffer + 1 boxes, the coarsest level's reach across its whole grid
+  int slotw = 7;
+  int slot_w() const { return slotw; }
   int nslot() const { return slot_w() * slot_w() * slot_w(); }
   const Level& level(int l) const { return lev[l - l0]; }
   Level& level(int l) { return lev[l - l0]; }

@@ -1,0 +1,480 @@
+// Target-major translations for several right-hand sides (Sec. 3, Eq. 12):
+// o_a = sum over b in IL(a) of D_{a-b} s_b, one workgroup per (target box a,
+// tile of GEMM columns, block of rows).  With 4 nrhs channel columns per box
+// (nrhs >= 8 gives 32 or more), the columns of one target already fill the
+// matrix-core tiles, so the sum over the interaction list runs inside the
+// accumulators: the pairs are consecutive K segments of one GEMM,
+//   o_a[rows, cols] = [D_{a-b1} D_{a-b2} ...] [s_b1; s_b2; ...][K, cols],
+// and every output is written once, in the list order, with no per-pair
+// partial results.  (One right-hand side has only 4 columns per box; there the
+// offset-major grouped GEMM of kernels.hip shares each D across many pairs.)
+//
+// FP32 form: complex products as three real 16x16x4 MFMAs (Ar Br, Ai Bi,
+// (Ar + Ai)(Br + Bi)).  Split form: each FP32 value v = hi + lo with
+// hi = bf16(v), lo = bf16(v - hi); a real product is hi hi + hi lo + lo hi on
+// 16x16x32 bf16 MFMAs with FP32 accumulation, and the complex product takes
+// the same three real products, i.e. nine bf16 MFMAs per complex k step.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace nesa {
+
+namespace {
+
+constexpr int TM_NT = 256;
+constexpr int TM_WAVE = 64;
+constexpr int TM_KC = 32;     // K chunk staged in LDS
+typedef float tm_f32x4 __attribute__((ext_vector_type(4)));
+
+// Work item of a workgroup: items dealt to the 8 XCDs so that each XCD takes a
+// contiguous range (neighbouring targets share sources and offsets in its L2).
+__device__ __forceinline__ int64_t tm_item(int64_t bid, int64_t nitems) {
+  const int64_t per = (nitems + 7) / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
+// NRT row tiles of 16 per workgroup, CT column tiles of 16 (CT = 4: wave w
+// owns column tile w and all row tiles; CT = 2: wave w owns column tile w % 2
+// and half of the row tiles).
+template <int NRT, int CT>
+__device__ __forceinline__ void translate_tm_body(const TmArgs& g) {
+  constexpr int KC = TM_KC;
+  constexpr int HALF = NRT * 8;                 // float4 per A column of the row block
+  constexpr int NA = KC * HALF / TM_NT;         // float4 of A per thread per chunk
+  constexpr int COLS = 16 * CT;
+  constexpr int NBT = KC * COLS / TM_NT;        // float2 of B per thread per chunk
+  constexpr int RPW = NRT * CT / 4;             // row tiles per wave
+  static_assert(KC * HALF % TM_NT == 0 && KC * COLS % TM_NT == 0, "chunks must split evenly");
+  static_assert(NRT * CT % 4 == 0, "row tiles must split over the waves");
+  // LDS padding as in the offset-major kernel: the four k rows a wave reads at
+  // once sit 32 banks apart, and neighbouring B columns fall in other banks
+  constexpr int APAD = (NRT % 2 == 0) ? 4 : 0;
+  constexpr int AST = 2 * (HALF + APAD);
+  __shared__ float4 As4[KC][HALF + APAD];
+  __shared__ float2 Bs[COLS][KC + 2];
+  const int64_t nitems = g.nbox * g.nct;
+  const int64_t item = tm_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int64_t a = item / g.nct;
+  const int c0 = (int)(item % g.nct) * COLS;
+  const int ncol = min(COLS, g.NC - c0);         // valid columns of the tile
+  const int r0 = blockIdx.y * NRT * 16;
+  const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
+  const int ct = w % CT, rt0 = (w / CT) * RPW;
+  const int K = g.K, M = g.M, NC = g.NC;
+  const int mr2 = g.Mr / 2;
+  const int kc0 = (K % KC) ? K % KC : KC;        // the partial chunk of every pair goes first
+  const int nch = 1 + (K - kc0) / KC;            // chunks per pair
+  const int jb = g.il_ptr[a], je = g.il_ptr[a + 1];
+  const bool active = 16 * ct < ncol;
+  // per-thread element offsets of a chunk (full chunks, and the partial chunk
+  // with k clamped to its last step so that its loads stay inside the pair)
+  int oa[NA], oap[NA], ob[NBT], obp[NBT];
+  bool bok[NBT];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int e = t + i * TM_NT, k = e / HALF, rp = e % HALF;
+    oa[i] = k * mr2 + rp;
+    oap[i] = min(k, kc0 - 1) * mr2 + rp;
+  }
+#pragma unroll
+  for (int i = 0; i < NBT; ++i) {
+    const int e = t + i * TM_NT, col = e / KC, k = e % KC;
+    const int cc = min(col, ncol - 1);
+    ob[i] = cc * K + k;
+    obp[i] = cc * K + min(k, kc0 - 1);
+    bok[i] = col < ncol;
+  }
+  tm_f32x4 c1[RPW], c2[RPW], c3[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    c1[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+    c2[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+    c3[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  float4 ra[NA];
+  float2 rb[NBT];
+  // chunk (pair j, chunk ci) into registers
+  auto load = [&](int j, int ci) {
+    const int slot = g.il_slot[j], src = g.il_src[j];
+    const int kk = ci == 0 ? 0 : kc0 + (ci - 1) * KC;
+    const float4* A4 = reinterpret_cast<const float4*>(g.D + (size_t)slot * g.a_stride + r0) + (size_t)kk * mr2;
+    const float2* B = g.s + ((size_t)src * NC + c0) * K + kk;
+    if (ci == 0) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) ra[i] = A4[oap[i]];
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) rb[i] = B[obp[i]];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) ra[i] = A4[oa[i]];
+#pragma unroll
+      for (int i = 0; i < NBT; ++i) rb[i] = B[ob[i]];
+    }
+  };
+  // registers -> LDS; k past a partial chunk and empty columns become zeros
+  auto stage = [&](int kc) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = t + i * TM_NT;
+      As4[e / HALF][e % HALF] = (e / HALF < kc) ? ra[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+      const int e = t + i * TM_NT;
+      Bs[e / KC][e % KC] = (e % KC < kc && bok[i]) ? rb[i] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+  };
+  const float2* As = reinterpret_cast<const float2*>(&As4[0][0]);
+  auto step = [&](int ks) {
+    const int kk = ks * 4 + lane / 16;
+    const float2 b = Bs[ct * 16 + lane % 16][kk];
+    const float bs = b.x + b.y;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const float2 av = As[kk * AST + (rt0 + r) * 16 + lane % 16];
+      c1[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, b.x, c1[r], 0, 0, 0);
+      c2[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, b.y, c2[r], 0, 0, 0);
+      c3[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bs, c3[r], 0, 0, 0);
+    }
+  };
+  if (jb < je) {
+    load(jb, 0);
+    for (int j = jb; j < je; ++j) {
+      for (int ci = 0; ci < nch; ++ci) {
+        const int kc = ci == 0 ? kc0 : KC;
+        stage(kc);
+        // the next chunk's loads stay in flight during this chunk's MFMAs
+        if (ci + 1 < nch)
+          load(j, ci + 1);
+        else if (j + 1 < je)
+          load(j + 1, 0);
+        if (active) {
+          if (kc == KC) {
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) step(ks);
+          } else {
+            for (int ks = 0; ks < (kc + 3) / 4; ++ks) step(ks);
+          }
+        }
+      }
+    }
+  }
+  // output through LDS ([column][row], row stride ROWS + 2), then runs of
+  // consecutive rows of each column: o[a][c0 + col][r0 + row]
+  constexpr int ROWS = NRT * 16;
+  constexpr int RS = ROWS + 2;
+  constexpr int ACAP = KC * (HALF + APAD) * 2;  // float2 in As4
+  constexpr int PC = (ACAP / RS) >= COLS ? COLS : (ACAP / RS) / 16 * 16;
+  static_assert(PC >= 16, "the LDS tile must hold one column tile");
+  float2* otile = reinterpret_cast<float2*>(&As4[0][0]);
+  const int mloc = min(ROWS, M - r0);
+  float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
+  for (int p0 = 0; p0 < COLS; p0 += PC) {
+    __syncthreads();
+    if (ct * 16 >= p0 && ct * 16 < p0 + PC) {
+      const int lc = ct * 16 - p0 + lane % 16;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          otile[lc * RS + (rt0 + r) * 16 + 4 * (lane / 16) + i] =
+              make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
+      }
+    }
+    __syncthreads();
+    const int nc = min(PC, ncol - p0);
+    for (int e = t; e < nc * mloc; e += TM_NT) {
+      const int lc = e / mloc, row = e % mloc;
+      obase[(size_t)(p0 + lc) * M + row] = otile[lc * RS + row];
+    }
+  }
+}
+
+template <int NRT, int CT>
+__global__ __launch_bounds__(TM_NT) void k_translate_tm(TmArgs g) {
+  translate_tm_body<NRT, CT>(g);
+}
+
+
+// Split form.  A (the translation matrices) arrives pre-split in six bf16
+// planes [slot][plane][Mr][Kp] with k contiguous (Kp = K rounded up to 32,
+// zero padded): re hi, re lo, im hi, im lo, (re + im) hi, (re + im) lo.  B (the
+// FP32 sources) is split while it is staged: each thread takes 8 consecutive k
+// of one column and writes them as 8 bf16 in each of six planes, which is the
+// operand layout of the 16x16x32 instruction (lane l: row or column l % 16,
+// k = 8 (l / 16) .. + 7).  Wave w owns column tile w and all row tiles.
+typedef __bf16 tm_bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short tm_bf16_rne(float v) {
+  const unsigned u = __float_as_uint(v);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ void tm_split(float v, unsigned short& hi, unsigned short& lo) {
+  hi = tm_bf16_rne(v);
+  lo = tm_bf16_rne(v - __uint_as_float((unsigned)hi << 16));
+}
+__device__ __forceinline__ unsigned tm_pack(unsigned short a, unsigned short b) {
+  return (unsigned)a | ((unsigned)b << 16);
+}
+
+template <int NRT>
+__device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
+  constexpr int KC = TM_KC;
+  constexpr int ROWS = NRT * 16;
+  constexpr int COLS = 64;
+  constexpr int NAQ = 6 * ROWS * 4;               // uint4 of A per chunk (6 planes x rows x 4 quarters)
+  constexpr int NAT = (NAQ + TM_NT - 1) / TM_NT;  // per thread
+  static_assert(COLS * KC / 8 == TM_NT, "one column quarter of B per thread");
+  // one LDS buffer: A planes [6][ROWS][5] and B planes [6][COLS][5] (uint4 of
+  // 8 bf16; row stride 5 keeps a wave's 16-byte reads free of bank
+  // conflicts), reused by the output tile at the end
+  constexpr int AQ = 6 * ROWS * 5, BQ = 6 * COLS * 5;
+  __shared__ uint4 lds[AQ + BQ];
+  auto Al = [&](int pl, int row, int qu) -> uint4& { return lds[(pl * ROWS + row) * 5 + qu]; };
+  auto Bl = [&](int pl, int col, int qu) -> uint4& { return lds[AQ + (pl * COLS + col) * 5 + qu]; };
+  const int64_t nitems = g.nbox * g.nct;
+  const int64_t item = tm_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int64_t a = item / g.nct;
+  const int c0 = (int)(item % g.nct) * COLS;
+  const int ncol = min(COLS, g.NC - c0);
+  const int r0 = blockIdx.y * ROWS;
+  const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
+  const int K = g.K, M = g.M, NC = g.NC, Kp = g.Kp;
+  const size_t plane = (size_t)g.Mr * Kp;
+  const int nch = Kp / KC;
+  const int jb = g.il_ptr[a], je = g.il_ptr[a + 1];
+  const bool active = 16 * w < ncol;
+  // A staging: element e = (plane, row, quarter) of the chunk
+  int oa[NAT];
+  bool aok[NAT];
+#pragma unroll
+  for (int i = 0; i < NAT; ++i) {
+    const int e = t + i * TM_NT;
+    aok[i] = e < NAQ;
+    const int ee = aok[i] ? e : 0;
+    const int pl = ee / (ROWS * 4), row = (ee / 4) % ROWS, qu = ee % 4;
+    oa[i] = (int)(pl * plane / 8) + row * (Kp / 8) + qu;     // in uint4 (8 bf16)
+  }
+  // B staging: column t / 4 of the tile, quarter t % 4 (k = 8 (t % 4) .. + 7)
+  const int bcol = t / 4, bq = t % 4;
+  const bool bok = bcol < ncol;
+  const int bcc = min(bcol, ncol - 1);
+  tm_f32x4 c1[NRT], c2[NRT], c3[NRT];
+#pragma unroll
+  for (int r = 0; r < NRT; ++r) {
+    c1[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+    c2[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+    c3[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  uint4 ra[NAT];
+  float2 rb[8];
+  auto load = [&](int j, int ci) {
+    const int slot = g.il_slot[j], src = g.il_src[j];
+    const int k0 = ci * KC;
+    const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp + k0);
+#pragma unroll
+    for (int i = 0; i < NAT; ++i)
+      if (aok[i]) ra[i] = A[oa[i]];
+    const float2* B = g.s + ((size_t)src * NC + c0 + bcc) * K;
+    const int kb = k0 + 8 * bq;
+    if (k0 + KC <= K) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rb[u] = B[kb + u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rb[u] = B[min(kb + u, K - 1)];
+    }
+  };
+  auto stage = [&](int ci) {
+    const int kv = K - ci * KC - 8 * bq;        // valid k of this thread's quarter
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NAT; ++i) {
+      const int e = t + i * TM_NT;
+      if (aok[i]) Al(e / (ROWS * 4), (e / 4) % ROWS, e % 4) = ra[i];
+    }
+    unsigned short h[6][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      float2 v = rb[u];
+      if (!(bok && u < kv)) v = make_float2(0.f, 0.f);
+      unsigned short hi, lo;
+      tm_split(v.x, hi, lo);
+      h[0][u] = hi;
+      h[1][u] = lo;
+      tm_split(v.y, hi, lo);
+      h[2][u] = hi;
+      h[3][u] = lo;
+      tm_split(v.x + v.y, hi, lo);
+      h[4][u] = hi;
+      h[5][u] = lo;
+    }
+#pragma unroll
+    for (int pl = 0; pl < 6; ++pl)
+      Bl(pl, bcol, bq) = make_uint4(tm_pack(h[pl][0], h[pl][1]), tm_pack(h[pl][2], h[pl][3]),
+                                    tm_pack(h[pl][4], h[pl][5]), tm_pack(h[pl][6], h[pl][7]));
+    __syncthreads();
+  };
+  auto mfma = [&]() {
+    const int col = w * 16 + lane % 16, qu = lane / 16;
+    const tm_bf16x8 brh = __builtin_bit_cast(tm_bf16x8, Bl(0, col, qu));
+    const tm_bf16x8 brl = __builtin_bit_cast(tm_bf16x8, Bl(1, col, qu));
+    const tm_bf16x8 bih = __builtin_bit_cast(tm_bf16x8, Bl(2, col, qu));
+    const tm_bf16x8 bil = __builtin_bit_cast(tm_bf16x8, Bl(3, col, qu));
+    const tm_bf16x8 bsh = __builtin_bit_cast(tm_bf16x8, Bl(4, col, qu));
+    const tm_bf16x8 bsl = __builtin_bit_cast(tm_bf16x8, Bl(5, col, qu));
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      const int row = r * 16 + lane % 16;
+      const tm_bf16x8 arh = __builtin_bit_cast(tm_bf16x8, Al(0, row, qu));
+      const tm_bf16x8 arl = __builtin_bit_cast(tm_bf16x8, Al(1, row, qu));
+      const tm_bf16x8 aih = __builtin_bit_cast(tm_bf16x8, Al(2, row, qu));
+      const tm_bf16x8 ail = __builtin_bit_cast(tm_bf16x8, Al(3, row, qu));
+      const tm_bf16x8 ash = __builtin_bit_cast(tm_bf16x8, Al(4, row, qu));
+      const tm_bf16x8 asl = __builtin_bit_cast(tm_bf16x8, Al(5, row, qu));
+      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, c1[r], 0, 0, 0);
+      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bih, c2[r], 0, 0, 0);
+      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsh, c3[r], 0, 0, 0);
+      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, c1[r], 0, 0, 0);
+      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bil, c2[r], 0, 0, 0);
+      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsl, c3[r], 0, 0, 0);
+      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, c1[r], 0, 0, 0);
+      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bih, c2[r], 0, 0, 0);
+      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asl, bsh, c3[r], 0, 0, 0);
+    }
+  };
+  if (jb < je) {
+    load(jb, 0);
+    for (int j = jb; j < je; ++j) {
+      for (int ci = 0; ci < nch; ++ci) {
+        stage(ci);
+        if (ci + 1 < nch)
+          load(j, ci + 1);
+        else if (j + 1 < je)
+          load(j + 1, 0);
+        if (active) mfma();
+      }
+    }
+  }
+  // output through LDS: o[a][c0 + col][r0 + row]
+  constexpr int RS = ROWS + 2;
+  static_assert((AQ + BQ) * 16 >= COLS * RS * 8, "LDS tile too small");
+  float2* otile = reinterpret_cast<float2*>(&lds[0]);
+  const int mloc = min(ROWS, M - r0);
+  float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
+  __syncthreads();
+  {
+    const int lc = w * 16 + lane % 16;
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        otile[lc * RS + r * 16 + 4 * (lane / 16) + i] =
+            make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < ncol * mloc; e += TM_NT) {
+    const int lc = e / mloc, row = e % mloc;
+    obase[(size_t)lc * M + row] = otile[lc * RS + row];
+  }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(TM_NT) void k_translate_tm_split(TmArgs g) {
+  translate_tm_split_body<NRT>(g);
+}
+
+// Device form of the host split of a grouped GEMM's A: FP64 column-major
+// [g][K][Mr] -> bf16 planes [g][6][Mr][Kp] (k contiguous, zero for k >= K) and,
+// when D32 is set, the FP32 copy [g][K][Mr].  One thread per (g, m, k < Kp).
+__global__ void k_split_planes(const double2* __restrict__ D, int64_t total, int K, int Mr, int Kp,
+                               float2* __restrict__ D32, unsigned short* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x;
+  if (i >= total) return;
+  const int64_t per = (int64_t)Mr * Kp;
+  const int64_t g = i / per;
+  const int m = (int)((i / Kp) % Mr), k = (int)(i % Kp);
+  double2 v = make_double2(0.0, 0.0);
+  if (k < K) v = D[((size_t)g * K + k) * Mr + m];
+  const float re = (float)v.x, im = (float)v.y, sm = re + im;
+  unsigned short h[6];
+  tm_split(re, h[0], h[1]);
+  tm_split(im, h[2], h[3]);
+  tm_split(sm, h[4], h[5]);
+  unsigned short* o = P + (size_t)g * 6 * per + (size_t)m * Kp + k;
+#pragma unroll
+  for (int pl = 0; pl < 6; ++pl) o[pl * per] = h[pl];
+  if (D32 && k < K) D32[((size_t)g * K + k) * Mr + m] = make_float2(re, im);
+}
+
+}  // namespace
+
+void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes,
+                         hipStream_t st) {
+  const int64_t total = ngroups * Mr * (int64_t)Kp;
+  if (total == 0) return;
+  k_split_planes<<<(unsigned)((total + TM_NT - 1) / TM_NT), TM_NT, 0, st>>>(
+      static_cast<const double2*>(D64), total, K, Mr, Kp, static_cast<float2*>(D32),
+      static_cast<unsigned short*>(planes));
+}
+
+// Row blocking of the target-major kernel: the fewest row tiles per workgroup
+// (even when CT = 2) whose blocks stay inside the Mr allocated rows.
+void tm_blocking(int M, int Mr, int NC, int& nrt, int& rblocks, int& ct) {
+  ct = NC >= 64 ? 4 : 2;
+  const int tiles = (M + 15) / 16;
+  for (int blocks = 1;; ++blocks) {
+    int n = (tiles + blocks - 1) / blocks;
+    if (ct == 2 && n % 2) ++n;
+    if (n <= 8 && blocks * n * 16 <= Mr) {
+      nrt = n;
+      rblocks = blocks;
+      return;
+    }
+    if (blocks > tiles) break;
+  }
+  nrt = 0;
+  rblocks = 0;
+}
+
+void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStream_t st) {
+  const int64_t nitems = g.nbox * g.nct;
+  if (nitems == 0) return;
+  dim3 grid((unsigned)((nitems + 7) / 8 * 8), (unsigned)rblocks);
+  if (g.Asplit) {
+#define NESA_TMS(N) \
+  case N:           \
+    k_translate_tm_split<N><<<grid, TM_NT, 0, st>>>(g); \
+    return;
+    switch (nrt) {
+      NESA_TMS(1) NESA_TMS(2) NESA_TMS(3) NESA_TMS(4) NESA_TMS(5) NESA_TMS(6) NESA_TMS(7) NESA_TMS(8)
+      default: return;
+    }
+#undef NESA_TMS
+  }
+#define NESA_TM(N, C) \
+  case N:             \
+    k_translate_tm<N, C><<<grid, TM_NT, 0, st>>>(g); \
+    return;
+  if (ct == 4) {
+    switch (nrt) {
+      NESA_TM(1, 4) NESA_TM(2, 4) NESA_TM(3, 4) NESA_TM(4, 4) NESA_TM(5, 4) NESA_TM(6, 4) NESA_TM(7, 4)
+      NESA_TM(8, 4)
+      default: return;
+    }
+  } else {
+    switch (nrt) {
+      NESA_TM(2, 2) NESA_TM(4, 2) NESA_TM(6, 2) NESA_TM(8, 2)
+      default: return;
+    }
+  }
+#undef NESA_TM
+}
+
+}  // namespace nesa

@@ -160,6 +160,8 @@ Tree* build_tree(const double* verts, int64_t nv, const int32_t* tris, int64_t n
   t.L = ext > leaf ? (int)std::ceil(std::log2(ext / leaf)) : 0;
   if (t.L > 20) throw Error(-1, "tree deeper than 20 levels");
   t.l0 = std::min(l0_max, t.L);
+  if (t.l0 > 6) throw Error(-1, "coarsest far level deeper than 6 (translation table too large)");
+  t.slotw = std::max(4 * buffer + 3, (1 << (t.l0 + 1)) - 1);
   for (int c = 0; c < 3; ++c) t.lo[c] = mn[c] - 1e-9;
   const int64_t n = t.rwg.n;
   const int32_t nside = 1 << t.L;
@@ -309,6 +311,10 @@ Tree* build_forest(int nbodies, const double* const* verts, const int64_t* nv, c
   // body i's level li sits at forest level li + (L - L_i)
   F->l0 = F->L;
   for (auto& b : B) F->l0 = std::min(F->l0, b->l0 + F->L - b->L);
+  // one slot encoding for all bodies: the widest of theirs
+  F->slotw = 0;
+  for (auto& b : B) F->slotw = std::max(F->slotw, b->slotw);
+  const int FW = F->slotw, FH = FW / 2;
   for (int c = 0; c < 3; ++c) F->lo[c] = B[0]->lo[c];
   F->lev.resize(F->L - F->l0 + 1);
   for (int l = F->l0; l <= F->L; ++l) {
@@ -364,7 +370,11 @@ Tree* build_forest(int nbodies, const double* const* verts, const int64_t* nv, c
       const int64_t io = (int64_t)d.il_src.size();
       for (int64_t k = 0; k < s.nbox; ++k) d.il_ptr.push_back(s.il_ptr[k] + io);
       for (int64_t x : s.il_src) d.il_src.push_back(x + off);
-      d.il_slot.insert(d.il_slot.end(), s.il_slot.begin(), s.il_slot.end());
+      const int BW = b.slotw, BH = BW / 2;
+      for (int32_t x : s.il_slot) {
+        const int dx = x / (BW * BW) - BH, dy = (x / BW) % BW - BH, dz = x % BW - BH;
+        d.il_slot.push_back(((dx + FH) * FW + (dy + FH)) * FW + (dz + FH));
+      }
     }
   }
   F->leaf_ptr.push_back(F->rwg.n);

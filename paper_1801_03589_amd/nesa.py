@@ -96,6 +96,7 @@ _SIGS = {
     "nesa_matvec_leaf": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "nesa_matvec_phase_times": (C.c_int, [_P, _P, _P, _P, _P]),
     "nesa_matvec_launch_times": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, _P]),
+    "nesa_matvec_launch_times_nrhs": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_int32, _P]),
     "nesa_rhs_plane_wave_host": (C.c_int, [_P, C.c_double, _P, _P, C.c_int64, _P]),
     "nesa_rhs_plane_wave": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "nesa_gmres_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
@@ -104,6 +105,8 @@ _SIGS = {
     "nesa_precond_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "nesa_mlp_num_params": (C.c_int, [C.POINTER(MlpParams), C.POINTER(C.c_int64)]),
     "nesa_mlp_create": (C.c_int, [_P, C.POINTER(MlpParams), _P, C.POINTER(_P)]),
+    "nesa_mlp_save": (C.c_int, [_P, C.c_char_p]),
+    "nesa_mlp_load": (C.c_int, [_P, C.c_char_p, C.POINTER(_P)]),
     "nesa_mlp_free": (None, [_P]),
     "nesa_mlp_set_params": (C.c_int, [_P, _P]),
     "nesa_mlp_get_params": (C.c_int, [_P, _P]),
@@ -303,14 +306,14 @@ KIND_NAMES = {1: "radiate", 2: "upward_gemm", 3: "upward_sum", 4: "upward_fp64",
               10: "near_recv", 11: "receive"}
 
 
-def matvec_launch_times(op, x, y, stream=None, max_launches=128):
-    """[(kind name, level, ms)] for every kernel launch of one product."""
+def matvec_launch_times(op, x, y, stream=None, max_launches=128, nrhs=1):
+    """[(kind name, level, ms)] for every kernel launch of one product (leaf order)."""
     ms = np.zeros(max_launches, dtype=np.float32)
     kind = np.zeros(max_launches, dtype=np.int32)
     lev = np.zeros(max_launches, dtype=np.int32)
     cnt = C.c_int32()
-    _check(lib().nesa_matvec_launch_times(op.h, _dptr(x), _dptr(y), _stream(stream), _ptr(ms), _ptr(kind),
-                                          _ptr(lev), max_launches, C.byref(cnt)))
+    _check(lib().nesa_matvec_launch_times_nrhs(op.h, _dptr(x), _dptr(y), nrhs, _stream(stream), _ptr(ms),
+                                               _ptr(kind), _ptr(lev), max_launches, C.byref(cnt)))
     return [(KIND_NAMES[int(kind[i])], int(lev[i]), float(ms[i])) for i in range(cnt.value)]
 
 
@@ -372,6 +375,22 @@ class Mlp(_Handle):
                                      C.byref(h)))
         super().__init__(h)
         self.op, self.s_max, self.hidden, self.base, self.n_params = op, s_max, hidden, base, n
+
+    @classmethod
+    def load(cls, op, path):
+        """Network for `op` from a file written by save()."""
+        h = C.c_void_p()
+        _check(lib().nesa_mlp_load(op.h, os.fsencode(path), C.byref(h)))
+        self = cls.__new__(cls)
+        _Handle.__init__(self, h)
+        with open(path, "rb") as f:             # s_max, hidden, base after the 8-byte tag
+            hdr = np.frombuffer(f.read(20)[8:], dtype=np.int32)
+        self.op, self.s_max, self.hidden, self.base = op, int(hdr[0]), int(hdr[1]), int(hdr[2])
+        self.n_params = mlp_num_params(self.s_max, self.hidden, self.base)
+        return self
+
+    def save(self, path):
+        _check(lib().nesa_mlp_save(self.h, os.fsencode(path)))
 
     def set_params(self, theta):
         theta = np.ascontiguousarray(theta, dtype=np.float32)

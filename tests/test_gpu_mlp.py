@@ -270,3 +270,28 @@ def test_trained_network_gain_reported(torch_dev, setup):
         print("loss %.3f -> %.3f; held-out incidence: base %d iters, learned %d iters (fell back: %d)"
               % (hist[0], hist[-1], out["base"]["iters"], out["learned"]["iters"], out["learned"]["fell_back"]))
     nesa.op_set_mlp(op, None)
+
+
+def test_save_load_round_trip(torch_dev, setup, tmp_path):
+    """nesa_mlp_save / nesa_mlp_load: the loaded network has the same sizes,
+    base and parameters, and applies bit for bit like the saved one; a file
+    that is not a network file is refused."""
+    torch = torch_dev
+    nesa, ref, tr, op, perm, leaf_ptr = setup
+    theta = synth.mlp_weights(S, H, seed=5, zero_last=False)
+    net = nesa.Mlp(op, S, H, nesa.PRECOND_BLOCKDIAG, theta)
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    net2 = nesa.Mlp.load(op, path)
+    assert (net2.s_max, net2.hidden, net2.base) == (S, H, nesa.PRECOND_BLOCKDIAG)
+    assert np.array_equal(net2.get_params(), net.get_params())
+    r = torch.from_numpy(synth.complex_normal(ref.m.n, 9)[perm]).cuda()
+    z1, z2 = torch.empty_like(r), torch.empty_like(r)
+    net.apply(r, z1)
+    net2.apply(r, z2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NESAMLP0" + bytes(64))
+    with pytest.raises(nesa.NesaError):
+        nesa.Mlp.load(op, str(bad))
