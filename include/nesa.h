@@ -288,6 +288,27 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,
                      const nesa_gmres_params* params, nesa_gmres_report* report,
                      double* history, int64_t history_len, void* stream);
 
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): the same solve as nesa_gmres_solve, right-hand sides
+ * one at a time (same arithmetic as its nrhs = 1 form, so the same iterates),
+ * with every work buffer taken from one fixed device array of
+ * NESA_NOALLOC_SCRATCH_BYTES per device, held from library load to process end,
+ * and the per-iteration host scalars from thread-local storage.  The call
+ * makes no hipMalloc, hipFree, hipHostMalloc or other allocating call.
+ * Workspace: 8 (complex64) or 16 (complex128) bytes x n x (m + 5, plus m when
+ * a preconditioner is used), plus under 1 MiB; a larger request returns
+ * NESA_EINVAL without touching the device.  A Schwarz preconditioner must have
+ * been built by nesa_precond_setup and a learned one attached beforehand
+ * (NESA_EINVAL otherwise).  Every call on a device shares that device's array
+ * and leaves its contents behind: calls that overlap in time on one device
+ * (any thread, any stream, any operator) race and are not allowed.  The solve
+ * synchronises `stream` once per iteration, so it cannot be captured in a HIP
+ * graph as a whole. */
+#define NESA_NOALLOC_SCRATCH_BYTES (256u << 20)
+int nesa_gmres_solve_noalloc(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,
+                             const nesa_gmres_params* params, nesa_gmres_report* report,
+                             double* history, int64_t history_len, void* stream);
+
 /* Learned per-leaf preconditioner network (no counterpart in the paper,
  * which does not precondition; flexible GMRES after Saad 1993).
  *   features of leaf a for a vector r and the base output b = M_base r

@@ -902,17 +902,37 @@ static void learned_apply(nesa_mlp* h, nesa::DevOp<T>& d, const void* r, void* z
 }
 
 // ------------------------------------------------------------------ GMRES driver
+// Device workspace of one GMRES(m) solve (bytes), carved in this order:
+// basis V (m + 1 vectors), preconditioned basis Z (m vectors, flexible only),
+// b, x, w, tmp in leaf order, the FP64 coefficients and the block partials.
+static size_t gmres_workspace_bytes(int64_t n, int m, bool flex, size_t es) {
+  auto r256 = [](size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; };
+  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  size_t b = r256((size_t)(m + 1) * n * es) + (flex ? r256((size_t)m * n * es) : 0) + 4 * r256(n * es);
+  b += r256(sizeof(double2) * (2 * (m + 2) + 2)) + r256(sizeof(double2) * nblocks * (m + 2));
+  return b;
+}
+
+// ws: caller-provided device workspace of gmres_workspace_bytes() and host
+// scalars hws (2 (m + 2) + 2 values); null: both allocated here and freed on return
 template <typename T>
 static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c, const nesa_gmres_params& prm,
-                     nesa_gmres_report& rep, double* history, int64_t hist_len, hipStream_t st) {
+                     nesa_gmres_report& rep, double* history, int64_t hist_len, hipStream_t st,
+                     char* ws = nullptr, double2* hws = nullptr) {
   const int64_t n = d.n;
   const int m = prm.restart;
   const size_t es = 2 * sizeof(T);
   auto t0 = std::chrono::steady_clock::now();
   const bool flex = prm.precond != NESA_PRECOND_NONE;
   std::vector<void*> mine;
+  size_t ws_used = 0;
   auto alloc = [&](size_t bytes) {
     void* p = nullptr;
+    if (ws) {
+      p = ws + ws_used;
+      ws_used += (std::max<size_t>(bytes, 16) + 255) / 256 * 256;
+      return p;
+    }
     hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), "hipMalloc");
     mine.push_back(p);
     return p;
@@ -934,9 +954,9 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   void* tmp = alloc(n * es);
   double2* hd = static_cast<double2*>(alloc(sizeof(double2) * (2 * (m + 2) + 2)));
   double2* partial = static_cast<double2*>(alloc(sizeof(double2) * nblocks * (m + 2)));
-  double2* hh = nullptr;
-  hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * (2 * (m + 2) + 2)), "hipHostMalloc");
-  Free guard{mine, hh};
+  double2* hh = hws;
+  if (!hh) hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * (2 * (m + 2) + 2)), "hipHostMalloc");
+  Free guard{mine, hws ? nullptr : hh};
   auto vec = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
   auto matvec = [&](const void* src, void* dst) { nesa::launch_matvec_leaf<T>(d, src, dst, 1, st, nullptr); };
   auto norm = [&](const void* v) {
@@ -962,7 +982,9 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   const double nb = norm(bl);
   rep = nesa_gmres_report{0, 0, 0.0, 0.0, 0};
   if (nb == 0) {
-    hip_check(hipMemsetAsync(x_c, 0, n * es, st), "hipMemsetAsync");
+    // x = 0: b gathered into leaf order is exactly zero; scattered back by a
+    // kernel (no memset node when the caller captures the stream)
+    nesa::launch_scatter<T>(bl, x_c, d.perm, n, st);
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     return NESA_OK;
   }
@@ -1824,6 +1846,73 @@ int nesa_gmres_solve(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs, 
         rc = gmres_one<double>(op, op->d, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st);
       else
         rc = gmres_one<float>(op, op->f, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st);
+      if (rc != NESA_OK && worst == NESA_OK) worst = rc;
+    }
+    return worst;
+  });
+}
+
+// ------------------------------------------------------------------ GMRES without allocation
+// Workspace of nesa_gmres_solve_noalloc: a fixed array in device memory (each
+// device holds its own copy from library load to process end).  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device, kept per device; the array's own name is a host-side stand-in.
+static __device__ __align__(256) unsigned char scratch[NESA_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+// host scalars of the solve (FP64 coefficients read back every iteration)
+static thread_local double2 g_noalloc_host[2 * (250 + 2) + 2];
+
+static char* scratch_for_current_device() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) throw Error(NESA_EINVAL, "device index above 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (!p) throw Error(NESA_EHIP, "no device address for the GMRES scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+int nesa_gmres_solve_noalloc(nesa_op* op, const void* b_dev, void* x_dev, int64_t nrhs,
+                             const nesa_gmres_params* params, nesa_gmres_report* report, double* history,
+                             int64_t history_len, void* stream) {
+  return guarded([&]() {
+    if (!op || !b_dev || !x_dev || !params || !report) return fail(NESA_EINVAL, "null argument");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
+    if (params->restart < 1 || params->restart > 250 || params->max_iters < 1 || !(params->tol > 0) ||
+        !(params->fallback_ratio >= 0 && params->fallback_ratio <= 1))
+      return fail(NESA_EINVAL, "bad GMRES parameters");
+    if (params->precond < 0 || params->precond > 3) return fail(NESA_EINVAL, "unknown preconditioner");
+    // preconditioners are built by nesa_precond_setup / nesa_op_set_mlp, which allocate
+    if (params->precond == NESA_PRECOND_SCHWARZ && !op->schwarz)
+      return fail(NESA_EINVAL, "Schwarz preconditioner not set up (call nesa_precond_setup first)");
+    if (params->precond == NESA_PRECOND_LEARNED && !op->mlp)
+      return fail(NESA_EINVAL, "no network attached for the learned preconditioner");
+    const int64_t n = op->geo.rwg.n;
+    const bool flex = params->precond != NESA_PRECOND_NONE;
+    const size_t need = gmres_workspace_bytes(n, params->restart, flex, op->esize);
+    if (need > NESA_NOALLOC_SCRATCH_BYTES)
+      return fail(NESA_EINVAL, "GMRES workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                   std::to_string((size_t)NESA_NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
+    char* ws = scratch_for_current_device();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int worst = NESA_OK;
+    // right-hand sides one after another, each through the same workspace
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const char* br = static_cast<const char*>(b_dev) + (size_t)r * n * op->esize;
+      char* xr = static_cast<char*>(x_dev) + (size_t)r * n * op->esize;
+      int rc;
+      if (op->precision == NESA_C128)
+        rc = gmres_one<double>(op, op->d, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st,
+                               ws, g_noalloc_host);
+      else
+        rc = gmres_one<float>(op, op->f, br, xr, *params, report[r], r == 0 ? history : nullptr, history_len, st,
+                              ws, g_noalloc_host);
       if (rc != NESA_OK && worst == NESA_OK) worst = rc;
     }
     return worst;

@@ -101,6 +101,8 @@ _SIGS = {
     "nesa_rhs_plane_wave": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P]),
     "nesa_gmres_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
                                    C.POINTER(GmresReport), _P, C.c_int64, _P]),
+    "nesa_gmres_solve_noalloc": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(GmresParams),
+                                           C.POINTER(GmresReport), _P, C.c_int64, _P]),
     "nesa_precond_setup": (C.c_int, [_P, C.c_int]),
     "nesa_precond_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "nesa_mlp_num_params": (C.c_int, [C.POINTER(MlpParams), C.POINTER(C.c_int64)]),
@@ -341,13 +343,18 @@ def precond_apply(op, precond, r, z, stream=None):
     _check(lib().nesa_precond_apply(op.h, precond, _dptr(r), _dptr(z), _stream(stream)))
 
 
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
 def gmres_solve(op, b, x, nrhs=1, restart=30, max_iters=1000, tol=1e-6, precond=PRECOND_NONE,
-                history_len=0, stream=None, check=True, fallback_ratio=0.5):
+                history_len=0, stream=None, check=True, fallback_ratio=0.5, noalloc=False):
+    """noalloc: nesa_gmres_solve_noalloc (work buffers from the library's fixed
+    device array; right-hand sides one at a time)."""
     prm = GmresParams(restart, max_iters, tol, precond, fallback_ratio)
     rep = (GmresReport * nrhs)()
     hist = np.zeros(max(1, history_len), dtype=np.float64)
-    rc = lib().nesa_gmres_solve(op.h, _dptr(b), _dptr(x), nrhs, C.byref(prm), rep,
-                                _ptr(hist), history_len, _stream(stream))
+    fn = lib().nesa_gmres_solve_noalloc if noalloc else lib().nesa_gmres_solve
+    rc = fn(op.h, _dptr(b), _dptr(x), nrhs, C.byref(prm), rep, _ptr(hist), history_len, _stream(stream))
     if check and rc not in (0, -5):
         _check(rc)
     reports = [{"iters": r.iters, "restarts": r.restarts, "true_rel_residual": r.true_rel_residual,
