@@ -188,6 +188,44 @@ def dense_rows_error(nesa, torch, op, n, stream):
     return {"dense_rows": int(len(rows)), "rel_err": float(np.linalg.norm(yr - yd) / np.linalg.norm(yd))}
 
 
+def split_section(args, nesa, torch, tree, near, far, n, stream, fp32_ms, fp32_batched_ms):
+    """The bench sphere with split-bf16x3 translations and transfers: product
+    time at one and at `nrhs` right-hand sides next to the complex64 (FP32
+    matrix-core) times of the same operator, and the split product's error
+    against the complex64 one."""
+    R = max(1, args.nrhs)
+    ops = nesa.op_create(tree, near, far, nesa.C64_SPLIT, max_nrhs=R)
+    x = torch.from_numpy(synth_rhs(n, 1)[0]).to(torch.complex64).cuda()
+    y = torch.empty_like(x)
+    X = torch.from_numpy(synth_rhs(n, R)).to(torch.complex64).cuda()
+    Y = torch.empty_like(X)
+    out = {}
+    for name, xx, yy, rr, reps in (("1", x, y, 1, args.steps), (str(R), X, Y, R, max(3, args.steps // 4))):
+        for _ in range(3):
+            nesa.matvec(ops, xx, yy, rr, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            nesa.matvec(ops, xx, yy, rr, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["ms_per_product_nrhs" + name] = round(e0.elapsed_time(e1) / reps, 4)
+    out["fp32_ms_per_product_nrhs1"] = round(fp32_ms, 4)
+    if fp32_batched_ms is not None:
+        out["fp32_ms_per_product_nrhs%d" % R] = round(fp32_batched_ms, 4)
+    # error of the split product against the complex64 product (one right-hand side)
+    op32 = nesa.op_create(tree, near, far, nesa.C64)
+    y32 = torch.empty_like(x)
+    nesa.matvec(op32, x, y32, stream=stream)
+    nesa.matvec(ops, x, y, stream=stream)
+    torch.cuda.synchronize()
+    out["rel_diff_vs_complex64"] = float(torch.linalg.norm(y - y32) / torch.linalg.norm(y32))
+    del ops, op32
+    return out
+
+
 def accurate_section(args, nesa, torch, tree, near, n, stream):
     """The bench sphere with d0 = 5 equivalent sources per box (Q = 576, 256,
     144, 81): the setting whose truncation error against the dense matrix is
@@ -414,6 +452,7 @@ def aircraft_section(args, nesa, torch, stream):
         peak = PEAK_BF16 if prec == nesa.C64_SPLIT else PEAK_FP32
         sec = {"ms_per_product": round(ms, 3),
                "Munknowns_matvec_per_s": round(n * R / (ms * 1e-3) / 1e6, 1),
+               "launches": [[kind, lev, round(m, 3)] for kind, lev, m in lt],
                "kernels": {k: {"ms_per_product": round(v_["ms"], 3), "launches": v_["launches"],
                                "TFLOP/s": round(v_["flops"] / (v_["ms"] * 1e-3) / 1e12, 1) if v_["flops"] else None}
                            for k, v_ in kern.items()}}
@@ -673,7 +712,7 @@ def main():
         phases[k] = {"ms": phase_ms[k], "GB/s": round(alg[k]["bytes"] / s_ / 1e9, 1),
                      "TFLOP/s": round(alg[k]["flops"] / s_ / 1e12, 2)}
     log("product: %.4f ms (%.1f Munknowns/s)" % (ms, value))
-    gm = batched = bodies = model2d = accurate = aircraft = trunc = None
+    gm = batched = bodies = model2d = accurate = aircraft = trunc = split = None
     if not args.only_product:
         trunc = dense_rows_error(nesa, torch, op, n, stream)
         trunc["bound"] = 3e-3
@@ -683,6 +722,9 @@ def main():
         gm = gmres_section(args, nesa, torch, op, info, x, stream)
         log("GMRES done; batched right-hand sides")
         batched = batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream)
+        log("split precision on the bench sphere")
+        split = split_section(args, nesa, torch, tree, near, far, n, stream, ms,
+                              batched["ms_per_product"] if batched else None) if prec == nesa.C64 else None
         del op
         log("batch of %d bodies" % args.bodies)
         bodies = bodies_section(args, nesa, torch, prec, dt, stream)
@@ -722,6 +764,7 @@ def main():
         "accurate": accurate,
         "gmres": gm,
         "batched": batched,
+        "split": split,
         "bodies": bodies,
         "model2d": model2d,
         "aircraft": aircraft,

@@ -495,7 +495,7 @@ static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs, hipStream
     if (dl.npairs > 0 && nrhs < nesa::TM_MIN_NRHS) {
       tune_plan(op, dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
     }
-    if (i > 0) {
+    if (i > 0 && nrhs < nesa::TM_MIN_NRHS) {     // (target-major transfers from TM_MIN_NRHS on)
       auto& pl = d.lev[i - 1];
       tune_plan(op, dl.up, nrhs, s + dl.s_off * nrhs, dl.child_out, false, st);
       tune_plan(op, dl.down, nrhs, o + pl.s_off * nrhs, o + dl.s_off * nrhs, false, st);
@@ -697,6 +697,11 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       const int nr_pair = std::min(op->max_nrhs, nesa::TM_MIN_NRHS - 1);
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * nr_pair * fl.Q * 2 * sizeof(T));
     }
+    // split form with many right-hand sides: the level's sources (and, in the
+    // potential transfer, its potentials) split into six bf16 planes
+    // (2 bytes x 6 x Kp x 4 max_nrhs per box, Kp = Q rounded up to 32)
+    if (sizeof(T) == 4 && op->precision == NESA_C64_SPLIT && 4 * op->max_nrhs >= nesa::TM2_MIN_COLS)
+      dl.s6 = dev_alloc(op, (size_t)lv.nbox * ((fl.Q + 31) / 32 * 32) * 6 * 4 * op->max_nrhs * sizeof(uint16_t));
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
     if (l < t.L) {
@@ -741,10 +746,43 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx,
                            reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
-        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * op->max_nrhs * Qp * 2 * sizeof(T));
+        // per-child outputs serve the offset-major form only (below TM_MIN_NRHS)
+        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * std::min(op->max_nrhs, nesa::TM_MIN_NRHS - 1) * Qp * 2 *
+                                         sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx,
                              reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.down, ad, 8);
+        // pair lists of the target-major transfers: the children of every box
+        // of level l-1 in increasing index (CSR), and the parent of every box
+        const int64_t np = t.level(l - 1).nbox;
+        std::vector<int32_t> uptr(np + 1, 0), usrc, uslot, dptr(lv.nbox + 1, 0), dsrc, dslot;
+        for (int64_t b = 0; b < lv.nbox; ++b)
+          if (lv.parent[b] >= 0) ++uptr[lv.parent[b] + 1];
+        for (int64_t P = 0; P < np; ++P) uptr[P + 1] += uptr[P];
+        usrc.resize(uptr[np]);
+        uslot.resize(uptr[np]);
+        {
+          std::vector<int32_t> fill(uptr.begin(), uptr.end() - 1);
+          for (int64_t b = 0; b < lv.nbox; ++b) {
+            if (lv.parent[b] < 0) continue;
+            const int32_t e = fill[lv.parent[b]]++;
+            usrc[e] = (int32_t)b;
+            uslot[e] = lv.octant[b];
+          }
+        }
+        for (int64_t b = 0; b < lv.nbox; ++b) {
+          dptr[b + 1] = dptr[b];
+          if (lv.parent[b] < 0) continue;
+          dsrc.push_back((int32_t)lv.parent[b]);
+          dslot.push_back(lv.octant[b]);
+          ++dptr[b + 1];
+        }
+        dl.up_ptr = upload(op, uptr);
+        dl.up_src = upload(op, usrc);
+        dl.up_slot = upload(op, uslot);
+        dl.dn_ptr = upload(op, dptr);
+        dl.dn_src = upload(op, dsrc);
+        dl.dn_slot = upload(op, dslot);
       }
     }
   }

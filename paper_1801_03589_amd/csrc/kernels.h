@@ -56,6 +56,13 @@ struct DevLevel {
   int32_t* il_slot = nullptr; // compact slot index
   GemmPlan trans;               // translation tiles (complex64): groups = offset slots
   void* pair_out = nullptr;     // [npairs][4][Q] D s_b of every pair
+  void* s6 = nullptr;           // split form with many right-hand sides: pre-split sources (TmArgs::s6)
+  int32_t* up_ptr = nullptr;    // target-major source transfer into level l-1: children of every
+  int32_t* up_src = nullptr;    //   box of level l-1 (CSR over those boxes), octant of each child
+  int32_t* up_slot = nullptr;
+  int32_t* dn_ptr = nullptr;    // target-major potential transfer into this level: the parent of
+  int32_t* dn_src = nullptr;    //   every box (CSR, none for a body's top box), its octant
+  int32_t* dn_slot = nullptr;
   GemmPlan up;                  // this level's children -> parents (groups = octants)
   void* child_out = nullptr;    // [nbox][4][Q_{l-1}] C s_child of every child
   GemmPlan down;                // parents -> this level's boxes (groups = octants, accumulate)
@@ -135,7 +142,15 @@ struct TmArgs {
   int64_t nbox = 0;
   int NC = 0;                             // 4 x nrhs
   int nct = 0;                            // column tiles per box
+  int accumulate = 0;                     // o += result (potential transfer) instead of o = result
+  const uint4* s6 = nullptr;              // split form, NC >= TM2_MIN_COLS: sources pre-split
+                                          // [box][Kp/16][6][NC][16] bf16 (rows of 64, 256-column tiles)
 };
+// columns per box (4 nrhs) from which the split translations use the pre-split
+// sources and 64 x 256 workgroup tiles
+constexpr int TM2_MIN_COLS = 128;
+// s6 = six bf16 planes of the sources s [nbox][NC][K] (layout of TmArgs::s6)
+void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, hipStream_t st);
 // right-hand sides from which the translations run target-major
 constexpr int TM_MIN_NRHS = 8;
 // row tiles per workgroup, row blocks and column tiles of 16 (4 or 2) for M

@@ -1914,6 +1914,62 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     }
     hip_ok(hipEventRecord(d.ev_join, d.side));
   };
+  // complex64 with TM_MIN_NRHS or more right-hand sides: translations and
+  // transfers run target-major (no per-pair or per-child partial results); the
+  // split form with TM2_MIN_COLS or more columns reads sources split once per
+  // level into the level's s6 planes
+  const bool tmode = mfma && R >= TM_MIN_NRHS;
+  bool v2 = tmode && NC >= TM2_MIN_COLS;
+  for (const auto& lv : d.lev) v2 = v2 && lv.s6 != nullptr;     // (allocated for split operators only)
+  auto split_of = [&](const DevLevel& lv, const V2* src, hipStream_t ss) {
+    if constexpr (sizeof(T) == 4)
+      launch_split_sources(src, lv.nbox, NC, lv.Q, (lv.Q + 31) / 32 * 32, lv.s6, ss);
+  };
+  auto tm_contract = [&](const GemmPlan& pl, const int32_t* ptr, const int32_t* src, const int32_t* slot,
+                         int64_t ntarget, int M, int K, const V2* sv, const void* s6v, V2* ov, int acc,
+                         hipStream_t ss) {
+    if constexpr (sizeof(T) == 4) {
+      TmArgs g;
+      g.D = static_cast<const float2*>(pl.A);
+      g.Asplit = static_cast<const unsigned short*>(pl.A_split);
+      g.a_stride = pl.a_stride;
+      g.M = M;
+      g.K = K;
+      g.Mr = pl.Mr;
+      g.Kp = pl.Kp;
+      g.s = reinterpret_cast<const float2*>(sv);
+      g.o = reinterpret_cast<float2*>(ov);
+      g.il_ptr = ptr;
+      g.il_src = src;
+      g.il_slot = slot;
+      g.nbox = ntarget;
+      g.NC = NC;
+      g.accumulate = acc;
+      int nrt = 0, rblocks = 0, ct = 0;
+      tm_blocking(M, pl.Mr, NC, nrt, rblocks, ct);
+      g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
+      if (v2) {
+        g.s6 = static_cast<const uint4*>(s6v);
+        g.nct = (NC + 255) / 256;
+      }
+      launch_translate_tm(g, nrt, rblocks, ct, ss);
+    }
+  };
+  // translations of one level (complex64)
+  auto translate = [&](const DevLevel& lv, hipStream_t ss, int l) {
+    if (tmode) {
+      tm_contract(lv.trans, lv.il_ptr, lv.il_src, lv.il_slot, lv.nbox, lv.Q, lv.Q, s + lv.s_off * R, lv.s6,
+                  o + lv.s_off * R, 0, ss);
+      if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
+      return;
+    }
+    launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, ss, true);
+    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
+    k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, ss>>>(static_cast<const V2*>(lv.pair_out),
+                                                                  o + lv.s_off * R, lv.il_ptr, lv.il_ptr + 1,
+                                                                  NC * lv.Q);
+    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_REDUCE);
+  };
   if (tm) tm->mark(st, 0, -1, 0);
   if (R == 1) {
     k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr, s + LL.s_off, LL.Q);
@@ -1923,6 +1979,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                                        s + LL.s_off * R, LL.Q, R, d.n);
   }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
+  if (v2) split_of(LL, s + LL.s_off * R, st);
   // the near field starts once radiation (also HBM-bound) is done, and runs
   // beside the transfers and translations
   if (overlap) fork_near();
@@ -1935,41 +1992,6 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   auto side_ok = [&](int l) {
     return overlap && !tm && mfma && d.side2 != nullptr && l > l0 && l == L && d.lev[l - l0].npairs > 0;
   };
-  // translations of one level (complex64): target-major from TM_MIN_NRHS
-  // right-hand sides, else offset-major tiles and the ordered per-target sums
-  auto translate = [&](const DevLevel& lv, hipStream_t ss, int l) {
-    if constexpr (sizeof(T) == 4) {
-      if (R >= TM_MIN_NRHS) {
-        TmArgs g;
-        g.D = static_cast<const float2*>(lv.trans.A);
-        g.Asplit = static_cast<const unsigned short*>(lv.trans.A_split);
-        g.a_stride = lv.trans.a_stride;
-        g.M = lv.Q;
-        g.K = lv.Q;
-        g.Mr = lv.trans.Mr;
-        g.Kp = lv.trans.Kp;
-        g.s = reinterpret_cast<const float2*>(s + lv.s_off * R);
-        g.o = reinterpret_cast<float2*>(o + lv.s_off * R);
-        g.il_ptr = lv.il_ptr;
-        g.il_src = lv.il_src;
-        g.il_slot = lv.il_slot;
-        g.nbox = lv.nbox;
-        g.NC = NC;
-        int nrt = 0, rblocks = 0, ct = 0;
-        tm_blocking(lv.Q, lv.trans.Mr, NC, nrt, rblocks, ct);
-        g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
-        launch_translate_tm(g, nrt, rblocks, ct, ss);
-        if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
-        return;
-      }
-    }
-    launch_tiles(lv.trans, R, s + lv.s_off * R, lv.pair_out, ss, true);
-    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_GEMM);
-    k_csr_reduce<V2><<<csr_grid(lv.nbox, NC * lv.Q), NT, 0, ss>>>(static_cast<const V2*>(lv.pair_out),
-                                                                  o + lv.s_off * R, lv.il_ptr, lv.il_ptr + 1,
-                                                                  NC * lv.Q);
-    if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_REDUCE);
-  };
   auto fork_trans = [&](int l, hipEvent_t fork, hipEvent_t join) {
     const auto& lv = d.lev[l - l0];
     hip_ok(hipEventRecord(fork, st));
@@ -1981,7 +2003,12 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   for (int l = L; l > l0; --l) {
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
-    if (mfma) {
+    if (tmode) {
+      tm_contract(c.up, c.up_ptr, c.up_src, c.up_slot, p.nbox, p.Q, c.Q, s + c.s_off * R, c.s6, s + p.s_off * R, 0,
+                  st);
+      if (tm) tm->mark(st, -1, l, K_UP_GEMM);
+      if (v2) split_of(p, s + p.s_off * R, st);
+    } else if (mfma) {
       launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
       k_csr_reduce<V2><<<csr_grid(p.nbox, NC * p.Q), NT, 0, st>>>(static_cast<const V2*>(c.child_out),
@@ -2018,7 +2045,14 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
     if (side_ok(l)) hip_ok(hipStreamWaitEvent(st, d.ev_join2, 0));
-    if (mfma) {
+    if (tmode) {
+      // the parent level's potentials split into its s6 planes (its
+      // translations, which read them as sources, were launched before)
+      if (v2) split_of(p, o + p.s_off * R, st);
+      tm_contract(c.down, c.dn_ptr, c.dn_src, c.dn_slot, c.nbox, c.Q, p.Q, o + p.s_off * R, p.s6, o + c.s_off * R, 1,
+                  st);
+      if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
+    } else if (mfma) {
       launch_tiles(c.down, R, o + p.s_off * R, o + c.s_off * R, st, false);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
     } else {

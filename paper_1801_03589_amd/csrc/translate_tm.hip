@@ -1,4 +1,8 @@
-// Target-major translations for several right-hand sides (Sec. 3, Eq. 12):
+// Target-major contractions for several right-hand sides: the translations
+// (Sec. 3, Eq. 12), and with the same kernels the transfers (Eq. 11: targets =
+// parents, pairs = children, matrix = C of the child's octant; Eq. 13: targets
+// = children, one pair = the parent, matrix = C^T, added to the translated
+// potentials).  For the translations:
 // o_a = sum over b in IL(a) of D_{a-b} s_b, one workgroup per (target box a,
 // tile of GEMM columns, block of rows).  With 4 nrhs channel columns per box
 // (nrhs >= 8 gives 32 or more), the columns of one target already fill the
@@ -189,7 +193,14 @@ __device__ __forceinline__ void translate_tm_body(const TmArgs& g) {
     const int nc = min(PC, ncol - p0);
     for (int e = t; e < nc * mloc; e += TM_NT) {
       const int lc = e / mloc, row = e % mloc;
-      obase[(size_t)(p0 + lc) * M + row] = otile[lc * RS + row];
+      float2 v = otile[lc * RS + row];
+      float2* out = obase + (size_t)(p0 + lc) * M + row;
+      if (g.accumulate) {
+        const float2 ov = *out;
+        v.x += ov.x;
+        v.y += ov.y;
+      }
+      *out = v;
     }
   }
 }
@@ -381,13 +392,205 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
   __syncthreads();
   for (int e = t; e < ncol * mloc; e += TM_NT) {
     const int lc = e / mloc, row = e % mloc;
-    obase[(size_t)lc * M + row] = otile[lc * RS + row];
+    float2 v = otile[lc * RS + row];
+    float2* out = obase + (size_t)lc * M + row;
+    if (g.accumulate) {
+      const float2 ov = *out;
+      v.x += ov.x;
+      v.y += ov.y;
+    }
+    *out = v;
   }
 }
 
 template <int NRT>
 __global__ __launch_bounds__(TM_NT) void k_translate_tm_split(TmArgs g) {
   translate_tm_split_body<NRT>(g);
+}
+
+// ---------------------------------------------------------------------------
+// Split form for 32 or more right-hand sides (NC >= 128 columns per box).
+// The sources of a level are split once per product (k_split_sources) into six
+// bf16 planes laid out by k chunks of 16, s6[box][kc][plane][NC][16], so that
+// a workgroup stages them as plain copies; the products run on 32x32x16 bf16
+// MFMAs, each wave owning a 64 x 64 block (2 x 2 tiles of 32 x 32) and the
+// four waves side by side along the columns (a 64 x 256 workgroup tile).  A
+// chunk of 16 k (both operands, six planes) is staged through registers into
+// one of two LDS buffers while the MFMAs of the other buffer run: one barrier
+// per chunk.  Operand layout of the instruction: lane l holds row (A) or
+// column (B) l % 32 and k = 8 (l / 32) .. + 7; result value i of lane l is row
+// 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
+typedef float tm_f32x16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(TM_NT) void k_split_sources(const float2* __restrict__ s, int64_t nbox, int NC, int K,
+                                                         int Kp, uint4* __restrict__ s6) {
+  // one thread per (box, column, 8 consecutive k)
+  const int per_box = NC * (Kp / 8);
+  const int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x;
+  if (i >= nbox * per_box) return;
+  const int64_t box = i / per_box;
+  const int r = (int)(i % per_box), c = r / (Kp / 8), k0 = 8 * (r % (Kp / 8));
+  const float2* src = s + ((size_t)box * NC + c) * K;
+  unsigned short h[6][8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const float2 v = (k0 + u < K) ? src[k0 + u] : make_float2(0.f, 0.f);
+    tm_split(v.x, h[0][u], h[1][u]);
+    tm_split(v.y, h[2][u], h[3][u]);
+    tm_split(v.x + v.y, h[4][u], h[5][u]);
+  }
+  const int kc = k0 / 16, half = (k0 % 16) / 8;
+  uint4* dst = s6 + ((((size_t)box * (Kp / 16) + kc) * 6) * NC + c) * 2 + half;
+#pragma unroll
+  for (int pl = 0; pl < 6; ++pl)
+    dst[(size_t)pl * NC * 2] = make_uint4(tm_pack(h[pl][0], h[pl][1]), tm_pack(h[pl][2], h[pl][3]),
+                                          tm_pack(h[pl][4], h[pl][5]), tm_pack(h[pl][6], h[pl][7]));
+}
+
+__global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
+  constexpr int ROWS = 64, COLS = 256;
+  constexpr int AQ = 6 * ROWS * 2, BQ = 6 * COLS * 2;         // uint4 per buffer (8 bf16 each)
+  constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;            // 3 and 12 per thread
+  static_assert(AQ % TM_NT == 0 && BQ % TM_NT == 0, "staging must split evenly");
+  __shared__ uint4 lds[2 * (AQ + BQ)];
+  const int64_t nitems = g.nbox * g.nct;
+  const int64_t item = tm_item(blockIdx.x, nitems);
+  if (item >= nitems) return;
+  const int64_t a = item / g.nct;
+  const int c0 = (int)(item % g.nct) * COLS;
+  const int ncol = min(COLS, g.NC - c0);
+  const int r0 = blockIdx.y * ROWS;
+  const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
+  const int NC = g.NC, M = g.M, Kp = g.Kp, KC = g.Kp / 16;
+  const size_t plane = (size_t)g.Mr * Kp;
+  const int jb = g.il_ptr[a], je = g.il_ptr[a + 1];
+  const bool active = 64 * w < ncol;
+  // staging offsets (uint4 units): A element e = (plane, row, half), from the
+  // pre-split translation planes [slot][6][Mr][Kp]; B element e = (plane,
+  // column, half), from s6[box][kc][plane][NC][16]
+  int oa[NAT], ob[NBT];
+  bool bok[NBT];
+#pragma unroll
+  for (int i = 0; i < NAT; ++i) {
+    const int e = t + i * TM_NT, pl = e / (ROWS * 2), row = (e / 2) % ROWS, hf = e % 2;
+    oa[i] = (int)(pl * plane / 8) + row * (Kp / 8) + hf;
+  }
+#pragma unroll
+  for (int i = 0; i < NBT; ++i) {
+    const int e = t + i * TM_NT, pl = e / (COLS * 2), col = (e / 2) % COLS, hf = e % 2;
+    bok[i] = col < ncol;
+    ob[i] = (pl * NC + min(col, ncol - 1)) * 2 + hf;
+  }
+  tm_f32x16 c1[2][2], c2[2][2], c3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        c1[i][j][u] = 0.f;
+        c2[i][j][u] = 0.f;
+        c3[i][j][u] = 0.f;
+      }
+  uint4 ra[NAT], rb[NBT];
+  auto load = [&](int j, int kc) {
+    const int slot = g.il_slot[j], src = g.il_src[j];
+    const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp) + kc * 2;
+    const uint4* B = g.s6 + (((size_t)src * KC + kc) * 6) * NC * 2 + (size_t)c0 * 2;
+#pragma unroll
+    for (int i = 0; i < NAT; ++i) ra[i] = A[oa[i]];
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) rb[i] = B[ob[i]];
+  };
+  auto store = [&](int buf) {
+    uint4* Ab = lds + buf * (AQ + BQ);
+    uint4* Bb = Ab + AQ;
+#pragma unroll
+    for (int i = 0; i < NAT; ++i) Ab[t + i * TM_NT] = ra[i];
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) Bb[t + i * TM_NT] = bok[i] ? rb[i] : make_uint4(0u, 0u, 0u, 0u);
+  };
+  auto mfma = [&](int buf) {
+    const uint4* Ab = lds + buf * (AQ + BQ);
+    const uint4* Bb = Ab + AQ;
+    const int hf = lane / 32;
+    tm_bf16x8 av[2][6];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        av[rt][pl] = __builtin_bit_cast(tm_bf16x8, Ab[(pl * ROWS + rt * 32 + lane % 32) * 2 + hf]);
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      tm_bf16x8 bv[6];
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl)
+        bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * 64 + ct * 32 + lane % 32) * 2 + hf]);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[0], c1[rt][ct], 0, 0, 0);
+        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[2], c2[rt][ct], 0, 0, 0);
+        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][4], bv[4], c3[rt][ct], 0, 0, 0);
+        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[1], c1[rt][ct], 0, 0, 0);
+        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[3], c2[rt][ct], 0, 0, 0);
+        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][4], bv[5], c3[rt][ct], 0, 0, 0);
+        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[0], c1[rt][ct], 0, 0, 0);
+        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], bv[2], c2[rt][ct], 0, 0, 0);
+        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][5], bv[4], c3[rt][ct], 0, 0, 0);
+      }
+    }
+  };
+  // chunks of 16 k over the pairs of the interaction list, in list order
+  const int nchunk = (je - jb) * KC;
+  if (nchunk > 0) {
+    load(jb, 0);
+    store(0);
+    __syncthreads();
+    for (int q = 0; q < nchunk; ++q) {
+      const int buf = q & 1;
+      const bool more = q + 1 < nchunk;
+      if (more) load(jb + (q + 1) / KC, (q + 1) % KC);      // in flight during the MFMAs
+      if (active) mfma(buf);
+      if (more) store(buf ^ 1);                              // the other buffer: last read two chunks ago
+      __syncthreads();
+    }
+  }
+  // output through LDS in two passes of 128 columns ([column][row], stride 66)
+  constexpr int RS = ROWS + 2;
+  static_assert(2 * (AQ + BQ) * 16 >= 128 * RS * 8, "LDS tile too small");
+  float2* otile = reinterpret_cast<float2*>(&lds[0]);
+  const int mloc = min(ROWS, M - r0);
+  float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
+  for (int p0 = 0; p0 < COLS; p0 += 128) {
+    __syncthreads();
+    if (w * 64 >= p0 && w * 64 < p0 + 128) {
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int lc = w * 64 - p0 + ct * 32 + lane % 32;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int row = rt * 32 + 8 * (u / 4) + 4 * (lane / 32) + u % 4;
+            otile[lc * RS + row] = make_float2(c1[rt][ct][u] - c2[rt][ct][u],
+                                               c3[rt][ct][u] - c1[rt][ct][u] - c2[rt][ct][u]);
+          }
+        }
+    }
+    __syncthreads();
+    const int nc = min(128, ncol - p0);
+    for (int e = t; e < nc * mloc; e += TM_NT) {
+      const int lc = e / mloc, row = e % mloc;
+      float2 v = otile[lc * RS + row];
+      float2* out = obase + (size_t)(p0 + lc) * M + row;
+      if (g.accumulate) {
+        const float2 ov = *out;
+        v.x += ov.x;
+        v.y += ov.y;
+      }
+      *out = v;
+    }
+  }
 }
 
 // Device form of the host split of a grouped GEMM's A: FP64 column-major
@@ -443,9 +646,22 @@ void tm_blocking(int M, int Mr, int NC, int& nrt, int& rblocks, int& ct) {
   rblocks = 0;
 }
 
+void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, hipStream_t st) {
+  const int64_t total = nbox * NC * (int64_t)(Kp / 8);
+  if (total == 0) return;
+  k_split_sources<<<(unsigned)((total + TM_NT - 1) / TM_NT), TM_NT, 0, st>>>(
+      static_cast<const float2*>(s), nbox, NC, K, Kp, static_cast<uint4*>(s6));
+}
+
 void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStream_t st) {
   const int64_t nitems = g.nbox * g.nct;
   if (nitems == 0) return;
+  if (g.Asplit && g.s6) {
+    // 64 x 256 workgroup tiles: nct counts 256-column tiles, rows in blocks of 64
+    dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 63) / 64));
+    k_translate_tm_split2<<<grid2, TM_NT, 0, st>>>(g);
+    return;
+  }
   dim3 grid((unsigned)((nitems + 7) / 8 * 8), (unsigned)rblocks);
   if (g.Asplit) {
 #define NESA_TMS(N) \

@@ -132,3 +132,43 @@ def test_uneven_body_batch_8_incidences(torch_dev, nesa):
         for r in (0, 7):
             yr = ref.matvec(X[r][ptr[i]:ptr[i + 1]])
             _check(Y[r][ptr[i]:ptr[i + 1]], yr, TOL_C64, "batch body %d (%s, N=%d) rhs %d" % (i, kind, ref.m.n, r))
+
+
+def test_aircraft_full_size_64_incidences_split(torch_dev, nesa):
+    """The aircraft-like body at full size (959,364 unknowns, leaf 0.25, far
+    field from the 4-wavelength level: levels 4..8, Q = 1156 / 441 / 196 / 81 /
+    49), 64 right-hand sides in one split-bf16x3 product, as the benchmark runs
+    it.  Right-hand side 0 is the dense-row fixture's vector: its rows against
+    the dense matrix (the stated truncation error); right-hand sides 17 and 63
+    are supported on a few leaves: sampled rows against the oracle built with
+    the same parameters."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_dense_rows as golden
+    torch = torch_dev
+    mesh, n, drows, yd = golden.load("aircraft959364")
+    v, t = eval(mesh, {"synth": synth})
+    tr = nesa.build_tree(v, t, 0.25, l0_max=4)
+    info = tr.info()
+    assert (info["l0"], info["L"], info["n_rwg"]) == (4, 8, n)
+    op = nesa.op_create(tr, nesa.assemble_near_device(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8),
+                        nesa.C64_SPLIT, max_nrhs=64)
+    ref = onesa.NesaOracle(v, t, leaf=0.25, d0=3, tau=1e-8, l0_max=4)
+    assert ref.levels == [4, 5, 6, 7, 8] and [ref.Q[l] for l in ref.levels] == [1156, 441, 196, 81, 49]
+    X = synth.complex_normal((64, n), 80).astype(np.complex64)
+    X[0] = synth.complex_normal(n, 0)
+    checks = {}
+    for r in (17, 63):
+        X[r], src = _sparse_x(ref, 3, 81 + r)
+        checks[r] = _rows(ref, src, 12, 82 + r)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    nesa.matvec(op, Xd, Yd, 64)
+    torch.cuda.synchronize()
+    e = np.linalg.norm(Yd[0].cpu().numpy().astype(np.complex128)[drows] - yd) / np.linalg.norm(yd)
+    print("aircraft N=%d: %d dense rows, NESA truncation error %.3e" % (n, len(drows), e))
+    assert e <= 1.2e-2          # measured 9.1e-3
+    for r, rows in checks.items():
+        y = Yd[r].cpu().numpy().astype(np.complex128)
+        _check(y[rows], ref.matvec_rows(X[r].astype(np.complex128), rows), 1e-4, "aircraft N=%d split rhs %d" % (n, r))

@@ -283,6 +283,22 @@ def test_blockdiag_preconditioned_fgmres(torch_dev, nesa):
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
 
 
+@pytest.mark.parametrize("nrhs", [8, 32, 37])
+def test_matvec_multi_rhs_split(torch_dev, nesa, nrhs):
+    """Split-bf16x3 products of several right-hand sides (target-major
+    translations; from 32 right-hand sides with the pre-split sources and 64 x
+    256 tiles, 37 leaving a partial column tile) against the oracle."""
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    op = nesa.op_create(tr, near, far, nesa.C64_SPLIT, max_nrhs=nrhs)
+    X = synth.complex_normal((nrhs, ref.m.n), 20 + nrhs)
+    Y = _run(torch_dev, nesa, op, X, nrhs=nrhs)
+    for r in sorted({0, nrhs // 2, nrhs - 1}):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("split nrhs %d rhs %d: rel err %.2e" % (nrhs, r, err))
+        assert err <= 1e-4, (r, err)
+
+
 @pytest.mark.parametrize("nrhs", [2, 8, 13])
 def test_matvec_multi_rhs(torch_dev, nesa, nrhs):
     """Batched right-hand sides (channels = 4 x nrhs in the GEMM columns)
