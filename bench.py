@@ -61,6 +61,9 @@ def parse():
     p.add_argument("--aircraft-fp32", action="store_true",
                    help="also time the aircraft's batched product with FP32 translations")
     p.add_argument("--only-aircraft", action="store_true", help="time only the aircraft-like body's line")
+    p.add_argument("--only-learned-family", action="store_true",
+                   help="run only the learned preconditioner on the aircraft family (held-out seed 999)")
+    p.add_argument("--learned-bodies", type=int, default=8, help="training bodies of that line")
     return p.parse_args()
 
 
@@ -314,6 +317,99 @@ def gmres_section(args, nesa, torch, op, info, x, stream):
     out["max_iters"] = args.gmres_iters
     if args.nrhs > 1:
         out["batched"] = gmres_batched(args, nesa, torch, op, b, tol, restart, stream)
+    return out
+
+
+AIRCRAFT_SMALL = dict(fuselage_radius=0.8, fuselage_length=6.0, span=2.5, chord_root=1.5, chord_tip=0.6,
+                      thickness=0.3, wing_x=2.5, gap=0.1)
+
+
+def learned_family_section(args, nesa, torch, stream):
+    """The learned preconditioner on the aircraft family: the network (one
+    set of weights, carried from body to body) is trained on residual / error
+    pairs of the method's own base-preconditioned FGMRES solves of bodies with
+    seeds 100 .. 100 + n - 1 (about 48k unknowns each), then FGMRES(50) to 1e-4
+    on the held-out body of seed 999: plain, block-diagonal, learned on
+    block-diagonal, Schwarz, learned on Schwarz (two incidences each)."""
+    import synth
+    tol, restart, cap = 1e-4, 50, 1500
+    incid = [([1.0, 0, 0], [0, 0, 1.0]), ([0, 0.6, 0.8], [1.0, 0, 0]), ([0, 0, 1.0], [0, 1.0, 0]),
+             ([0.6, 0.8, 0], [0, 0, 1.0])]
+
+    def build(seed):
+        # the family: dimensions drawn from the seed around the small member
+        rg = np.random.default_rng(seed)
+        kw = dict(AIRCRAFT_SMALL)
+        kw.update(fuselage_radius=float(rg.uniform(0.6, 0.9)), fuselage_length=float(rg.uniform(5.0, 8.0)),
+                  span=float(rg.uniform(2.0, 3.2)), chord_root=float(rg.uniform(1.2, 1.8)))
+        v, t = synth.aircraft_like(seed, **kw)
+        tr = nesa.build_tree(v, t, 0.25)
+        op = nesa.op_create(tr, nesa.assemble_near_device(tr), nesa.assemble_translations(tr, d0=3, tau=1e-8),
+                            nesa.C64)
+        nesa.precond_setup(op, nesa.PRECOND_SCHWARZ)
+        return tr, op
+
+    def rhs(op, n, d, p_):
+        b = torch.empty(n, dtype=torch.complex64, device="cuda")
+        nesa.rhs_plane_wave(op, d, p_, b, stream=stream)
+        return b
+
+    def solve(op, b, pc, max_iters=cap, tol_=tol):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep, _ = nesa.gmres_solve(op, b, x, restart=restart, max_iters=max_iters, tol=tol_, precond=pc,
+                                      stream=stream, check=False)
+        torch.cuda.synchronize()
+        return x, {"iters": rep[0]["iters"], "seconds": round(time.perf_counter() - t0, 3), "converged": rc == 0,
+                   "true_rel_residual": rep[0]["true_rel_residual"], "fell_back": rep[0]["fell_back"]}
+
+    S, H = 256, 128
+    out = {"family": "synth.aircraft_like(seed) with fuselage radius U(0.6, 0.9), length U(5, 8), span U(2, 3.2), "
+                     "root chord U(1.2, 1.8) drawn from the seed, wing thickness 0.3", "s_max": S,
+           "hidden": H, "tol": tol, "restart": restart, "max_iters": cap}
+    for base, bname in ((nesa.PRECOND_BLOCKDIAG, "blockdiag"), (nesa.PRECOND_SCHWARZ, "schwarz")):
+        theta = synth.mlp_weights(S, H, seed=1)
+        t0 = time.perf_counter()
+        losses, npairs, sizes = [], 0, []
+        for seed in range(100, 100 + args.learned_bodies):
+            tr, op = build(seed)
+            n = tr.info()["n_rwg"]
+            sizes.append(n)
+            Rs, Es = [], []
+            for d, p_ in incid[:2]:
+                b = rhs(op, n, d, p_)
+                xs, _ = solve(op, b, nesa.PRECOND_SCHWARZ, 600, 1e-6)       # converged solution
+                ks = [0, 2, 5, 10, 20, 40]
+                R, E = nesa.solve_pairs(op, b, xs, ks, restart=restart, precond=base)
+                Rs.append(R)
+                Es.append(E)
+            net = nesa.Mlp(op, S, H, base, theta)
+            net.set_data(torch.cat(Rs), torch.cat(Es))
+            hist = net.train(200, lr=1e-3)
+            losses.append([round(float(hist[0]), 4), round(float(hist[-1]), 4)])
+            theta = net.get_params()
+            npairs += sum(r.shape[0] for r in Rs)
+            del net, op, tr
+        train_s = time.perf_counter() - t0
+        tr, op = build(999)
+        n = tr.info()["n_rwg"]
+        net = nesa.Mlp(op, S, H, base, theta)
+        nesa.op_set_mlp(op, net)
+        res = {"train_bodies": len(sizes), "train_unknowns": [min(sizes), max(sizes)], "pairs": npairs,
+               "train_s": round(train_s, 1), "loss_first_last_per_body": losses, "held_out_unknowns": n}
+        for i, (d, p_) in enumerate(incid[2:]):
+            b = rhs(op, n, d, p_)
+            r = {}
+            if bname == "blockdiag":
+                _, r["plain"] = solve(op, b, nesa.PRECOND_NONE)
+            _, r[bname] = solve(op, b, base)
+            _, r["learned_" + bname] = solve(op, b, nesa.PRECOND_LEARNED)
+            res["incidence_%d" % i] = r
+        out[bname] = res
+        log("learned on %s: %s" % (bname, {k: v for k, v in res.items() if k.startswith("incidence")}))
+        nesa.op_set_mlp(op, None)
+        del net, op, tr
     return out
 
 
@@ -577,6 +673,9 @@ def main():
         return
     if args.only_aircraft:
         print(json.dumps({"aircraft": aircraft_section(args, nesa, torch, torch.cuda.current_stream())}))
+        return
+    if args.only_learned_family:
+        print(json.dumps({"learned_family": learned_family_section(args, nesa, torch, torch.cuda.current_stream())}))
         return
     prec = {"c64": nesa.C64, "c128": nesa.C128, "split": nesa.C64_SPLIT}[args.precision]
     esize = 16 if prec == nesa.C128 else 8

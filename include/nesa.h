@@ -198,6 +198,19 @@ void nesa_op_free(nesa_op* op);
  * work buffers: calls that overlap in time race. */
 int nesa_matvec(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream);
 
+/* Products of several operators in one call (batching, not in the paper: its
+ * Sec. 5.1 suggests letting one task handle several groups): y_i = Z_i x_i for
+ * operator ops[i] with nrhs[i] right-hand sides (canonical order, RHS-major),
+ * i < n_ops.  The products of different operators are independent and run side
+ * by side on the library's worker streams (four per device, forked from and
+ * joined back into `stream`, so the call is ordered on `stream` as a whole).
+ * An operator may appear once (NESA_EINVAL otherwise: its buffers would race);
+ * arguments are checked before any work is queued.  (Bodies that share one tree
+ * are better batched as a forest, nesa_build_forest: one launch per stage for
+ * all of them.) */
+int nesa_matvec_batched(nesa_op* const* ops, int n_ops, const void* const* x_dev, void* const* y_dev,
+                        const int64_t* nrhs, void* stream);
+
 /* Same product in leaf order (no permutation), for callers that keep their
  * vectors in the order of nesa_tree_perm. */
 int nesa_matvec_leaf(nesa_op* op, const void* x_dev, void* y_dev, int64_t nrhs, void* stream);

@@ -490,12 +490,12 @@ static void ensure_all_tiles(nesa_op* op, nesa::DevOp<T>& d, int nrhs, hipStream
   V2* o = static_cast<V2*>(d.o);
   for (size_t i = 0; i < d.lev.size(); ++i) {
     auto& dl = d.lev[i];
-    // from TM_MIN_NRHS right-hand sides the translations run target-major
+    // above pair_cap right-hand sides the translations run target-major
     // (no tiles, no per-pair outputs)
-    if (dl.npairs > 0 && nrhs < nesa::TM_MIN_NRHS) {
+    if (dl.npairs > 0 && nrhs <= d.pair_cap) {
       tune_plan(op, dl.trans, nrhs, s + dl.s_off * nrhs, dl.pair_out, true, st);
     }
-    if (i > 0 && nrhs < nesa::TM_MIN_NRHS) {     // (target-major transfers from TM_MIN_NRHS on)
+    if (i > 0 && nrhs <= d.pair_cap) {     // (target-major transfers above pair_cap)
       auto& pl = d.lev[i - 1];
       tune_plan(op, dl.up, nrhs, s + dl.s_off * nrhs, dl.child_out, false, st);
       tune_plan(op, dl.down, nrhs, o + pl.s_off * nrhs, o + dl.s_off * nrhs, false, st);
@@ -617,6 +617,21 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   d.w[2] = 0.0;
   d.w[3] = fr.eta / fr.k;
   d.lev.resize(t.L - t.l0 + 1);
+  {
+    // right-hand sides up to which the offset-major form (per-pair and
+    // per-child partial results) runs: at most PAIR_CAP_MAX, and its partial
+    // buffers within PAIR_BUFFER_BUDGET bytes
+    double per_rhs = 0;
+    for (int l = t.l0; l <= t.L; ++l) {
+      const double Q = fr.lev[l - t.l0].Q;
+      per_rhs += (double)t.level(l).il_src.size() * 4 * Q * 2 * sizeof(T);
+      if (l > t.l0) per_rhs += (double)t.level(l).nbox * 4 * fr.lev[l - 1 - t.l0].Q * 2 * sizeof(T);
+    }
+    int cap = std::min(op->max_nrhs, nesa::PAIR_CAP_MAX);
+    while (cap > 1 && cap * per_rhs > nesa::PAIR_BUFFER_BUDGET) --cap;
+    if (const char* e = std::getenv("NESA_PAIR_CAP")) cap = std::max(1, std::min(cap, std::atoi(e)));   // tests
+    d.pair_cap = sizeof(T) == 4 ? cap : 1;
+  }
   int64_t soff = 0;
   for (int l = t.l0; l <= t.L; ++l) {
     const nesa::Level& lv = t.level(l);
@@ -693,15 +708,14 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         dl.trans.A_split = d_split;
         dl.trans.Kp = d_split_kp;
       }
-      // per-pair outputs serve the offset-major form only (below TM_MIN_NRHS)
-      const int nr_pair = std::min(op->max_nrhs, nesa::TM_MIN_NRHS - 1);
-      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * nr_pair * fl.Q * 2 * sizeof(T));
+      // per-pair outputs serve the offset-major form only (up to pair_cap)
+      dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * d.pair_cap * fl.Q * 2 * sizeof(T));
     }
     // split form with many right-hand sides: the level's sources (and, in the
-    // potential transfer, its potentials) split into six bf16 planes
-    // (2 bytes x 6 x Kp x 4 max_nrhs per box, Kp = Q rounded up to 32)
+    // potential transfer, its potentials) split into four bf16 planes
+    // (2 bytes x 4 x Kp x 4 max_nrhs per box, Kp = Q rounded up to 32)
     if (sizeof(T) == 4 && op->precision == NESA_C64_SPLIT && 4 * op->max_nrhs >= nesa::TM2_MIN_COLS)
-      dl.s6 = dev_alloc(op, (size_t)lv.nbox * ((fl.Q + 31) / 32 * 32) * 6 * 4 * op->max_nrhs * sizeof(uint16_t));
+      dl.s6 = dev_alloc(op, (size_t)lv.nbox * ((fl.Q + 31) / 32 * 32) * 4 * 4 * op->max_nrhs * sizeof(uint16_t));
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
     if (l < t.L) {
@@ -746,9 +760,8 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx,
                            reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
-        // per-child outputs serve the offset-major form only (below TM_MIN_NRHS)
-        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * std::min(op->max_nrhs, nesa::TM_MIN_NRHS - 1) * Qp * 2 *
-                                         sizeof(T));
+        // per-child outputs serve the offset-major form only (up to pair_cap)
+        dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * d.pair_cap * Qp * 2 * sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx,
                              reg);
         if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.down, ad, 8);
@@ -1710,6 +1723,58 @@ static int matvec_impl(nesa_op* op, const void* x, void* y, int64_t nrhs, void* 
     }
     hip_check(hipGetLastError(), "kernel launch");
     return (int)NESA_OK;
+  });
+}
+
+// worker streams of nesa_matvec_batched (default priority, non-blocking),
+// created once per device and kept until the process ends
+static std::mutex g_batch_mu;
+static std::map<int, std::vector<hipStream_t>> g_batch_streams;
+static std::map<int, std::vector<hipEvent_t>> g_batch_events;     // fork, then one join per worker
+static constexpr int BATCH_STREAMS = 4;
+
+int nesa_matvec_batched(nesa_op* const* ops, int n_ops, const void* const* x_dev, void* const* y_dev,
+                        const int64_t* nrhs, void* stream) {
+  return guarded([&]() {
+    if (n_ops < 0 || (n_ops > 0 && (!ops || !x_dev || !y_dev || !nrhs))) return fail(NESA_EINVAL, "null argument");
+    for (int i = 0; i < n_ops; ++i) {
+      if (!ops[i] || !x_dev[i] || !y_dev[i]) return fail(NESA_EINVAL, "null operator or vector");
+      if (nrhs[i] < 1 || nrhs[i] > ops[i]->max_nrhs) return fail(NESA_EINVAL, "nrhs out of range");
+      for (int j = 0; j < i; ++j)
+        if (ops[j] == ops[i]) return fail(NESA_EINVAL, "an operator appears twice (its work buffers would race)");
+    }
+    if (n_ops == 0) return (int)NESA_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_ops == 1) return matvec_impl(ops[0], x_dev[0], y_dev[0], nrhs[0], stream, true);
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_batch_mu);      // one batched call at a time per process
+    auto& ws = g_batch_streams[dev];
+    auto& ev = g_batch_events[dev];
+    while ((int)ws.size() < BATCH_STREAMS) {
+      hipStream_t s2 = nullptr;
+      hip_check(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+      ws.push_back(s2);
+    }
+    while ((int)ev.size() < BATCH_STREAMS + 1) {
+      hipEvent_t e = nullptr;
+      hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+      ev.push_back(e);
+    }
+    // fork: every worker stream waits for the work queued on `stream`; the
+    // products of different operators (independent buffers) then run side by
+    // side, operator i on worker i mod BATCH_STREAMS; join back into `stream`
+    hip_check(hipEventRecord(ev[0], st), "hipEventRecord");
+    const int nw = std::min(n_ops, BATCH_STREAMS);
+    for (int k = 0; k < nw; ++k) hip_check(hipStreamWaitEvent(ws[k], ev[0], 0), "hipStreamWaitEvent");
+    int rc = NESA_OK;
+    for (int i = 0; i < n_ops && rc == NESA_OK; ++i)
+      rc = matvec_impl(ops[i], x_dev[i], y_dev[i], nrhs[i], ws[i % BATCH_STREAMS], true);
+    for (int k = 0; k < nw; ++k) {
+      hip_check(hipEventRecord(ev[k + 1], ws[k]), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(st, ev[k + 1], 0), "hipStreamWaitEvent");
+    }
+    return rc;
   });
 }
 

@@ -56,7 +56,7 @@ struct DevLevel {
   int32_t* il_slot = nullptr; // compact slot index
   GemmPlan trans;               // translation tiles (complex64): groups = offset slots
   void* pair_out = nullptr;     // [npairs][4][Q] D s_b of every pair
-  void* s6 = nullptr;           // split form with many right-hand sides: pre-split sources (TmArgs::s6)
+  void* s6 = nullptr;           // split form with many right-hand sides: pre-split sources (TmArgs::s6, four planes)
   int32_t* up_ptr = nullptr;    // target-major source transfer into level l-1: children of every
   int32_t* up_src = nullptr;    //   box of level l-1 (CSR over those boxes), octant of each child
   int32_t* up_slot = nullptr;
@@ -102,6 +102,7 @@ struct DevOp {
   hipStream_t side2 = nullptr;   // second side stream: the finest level's translations (untimed products)
   hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
   int max_nrhs = 1;              // right-hand sides the work buffers hold
+  int pair_cap = 1;              // offset-major up to this many right-hand sides, target-major above
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   std::vector<DevLevel> lev;
 };
@@ -144,15 +145,21 @@ struct TmArgs {
   int nct = 0;                            // column tiles per box
   int accumulate = 0;                     // o += result (potential transfer) instead of o = result
   const uint4* s6 = nullptr;              // split form, NC >= TM2_MIN_COLS: sources pre-split
-                                          // [box][Kp/16][6][NC][16] bf16 (rows of 64, 256-column tiles)
+                                          // [box][Kp/16][4][NC][16] bf16 (rows of 64, 256-column tiles)
 };
 // columns per box (4 nrhs) from which the split translations use the pre-split
 // sources and 64 x 256 workgroup tiles
 constexpr int TM2_MIN_COLS = 128;
-// s6 = six bf16 planes of the sources s [nbox][NC][K] (layout of TmArgs::s6)
+// s6 = four bf16 planes (re hi, re lo, im hi, im lo) of the sources s
+// [nbox][NC][K] (layout of TmArgs::s6)
 void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, hipStream_t st);
-// right-hand sides from which the translations run target-major
-constexpr int TM_MIN_NRHS = 8;
+// Products of up to DevOp::pair_cap right-hand sides run the translations and
+// transfers offset-major (grouped GEMMs sharing each matrix over many pairs,
+// partial results per pair or child summed in a fixed order); more right-hand
+// sides run them target-major (no partial results).  pair_cap is at most
+// PAIR_CAP_MAX and limited by the bytes of the partial-result buffers.
+constexpr int PAIR_CAP_MAX = 31;
+constexpr double PAIR_BUFFER_BUDGET = 12.0 * (1 << 30);
 // row tiles per workgroup, row blocks and column tiles of 16 (4 or 2) for M
 // rows inside Mr allocated rows and NC columns; nrt = 0 if none fits
 void tm_blocking(int M, int Mr, int NC, int& nrt, int& rblocks, int& ct);

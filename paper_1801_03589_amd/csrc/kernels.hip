@@ -484,9 +484,12 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 
 // Split-precision variant (complex64 vectors, bf16x3 products): every FP32
 // value v is split as hi = bf16(v), lo = bf16(v - hi); a real product is
-// hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMAs with FP32 accumulation.  A is
-// pre-split on the host into planes (re hi, re lo, im hi, im lo, and the two of
-// re + im that the target-major kernel uses), each
+// hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMAs with FP32 accumulation, and a
+// complex product is four real ones (twelve MFMAs per k step: at one right-hand
+// side the kernel is bound by staging, not by the matrix cores, and three real
+// products would need two more planes of both operands).  A is pre-split into
+// planes (re hi, re lo, im hi, im lo, then two planes of re + im that this
+// kernel does not read), each
 // [Mr][Kp] with k contiguous (Kp = K rounded up to 32, zero padded); B is split
 // in the kernel from the FP32 tile in LDS.  Fragment layout of the 16x16x32
 // instruction: lane l holds rows/columns l % 16 and k = 8 (l / 16) .. +7.
@@ -505,7 +508,7 @@ template <int NRT>
 __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, const unsigned short* __restrict__ As,
                                                         int Kp) {
   static_assert(TR_KC == 32, "one bf16 MFMA k-step per chunk");
-  __shared__ uint4 Al[6][NRT * 16][4];                        // [plane][row][8 k], split planes of A
+  __shared__ uint4 Al[4][NRT * 16][4];                        // [plane][row][8 k], split planes of A
   __shared__ float2 Bs[TR_COLS][TR_KC + 1];                   // [column][k] FP32 B, split in place
   __shared__ int64_t col_src[TR_COLS];
   __shared__ int64_t col_dst[TR_COLS];
@@ -522,28 +525,20 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   __syncthreads();
   const bool active = 16 * w < cnt;
   const size_t plane = (size_t)g.Mr * Kp;
-  const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 6 * plane + (size_t)r0 * Kp;
-  // three real products per complex one (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)
-  // (Br + Bi)), each as bf16 hi hi + hi lo + lo hi: nine MFMAs per k step
-  f32x4 c1[NRT], c2[NRT], c3[NRT];
+  const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 6 * plane + (size_t)r0 * Kp;   // planes 0-3
+  f32x4 cre[NRT], cim[NRT];
 #pragma unroll
   for (int r = 0; r < NRT; ++r) {
-    c1[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-    c2[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-    c3[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  // A staging: 6 planes x NRT*16 rows x 4 quarters of 8 k (uint4) per chunk
-  constexpr int NAQ = 6 * NRT * 16 * 4;
-  constexpr int NAT = (NAQ + NT - 1) / NT;
-  uint4 ra[NAT];
-  const uint4* a_ptr[NAT];
-  bool a_ok[NAT];
+  // A staging: NRT x 16 B per thread per chunk (4 planes x NRT*16 rows x 4 quarters of 8 k)
+  uint4 ra[NRT];
+  const uint4* a_ptr[NRT];
 #pragma unroll
-  for (int i = 0; i < NAT; ++i) {
+  for (int i = 0; i < NRT; ++i) {
     const int e = t + i * NT;
-    a_ok[i] = e < NAQ;
-    const int ee = a_ok[i] ? e : 0;
-    const int pl = ee / (NRT * 16 * 4), row = (ee / 4) % (NRT * 16), qu = ee % 4;
+    const int pl = e / (NRT * 16 * 4), row = (e / 4) % (NRT * 16), qu = e % 4;
     a_ptr[i] = reinterpret_cast<const uint4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
   }
   // B staging: TR_NB float2 per thread per chunk
@@ -563,8 +558,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   // LDS store, so the loads stay in flight during the MFMAs
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < NAT; ++i)
-      if (a_ok[i]) ra[i] = a_ptr[i][k0 / 8];
+    for (int i = 0; i < NRT; ++i) ra[i] = a_ptr[i][k0 / 8];
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
   };
@@ -572,9 +566,9 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   for (int k0 = 0; k0 < K; k0 += TR_KC) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NAT; ++i) {
+    for (int i = 0; i < NRT; ++i) {
       const int e = t + i * NT;
-      if (a_ok[i]) Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
+      Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) {
@@ -584,9 +578,8 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
     __syncthreads();
     if (k0 + TR_KC < K) load(k0 + TR_KC);
     if (active) {
-      // B fragments of this wave's column tile as bf16 hi / lo planes of the
-      // real part, the imaginary part and their sum
-      bf16x8 brh, brl, bih, bil, bsh, bsl;
+      // B fragments of this wave's column tile as bf16 hi / lo planes
+      bf16x8 brh, brl, bih, bil, nbih, nbil;
       const float2* bcol = &Bs[w * 16 + lane % 16][8 * (lane / 16)];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -598,9 +591,8 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         split_bf16(v.y, h, l);
         bih[j] = __builtin_bit_cast(__bf16, h);
         bil[j] = __builtin_bit_cast(__bf16, l);
-        split_bf16(v.x + v.y, h, l);
-        bsh[j] = __builtin_bit_cast(__bf16, h);
-        bsl[j] = __builtin_bit_cast(__bf16, l);
+        nbih[j] = __builtin_bit_cast(__bf16, (unsigned short)(h ^ 0x8000u));
+        nbil[j] = __builtin_bit_cast(__bf16, (unsigned short)(l ^ 0x8000u));
       }
 #pragma unroll
       for (int r = 0; r < NRT; ++r) {
@@ -609,17 +601,18 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         const bf16x8 arl = __builtin_bit_cast(bf16x8, Al[1][row][qu]);
         const bf16x8 aih = __builtin_bit_cast(bf16x8, Al[2][row][qu]);
         const bf16x8 ail = __builtin_bit_cast(bf16x8, Al[3][row][qu]);
-        const bf16x8 ash = __builtin_bit_cast(bf16x8, Al[4][row][qu]);
-        const bf16x8 asl = __builtin_bit_cast(bf16x8, Al[5][row][qu]);
-        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, c1[r], 0, 0, 0);
-        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bih, c2[r], 0, 0, 0);
-        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsh, c3[r], 0, 0, 0);
-        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, c1[r], 0, 0, 0);
-        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bil, c2[r], 0, 0, 0);
-        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsl, c3[r], 0, 0, 0);
-        c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, c1[r], 0, 0, 0);
-        c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bih, c2[r], 0, 0, 0);
-        c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asl, bsh, c3[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbih, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbil, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, cim[r], 0, 0, 0);
+        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nbih, cre[r], 0, 0, 0);
+        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, cim[r], 0, 0, 0);
       }
     }
   }
@@ -632,7 +625,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
       for (int i = 0; i < 4; ++i) {
         const int row = r0 + r * 16 + 4 * (lane / 16) + i;
         if (row < M) {
-          float2 v = make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
+          float2 v = make_float2(cre[r][i], cim[r][i]);
           if (g.accumulate) {
             const float2 o = out[row];
             v.x += o.x;
@@ -1914,11 +1907,11 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     }
     hip_ok(hipEventRecord(d.ev_join, d.side));
   };
-  // complex64 with TM_MIN_NRHS or more right-hand sides: translations and
+  // complex64 with more than pair_cap right-hand sides: translations and
   // transfers run target-major (no per-pair or per-child partial results); the
   // split form with TM2_MIN_COLS or more columns reads sources split once per
   // level into the level's s6 planes
-  const bool tmode = mfma && R >= TM_MIN_NRHS;
+  const bool tmode = mfma && R > d.pair_cap;
   bool v2 = tmode && NC >= TM2_MIN_COLS;
   for (const auto& lv : d.lev) v2 = v2 && lv.s6 != nullptr;     // (allocated for split operators only)
   auto split_of = [&](const DevLevel& lv, const V2* src, hipStream_t ss) {

@@ -410,20 +410,24 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split(TmArgs g) {
 
 // ---------------------------------------------------------------------------
 // Split form for 32 or more right-hand sides (NC >= 128 columns per box).
-// The sources of a level are split once per product (k_split_sources) into six
-// bf16 planes laid out by k chunks of 16, s6[box][kc][plane][NC][16], so that
-// a workgroup stages them as plain copies; the products run on 32x32x16 bf16
-// MFMAs, each wave owning a 64 x 64 block (2 x 2 tiles of 32 x 32) and the
-// four waves side by side along the columns (a 64 x 256 workgroup tile).  A
-// chunk of 16 k (both operands, six planes) is staged through registers into
-// one of two LDS buffers while the MFMAs of the other buffer run: one barrier
-// per chunk.  Operand layout of the instruction: lane l holds row (A) or
-// column (B) l % 32 and k = 8 (l / 32) .. + 7; result value i of lane l is row
-// 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
+// These products move more bytes than the matrix cores can use (each source
+// block serves one target's 64 rows per read), so the operands are kept at 8
+// bytes per complex value: four bf16 planes (re hi, re lo, im hi, im lo) and
+// complex products as four real ones (re = Ar Br - Ai Bi, im = Ar Bi + Ai Br),
+// each hi hi + hi lo + lo hi: twelve MFMAs per k step.  The sources of a level
+// are split once per product (k_split_sources) into s4[box][kc][plane][NC][16]
+// (k chunks of 16), so that a workgroup stages them as plain copies; the
+// products run on 32x32x16 bf16 MFMAs, each wave owning a 64 x 64 block (2 x 2
+// tiles of 32 x 32) and the four waves side by side along the columns (a 64 x
+// 256 workgroup tile).  A chunk of 16 k (both operands, four planes) is staged
+// through registers into one of two LDS buffers while the MFMAs of the other
+// buffer run: one barrier per chunk.  Operand layout of the instruction: lane l
+// holds row (A) or column (B) l % 32 and k = 8 (l / 32) .. + 7; result value i
+// of lane l is row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
 typedef float tm_f32x16 __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(TM_NT) void k_split_sources(const float2* __restrict__ s, int64_t nbox, int NC, int K,
-                                                         int Kp, uint4* __restrict__ s6) {
+                                                         int Kp, uint4* __restrict__ s4) {
   // one thread per (box, column, 8 consecutive k)
   const int per_box = NC * (Kp / 8);
   const int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x;
@@ -431,26 +435,34 @@ __global__ __launch_bounds__(TM_NT) void k_split_sources(const float2* __restric
   const int64_t box = i / per_box;
   const int r = (int)(i % per_box), c = r / (Kp / 8), k0 = 8 * (r % (Kp / 8));
   const float2* src = s + ((size_t)box * NC + c) * K;
-  unsigned short h[6][8];
+  unsigned short h[4][8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const float2 v = (k0 + u < K) ? src[k0 + u] : make_float2(0.f, 0.f);
     tm_split(v.x, h[0][u], h[1][u]);
     tm_split(v.y, h[2][u], h[3][u]);
-    tm_split(v.x + v.y, h[4][u], h[5][u]);
   }
   const int kc = k0 / 16, half = (k0 % 16) / 8;
-  uint4* dst = s6 + ((((size_t)box * (Kp / 16) + kc) * 6) * NC + c) * 2 + half;
+  uint4* dst = s4 + ((((size_t)box * (Kp / 16) + kc) * 4) * NC + c) * 2 + half;
 #pragma unroll
-  for (int pl = 0; pl < 6; ++pl)
+  for (int pl = 0; pl < 4; ++pl)
     dst[(size_t)pl * NC * 2] = make_uint4(tm_pack(h[pl][0], h[pl][1]), tm_pack(h[pl][2], h[pl][3]),
                                           tm_pack(h[pl][4], h[pl][5]), tm_pack(h[pl][6], h[pl][7]));
 }
 
-__global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
-  constexpr int ROWS = 64, COLS = 256;
-  constexpr int AQ = 6 * ROWS * 2, BQ = 6 * COLS * 2;         // uint4 per buffer (8 bf16 each)
-  constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;            // 3 and 12 per thread
+__device__ __forceinline__ tm_bf16x8 tm_neg(tm_bf16x8 v) {
+  uint4 u = __builtin_bit_cast(uint4, v);
+  u.x ^= 0x80008000u;
+  u.y ^= 0x80008000u;
+  u.z ^= 0x80008000u;
+  u.w ^= 0x80008000u;
+  return __builtin_bit_cast(tm_bf16x8, u);
+}
+
+__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_translate_tm_split2(TmArgs g) {
+  constexpr int ROWS = 64, COLS = 256, NP = 4;
+  constexpr int AQ = NP * ROWS * 2, BQ = NP * COLS * 2;        // uint4 per buffer (8 bf16 each)
+  constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;            // 2 and 8 per thread
   static_assert(AQ % TM_NT == 0 && BQ % TM_NT == 0, "staging must split evenly");
   __shared__ uint4 lds[2 * (AQ + BQ)];
   const int64_t nitems = g.nbox * g.nct;
@@ -466,8 +478,8 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
   const int jb = g.il_ptr[a], je = g.il_ptr[a + 1];
   const bool active = 64 * w < ncol;
   // staging offsets (uint4 units): A element e = (plane, row, half), from the
-  // pre-split translation planes [slot][6][Mr][Kp]; B element e = (plane,
-  // column, half), from s6[box][kc][plane][NC][16]
+  // pre-split matrix planes [slot][6][Mr][Kp] (planes 0-3); B element e =
+  // (plane, column, half), from s4[box][kc][plane][NC][16]
   int oa[NAT], ob[NBT];
   bool bok[NBT];
 #pragma unroll
@@ -481,22 +493,21 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
     bok[i] = col < ncol;
     ob[i] = (pl * NC + min(col, ncol - 1)) * 2 + hf;
   }
-  tm_f32x16 c1[2][2], c2[2][2], c3[2][2];
+  tm_f32x16 cre[2][2], cim[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        c1[i][j][u] = 0.f;
-        c2[i][j][u] = 0.f;
-        c3[i][j][u] = 0.f;
+        cre[i][j][u] = 0.f;
+        cim[i][j][u] = 0.f;
       }
   uint4 ra[NAT], rb[NBT];
   auto load = [&](int j, int kc) {
     const int slot = g.il_slot[j], src = g.il_src[j];
     const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp) + kc * 2;
-    const uint4* B = g.s6 + (((size_t)src * KC + kc) * 6) * NC * 2 + (size_t)c0 * 2;
+    const uint4* B = g.s6 + (((size_t)src * KC + kc) * NP) * NC * 2 + (size_t)c0 * 2;
 #pragma unroll
     for (int i = 0; i < NAT; ++i) ra[i] = A[oa[i]];
 #pragma unroll
@@ -514,29 +525,34 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
     const uint4* Ab = lds + buf * (AQ + BQ);
     const uint4* Bb = Ab + AQ;
     const int hf = lane / 32;
-    tm_bf16x8 av[2][6];
+    tm_bf16x8 av[2][NP];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
+      for (int pl = 0; pl < NP; ++pl)
         av[rt][pl] = __builtin_bit_cast(tm_bf16x8, Ab[(pl * ROWS + rt * 32 + lane % 32) * 2 + hf]);
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      tm_bf16x8 bv[6];
+      tm_bf16x8 bv[NP];
 #pragma unroll
-      for (int pl = 0; pl < 6; ++pl)
+      for (int pl = 0; pl < NP; ++pl)
         bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * 64 + ct * 32 + lane % 32) * 2 + hf]);
+      const tm_bf16x8 nbih = tm_neg(bv[2]), nbil = tm_neg(bv[3]);
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
-        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[0], c1[rt][ct], 0, 0, 0);
-        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[2], c2[rt][ct], 0, 0, 0);
-        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][4], bv[4], c3[rt][ct], 0, 0, 0);
-        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[1], c1[rt][ct], 0, 0, 0);
-        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[3], c2[rt][ct], 0, 0, 0);
-        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][4], bv[5], c3[rt][ct], 0, 0, 0);
-        c1[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[0], c1[rt][ct], 0, 0, 0);
-        c2[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], bv[2], c2[rt][ct], 0, 0, 0);
-        c3[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][5], bv[4], c3[rt][ct], 0, 0, 0);
+        // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br, each real product hi hi + hi lo + lo hi
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[0], cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[2], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[1], cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[3], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[0], cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[2], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], nbih, cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[0], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], nbil, cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[1], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], nbih, cre[rt][ct], 0, 0, 0);
+        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], bv[0], cim[rt][ct], 0, 0, 0);
       }
     }
   };
@@ -572,8 +588,7 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split2(TmArgs g) {
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int row = rt * 32 + 8 * (u / 4) + 4 * (lane / 32) + u % 4;
-            otile[lc * RS + row] = make_float2(c1[rt][ct][u] - c2[rt][ct][u],
-                                               c3[rt][ct][u] - c1[rt][ct][u] - c2[rt][ct][u]);
+            otile[lc * RS + row] = make_float2(cre[rt][ct][u], cim[rt][ct][u]);
           }
         }
     }

@@ -94,6 +94,7 @@ _SIGS = {
     "nesa_op_free": (None, [_P]),
     "nesa_matvec": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "nesa_matvec_leaf": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "nesa_matvec_batched": (C.c_int, [_P, C.c_int, _P, _P, _P, _P]),
     "nesa_matvec_phase_times": (C.c_int, [_P, _P, _P, _P, _P]),
     "nesa_matvec_launch_times": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, _P]),
     "nesa_matvec_launch_times_nrhs": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P, _P, C.c_int32, _P]),
@@ -291,6 +292,16 @@ def op_create(tree, near, far, precision=C64, max_nrhs=1):
 
 def matvec(op, x, y, nrhs=1, stream=None):
     _check(lib().nesa_matvec(op.h, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+
+
+def matvec_batched(ops, xs, ys, nrhs=None, stream=None):
+    """y_i = Z_i x_i for several operators in one call (nesa_matvec_batched)."""
+    n = len(ops)
+    nr = np.ascontiguousarray(nrhs if nrhs is not None else [1] * n, dtype=np.int64)
+    oh = (C.c_void_p * n)(*[o.h for o in ops])
+    xp = (C.c_void_p * n)(*[_dptr(x).value for x in xs])
+    yp = (C.c_void_p * n)(*[_dptr(y).value for y in ys])
+    _check(lib().nesa_matvec_batched(oh, n, xp, yp, _ptr(nr), _stream(stream)))
 
 
 def matvec_leaf(op, x, y, nrhs=1, stream=None):

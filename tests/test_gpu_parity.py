@@ -299,7 +299,32 @@ def test_matvec_multi_rhs_split(torch_dev, nesa, nrhs):
         assert err <= 1e-4, (r, err)
 
 
-@pytest.mark.parametrize("nrhs", [2, 8, 13])
+@pytest.mark.parametrize("prec", ["c64", "split"])
+@pytest.mark.parametrize("nrhs", [8, 13])
+def test_matvec_target_major_below_cap(torch_dev, nesa, prec, nrhs, monkeypatch):
+    """The target-major translations and transfers at 8 and 13 right-hand sides
+    (FP32 32-column tiles with a partial one at 13; split with the sources split
+    in the kernel), forced by capping the offset-major form at one right-hand
+    side, against the oracle and the offset-major product."""
+    monkeypatch.setenv("NESA_PAIR_CAP", "1")
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    P = nesa.C64 if prec == "c64" else nesa.C64_SPLIT
+    op = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
+    monkeypatch.delenv("NESA_PAIR_CAP")
+    op_om = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
+    X = synth.complex_normal((nrhs, ref.m.n), 30 + nrhs)
+    Y = _run(torch_dev, nesa, op, X, nrhs=nrhs)
+    Yo = _run(torch_dev, nesa, op_om, X, nrhs=nrhs)
+    tol = TOL["c64"] if prec == "c64" else 1e-4
+    for r in sorted({0, nrhs - 1}):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("target-major %s nrhs %d rhs %d: rel err %.2e" % (prec, nrhs, r, err))
+        assert err <= tol, (r, err)
+    assert np.linalg.norm(Y - Yo) <= 10 * tol * np.linalg.norm(Yo)
+
+
+@pytest.mark.parametrize("nrhs", [2, 8, 13, 32])
 def test_matvec_multi_rhs(torch_dev, nesa, nrhs):
     """Batched right-hand sides (channels = 4 x nrhs in the GEMM columns)
     against the oracle column by column, and against single-RHS products."""
@@ -485,3 +510,32 @@ def test_product_on_user_stream_and_in_hip_graph(torch_dev, nesa):
         nesa.matvec(op, x, z)                  # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(z, y0)
+
+
+def test_matvec_batched_matches_single(torch_dev, nesa):
+    """nesa_matvec_batched over five operators of different meshes, precisions
+    and right-hand side counts (independent products on the worker streams)
+    against one nesa_matvec each: identical outputs; an operator listed twice
+    is refused."""
+    torch = torch_dev
+    cases = [("sphere1", nesa.C128, 1), ("sphere1_nested", nesa.C64, 3), ("box", nesa.C64_SPLIT, 2),
+             ("sphere_2lev", nesa.C64, 1), ("sphere_3lev", nesa.C64, 8)]
+    ops, xs, ys, refs, nr = [], [], [], [], []
+    for i, (name, P, R) in enumerate(cases):
+        ref, tr, near, far = _case(nesa, name)
+        op = nesa.op_create(tr, near, far, P, max_nrhs=R)
+        dt = torch.complex128 if P == nesa.C128 else torch.complex64
+        x = torch.from_numpy(synth.complex_normal((R, ref.m.n), 40 + i)).to(dt).cuda()
+        y1 = torch.empty_like(x)
+        nesa.matvec(op, x, y1, R)
+        ops.append(op)
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+        refs.append(y1)
+        nr.append(R)
+    nesa.matvec_batched(ops, xs, ys, nr)
+    torch.cuda.synchronize()
+    for y, y1 in zip(ys, refs):
+        assert torch.equal(y, y1)
+    with pytest.raises(nesa.NesaError):
+        nesa.matvec_batched([ops[0], ops[0]], [xs[0], xs[0]], [ys[0], ys[0]], [1, 1])
