@@ -144,6 +144,7 @@ struct TmArgs {
   int NC = 0;                             // 4 x nrhs
   int nct = 0;                            // column tiles per box
   int accumulate = 0;                     // o += result (potential transfer) instead of o = result
+  int nct_cols = 256;                     // split form from TM2_MIN_COLS: columns per workgroup tile (256 or 128)
   const uint4* s6 = nullptr;              // split form, NC >= TM2_MIN_COLS: sources pre-split
                                           // [box][Kp/16][4][NC][16] bf16 (rows of 64, 256-column tiles)
 };

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -1740,6 +1741,17 @@ __global__ __launch_bounds__(NT) void k_blockdiag(const typename C2<T>::type* __
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+// columns per workgroup of the split target-major kernel (NESA_TM_COLS=128
+// selects the narrower tile: half the source bytes per workgroup, twice the
+// matrix reads)
+static int tm_split_cols() {
+  static const int c = []() {
+    const char* e = std::getenv("NESA_TM_COLS");
+    return (e && std::atoi(e) == 128) ? 128 : 256;
+  }();
+  return c;
+}
+
 static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st,
                          bool translation) {
   const TileList& tl = p.by_nrhs[nrhs];
@@ -1943,7 +1955,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
       if (v2) {
         g.s6 = static_cast<const uint4*>(s6v);
-        g.nct = (NC + 255) / 256;
+        g.nct_cols = tm_split_cols();
+        g.nct = (NC + g.nct_cols - 1) / g.nct_cols;
       }
       launch_translate_tm(g, nrt, rblocks, ct, ss);
     }

@@ -459,8 +459,11 @@ __device__ __forceinline__ tm_bf16x8 tm_neg(tm_bf16x8 v) {
   return __builtin_bit_cast(tm_bf16x8, u);
 }
 
-__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_translate_tm_split2(TmArgs g) {
-  constexpr int ROWS = 64, COLS = 256, NP = 4;
+template <int COLS>
+__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS == 128 ? 3 : 2))) void k_translate_tm_split2(TmArgs g) {
+  constexpr int ROWS = 64, NP = 4;
+  constexpr int WC = COLS / 4;                                 // columns per wave (64 or 32)
+  constexpr int CTW = WC / 32;                                 // 32-column tiles per wave
   constexpr int AQ = NP * ROWS * 2, BQ = NP * COLS * 2;        // uint4 per buffer (8 bf16 each)
   constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;            // 2 and 8 per thread
   static_assert(AQ % TM_NT == 0 && BQ % TM_NT == 0, "staging must split evenly");
@@ -468,15 +471,17 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   const int64_t nitems = g.nbox * g.nct;
   const int64_t item = tm_item(blockIdx.x, nitems);
   if (item >= nitems) return;
-  const int64_t a = item / g.nct;
-  const int c0 = (int)(item % g.nct) * COLS;
+  // column tile major: the workgroups an XCD runs side by side take
+  // neighbouring targets of one column tile, whose sources overlap in its L2
+  const int64_t a = item % g.nbox;
+  const int c0 = (int)(item / g.nbox) * COLS;
   const int ncol = min(COLS, g.NC - c0);
   const int r0 = blockIdx.y * ROWS;
   const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
   const int NC = g.NC, M = g.M, Kp = g.Kp, KC = g.Kp / 16;
   const size_t plane = (size_t)g.Mr * Kp;
   const int jb = g.il_ptr[a], je = g.il_ptr[a + 1];
-  const bool active = 64 * w < ncol;
+  const bool active = WC * w < ncol;
   // staging offsets (uint4 units): A element e = (plane, row, half), from the
   // pre-split matrix planes [slot][6][Mr][Kp] (planes 0-3); B element e =
   // (plane, column, half), from s4[box][kc][plane][NC][16]
@@ -493,11 +498,11 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     bok[i] = col < ncol;
     ob[i] = (pl * NC + min(col, ncol - 1)) * 2 + hf;
   }
-  tm_f32x16 cre[2][2], cim[2][2];
+  tm_f32x16 cre[2][CTW], cim[2][CTW];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < CTW; ++j)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         cre[i][j][u] = 0.f;
@@ -532,11 +537,11 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       for (int pl = 0; pl < NP; ++pl)
         av[rt][pl] = __builtin_bit_cast(tm_bf16x8, Ab[(pl * ROWS + rt * 32 + lane % 32) * 2 + hf]);
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
+    for (int ct = 0; ct < CTW; ++ct) {
       tm_bf16x8 bv[NP];
 #pragma unroll
       for (int pl = 0; pl < NP; ++pl)
-        bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * 64 + ct * 32 + lane % 32) * 2 + hf]);
+        bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * WC + ct * 32 + lane % 32) * 2 + hf]);
       const tm_bf16x8 nbih = tm_neg(bv[2]), nbil = tm_neg(bv[3]);
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
@@ -571,20 +576,21 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
       __syncthreads();
     }
   }
-  // output through LDS in two passes of 128 columns ([column][row], stride 66)
+  // output through LDS in passes of PC columns ([column][row], stride 66)
   constexpr int RS = ROWS + 2;
-  static_assert(2 * (AQ + BQ) * 16 >= 128 * RS * 8, "LDS tile too small");
+  constexpr int PC = (2 * (AQ + BQ) * 16 >= 128 * RS * 8) ? 128 : 64;    // columns per output pass
+  static_assert(2 * (AQ + BQ) * 16 >= PC * RS * 8, "LDS tile too small");
   float2* otile = reinterpret_cast<float2*>(&lds[0]);
   const int mloc = min(ROWS, M - r0);
   float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
-  for (int p0 = 0; p0 < COLS; p0 += 128) {
+  for (int p0 = 0; p0 < COLS; p0 += PC) {
     __syncthreads();
-    if (w * 64 >= p0 && w * 64 < p0 + 128) {
+    if (w * WC >= p0 && w * WC < p0 + PC) {
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const int lc = w * 64 - p0 + ct * 32 + lane % 32;
+        for (int ct = 0; ct < CTW; ++ct) {
+          const int lc = w * WC - p0 + ct * 32 + lane % 32;
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int row = rt * 32 + 8 * (u / 4) + 4 * (lane / 32) + u % 4;
@@ -593,7 +599,7 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         }
     }
     __syncthreads();
-    const int nc = min(128, ncol - p0);
+    const int nc = min(PC, ncol - p0);
     for (int e = t; e < nc * mloc; e += TM_NT) {
       const int lc = e / mloc, row = e % mloc;
       float2 v = otile[lc * RS + row];
@@ -672,9 +678,13 @@ void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStrea
   const int64_t nitems = g.nbox * g.nct;
   if (nitems == 0) return;
   if (g.Asplit && g.s6) {
-    // 64 x 256 workgroup tiles: nct counts 256-column tiles, rows in blocks of 64
+    // 64 x 256 (or 64 x 128) workgroup tiles: nct counts those column tiles,
+    // rows in blocks of 64
     dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 63) / 64));
-    k_translate_tm_split2<<<grid2, TM_NT, 0, st>>>(g);
+    if (g.nct_cols == 128)
+      k_translate_tm_split2<128><<<grid2, TM_NT, 0, st>>>(g);
+    else
+      k_translate_tm_split2<256><<<grid2, TM_NT, 0, st>>>(g);
     return;
   }
   dim3 grid((unsigned)((nitems + 7) / 8 * 8), (unsigned)rblocks);
