@@ -98,6 +98,26 @@ def block_diagonal(blocks):
     return apply
 
 
+def near_schwarz_rows(a, leaf_rwgs, near, near_block, is_near):
+    """Leaf a's part of the restricted additive Schwarz preconditioner (see
+    near_schwarz): (RWGs of a, RWGs of N(a) in near-list order, the rows of
+    Z_N^-1 that belong to a)."""
+    nb = near[a]
+    cols = np.concatenate([leaf_rwgs[b] for b in nb])
+    off = np.cumsum([0] + [len(leaf_rwgs[b]) for b in nb])
+    ZN = np.zeros((len(cols), len(cols)), dtype=np.complex128)
+    for i, b in enumerate(nb):
+        rows_b, cols_b, Zb = near_block(b)
+        pos = {c: j for j, c in enumerate(cols_b)}
+        for j, c in enumerate(nb):
+            if is_near(b, c):
+                idx = [pos[x] for x in leaf_rwgs[c]]
+                ZN[off[i]:off[i + 1], off[j]:off[j + 1]] = Zb[:, idx]
+    Mi = np.linalg.inv(ZN)
+    ia = nb.index(a)
+    return leaf_rwgs[a], cols, Mi[off[ia]:off[ia + 1]]
+
+
 def near_schwarz(leaf_rwgs, near, near_block, is_near):
     """Restricted additive Schwarz over the near lists: for leaf a, with N(a) its
     near leaves and Z_N the near-field matrix restricted to the RWGs of N(a)
@@ -105,22 +125,7 @@ def near_schwarz(leaf_rwgs, near, near_block, is_near):
     not part of the near-field matrix), z_a = [Z_N^-1 r_N]_a.
     leaf_rwgs[a]: RWGs of leaf a; near[a]: its near leaves; near_block(a) ->
     (rows, cols, Z rows of leaf a against the RWGs of near[a]); is_near(b, c)."""
-    blocks = []
-    for a, rw in enumerate(leaf_rwgs):
-        nb = near[a]
-        cols = np.concatenate([leaf_rwgs[b] for b in nb])
-        off = np.cumsum([0] + [len(leaf_rwgs[b]) for b in nb])
-        ZN = np.zeros((len(cols), len(cols)), dtype=np.complex128)
-        for i, b in enumerate(nb):
-            rows_b, cols_b, Zb = near_block(b)
-            pos = {c: j for j, c in enumerate(cols_b)}
-            for j, c in enumerate(nb):
-                if is_near(b, c):
-                    idx = [pos[x] for x in leaf_rwgs[c]]
-                    ZN[off[i]:off[i + 1], off[j]:off[j + 1]] = Zb[:, idx]
-        Mi = np.linalg.inv(ZN)
-        ia = nb.index(a)
-        blocks.append((rw, cols, Mi[off[ia]:off[ia + 1]]))
+    blocks = [near_schwarz_rows(a, leaf_rwgs, near, near_block, is_near) for a in range(len(leaf_rwgs))]
 
     def apply(r):
         z = np.zeros_like(r)

@@ -20,6 +20,7 @@
 #include "../../include/nesa.h"
 #include "kernels.h"
 #include "mlp.h"
+#include "precond_dev.h"
 #include "nesa_host.h"
 
 using nesa::cd;
@@ -860,10 +861,145 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   ensure_all_tiles<T>(op, d, 1);
 }
 
-// Schwarz preconditioner: built on the host at first use, uploaded in the
-// near-block layout of the op's precision
+// device memory released at scope exit
+struct DevTmp {
+  void* p = nullptr;
+  DevTmp() = default;
+  DevTmp(const DevTmp&) = delete;
+  DevTmp& operator=(const DevTmp&) = delete;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename X>
+  X* alloc(size_t count) {
+    hip_check(hipMalloc(&p, std::max<size_t>(count * sizeof(X), 16)), "hipMalloc");
+    return static_cast<X*>(p);
+  }
+  template <typename X>
+  X* put(const std::vector<X>& h) {
+    X* d = alloc<X>(h.size());
+    if (!h.empty()) hip_check(hipMemcpy(d, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice), "hipMemcpy");
+    return d;
+  }
+};
+
+// Schwarz preconditioner of a complex64 operator assembled on the device
+// (precond_dev.hip): per-leaf tables of the near lists on the host, then the
+// matrices Z_N^T gathered from the near blocks, factored and solved in batches
+// of leaves whose matrices fit a workspace of at most 8 GiB.  Returns false
+// (nothing built) when a near list holds more than 27 leaves.
+static bool schwarz_device(nesa_op* op) {
+  const nesa::Tree& t = *op->tree;
+  const nesa::Near& nr = *op->near;
+  const int64_t nleaf = t.level(t.L).nbox;
+  constexpr int MX = nesa::SCHWARZ_MAXN;
+  for (int64_t a = 0; a < nleaf; ++a)
+    if (t.near_ptr[a + 1] - t.near_ptr[a] > MX) return false;
+  std::vector<int32_t> na(nleaf), W(nleaf), rowa(nleaf, -1), nb((size_t)nleaf * MX, 0),
+      off((size_t)nleaf * (MX + 1), 0), colpos((size_t)nleaf * MX * MX, -1);
+  auto size_of = [&](int64_t b) { return (int32_t)(t.leaf_ptr[b + 1] - t.leaf_ptr[b]); };
+  nesa::parallel_for(nleaf, [&](int64_t a) {
+    const int n = (int)(t.near_ptr[a + 1] - t.near_ptr[a]);
+    int32_t* nba = &nb[(size_t)a * MX];
+    int32_t* offa = &off[(size_t)a * (MX + 1)];
+    for (int i = 0; i < n; ++i) {
+      nba[i] = (int32_t)t.near_idx[t.near_ptr[a] + i];
+      offa[i + 1] = offa[i] + size_of(nba[i]);
+      if (nba[i] == a) rowa[a] = offa[i];
+    }
+    na[a] = n;
+    W[a] = offa[n];
+    for (int jb = 0; jb < n; ++jb) {
+      int32_t cb = 0;
+      for (int64_t q = t.near_ptr[nba[jb]]; q < t.near_ptr[nba[jb] + 1]; ++q) {
+        const int64_t c = t.near_idx[q];
+        for (int ib = 0; ib < n; ++ib)
+          if (nba[ib] == c) colpos[(size_t)a * MX * MX + jb * MX + ib] = cb;
+        cb += size_of(c);
+      }
+    }
+  });
+  for (int64_t a = 0; a < nleaf; ++a)
+    if (rowa[a] < 0) throw Error(NESA_EINVAL, "a leaf is missing from its own near list");
+  // batches: consecutive leaves, matrices within the workspace budget
+  size_t free_b = 0, total_b = 0;
+  hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+  const int64_t budget = std::max<int64_t>(std::min<int64_t>(int64_t(8) << 30, (int64_t)(free_b / 4)), 1 << 26);
+  std::vector<int64_t> ws_off(nleaf), piv_off(nleaf);
+  std::vector<std::pair<int64_t, int64_t>> batches;   // (first, count)
+  int64_t ws_max = 0, piv_max = 0;
+  {
+    int64_t first = 0, ws = 0, pv = 0;
+    for (int64_t a = 0; a < nleaf; ++a) {
+      const int64_t m = (int64_t)W[a] * W[a];
+      if (a > first && ((ws + m) * 8 > budget || a - first >= 65535)) {
+        batches.push_back({first, a - first});
+        first = a;
+        ws = pv = 0;
+      }
+      ws_off[a] = ws;
+      piv_off[a] = pv;
+      ws += m;
+      pv += W[a];
+      ws_max = std::max(ws_max, ws);
+      piv_max = std::max(piv_max, pv);
+    }
+    if (nleaf > first) batches.push_back({first, nleaf - first});
+  }
+  nesa::DevOp<float>& d = op->f;
+  DevTmp zt, t_na, t_w, t_rowa, t_nb, t_off, t_cp, t_wso, t_pvo, t_ws, t_piv, t_st;
+  const float2* Z = static_cast<const float2*>(d.Z);
+  if (!Z) {
+    // complex64 copy of the full near blocks (the op keeps only the
+    // reciprocity half when it serves one right-hand side)
+    float2* zd = zt.alloc<float2>(nr.z.size());
+    const int64_t chunk = int64_t(1) << 24;
+    std::vector<float2> buf((size_t)std::min<int64_t>(chunk, (int64_t)nr.z.size()));
+    for (int64_t s0 = 0; s0 < (int64_t)nr.z.size(); s0 += chunk) {
+      const int64_t cnt = std::min<int64_t>(chunk, (int64_t)nr.z.size() - s0);
+      nesa::parallel_for((cnt + 65535) / 65536, [&](int64_t blk) {
+        const int64_t e1 = std::min<int64_t>(cnt, (blk + 1) * 65536);
+        for (int64_t e = blk * 65536; e < e1; ++e)
+          buf[e] = make_float2((float)nr.z[s0 + e].real(), (float)nr.z[s0 + e].imag());
+      });
+      hip_check(hipMemcpy(zd + s0, buf.data(), cnt * sizeof(float2), hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    Z = zd;
+  }
+  nesa::SchwarzBatch b;
+  b.na = t_na.put(na);
+  b.W = t_w.put(W);
+  b.rowa = t_rowa.put(rowa);
+  b.nb = t_nb.put(nb);
+  b.off = t_off.put(off);
+  b.colpos = t_cp.put(colpos);
+  b.ws_off = t_wso.put(ws_off);
+  b.piv_off = t_pvo.put(piv_off);
+  b.ws = t_ws.alloc<float2>(ws_max);
+  b.piv = t_piv.alloc<int32_t>(piv_max);
+  b.status = t_st.alloc<int32_t>(1);
+  hip_check(hipMemset(b.status, 0, sizeof(int32_t)), "hipMemset");
+  float2* out = static_cast<float2*>(dev_alloc(op, nr.z.size() * sizeof(float2)));
+  for (const auto& bt : batches) {
+    b.first = (int)bt.first;
+    b.count = (int)bt.second;
+    nesa::launch_schwarz_batch(Z, d.zoff, d.leaf_ptr, b, out, nullptr);
+    hip_check(hipGetLastError(), "kernel launch");
+  }
+  int32_t status = 0;
+  hip_check(hipMemcpy(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (status) throw Error(-1, "singular near-field matrix in the Schwarz preconditioner");
+  op->schwarz = out;
+  return true;
+}
+
+// Schwarz preconditioner, built at first use in the near-block layout of the
+// op's precision: on the device for complex64 operators (on the host in FP32
+// when NESA_SCHWARZ_HOST=1), on the host in FP64 for complex128 ones
 static void ensure_schwarz(nesa_op* op) {
   if (op->schwarz) return;
+  const char* host = std::getenv("NESA_SCHWARZ_HOST");
+  if (op->precision != NESA_C128 && !(host && std::atoi(host) == 1) && schwarz_device(op)) return;
   std::unique_ptr<nesa::Near> P(nesa::near_schwarz(*op->tree, *op->near, op->precision != NESA_C128));
   if (op->precision == NESA_C128)
     op->schwarz = upload_complex<double>(op, P->z);

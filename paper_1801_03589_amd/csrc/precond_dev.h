@@ -1,0 +1,42 @@
+// Restricted additive Schwarz preconditioner assembled on the device
+// (precond_dev.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nesa {
+
+// near leaves of one leaf at most (its 3 x 3 x 3 neighbourhood)
+constexpr int SCHWARZ_MAXN = 27;
+
+// Per-leaf tables (device, indexed by leaf) and one batch's work arrays.
+// For leaf a with near list N(a) = nb[0 .. na): off[i] is the first RWG of
+// nb[i] inside N(a) (off[na] = W), rowa the one of a itself, and colpos[j][i]
+// the first column of leaf nb[i] inside leaf nb[j]'s near block, -1 when
+// nb[i] is not near nb[j].
+struct SchwarzBatch {
+  int first = 0;                    // leaves [first, first + count)
+  int count = 0;
+  const int32_t* na = nullptr;      // [nleaf]
+  const int32_t* W = nullptr;       // [nleaf]
+  const int32_t* rowa = nullptr;    // [nleaf]
+  const int32_t* nb = nullptr;      // [nleaf][27]
+  const int32_t* off = nullptr;     // [nleaf][28]
+  const int32_t* colpos = nullptr;  // [nleaf][27][27]
+  const int64_t* ws_off = nullptr;  // [nleaf] offset of leaf's W x W matrix in its batch's workspace
+  const int64_t* piv_off = nullptr; // [nleaf] offset of its pivots in the batch's pivot array
+  float2* ws = nullptr;             // the batch's matrices
+  int32_t* piv = nullptr;
+  int32_t* status = nullptr;        // set to 1 when a pivot is zero (singular Z_N)
+};
+
+// Builds, factors and solves one batch: out (the preconditioner's arena, the
+// layout of the near blocks: leaf a at zoff[a], S_a x W_a column-major) gets
+// the rows of Z_N^-1 of every leaf of the batch.  Z: the full near blocks
+// (complex64, same layout); leaf_ptr [nleaf + 1].
+void launch_schwarz_batch(const float2* Z, const int64_t* zoff, const int32_t* leaf_ptr, const SchwarzBatch& b,
+                          float2* out, hipStream_t st);
+
+}  // namespace nesa
