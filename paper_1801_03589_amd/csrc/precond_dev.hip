@@ -27,9 +27,11 @@ namespace nesa {
 namespace {
 
 constexpr int SW_NT = 256;
-constexpr int SW_NB = 16;
+constexpr int SW_NB = 32;      // panel width of the factorisation, block size of the solves
+constexpr int SW_NS = 8;       // sub-panel width
+constexpr int SW_TM = 64;      // GEMM tile (rows and columns)
 constexpr int SW_MAXN = SCHWARZ_MAXN;
-constexpr int SW_TILE = 32;
+constexpr int SW_TILE = 32;    // gather transpose tile
 
 __device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -83,160 +85,353 @@ __global__ __launch_bounds__(SW_NT) void k_schwarz_gather(const float2* __restri
     }
 }
 
-__global__ __launch_bounds__(SW_NT) void k_schwarz_lu(SchwarzBatch b, float2* __restrict__ out,
-                                                      const int64_t* __restrict__ zoff,
-                                                      const int32_t* __restrict__ leaf_ptr) {
-  __shared__ float red_v[SW_NT];
-  __shared__ int red_i[SW_NT];
-  const int a = b.first + blockIdx.x;
-  const int W = b.W[a], r0 = b.rowa[a];
-  const int S = leaf_ptr[a + 1] - leaf_ptr[a];
-  float2* T = b.ws + b.ws_off[a];
-  int32_t* piv = b.piv + b.piv_off[a];
-  const int t = threadIdx.x;
-  for (int k0 = 0; k0 < W; k0 += SW_NB) {
-    const int kb = min(SW_NB, W - k0);
-    // ---- panel: columns k0 .. k0 + kb - 1, unblocked with partial pivoting
-    for (int jj = 0; jj < kb; ++jj) {
-      const int c = k0 + jj;
-      float2* cw = T + (int64_t)c * W;
-      float best = -1.f;
-      int bi = W;
-      for (int i = c + t; i < W; i += SW_NT) {
-        const float m = fabsf(cw[i].x) + fabsf(cw[i].y);
-        if (m > best) {
-          best = m;
-          bi = i;
-        }
-      }
-      red_v[t] = best;
-      red_i[t] = bi;
-      __syncthreads();
-      for (int s = SW_NT / 2; s > 0; s >>= 1) {
-        if (t < s) {
-          const float v2 = red_v[t + s];
-          const int i2 = red_i[t + s];
-          if (v2 > red_v[t] || (v2 == red_v[t] && i2 < red_i[t])) {
-            red_v[t] = v2;
-            red_i[t] = i2;
-          }
-        }
-        __syncthreads();
-      }
-      const int p = red_i[0] < W ? red_i[0] : c;
-      if (t == 0) {
-        piv[c] = p;
-        if (!(red_v[0] > 0.f)) b.status[0] = 1;
-      }
-      if (p != c)
-        for (int jc = t; jc < W; jc += SW_NT) {
-          float2* cc = T + (int64_t)jc * W;
-          const float2 x = cc[c];
-          cc[c] = cc[p];
-          cc[p] = x;
-        }
-      __syncthreads();
-      const float2 d = cw[c];
-      for (int i = c + 1 + t; i < W; i += SW_NT) cw[i] = c_div(cw[i], d);
-      __syncthreads();
-      // rank-1 update of the panel's remaining columns
-      const int nr = W - c - 1, ncw = k0 + kb - c - 1;
-      for (int e = t; e < nr * ncw; e += SW_NT) {
-        const int i = c + 1 + e % nr, jc = c + 1 + e / nr;
-        float2* cj = T + (int64_t)jc * W;
-        const float2 lf = c_mul(cw[i], cj[c]);
-        cj[i].x -= lf.x;
-        cj[i].y -= lf.y;
-      }
-      __syncthreads();
+struct SwLds {
+  float2 As[SW_NB * SW_TM];          // GEMM: A tile, As[q][i]
+  float2 Bs[SW_NB * (SW_TM + 1)];    // GEMM: B tile, Bs[q][j] (rows padded)
+  float2 Ls[SW_NB * SW_NB];          // triangular block, Ls[q][i] = T(k0 + i, k0 + q)
+  float rv[SW_NT / 64];
+  int ri[SW_NT / 64];
+  int mv_dst[2 * SW_NB], mv_src[2 * SW_NB];
+  int nmv;
+};
+
+// Columns [c0, c1) of a panel whose columns are [p0, p1): for every column the
+// pivot (largest |re| + |im| on or below the diagonal, the first such row), the
+// row swap across the panel's columns, the multipliers and the rank-1 update of
+// the columns up to c1 (row-owned; the updated next column's pivot search is
+// taken on the way).
+__device__ void sw_factor_cols(SwLds& s, float2* T, int W, int c0, int c1, int p0, int p1, int32_t* piv,
+                               int32_t* status) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  float best = -1.f;
+  int bi = W;
+  for (int i = c0 + t; i < W; i += SW_NT) {
+    const float2 v = T[(int64_t)c0 * W + i];
+    const float m = fabsf(v.x) + fabsf(v.y);
+    if (m > best) {
+      best = m;
+      bi = i;
     }
-    const int k1 = k0 + kb, n2 = W - k1;
-    if (n2 <= 0) break;
-    // ---- U12 = L11^-1 A12 (unit lower triangular), one column per thread
-    for (int jc = k1 + t; jc < W; jc += SW_NT) {
-      float2* cj = T + (int64_t)jc * W;
-      for (int r = 1; r < kb; ++r) {
-        float2 acc = cj[k0 + r];
-        for (int q = 0; q < r; ++q) {
-          const float2 lv = c_mul(T[(int64_t)(k0 + q) * W + k0 + r], cj[k0 + q]);
-          acc.x -= lv.x;
-          acc.y -= lv.y;
-        }
-        cj[k0 + r] = acc;
+  }
+  for (int c = c0; c < c1; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float v2 = __shfl_xor(best, o);
+      const int i2 = __shfl_xor(bi, o);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
       }
+    }
+    if (lane == 0) {
+      s.rv[wv] = best;
+      s.ri[wv] = bi;
     }
     __syncthreads();
-    // ---- A22 -= L21 U12 in 4 x 4 tiles
-    const int nt4 = (n2 + 3) / 4;
-    for (int e = t; e < nt4 * nt4; e += SW_NT) {
-      const int i0 = k1 + 4 * (e % nt4), j0 = k1 + 4 * (e / nt4);
+    float bv = s.rv[0];
+    int bix = s.ri[0];
+#pragma unroll
+    for (int w = 1; w < SW_NT / 64; ++w)
+      if (s.rv[w] > bv || (s.rv[w] == bv && s.ri[w] < bix)) {
+        bv = s.rv[w];
+        bix = s.ri[w];
+      }
+    const int p = bix < W ? bix : c;
+    if (t == 0) {
+      piv[c] = p;
+      if (!(bv > 0.f)) status[0] = 1;
+    }
+    if (p != c && t < p1 - p0) {
+      float2* col = T + (int64_t)(p0 + t) * W;
+      const float2 x = col[c];
+      col[c] = col[p];
+      col[p] = x;
+    }
+    __syncthreads();
+    const float2 d = T[(int64_t)c * W + c];
+    float2 u[SW_NS - 1];
+#pragma unroll
+    for (int jj = 0; jj < SW_NS - 1; ++jj)
+      u[jj] = (c + 1 + jj < c1) ? T[(int64_t)(c + 1 + jj) * W + c] : make_float2(0.f, 0.f);
+    best = -1.f;
+    bi = W;
+    float2* cc = T + (int64_t)c * W;
+    for (int i = c + 1 + t; i < W; i += SW_NT) {
+      const float2 l = c_div(cc[i], d);
+      cc[i] = l;
+#pragma unroll
+      for (int jj = 0; jj < SW_NS - 1; ++jj) {
+        if (c + 1 + jj < c1) {
+          float2* cj = T + (int64_t)(c + 1 + jj) * W;
+          float2 v = cj[i];
+          v.x -= l.x * u[jj].x - l.y * u[jj].y;
+          v.y -= l.x * u[jj].y + l.y * u[jj].x;
+          cj[i] = v;
+          if (jj == 0) {
+            const float m = fabsf(v.x) + fabsf(v.y);
+            if (m > best) {
+              best = m;
+              bi = i;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Diagonal block T[k0 .. k0 + nb)^2 into s.Ls, the NBT x NBT frame padded with
+// the identity (so that the padded unknowns stay zero in either solve).
+template <int NBT>
+__device__ void sw_stage_tri(SwLds& s, const float2* T, int W, int k0, int nb) {
+  __syncthreads();
+  for (int e = threadIdx.x; e < NBT * NBT; e += SW_NT) {
+    const int q = e / NBT, i = e % NBT;
+    float2 v = make_float2(i == q ? 1.f : 0.f, 0.f);
+    if (q < nb && i < nb) v = T[(int64_t)(k0 + q) * W + k0 + i];
+    s.Ls[q * SW_NB + i] = v;
+  }
+  __syncthreads();
+}
+
+// X = L^-1 X (L unit lower, from s.Ls) or X = U^-1 X (U upper, non-unit) for
+// ncols columns of nb <= NBT rows: element (q, j) of X at X[q rs + j cs]; one
+// column per thread, in blocks of 8 rows held in registers (the block solved,
+// then the rows after it (lower) or before it (upper) updated in memory).
+template <int NBT, bool UPPER>
+__device__ void sw_trsm(SwLds& s, int nb, float2* X, int64_t rs, int64_t cs, int ncols) {
+  constexpr int R = 8;
+  static_assert(NBT % R == 0, "blocks of 8 rows");
+  for (int j = threadIdx.x; j < ncols; j += SW_NT) {
+    float2* x = X + j * cs;
+#pragma unroll 1
+    for (int bb = 0; bb < NBT / R; ++bb) {
+      const int rb = UPPER ? (NBT / R - 1 - bb) * R : bb * R;
+      if (rb >= nb) continue;
+      float2 y[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) y[q] = rb + q < nb ? x[(rb + q) * rs] : make_float2(0.f, 0.f);
+      if (!UPPER) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int i = q + 1; i < R; ++i) {
+            const float2 l = s.Ls[(rb + q) * SW_NB + rb + i];
+            y[i].x -= l.x * y[q].x - l.y * y[q].y;
+            y[i].y -= l.x * y[q].y + l.y * y[q].x;
+          }
+      } else {
+#pragma unroll
+        for (int q = R - 1; q >= 0; --q) {
+          y[q] = c_div(y[q], s.Ls[(rb + q) * SW_NB + rb + q]);
+#pragma unroll
+          for (int i = 0; i < q; ++i) {
+            const float2 uv = s.Ls[(rb + q) * SW_NB + rb + i];
+            y[i].x -= uv.x * y[q].x - uv.y * y[q].y;
+            y[i].y -= uv.x * y[q].y + uv.y * y[q].x;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (rb + q < nb) x[(rb + q) * rs] = y[q];
+      const int i0 = UPPER ? 0 : rb + R, i1 = UPPER ? rb : nb;
+#pragma unroll 1
+      for (int i = i0; i < i1; ++i) {
+        float2 v = x[i * rs];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const float2 l = s.Ls[(rb + q) * SW_NB + i];
+          v.x -= l.x * y[q].x - l.y * y[q].y;
+          v.y -= l.x * y[q].y + l.y * y[q].x;
+        }
+        x[i * rs] = v;
+      }
+    }
+  }
+}
+
+// C -= A B for m x n, inner size kb <= SW_NB: A(i, q) = A[q lda + i], B(q, j)
+// at B[q + j ldb] (BQ) or B[q ldb + j], C(i, j) at C[i + j ldc] (CI) or
+// C[i ldc + j].  64 x 64 tiles staged through LDS, 4 x 4 outputs per thread.
+template <bool BQ, bool CI>
+__device__ void sw_gemm(SwLds& s, const float2* A, int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
+                        int m, int n, int kb) {
+  const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+  for (int tm = 0; tm < m; tm += SW_TM) {
+    __syncthreads();
+    for (int e = t; e < SW_TM * SW_NB; e += SW_NT) {
+      const int i = e % SW_TM, q = e / SW_TM;
+      s.As[q * SW_TM + i] = (q < kb && tm + i < m) ? A[q * lda + tm + i] : make_float2(0.f, 0.f);
+    }
+    for (int tn = 0; tn < n; tn += SW_TM) {
+      if (tn > 0) __syncthreads();
+      for (int e = t; e < SW_TM * SW_NB; e += SW_NT) {
+        int q, j;
+        if (BQ) {
+          q = e % SW_NB;
+          j = e / SW_NB;
+        } else {
+          j = e % SW_TM;
+          q = e / SW_TM;
+        }
+        float2 v = make_float2(0.f, 0.f);
+        if (q < kb && tn + j < n) v = BQ ? B[q + (int64_t)(tn + j) * ldb] : B[q * ldb + tn + j];
+        s.Bs[q * (SW_TM + 1) + j] = v;
+      }
+      __syncthreads();
       float2 acc[4][4];
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = make_float2(0.f, 0.f);
       for (int q = 0; q < kb; ++q) {
-        float2 l[4], u[4];
+        float2 a[4], b[4];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) l[x] = (i0 + x < W) ? T[(int64_t)(k0 + q) * W + i0 + x] : make_float2(0.f, 0.f);
+        for (int x = 0; x < 4; ++x) a[x] = s.As[q * SW_TM + 4 * ti + x];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) u[y] = (j0 + y < W) ? T[(int64_t)(j0 + y) * W + k0 + q] : make_float2(0.f, 0.f);
+        for (int y = 0; y < 4; ++y) b[y] = s.Bs[q * (SW_TM + 1) + 4 * tj + y];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y) {
-            acc[x][y].x += l[x].x * u[y].x - l[x].y * u[y].y;
-            acc[x][y].y += l[x].x * u[y].y + l[x].y * u[y].x;
+            acc[x][y].x += a[x].x * b[y].x - a[x].y * b[y].y;
+            acc[x][y].y += a[x].x * b[y].y + a[x].y * b[y].x;
           }
       }
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-          if (i0 + x < W && j0 + y < W) {
-            float2& v = T[(int64_t)(j0 + y) * W + i0 + x];
-            v.x -= acc[x][y].x;
-            v.y -= acc[x][y].y;
+        for (int y = 0; y < 4; ++y) {
+          const int i = tm + 4 * ti + x, j = tn + 4 * tj + y;
+          if (i < m && j < n) {
+            float2& c = CI ? C[i + (int64_t)j * ldc] : C[(int64_t)i * ldc + j];
+            c.x -= acc[x][y].x;
+            c.y -= acc[x][y].y;
           }
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// The net row moves of the swaps of rows k0 .. k0 + kb (in order; row k0 + c
+// with piv[k0 + c] >= k0 + c): rows involved in lanes of the first wave,
+// their final contents by simulation, the moves (dst <- src) into s.mv_*.
+__device__ void sw_build_moves(SwLds& s, const int32_t* piv, int k0, int kb) {
+  const int t = threadIdx.x, lane = t & 63;
+  if (t < 64) {
+    int pos = lane < kb ? k0 + lane : -1;
+    int np = kb;
+    for (int c = 0; c < kb; ++c) {
+      const int p = piv[k0 + c];
+      if (p >= k0 + kb && __ballot(pos == p) == 0) {
+        if (lane == np) pos = p;
+        ++np;
+      }
+    }
+    int content = lane;
+    for (int c = 0; c < kb; ++c) {
+      const int p = piv[k0 + c];
+      const int b = __ffsll((unsigned long long)__ballot(pos == p)) - 1;
+      const int ca = __shfl(content, c), cb = __shfl(content, b);
+      if (lane == c) content = cb;
+      if (lane == b) content = ca;
+    }
+    const int src = __shfl(pos, content);
+    const bool mv = lane < np && content != lane;
+    const unsigned long long mm = __ballot(mv);
+    if (mv) {
+      const int idx = __popcll(mm & ((1ull << lane) - 1ull));
+      s.mv_dst[idx] = pos;
+      s.mv_src[idx] = src;
+    }
+    if (lane == 0) s.nmv = __popcll(mm);
+  }
+  __syncthreads();
+}
+
+// The moves applied to ncols columns: element (row, col) at X[row rs + col cs];
+// four threads per column take 16 moves each, all loads before any store.
+__device__ void sw_apply_moves(SwLds& s, float2* X, int64_t rs, int64_t cs, int ncols) {
+  const int nmv = s.nmv;
+  if (nmv == 0) return;
+  const int t = threadIdx.x, chunk = t & 3;
+  for (int cb = 0; cb < ncols; cb += SW_NT / 4) {
+    const int col = cb + (t >> 2);
+    float2 v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int m = chunk + 4 * k;
+      if (m < nmv && col < ncols) v[k] = X[s.mv_src[m] * rs + col * cs];
     }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int m = chunk + 4 * k;
+      if (m < nmv && col < ncols) X[s.mv_dst[m] * rs + col * cs] = v[k];
+    }
   }
-  // ---- solves in place: Y[j S + r] = y_r[j], right-hand side e_{r0 + r}
+  __syncthreads();
+}
+
+// One workgroup per leaf: T = P^T L U (right-looking, panels of SW_NB columns
+// factored in sub-panels of SW_NS; a panel's swaps are applied to its own
+// columns at once and to the columns right of it before their update, never
+// to the columns left of it), then Y = U^-1 L^-1 P E for the unit vectors of
+// leaf a's RWGs, the swaps replayed panel by panel in the forward solve.
+__global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(3, 4))) void k_schwarz_lu(SchwarzBatch b, float2* __restrict__ out,
+                                                      const int64_t* __restrict__ zoff,
+                                                      const int32_t* __restrict__ leaf_ptr) {
+  __shared__ SwLds s;
+  const int a = b.first + blockIdx.x;
+  const int W = b.W[a], r0 = b.rowa[a];
+  const int S = leaf_ptr[a + 1] - leaf_ptr[a];
+  float2* T = b.ws + b.ws_off[a];
+  int32_t* piv = b.piv + b.piv_off[a];
+  for (int k0 = 0; k0 < W; k0 += SW_NB) {
+    const int kb = min(SW_NB, W - k0), k1 = k0 + kb;
+    for (int s0 = k0; s0 < k1; s0 += SW_NS) {
+      const int s1 = min(s0 + SW_NS, k1);
+      sw_factor_cols(s, T, W, s0, s1, k0, k1, piv, b.status);
+      if (s1 < k1) {
+        sw_stage_tri<SW_NS>(s, T, W, s0, s1 - s0);
+        sw_trsm<SW_NS, false>(s, s1 - s0, T + (int64_t)s1 * W + s0, 1, W, k1 - s1);
+        sw_gemm<true, true>(s, T + (int64_t)s0 * W + s1, W, T + (int64_t)s1 * W + s0, W, T + (int64_t)s1 * W + s1, W,
+                            W - s1, k1 - s1, s1 - s0);
+      }
+    }
+    if (k1 < W) {
+      sw_build_moves(s, piv, k0, kb);
+      sw_apply_moves(s, T + (int64_t)k1 * W, 1, W, W - k1);
+      sw_stage_tri<SW_NB>(s, T, W, k0, kb);
+      sw_trsm<SW_NB, false>(s, kb, T + (int64_t)k1 * W + k0, 1, W, W - k1);
+      sw_gemm<true, true>(s, T + (int64_t)k0 * W + k1, W, T + (int64_t)k1 * W + k0, W, T + (int64_t)k1 * W + k1, W,
+                          W - k1, W - k1, kb);
+    }
+  }
+  // Y[j S + r] = y_r[j]: the arena of leaf a (S x W column-major)
   float2* Y = out + zoff[a];
-  for (int e = t; e < S * W; e += SW_NT) {
+  for (int e = threadIdx.x; e < S * W; e += SW_NT) {
     const int r = e % S, j = e / S;
     Y[e] = make_float2(j == r0 + r ? 1.f : 0.f, 0.f);
   }
   __syncthreads();
-  for (int r = t; r < S; r += SW_NT) {
-    for (int k = 0; k < W; ++k) {                 // the row swaps in factorisation order
-      const int p = piv[k];
-      if (p != k) {
-        const float2 x = Y[(int64_t)k * S + r];
-        Y[(int64_t)k * S + r] = Y[(int64_t)p * S + r];
-        Y[(int64_t)p * S + r] = x;
-      }
-    }
-    for (int j = 0; j < W; ++j) {                 // unit lower L, column by column
-      const float2 yj = Y[(int64_t)j * S + r];
-      if (yj.x == 0.f && yj.y == 0.f) continue;
-      const float2* cl = T + (int64_t)j * W;
-      for (int i = j + 1; i < W; ++i) {
-        const float2 lv = c_mul(cl[i], yj);
-        Y[(int64_t)i * S + r].x -= lv.x;
-        Y[(int64_t)i * S + r].y -= lv.y;
-      }
-    }
-    for (int j = W - 1; j >= 0; --j) {            // upper U, from the last column
-      const float2* cu = T + (int64_t)j * W;
-      const float2 yj = c_div(Y[(int64_t)j * S + r], cu[j]);
-      Y[(int64_t)j * S + r] = yj;
-      for (int i = 0; i < j; ++i) {
-        const float2 uv = c_mul(cu[i], yj);
-        Y[(int64_t)i * S + r].x -= uv.x;
-        Y[(int64_t)i * S + r].y -= uv.y;
-      }
-    }
+  for (int k0 = 0; k0 < W; k0 += SW_NB) {
+    const int kb = min(SW_NB, W - k0), k1 = k0 + kb;
+    sw_build_moves(s, piv, k0, kb);
+    sw_apply_moves(s, Y, S, 1, S);
+    sw_stage_tri<SW_NB>(s, T, W, k0, kb);
+    sw_trsm<SW_NB, false>(s, kb, Y + (int64_t)k0 * S, S, 1, S);
+    if (k1 < W)
+      sw_gemm<false, false>(s, T + (int64_t)k0 * W + k1, W, Y + (int64_t)k0 * S, S, Y + (int64_t)k1 * S, S, W - k1, S, kb);
+  }
+  for (int k0 = (W - 1) / SW_NB * SW_NB; k0 >= 0; k0 -= SW_NB) {
+    const int kb = min(SW_NB, W - k0);
+    sw_stage_tri<SW_NB>(s, T, W, k0, kb);
+    sw_trsm<SW_NB, true>(s, kb, Y + (int64_t)k0 * S, S, 1, S);
+    if (k0 > 0) sw_gemm<false, false>(s, T + (int64_t)k0 * W, W, Y + (int64_t)k0 * S, S, Y, S, k0, S, kb);
   }
 }
 
