@@ -33,6 +33,8 @@ constexpr int SW_TM = 64;      // GEMM tile (rows and columns)
 constexpr int SW_MAXN = SCHWARZ_MAXN;
 constexpr int SW_TILE = 32;    // gather transpose tile
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -197,17 +199,18 @@ __device__ void sw_stage_tri(SwLds& s, const float2* T, int W, int k0, int nb) {
 
 // X = L^-1 X (L unit lower, from s.Ls) or X = U^-1 X (U upper, non-unit) for
 // ncols columns of nb <= NBT rows: element (q, j) of X at X[q rs + j cs]; one
-// column per thread, in blocks of 8 rows held in registers (the block solved,
-// then the rows after it (lower) or before it (upper) updated in memory).
+// column per thread, in blocks of 8 rows: a block is solved in registers,
+// then every later (lower) or earlier (upper) block of the column is loaded
+// whole, updated and stored.
 template <int NBT, bool UPPER>
 __device__ void sw_trsm(SwLds& s, int nb, float2* X, int64_t rs, int64_t cs, int ncols) {
-  constexpr int R = 8;
+  constexpr int R = 8, NR = NBT / R;
   static_assert(NBT % R == 0, "blocks of 8 rows");
   for (int j = threadIdx.x; j < ncols; j += SW_NT) {
     float2* x = X + j * cs;
 #pragma unroll 1
-    for (int bb = 0; bb < NBT / R; ++bb) {
-      const int rb = UPPER ? (NBT / R - 1 - bb) * R : bb * R;
+    for (int bb = 0; bb < NR; ++bb) {
+      const int rb = UPPER ? (NR - 1 - bb) * R : bb * R;
       if (rb >= nb) continue;
       float2 y[R];
 #pragma unroll
@@ -236,81 +239,127 @@ __device__ void sw_trsm(SwLds& s, int nb, float2* X, int64_t rs, int64_t cs, int
 #pragma unroll
       for (int q = 0; q < R; ++q)
         if (rb + q < nb) x[(rb + q) * rs] = y[q];
-      const int i0 = UPPER ? 0 : rb + R, i1 = UPPER ? rb : nb;
+      const int ib0 = UPPER ? 0 : rb + R, ib1 = UPPER ? rb : nb;
 #pragma unroll 1
-      for (int i = i0; i < i1; ++i) {
-        float2 v = x[i * rs];
+      for (int ib = ib0; ib < ib1; ib += R) {
+        float2 z[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const float2 l = s.Ls[(rb + q) * SW_NB + i];
-          v.x -= l.x * y[q].x - l.y * y[q].y;
-          v.y -= l.x * y[q].y + l.y * y[q].x;
-        }
-        x[i * rs] = v;
+        for (int i = 0; i < R; ++i) z[i] = ib + i < ib1 ? x[(ib + i) * rs] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const float2 l = s.Ls[(rb + q) * SW_NB + ib + i];
+            z[i].x -= l.x * y[q].x - l.y * y[q].y;
+            z[i].y -= l.x * y[q].y + l.y * y[q].x;
+          }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (ib + i < ib1) x[(ib + i) * rs] = z[i];
       }
     }
   }
 }
 
-// C -= A B for m x n, inner size kb <= SW_NB: A(i, q) = A[q lda + i], B(q, j)
+// C -= A B for m x n, inner size kb <= SW_NB (32-bit element offsets: every
+// operand lies inside one leaf's matrix or arena): A(i, q) = A[q lda + i], B(q, j)
 // at B[q + j ldb] (BQ) or B[q ldb + j], C(i, j) at C[i + j ldc] (CI) or
-// C[i ldc + j].  64 x 64 tiles staged through LDS, 4 x 4 outputs per thread.
+// C[i ldc + j].  64 x 64 tiles with A and B staged through LDS; each wave
+// takes a 32 x 32 quarter as 2 x 2 FP32 matrix-core tiles of 16 x 16
+// (v_mfma_f32_16x16x4f32, four real products per complex product).  With a
+// column-major C the transposed product C^T -= B^T A^T is formed, so that the
+// 16 consecutive output columns of an instruction are consecutive rows of C.
 template <bool BQ, bool CI>
-__device__ void sw_gemm(SwLds& s, const float2* A, int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
-                        int m, int n, int kb) {
-  const int t = threadIdx.x, ti = t % 16, tj = t / 16;
+__device__ void sw_gemm(SwLds& s, const float2* A, int lda, const float2* B, int ldb, float2* C, int ldc, int m,
+                        int n, int kb) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32, l16 = lane & 15, lq = lane >> 4;
   for (int tm = 0; tm < m; tm += SW_TM) {
     __syncthreads();
     for (int e = t; e < SW_TM * SW_NB; e += SW_NT) {
       const int i = e % SW_TM, q = e / SW_TM;
       s.As[q * SW_TM + i] = (q < kb && tm + i < m) ? A[q * lda + tm + i] : make_float2(0.f, 0.f);
     }
+    // B tiles go through registers: the next tile's loads, and this tile's C
+    // values, are in flight during the matrix-core products
+    constexpr int NBE = SW_TM * SW_NB / SW_NT;
+    float2 rb[NBE];
+    auto load_b = [&](int tn) {
+#pragma unroll
+      for (int k = 0; k < NBE; ++k) {
+        const int e = t + k * SW_NT;
+        const int q = BQ ? e % SW_NB : e / SW_TM, j = BQ ? e / SW_NB : e % SW_TM;
+        rb[k] = make_float2(0.f, 0.f);
+        if (q < kb && tn + j < n) rb[k] = BQ ? B[q + (tn + j) * ldb] : B[q * ldb + tn + j];
+      }
+    };
+    load_b(0);
     for (int tn = 0; tn < n; tn += SW_TM) {
       if (tn > 0) __syncthreads();
-      for (int e = t; e < SW_TM * SW_NB; e += SW_NT) {
-        int q, j;
-        if (BQ) {
-          q = e % SW_NB;
-          j = e / SW_NB;
-        } else {
-          j = e % SW_TM;
-          q = e / SW_TM;
-        }
-        float2 v = make_float2(0.f, 0.f);
-        if (q < kb && tn + j < n) v = BQ ? B[q + (int64_t)(tn + j) * ldb] : B[q * ldb + tn + j];
-        s.Bs[q * (SW_TM + 1) + j] = v;
+#pragma unroll
+      for (int k = 0; k < NBE; ++k) {
+        const int e = t + k * SW_NT;
+        const int q = BQ ? e % SW_NB : e / SW_TM, j = BQ ? e / SW_NB : e % SW_TM;
+        s.Bs[q * (SW_TM + 1) + j] = rb[k];
       }
       __syncthreads();
-      float2 acc[4][4];
+      if (tn + SW_TM < n) load_b(tn + SW_TM);
+      // accumulator element e of tile (u, v): matrix-core row 16 u + 4 lq + e,
+      // column 16 v + l16
+      float2 cv[2][2][4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = make_float2(0.f, 0.f);
-      for (int q = 0; q < kb; ++q) {
-        float2 a[4], b[4];
+        for (int v = 0; v < 2; ++v)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) a[x] = s.As[q * SW_TM + 4 * ti + x];
+          for (int e = 0; e < 4; ++e) {
+            const int i = CI ? tm + wr + 16 * v + l16 : tm + wr + 16 * u + 4 * lq + e;
+            const int j = CI ? tn + wc + 16 * u + 4 * lq + e : tn + wc + 16 * v + l16;
+            cv[u][v][e] = make_float2(0.f, 0.f);
+            if (i < m && j < n) cv[u][v][e] = CI ? C[i + j * ldc] : C[i * ldc + j];
+          }
+      floatx4 re[2][2], im[2][2];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) b[y] = s.Bs[q * (SW_TM + 1) + 4 * tj + y];
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int v = 0; v < 2; ++v) {
+          re[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+          im[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll 2
+      for (int kk = 0; kk < kb; kk += 4) {
+        const int q = kk + lq;
+        float2 x[2], y[2];
 #pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            acc[x][y].x += a[x].x * b[y].x - a[x].y * b[y].y;
-            acc[x][y].y += a[x].x * b[y].y + a[x].y * b[y].x;
+        for (int u = 0; u < 2; ++u) {
+          const float2 av = s.As[q * SW_TM + wr + 16 * u + l16];
+          const float2 bv = s.Bs[q * (SW_TM + 1) + wc + 16 * u + l16];
+          x[u] = CI ? bv : av;
+          y[u] = CI ? av : bv;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            re[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].x, y[v].x, re[u][v], 0, 0, 0);
+            re[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x[u].y, y[v].y, re[u][v], 0, 0, 0);
+            im[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].x, y[v].y, im[u][v], 0, 0, 0);
+            im[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].y, y[v].x, im[u][v], 0, 0, 0);
           }
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int i = tm + 4 * ti + x, j = tn + 4 * tj + y;
-          if (i < m && j < n) {
-            float2& c = CI ? C[i + (int64_t)j * ldc] : C[(int64_t)i * ldc + j];
-            c.x -= acc[x][y].x;
-            c.y -= acc[x][y].y;
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = CI ? tm + wr + 16 * v + l16 : tm + wr + 16 * u + 4 * lq + e;
+            const int j = CI ? tn + wc + 16 * u + 4 * lq + e : tn + wc + 16 * v + l16;
+            if (i < m && j < n) {
+              float2& c = CI ? C[i + j * ldc] : C[i * ldc + j];
+              c = make_float2(cv[u][v][e].x - re[u][v][e], cv[u][v][e].y - im[u][v][e]);
+            }
           }
-        }
     }
   }
   __syncthreads();
@@ -381,7 +430,7 @@ __device__ void sw_apply_moves(SwLds& s, float2* X, int64_t rs, int64_t cs, int 
 // columns at once and to the columns right of it before their update, never
 // to the columns left of it), then Y = U^-1 L^-1 P E for the unit vectors of
 // leaf a's RWGs, the swaps replayed panel by panel in the forward solve.
-__global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(3, 4))) void k_schwarz_lu(SchwarzBatch b, float2* __restrict__ out,
+__global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_schwarz_lu(SchwarzBatch b, float2* __restrict__ out,
                                                       const int64_t* __restrict__ zoff,
                                                       const int32_t* __restrict__ leaf_ptr) {
   __shared__ SwLds s;
