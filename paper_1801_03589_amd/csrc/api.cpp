@@ -885,8 +885,9 @@ struct DevTmp {
 
 // Schwarz preconditioner of a complex64 operator assembled on the device
 // (precond_dev.hip): per-leaf tables of the near lists on the host, then the
-// matrices Z_N^T gathered from the near blocks, factored and solved in batches
-// of leaves whose matrices fit a workspace of at most 8 GiB.  Returns false
+// matrices Z_N^T gathered from the device's near blocks (reciprocity half
+// storage, the form the one-right-hand-side product applies), factored and
+// solved in batches of leaves whose matrices fit a workspace of at most 8 GiB.  Returns false
 // (nothing built) when a near list holds more than 27 leaves.
 static bool schwarz_device(nesa_op* op) {
   const nesa::Tree& t = *op->tree;
@@ -898,6 +899,22 @@ static bool schwarz_device(nesa_op* op) {
   std::vector<int32_t> na(nleaf), W(nleaf), rowa(nleaf, -1), nb((size_t)nleaf * MX, 0),
       off((size_t)nleaf * (MX + 1), 0), colpos((size_t)nleaf * MX * MX, -1);
   auto size_of = [&](int64_t b) { return (int32_t)(t.leaf_ptr[b + 1] - t.leaf_ptr[b]); };
+  // npos[q]: first column of near-list entry q inside its leaf's full block
+  std::vector<int32_t> npos(t.near_idx.size());
+  nesa::parallel_for(nleaf, [&](int64_t x) {
+    int32_t c = 0;
+    for (int64_t q = t.near_ptr[x]; q < t.near_ptr[x + 1]; ++q) {
+      npos[q] = c;
+      c += size_of(t.near_idx[q]);
+    }
+  });
+  // entry of leaf y in leaf x's (sorted) near list, -1 if absent
+  auto entry = [&](int64_t x, int64_t y) -> int64_t {
+    const int64_t* lo = t.near_idx.data() + t.near_ptr[x];
+    const int64_t* hi = t.near_idx.data() + t.near_ptr[x + 1];
+    const int64_t* it = std::lower_bound(lo, hi, y);
+    return (it != hi && *it == y) ? it - t.near_idx.data() : -1;
+  };
   nesa::parallel_for(nleaf, [&](int64_t a) {
     const int n = (int)(t.near_ptr[a + 1] - t.near_ptr[a]);
     int32_t* nba = &nb[(size_t)a * MX];
@@ -909,15 +926,12 @@ static bool schwarz_device(nesa_op* op) {
     }
     na[a] = n;
     W[a] = offa[n];
-    for (int jb = 0; jb < n; ++jb) {
-      int32_t cb = 0;
-      for (int64_t q = t.near_ptr[nba[jb]]; q < t.near_ptr[nba[jb] + 1]; ++q) {
-        const int64_t c = t.near_idx[q];
-        for (int ib = 0; ib < n; ++ib)
-          if (nba[ib] == c) colpos[(size_t)a * MX * MX + jb * MX + ib] = cb;
-        cb += size_of(c);
+    for (int jb = 0; jb < n; ++jb)
+      for (int ib = 0; ib < n; ++ib) {
+        const int64_t x = std::min(nba[jb], nba[ib]), y = std::max(nba[jb], nba[ib]);
+        const int64_t qy = entry(x, y), qx = entry(x, x);
+        if (qy >= 0 && qx >= 0) colpos[(size_t)a * MX * MX + jb * MX + ib] = npos[qy] - npos[qx];
       }
-    }
   });
   for (int64_t a = 0; a < nleaf; ++a)
     if (rowa[a] < 0) throw Error(NESA_EINVAL, "a leaf is missing from its own near list");
@@ -947,25 +961,7 @@ static bool schwarz_device(nesa_op* op) {
     if (nleaf > first) batches.push_back({first, nleaf - first});
   }
   nesa::DevOp<float>& d = op->f;
-  DevTmp zt, t_na, t_w, t_rowa, t_nb, t_off, t_cp, t_wso, t_pvo, t_ws, t_piv, t_st;
-  const float2* Z = static_cast<const float2*>(d.Z);
-  if (!Z) {
-    // complex64 copy of the full near blocks (the op keeps only the
-    // reciprocity half when it serves one right-hand side)
-    float2* zd = zt.alloc<float2>(nr.z.size());
-    const int64_t chunk = int64_t(1) << 24;
-    std::vector<float2> buf((size_t)std::min<int64_t>(chunk, (int64_t)nr.z.size()));
-    for (int64_t s0 = 0; s0 < (int64_t)nr.z.size(); s0 += chunk) {
-      const int64_t cnt = std::min<int64_t>(chunk, (int64_t)nr.z.size() - s0);
-      nesa::parallel_for((cnt + 65535) / 65536, [&](int64_t blk) {
-        const int64_t e1 = std::min<int64_t>(cnt, (blk + 1) * 65536);
-        for (int64_t e = blk * 65536; e < e1; ++e)
-          buf[e] = make_float2((float)nr.z[s0 + e].real(), (float)nr.z[s0 + e].imag());
-      });
-      hip_check(hipMemcpy(zd + s0, buf.data(), cnt * sizeof(float2), hipMemcpyHostToDevice), "hipMemcpy");
-    }
-    Z = zd;
-  }
+  DevTmp t_na, t_w, t_rowa, t_nb, t_off, t_cp, t_wso, t_pvo, t_ws, t_piv, t_st;
   nesa::SchwarzBatch b;
   b.na = t_na.put(na);
   b.W = t_w.put(W);
@@ -983,7 +979,7 @@ static bool schwarz_device(nesa_op* op) {
   for (const auto& bt : batches) {
     b.first = (int)bt.first;
     b.count = (int)bt.second;
-    nesa::launch_schwarz_batch(Z, d.zoff, d.leaf_ptr, b, out, nullptr);
+    nesa::launch_schwarz_batch(static_cast<const float2*>(d.Zh), d.zh_off, d.zoff, d.leaf_ptr, b, out, nullptr);
     hip_check(hipGetLastError(), "kernel launch");
   }
   int32_t status = 0;

@@ -14,8 +14,10 @@ constexpr int SCHWARZ_MAXN = 27;
 // Per-leaf tables (device, indexed by leaf) and one batch's work arrays.
 // For leaf a with near list N(a) = nb[0 .. na): off[i] is the first RWG of
 // nb[i] inside N(a) (off[na] = W), rowa the one of a itself, and colpos[j][i]
-// the first column of leaf nb[i] inside leaf nb[j]'s near block, -1 when
-// nb[i] is not near nb[j].
+// (-1 when nb[i] is not near nb[j]) the first column, inside the reciprocity
+// half block of leaf x = min(nb[i], nb[j]), of leaf y = max(nb[i], nb[j]) (the
+// half block of x holds Z_xz for its near leaves z >= x, S_x rows, columns in
+// near-list order from x's own).
 struct SchwarzBatch {
   int first = 0;                    // leaves [first, first + count)
   int count = 0;
@@ -33,10 +35,11 @@ struct SchwarzBatch {
 };
 
 // Builds, factors and solves one batch: out (the preconditioner's arena, the
-// layout of the near blocks: leaf a at zoff[a], S_a x W_a column-major) gets
-// the rows of Z_N^-1 of every leaf of the batch.  Z: the full near blocks
-// (complex64, same layout); leaf_ptr [nleaf + 1].
-void launch_schwarz_batch(const float2* Z, const int64_t* zoff, const int32_t* leaf_ptr, const SchwarzBatch& b,
-                          float2* out, hipStream_t st);
+// layout of the full near blocks: leaf a at zoff[a], S_a x W_a column-major)
+// gets the rows of Z_N^-1 of every leaf of the batch.  Zh: the near blocks in
+// reciprocity half storage (complex64, leaf x at zh_off[x]); leaf_ptr
+// [nleaf + 1].
+void launch_schwarz_batch(const float2* Zh, const int64_t* zh_off, const int64_t* zoff, const int32_t* leaf_ptr,
+                          const SchwarzBatch& b, float2* out, hipStream_t st);
 
 }  // namespace nesa

@@ -43,12 +43,17 @@ __device__ __forceinline__ float2 c_div(float2 a, float2 b) {
   return make_float2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-// T[j W + i] = Z_N[j][i]: row j of Z_N is RWG jr of leaf nb[jb], column i is
-// RWG ic of leaf nb[ib]; when nb[ib] is near nb[jb] the entry is element
-// (jr, colpos[jb][ib] + ic) of leaf nb[jb]'s near block (column-major, S_jb
-// rows), else zero.  Workgroup (pair p = jb * 27 + ib, leaf) moves that
-// S_jb x S_ib block in 32 x 32 tiles: read along jr, written along ic.
-__global__ __launch_bounds__(SW_NT) void k_schwarz_gather(const float2* __restrict__ Z, const int64_t* __restrict__ zoff,
+// T[j W + i] = Z_N[j][i]: row j of Z_N is RWG jr of leaf lb = nb[jb], column
+// i is RWG ic of leaf lc = nb[ib].  The near field is read from its
+// reciprocity half storage (leaf x keeps Z_xy for its near leaves y >= x,
+// S_x rows, columns in near-list order from its own on): for lc >= lb the
+// entry is element (jr, colpos + ic) of lb's half block, for lc < lb it is
+// element (ic, colpos + jr) of lc's (Z_{lb lc} = Z_{lc lb}^T); colpos < 0 when
+// the two leaves are not near each other (zero block).  Workgroup (pair
+// p = jb * 27 + ib, leaf) moves that S_lb x S_lc block; the first case goes
+// through an LDS transpose in 32 x 32 tiles (read along jr, written along ic).
+__global__ __launch_bounds__(SW_NT) void k_schwarz_gather(const float2* __restrict__ Zh,
+                                                          const int64_t* __restrict__ zh_off,
                                                           const int32_t* __restrict__ leaf_ptr, SchwarzBatch b) {
   __shared__ float2 tile[SW_TILE][SW_TILE + 1];
   const int a = b.first + blockIdx.y;
@@ -67,15 +72,21 @@ __global__ __launch_bounds__(SW_NT) void k_schwarz_gather(const float2* __restri
       for (int ic = tx; ic < Si; ic += SW_TILE) T[(int64_t)(j0 + jr) * W + i0 + ic] = make_float2(0.f, 0.f);
     return;
   }
-  const int lb = b.nb[(int64_t)a * SW_MAXN + jb];
-  const float2* Zb = Z + zoff[lb];
-  const int Sb = leaf_ptr[lb + 1] - leaf_ptr[lb];   // = Sj
+  const int lb = b.nb[(int64_t)a * SW_MAXN + jb], lc = b.nb[(int64_t)a * SW_MAXN + ib];
+  if (lc < lb) {
+    const float2* Zc = Zh + zh_off[lc];      // S_lc rows
+    for (int jr = ty; jr < Sj; jr += SW_NT / SW_TILE)
+      for (int ic = tx; ic < Si; ic += SW_TILE)
+        T[(int64_t)(j0 + jr) * W + i0 + ic] = Zc[(int64_t)(cp + jr) * Si + ic];
+    return;
+  }
+  const float2* Zb = Zh + zh_off[lb];        // S_lb = Sj rows
   for (int r0 = 0; r0 < Sj; r0 += SW_TILE)
     for (int c0 = 0; c0 < Si; c0 += SW_TILE) {
-      // load: tx along jr (contiguous in Z), ty along ic
+      // load: tx along jr (contiguous in the half block), ty along ic
       for (int y = ty; y < SW_TILE; y += SW_NT / SW_TILE) {
         const int jr = r0 + tx, ic = c0 + y;
-        tile[y][tx] = (jr < Sj && ic < Si) ? Zb[(int64_t)(cp + ic) * Sb + jr] : make_float2(0.f, 0.f);
+        tile[y][tx] = (jr < Sj && ic < Si) ? Zb[(int64_t)(cp + ic) * Sj + jr] : make_float2(0.f, 0.f);
       }
       __syncthreads();
       // store: tx along ic (contiguous in T), ty along jr
@@ -486,10 +497,10 @@ __global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
 
 }  // namespace
 
-void launch_schwarz_batch(const float2* Z, const int64_t* zoff, const int32_t* leaf_ptr, const SchwarzBatch& b,
-                          float2* out, hipStream_t st) {
+void launch_schwarz_batch(const float2* Zh, const int64_t* zh_off, const int64_t* zoff, const int32_t* leaf_ptr,
+                          const SchwarzBatch& b, float2* out, hipStream_t st) {
   if (b.count <= 0) return;
-  k_schwarz_gather<<<dim3(SW_MAXN * SW_MAXN, (unsigned)b.count), SW_NT, 0, st>>>(Z, zoff, leaf_ptr, b);
+  k_schwarz_gather<<<dim3(SW_MAXN * SW_MAXN, (unsigned)b.count), SW_NT, 0, st>>>(Zh, zh_off, leaf_ptr, b);
   k_schwarz_lu<<<(unsigned)b.count, SW_NT, 0, st>>>(b, out, zoff, leaf_ptr);
 }
 
