@@ -887,8 +887,9 @@ struct DevTmp {
 // (precond_dev.hip): per-leaf tables of the near lists on the host, then the
 // matrices Z_N^T gathered from the device's near blocks (reciprocity half
 // storage, the form the one-right-hand-side product applies), factored and
-// solved in batches of leaves whose matrices fit a workspace of at most 8 GiB.  Returns false
-// (nothing built) when a near list holds more than 27 leaves.
+// solved by persistent workgroups, each with a workspace for the largest
+// matrix (at most 32 GiB in all).  Returns false (nothing built) when a near
+// list holds more than 27 leaves or more than SCHWARZ_WMAX RWGs.
 static bool schwarz_device(nesa_op* op) {
   const nesa::Tree& t = *op->tree;
   const nesa::Near& nr = *op->near;
@@ -935,55 +936,43 @@ static bool schwarz_device(nesa_op* op) {
   });
   for (int64_t a = 0; a < nleaf; ++a)
     if (rowa[a] < 0) throw Error(NESA_EINVAL, "a leaf is missing from its own near list");
-  // batches: consecutive leaves, matrices within the workspace budget
+  // persistent workgroups, each with a workspace for the largest W; leaves
+  // taken largest first
+  int32_t wmax = 0;
+  for (int64_t a = 0; a < nleaf; ++a) wmax = std::max(wmax, W[a]);
+  if (wmax > nesa::SCHWARZ_WMAX) return false;
+  std::vector<int32_t> order(nleaf);
+  for (int64_t a = 0; a < nleaf; ++a) order[a] = (int32_t)a;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return W[x] > W[y]; });
   size_t free_b = 0, total_b = 0;
   hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-  const int64_t budget = std::max<int64_t>(std::min<int64_t>(int64_t(8) << 30, (int64_t)(free_b / 4)), 1 << 26);
-  std::vector<int64_t> ws_off(nleaf), piv_off(nleaf);
-  std::vector<std::pair<int64_t, int64_t>> batches;   // (first, count)
-  int64_t ws_max = 0, piv_max = 0;
-  {
-    int64_t first = 0, ws = 0, pv = 0;
-    for (int64_t a = 0; a < nleaf; ++a) {
-      const int64_t m = (int64_t)W[a] * W[a];
-      if (a > first && ((ws + m) * 8 > budget || a - first >= 65535)) {
-        batches.push_back({first, a - first});
-        first = a;
-        ws = pv = 0;
-      }
-      ws_off[a] = ws;
-      piv_off[a] = pv;
-      ws += m;
-      pv += W[a];
-      ws_max = std::max(ws_max, ws);
-      piv_max = std::max(piv_max, pv);
-    }
-    if (nleaf > first) batches.push_back({first, nleaf - first});
-  }
+  const int64_t slot_bytes = (int64_t)wmax * wmax * (int64_t)sizeof(float2);
+  const int64_t budget = std::min<int64_t>(int64_t(32) << 30, (int64_t)(free_b / 2));
+  int64_t slots = std::min<int64_t>(nesa::schwarz_slots(), nleaf);
+  slots = std::max<int64_t>(1, std::min<int64_t>(slots, budget / std::max<int64_t>(slot_bytes, 1)));
   nesa::DevOp<float>& d = op->f;
-  DevTmp t_na, t_w, t_rowa, t_nb, t_off, t_cp, t_wso, t_pvo, t_ws, t_piv, t_st;
-  nesa::SchwarzBatch b;
-  b.na = t_na.put(na);
-  b.W = t_w.put(W);
-  b.rowa = t_rowa.put(rowa);
-  b.nb = t_nb.put(nb);
-  b.off = t_off.put(off);
-  b.colpos = t_cp.put(colpos);
-  b.ws_off = t_wso.put(ws_off);
-  b.piv_off = t_pvo.put(piv_off);
-  b.ws = t_ws.alloc<float2>(ws_max);
-  b.piv = t_piv.alloc<int32_t>(piv_max);
-  b.status = t_st.alloc<int32_t>(1);
-  hip_check(hipMemset(b.status, 0, sizeof(int32_t)), "hipMemset");
+  DevTmp t_ord, t_cnt, t_na, t_w, t_rowa, t_nb, t_off, t_cp, t_ws, t_piv, t_st;
+  nesa::SchwarzWork w;
+  w.nleaf = (int)nleaf;
+  w.order = t_ord.put(order);
+  w.counter = t_cnt.alloc<int32_t>(1);
+  w.na = t_na.put(na);
+  w.W = t_w.put(W);
+  w.rowa = t_rowa.put(rowa);
+  w.nb = t_nb.put(nb);
+  w.off = t_off.put(off);
+  w.colpos = t_cp.put(colpos);
+  w.ws_stride = (int64_t)wmax * wmax;
+  w.ws = t_ws.alloc<float2>((size_t)(slots * w.ws_stride));
+  w.piv_stride = std::max<int32_t>(wmax, 1);
+  w.piv = t_piv.alloc<int32_t>((size_t)(slots * w.piv_stride));
+  w.status = t_st.alloc<int32_t>(1);
+  hip_check(hipMemset(w.status, 0, sizeof(int32_t)), "hipMemset");
   float2* out = static_cast<float2*>(dev_alloc(op, nr.z.size() * sizeof(float2)));
-  for (const auto& bt : batches) {
-    b.first = (int)bt.first;
-    b.count = (int)bt.second;
-    nesa::launch_schwarz_batch(static_cast<const float2*>(d.Zh), d.zh_off, d.zoff, d.leaf_ptr, b, out, nullptr);
-    hip_check(hipGetLastError(), "kernel launch");
-  }
+  nesa::launch_schwarz(static_cast<const float2*>(d.Zh), d.zh_off, d.zoff, d.leaf_ptr, w, (int)slots, out, nullptr);
+  hip_check(hipGetLastError(), "kernel launch");
   int32_t status = 0;
-  hip_check(hipMemcpy(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  hip_check(hipMemcpy(&status, w.status, sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
   if (status) throw Error(-1, "singular near-field matrix in the Schwarz preconditioner");
   op->schwarz = out;
   return true;

@@ -6,15 +6,14 @@
 // (S_a x W_a column-major, columns in near-list order).  Those rows are the
 // solutions y_r of T y_r = e_r with T = Z_N^T, one per RWG r of leaf a.
 //
-// Per batch of leaves: k_schwarz_gather builds every T (W x W column-major,
-// FP32 complex) from the near blocks, one workgroup per (leaf, pair of near
-// leaves), through an LDS transpose; k_schwarz_lu factors each T = P^T L U by
-// right-looking LU with partial pivoting (pivot = largest |re| + |im|, the
-// first such row; rows swapped across the whole matrix), one workgroup per
-// leaf, panels of SW_NB columns and rank-SW_NB trailing updates in 4 x 4
-// register tiles, then solves the S_a unit right-hand sides, one thread each,
-// in place in the preconditioner's arena (element (r, j) of leaf a's block is
-// y_r[j]; a step of all threads touches consecutive addresses).
+// Persistent workgroups (as many as fit the device at once) take the leaves,
+// largest first, from a counter.  For each the workgroup builds T (W x W
+// column-major, FP32 complex) from the near blocks in its own workspace,
+// factors T = P^T L U (right-looking LU with partial pivoting: pivot = the
+// largest |re| + |im| on or below the diagonal, the first such row; panels of
+// 32 columns factored in sub-panels of 8; complex updates on the FP32 matrix
+// cores) and solves T y_r = e_r for the S_a RWGs r of leaf a, in place in the
+// preconditioner's arena (element (r, j) of leaf a's block is y_r[j]).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +30,6 @@ constexpr int SW_NB = 32;      // panel width of the factorisation, block size o
 constexpr int SW_NS = 8;       // sub-panel width
 constexpr int SW_TM = 64;      // GEMM tile (rows and columns)
 constexpr int SW_MAXN = SCHWARZ_MAXN;
-constexpr int SW_TILE = 32;    // gather transpose tile
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -43,70 +41,73 @@ __device__ __forceinline__ float2 c_div(float2 a, float2 b) {
   return make_float2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
+struct SwLds {
+  union {
+    struct {
+      float2 As[SW_NB * SW_TM];          // GEMM: A tile, As[q][i]
+      float2 Bs[SW_NB * (SW_TM + 1)];    // GEMM: B tile, Bs[q][j] (rows padded)
+    };
+    struct {                             // gather
+      short seg[SCHWARZ_WMAX];           // near leaf (entry of N(a)) of every RWG of N(a)
+      int cps[SW_MAXN * SW_MAXN];
+      int nbs[SW_MAXN], offs[SW_MAXN + 1];
+      int64_t zho[SW_MAXN];
+    };
+  };
+  float2 Ls[SW_NB * SW_NB];          // triangular block, Ls[q][i] = T(k0 + i, k0 + q)
+  float rv[SW_NT / 64];
+  int ri[SW_NT / 64];
+  int mv_dst[2 * SW_NB], mv_src[2 * SW_NB];
+  int nmv;
+  int item;
+};
+
 // T[j W + i] = Z_N[j][i]: row j of Z_N is RWG jr of leaf lb = nb[jb], column
 // i is RWG ic of leaf lc = nb[ib].  The near field is read from its
 // reciprocity half storage (leaf x keeps Z_xy for its near leaves y >= x,
 // S_x rows, columns in near-list order from its own on): for lc >= lb the
 // entry is element (jr, colpos + ic) of lb's half block, for lc < lb it is
 // element (ic, colpos + jr) of lc's (Z_{lb lc} = Z_{lc lb}^T); colpos < 0 when
-// the two leaves are not near each other (zero block).  Workgroup (pair
-// p = jb * 27 + ib, leaf) moves that S_lb x S_lc block; the first case goes
-// through an LDS transpose in 32 x 32 tiles (read along jr, written along ic).
-__global__ __launch_bounds__(SW_NT) void k_schwarz_gather(const float2* __restrict__ Zh,
-                                                          const int64_t* __restrict__ zh_off,
-                                                          const int32_t* __restrict__ leaf_ptr, SchwarzBatch b) {
-  __shared__ float2 tile[SW_TILE][SW_TILE + 1];
-  const int a = b.first + blockIdx.y;
-  const int na = b.na[a];
-  const int jb = blockIdx.x / SW_MAXN, ib = blockIdx.x % SW_MAXN;
-  if (jb >= na || ib >= na) return;
-  const int W = b.W[a];
-  const int32_t* off = b.off + (int64_t)a * (SW_MAXN + 1);
-  const int cp = b.colpos[(int64_t)a * SW_MAXN * SW_MAXN + jb * SW_MAXN + ib];
-  const int j0 = off[jb], Sj = off[jb + 1] - j0;
-  const int i0 = off[ib], Si = off[ib + 1] - i0;
-  float2* T = b.ws + b.ws_off[a];
-  const int tx = threadIdx.x % SW_TILE, ty = threadIdx.x / SW_TILE;   // 32 x 8
-  if (cp < 0) {
-    for (int jr = ty; jr < Sj; jr += SW_NT / SW_TILE)
-      for (int ic = tx; ic < Si; ic += SW_TILE) T[(int64_t)(j0 + jr) * W + i0 + ic] = make_float2(0.f, 0.f);
-    return;
+// the two leaves are not near each other (zero block).  Column j of T at a
+// time, threads along i.
+__device__ void sw_gather(SwLds& s, const SchwarzWork& b, int a, float2* T, const float2* __restrict__ Zh,
+                          const int64_t* __restrict__ zh_off) {
+  const int t = threadIdx.x;
+  const int na = b.na[a], W = b.W[a];
+  __syncthreads();
+  for (int e = t; e < na * na; e += SW_NT)
+    s.cps[e] = b.colpos[(int64_t)a * SW_MAXN * SW_MAXN + (e / na) * SW_MAXN + e % na];
+  if (t < na) {
+    const int l = b.nb[(int64_t)a * SW_MAXN + t];
+    s.nbs[t] = l;
+    s.zho[t] = zh_off[l];
   }
-  const int lb = b.nb[(int64_t)a * SW_MAXN + jb], lc = b.nb[(int64_t)a * SW_MAXN + ib];
-  if (lc < lb) {
-    const float2* Zc = Zh + zh_off[lc];      // S_lc rows
-    for (int jr = ty; jr < Sj; jr += SW_NT / SW_TILE)
-      for (int ic = tx; ic < Si; ic += SW_TILE)
-        T[(int64_t)(j0 + jr) * W + i0 + ic] = Zc[(int64_t)(cp + jr) * Si + ic];
-    return;
+  if (t <= na) s.offs[t] = b.off[(int64_t)a * (SW_MAXN + 1) + t];
+  __syncthreads();
+  for (int i = t; i < W; i += SW_NT) {
+    int k = 0;
+    while (k + 1 < na && s.offs[k + 1] <= i) ++k;
+    s.seg[i] = (short)k;
   }
-  const float2* Zb = Zh + zh_off[lb];        // S_lb = Sj rows
-  for (int r0 = 0; r0 < Sj; r0 += SW_TILE)
-    for (int c0 = 0; c0 < Si; c0 += SW_TILE) {
-      // load: tx along jr (contiguous in the half block), ty along ic
-      for (int y = ty; y < SW_TILE; y += SW_NT / SW_TILE) {
-        const int jr = r0 + tx, ic = c0 + y;
-        tile[y][tx] = (jr < Sj && ic < Si) ? Zb[(int64_t)(cp + ic) * Sj + jr] : make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int j = 0; j < W; ++j) {
+    const int jb = s.seg[j], jr = j - s.offs[jb], Sj = s.offs[jb + 1] - s.offs[jb], lb = s.nbs[jb];
+    float2* col = T + (int64_t)j * W;
+    for (int i = t; i < W; i += SW_NT) {
+      const int ib = s.seg[i], cp = s.cps[jb * na + ib];
+      float2 v = make_float2(0.f, 0.f);
+      if (cp >= 0) {
+        const int ic = i - s.offs[ib];
+        if (s.nbs[ib] >= lb)
+          v = Zh[s.zho[jb] + (int64_t)(cp + ic) * Sj + jr];
+        else
+          v = Zh[s.zho[ib] + (int64_t)(cp + jr) * (s.offs[ib + 1] - s.offs[ib]) + ic];
       }
-      __syncthreads();
-      // store: tx along ic (contiguous in T), ty along jr
-      for (int y = ty; y < SW_TILE; y += SW_NT / SW_TILE) {
-        const int jr = r0 + y, ic = c0 + tx;
-        if (jr < Sj && ic < Si) T[(int64_t)(j0 + jr) * W + i0 + ic] = tile[tx][y];
-      }
-      __syncthreads();
+      col[i] = v;
     }
+  }
+  __syncthreads();
 }
-
-struct SwLds {
-  float2 As[SW_NB * SW_TM];          // GEMM: A tile, As[q][i]
-  float2 Bs[SW_NB * (SW_TM + 1)];    // GEMM: B tile, Bs[q][j] (rows padded)
-  float2 Ls[SW_NB * SW_NB];          // triangular block, Ls[q][i] = T(k0 + i, k0 + q)
-  float rv[SW_NT / 64];
-  int ri[SW_NT / 64];
-  int mv_dst[2 * SW_NB], mv_src[2 * SW_NB];
-  int nmv;
-};
 
 // Columns [c0, c1) of a panel whose columns are [p0, p1): for every column the
 // pivot (largest |re| + |im| on or below the diagonal, the first such row), the
@@ -436,20 +437,15 @@ __device__ void sw_apply_moves(SwLds& s, float2* X, int64_t rs, int64_t cs, int 
   __syncthreads();
 }
 
-// One workgroup per leaf: T = P^T L U (right-looking, panels of SW_NB columns
+// Leaf a by one workgroup: T = P^T L U (right-looking, panels of SW_NB columns
 // factored in sub-panels of SW_NS; a panel's swaps are applied to its own
 // columns at once and to the columns right of it before their update, never
 // to the columns left of it), then Y = U^-1 L^-1 P E for the unit vectors of
 // leaf a's RWGs, the swaps replayed panel by panel in the forward solve.
-__global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_schwarz_lu(SchwarzBatch b, float2* __restrict__ out,
-                                                      const int64_t* __restrict__ zoff,
-                                                      const int32_t* __restrict__ leaf_ptr) {
-  __shared__ SwLds s;
-  const int a = b.first + blockIdx.x;
+__device__ void sw_leaf(SwLds& s, const SchwarzWork& b, int a, float2* T, int32_t* piv, float2* __restrict__ out,
+                        const int64_t* __restrict__ zoff, const int32_t* __restrict__ leaf_ptr) {
   const int W = b.W[a], r0 = b.rowa[a];
   const int S = leaf_ptr[a + 1] - leaf_ptr[a];
-  float2* T = b.ws + b.ws_off[a];
-  int32_t* piv = b.piv + b.piv_off[a];
   for (int k0 = 0; k0 < W; k0 += SW_NB) {
     const int kb = min(SW_NB, W - k0), k1 = k0 + kb;
     for (int s0 = k0; s0 < k1; s0 += SW_NS) {
@@ -495,13 +491,41 @@ __global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) v
   }
 }
 
+// Persistent workgroups, each with its own W x W matrix and pivots, take the
+// leaves in order from the counter until none is left.
+__global__ __launch_bounds__(SW_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_schwarz(
+    SchwarzWork b, const float2* __restrict__ Zh, const int64_t* __restrict__ zh_off, float2* __restrict__ out,
+    const int64_t* __restrict__ zoff, const int32_t* __restrict__ leaf_ptr) {
+  __shared__ SwLds s;
+  float2* T = b.ws + (int64_t)blockIdx.x * b.ws_stride;
+  int32_t* piv = b.piv + (int64_t)blockIdx.x * b.piv_stride;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s.item = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int it = s.item;
+    if (it >= b.nleaf) break;
+    const int a = b.order[it];
+    sw_gather(s, b, a, T, Zh, zh_off);
+    sw_leaf(s, b, a, T, piv, out, zoff, leaf_ptr);
+  }
+}
+
 }  // namespace
 
-void launch_schwarz_batch(const float2* Zh, const int64_t* zh_off, const int64_t* zoff, const int32_t* leaf_ptr,
-                          const SchwarzBatch& b, float2* out, hipStream_t st) {
-  if (b.count <= 0) return;
-  k_schwarz_gather<<<dim3(SW_MAXN * SW_MAXN, (unsigned)b.count), SW_NT, 0, st>>>(Zh, zh_off, leaf_ptr, b);
-  k_schwarz_lu<<<(unsigned)b.count, SW_NT, 0, st>>>(b, out, zoff, leaf_ptr);
+int schwarz_slots() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_schwarz, SW_NT, 0) != hipSuccess) return 0;
+  return cus * per;
+}
+
+void launch_schwarz(const float2* Zh, const int64_t* zh_off, const int64_t* zoff, const int32_t* leaf_ptr,
+                    const SchwarzWork& w, int slots, float2* out, hipStream_t st) {
+  if (w.nleaf <= 0 || slots <= 0) return;
+  (void)hipMemsetAsync(w.counter, 0, sizeof(int32_t), st);
+  k_schwarz<<<(unsigned)slots, SW_NT, 0, st>>>(w, Zh, zh_off, out, zoff, leaf_ptr);
 }
 
 }  // namespace nesa
