@@ -59,7 +59,8 @@ struct SwLds {
   int ri[SW_NT / 64];
   int mv_dst[2 * SW_NB], mv_src[2 * SW_NB];
   int nmv;
-  int item;
+  int item;      // entry of the leaf order taken by the workgroup
+  int first;     // first step of the forward solve that touches a nonzero row
 };
 
 // T[j W + i] = Z_N[j][i]: row j of Z_N is RWG jr of leaf lb = nb[jb], column
@@ -473,8 +474,16 @@ __device__ void sw_leaf(SwLds& s, const SchwarzWork& b, int a, float2* T, int32_
     const int r = e % S, j = e / S;
     Y[e] = make_float2(j == r0 + r ? 1.f : 0.f, 0.f);
   }
+  // rows above r0 of P E are zero and stay so through every step c < r0 whose
+  // pivot row is above r0 too: the forward solve starts at the block of the
+  // first other step
+  if (threadIdx.x == 0) s.first = r0;
   __syncthreads();
-  for (int k0 = 0; k0 < W; k0 += SW_NB) {
+  for (int c = threadIdx.x; c < r0; c += SW_NT)
+    if (piv[c] >= r0) atomicMin(&s.first, c);
+  __syncthreads();
+  const int kfirst = s.first / SW_NB * SW_NB;
+  for (int k0 = kfirst; k0 < W; k0 += SW_NB) {
     const int kb = min(SW_NB, W - k0), k1 = k0 + kb;
     sw_build_moves(s, piv, k0, kb);
     sw_apply_moves(s, Y, S, 1, S);
