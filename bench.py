@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--only-learned-family", action="store_true",
                    help="run only the learned preconditioner on the aircraft family (held-out seed 999)")
     p.add_argument("--learned-bodies", type=int, default=8, help="training bodies of that line")
+    p.add_argument("--only-schwarz", action="store_true",
+                   help="time only the device setup of the Schwarz preconditioner on the bench sphere")
     return p.parse_args()
 
 
@@ -481,6 +483,34 @@ def batched_section(args, nesa, torch, tree, near, far, prec, dt, n, stream):
             "Munknowns_matvec_per_s": round(n * args.nrhs / (ms * 1e-3) / 1e6, 2)}
 
 
+def schwarz_section(args, nesa, torch):
+    """Device setup of the near-list Schwarz preconditioner of the bench sphere
+    (complex64, one right-hand side): per leaf a, the LU of the W_a x W_a
+    near-list matrix and S_a unit solves.  Algorithmic work: 8/3 W^3 real flops
+    per LU plus 8 W^2 S per leaf for the solves (complex FMA = 8 flops)."""
+    import synth
+    v, t = synth.icosphere(args.nu, args.radius)
+    tree = nesa.build_tree(v, t, 0.25)
+    near = nesa.assemble_near_device(tree)
+    far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
+    S, W = tree.leaf_sizes()
+    flops = float(np.sum(8.0 / 3.0 * W.astype(float) ** 3 + 8.0 * W.astype(float) ** 2 * S))
+    runs = []
+    for _ in range(2):
+        op = nesa.op_create(tree, near, far, nesa.C64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nesa.precond_setup(op, nesa.PRECOND_SCHWARZ)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+        del op
+    best = min(runs)
+    log("Schwarz setup on the device: %.3f s (%d leaves, W mean %.0f, max %d)" % (best, len(W), W.mean(), W.max()))
+    return {"leaves": int(len(W)), "W_mean": round(float(W.mean()), 1), "W_max": int(W.max()),
+            "setup_s": [round(x, 4) for x in runs], "algorithmic_tflop": round(flops / 1e12, 3),
+            "achieved_tflops": round(flops / best / 1e12, 2), "fp32_peak_frac": round(flops / best / PEAK_FP32, 4)}
+
+
 def aircraft_section(args, nesa, torch, stream):
     """Aircraft-like body (seed 3: 959,364 unknowns, 50-wavelength fuselage, two
     swept wings), leaf 0.25, far field from the 4-wavelength level (l0 = 4:
@@ -673,6 +703,9 @@ def main():
         return
     if args.only_aircraft:
         print(json.dumps({"aircraft": aircraft_section(args, nesa, torch, torch.cuda.current_stream())}))
+        return
+    if args.only_schwarz:
+        print(json.dumps({"schwarz_setup": schwarz_section(args, nesa, torch)}))
         return
     if args.only_learned_family:
         print(json.dumps({"learned_family": learned_family_section(args, nesa, torch, torch.cuda.current_stream())}))

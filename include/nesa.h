@@ -147,6 +147,10 @@ int nesa_tree_bodies(const nesa_tree* tree, int64_t* rwg_ptr, int nmax, int* nbo
 int nesa_tree_get_info(const nesa_tree* tree, nesa_tree_info* info);
 /* perm[i] = canonical RWG index of leaf-order position i (host [n_rwg]). */
 int nesa_tree_perm(const nesa_tree* tree, int64_t* perm);
+/* Per leaf a (leaf order, host [n_box[L - l0]] each, either nullable): S[a] =
+ * RWGs of leaf a, W[a] = RWGs of its near leaves (Sec. 3, the near field of
+ * Eq. 9: leaf a's near block is S[a] x W[a], sum S W = near_entries). */
+int nesa_tree_leaf_sizes(const nesa_tree* tree, int64_t* S, int64_t* W);
 void nesa_tree_free(nesa_tree* tree);
 
 /* Near-field Galerkin blocks Z_ab, b in the near list of leaf a (Sec. 2;

@@ -1689,6 +1689,24 @@ int nesa_tree_perm(const nesa_tree* tree, int64_t* perm) {
   });
 }
 
+int nesa_tree_leaf_sizes(const nesa_tree* tree, int64_t* S, int64_t* W) {
+  return guarded([&]() {
+    if (!tree) return fail(NESA_EINVAL, "null argument");
+    const nesa::Tree& t = *tree->t;
+    const int64_t nleaf = t.level(t.L).nbox;
+    for (int64_t a = 0; a < nleaf; ++a) {
+      if (S) S[a] = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
+      if (W) {
+        int64_t w = 0;
+        for (int64_t q = t.near_ptr[a]; q < t.near_ptr[a + 1]; ++q)
+          w += t.leaf_ptr[t.near_idx[q] + 1] - t.leaf_ptr[t.near_idx[q]];
+        W[a] = w;
+      }
+    }
+    return (int)NESA_OK;
+  });
+}
+
 void nesa_tree_free(nesa_tree* tree) { delete tree; }
 
 int nesa_assemble_near(const nesa_tree* tree, const nesa_em_params* em, nesa_near** out) {

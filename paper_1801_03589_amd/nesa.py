@@ -82,6 +82,7 @@ _SIGS = {
     "nesa_build_forest": (C.c_int, [C.c_int, _P, _P, _P, _P, C.POINTER(TreeParams), C.POINTER(_P)]),
     "nesa_tree_bodies": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_int)]),
     "nesa_tree_perm": (C.c_int, [_P, _P]),
+    "nesa_tree_leaf_sizes": (C.c_int, [_P, _P, _P]),
     "nesa_tree_free": (None, [_P]),
     "nesa_assemble_near": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
     "nesa_assemble_near_device": (C.c_int, [_P, C.POINTER(EmParams), C.POINTER(_P)]),
@@ -207,6 +208,14 @@ class Tree(_Handle):
         p = np.zeros(self.info()["n_rwg"], dtype=np.int64)
         _check(lib().nesa_tree_perm(self.h, _ptr(p)))
         return p
+
+    def leaf_sizes(self):
+        """(S, W) per leaf: RWGs of the leaf and of its near leaves."""
+        nleaf = self.info()["n_box"][-1]
+        S = np.zeros(nleaf, dtype=np.int64)
+        W = np.zeros(nleaf, dtype=np.int64)
+        _check(lib().nesa_tree_leaf_sizes(self.h, _ptr(S), _ptr(W)))
+        return S, W
 
 
 class Near(_Handle):

@@ -103,6 +103,11 @@ def test_half_storage_counts_match_oracle(nesa, sphere1, leaf):
     assert 2 * half - diag == full          # every off-diagonal block once
     assert (info["near_entries"], info["near_entries_half"], info["near_transposed"]) == (full, half, trans)
     assert half < 0.6 * full
+    # per-leaf sizes in leaf order: S_a and the RWGs W_a of a's near leaves
+    Sl, Wl = nesa.build_tree(v, t, leaf).leaf_sizes()
+    order = sorted(range(nleaf), key=lambda a: rank[a])
+    assert Sl.tolist() == [S[a] for a in order]
+    assert Wl.tolist() == [sum(S[b] for b in ot.near[a]) for a in order]
 
 
 def test_rhs_matches_oracle(nesa, sphere1, rwg1):
