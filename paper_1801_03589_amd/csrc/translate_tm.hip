@@ -469,14 +469,20 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
   static_assert(AQ % TM_NT == 0 && BQ % TM_NT == 0, "staging must split evenly");
   __shared__ uint4 lds[2 * (AQ + BQ)];
   const int64_t nitems = g.nbox * g.nct;
-  const int64_t item = tm_item(blockIdx.x, nitems);
+  // workgroup L (dispatch order) runs on XCD L % 8: each XCD takes a
+  // contiguous eighth of the items, and the row blocks of an item one after
+  // the other, so that they run side by side and read every source block of
+  // the item once from the XCD's L2; column tile major: neighbouring targets
+  // of one column tile, whose sources overlap, follow each other
+  const int nrb = (int)gridDim.y;
+  const int64_t lin = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  const int64_t per = (nitems + 7) / 8, seq = lin / 8;
+  const int64_t item = (lin % 8) * per + seq / nrb;
   if (item >= nitems) return;
-  // column tile major: the workgroups an XCD runs side by side take
-  // neighbouring targets of one column tile, whose sources overlap in its L2
   const int64_t a = item % g.nbox;
   const int c0 = (int)(item / g.nbox) * COLS;
   const int ncol = min(COLS, g.NC - c0);
-  const int r0 = blockIdx.y * ROWS;
+  const int r0 = (int)(seq % nrb) * ROWS;
   const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
   const int NC = g.NC, M = g.M, Kp = g.Kp, KC = g.Kp / 16;
   const size_t plane = (size_t)g.Mr * Kp;
