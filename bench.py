@@ -51,7 +51,7 @@ def parse():
                    help="time the product only (no GMRES, batched or CPU lines): the profiled command")
     p.add_argument("--counters", action="store_true",
                    help="run 5 products and a 512 MiB device copy for hardware-counter passes, then exit")
-    p.add_argument("--bodies", type=int, default=32,
+    p.add_argument("--bodies", type=int, default=256,
                    help="uneven bodies in the batched-forest line (256: the full batch; 0: skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only-model2d", action="store_true",
