@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnesa.so")
-SOURCES = ["tree.cpp", "assemble.cpp", "assemble_dev.hip", "precond.cpp", "precond_dev.hip", "api.cpp", "kernels.hip", "translate_tm.hip",
+SOURCES = ["tree.cpp", "assemble.cpp", "assemble_dev.hip", "precond.cpp", "precond_dev.hip", "api.cpp", "kernels.hip", "translate_tm.hip", "leaf_mfma.hip",
            "mlp.hip", "model2d.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

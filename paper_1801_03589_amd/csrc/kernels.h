@@ -172,6 +172,21 @@ void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStrea
 void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes,
                          hipStream_t st);
 
+// Leaf-level stages of products of LEAF_MFMA_MIN_R or more right-hand sides
+// (complex64) as per-leaf GEMMs on the FP32 matrix cores (leaf_mfma.hip): the
+// near field y = Z_near x (full blocks, zoff layout; y overwritten), the
+// radiation s_L = V^T x (s in the [box][4 R][Q] layout) and the reception
+// y += V (w o_L); 64 right-hand sides per workgroup.  w: the channel weights
+// (re, im of w_xyz, re, im of w_div).
+constexpr int LEAF_MFMA_MIN_R = 16;
+void launch_near_mfma(const float2* Z, const int64_t* zoff, const int32_t* leaf_ptr, const int32_t* near_ptr,
+                      const int32_t* near_idx, const float2* x, float2* y, int64_t nleaf, int R, int64_t n,
+                      hipStream_t st);
+void launch_radiate_mfma(const float2* V, const float2* x, const int32_t* leaf_ptr, float2* s, int64_t nleaf, int Q,
+                         int R, int64_t n, hipStream_t st);
+void launch_recv_mfma(const float2* V, const float2* o, const int32_t* leaf_ptr, float2* y, int64_t nleaf, int Q,
+                      int R, int64_t n, const double* w, hipStream_t st);
+
 // kernel kinds of the per-launch timing
 enum { K_RADIATE = 1, K_UP_GEMM, K_UP_REDUCE, K_UP_VALU, K_TRANS_GEMM, K_TRANS_REDUCE, K_TRANS_VALU,
        K_DOWN_GEMM, K_DOWN_VALU, K_NEAR_RECV, K_RECV };

@@ -1912,10 +1912,16 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                             d.near_ptr, d.near_idx, d.toff, xl, yl, static_cast<V2*>(d.tpart),
                                             d.nleaf, d.near_order);
     } else {
-      if constexpr (sizeof(T) == 4)
-        k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff,
-                                                                          d.leaf_ptr, d.near_ptr, d.near_idx, xl,
-                                                                          yl, R, d.n);
+      if constexpr (sizeof(T) == 4) {
+        if (R >= LEAF_MFMA_MIN_R)
+          launch_near_mfma(static_cast<const float2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr, d.near_idx,
+                           reinterpret_cast<const float2*>(xl), reinterpret_cast<float2*>(yl), d.nleaf, R, d.n,
+                           d.side);
+        else
+          k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, d.side>>>(static_cast<const V2*>(d.Z), d.zoff,
+                                                                            d.leaf_ptr, d.near_ptr, d.near_idx, xl,
+                                                                            yl, R, d.n);
+      }
     }
     hip_ok(hipEventRecord(d.ev_join, d.side));
   };
@@ -1980,9 +1986,14 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   if (R == 1) {
     k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr, s + LL.s_off, LL.Q);
   } else {
-    if constexpr (sizeof(T) == 4)
-      k_radiate_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr,
-                                                                       s + LL.s_off * R, LL.Q, R, d.n);
+    if constexpr (sizeof(T) == 4) {
+      if (R >= LEAF_MFMA_MIN_R)
+        launch_radiate_mfma(static_cast<const float2*>(d.V), reinterpret_cast<const float2*>(xl), d.leaf_ptr,
+                            reinterpret_cast<float2*>(s + LL.s_off * R), d.nleaf, LL.Q, R, d.n, st);
+      else
+        k_radiate_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V), xl,
+                                                                         d.leaf_ptr, s + LL.s_off * R, LL.Q, R, d.n);
+    }
   }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
   if (v2) split_of(LL, s + LL.s_off * R, st);
@@ -2078,10 +2089,15 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                     d.near_ptr, d.nh_ptr, d.tsrc,
                                                     static_cast<const V2*>(d.tpart), yl, LL.Q, (T)d.w[0],
                                                     (T)d.w[1], (T)d.w[2], (T)d.w[3]);
-    else
-      k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V),
-                                                                   o + LL.s_off * R, d.leaf_ptr, yl, LL.Q, R, d.n,
-                                                                   (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+    else if constexpr (sizeof(T) == 4) {
+      if (R >= LEAF_MFMA_MIN_R)
+        launch_recv_mfma(static_cast<const float2*>(d.V), reinterpret_cast<const float2*>(o + LL.s_off * R),
+                         d.leaf_ptr, reinterpret_cast<float2*>(yl), d.nleaf, LL.Q, R, d.n, d.w, st);
+      else
+        k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V),
+                                                                     o + LL.s_off * R, d.leaf_ptr, yl, LL.Q, R, d.n,
+                                                                     (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+    }
   } else if (R == 1) {
     k_near_half<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.Zh), d.zh_off, d.leaf_ptr, d.nh_ptr,
                                                     d.near_ptr, d.near_idx, d.toff, xl, yl,
@@ -2091,12 +2107,19 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                   (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
   } else {
     if constexpr (sizeof(T) == 4) {
-      k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,
-                                                                    d.leaf_ptr, d.near_ptr, d.near_idx, xl, yl, R,
-                                                                    d.n);
-      k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V), o + LL.s_off * R,
-                                                                   d.leaf_ptr, yl, LL.Q, R, d.n, (T)d.w[0],
-                                                                   (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+      if (R >= LEAF_MFMA_MIN_R) {
+        launch_near_mfma(static_cast<const float2*>(d.Z), d.zoff, d.leaf_ptr, d.near_ptr, d.near_idx,
+                         reinterpret_cast<const float2*>(xl), reinterpret_cast<float2*>(yl), d.nleaf, R, d.n, st);
+        launch_recv_mfma(static_cast<const float2*>(d.V), reinterpret_cast<const float2*>(o + LL.s_off * R),
+                         d.leaf_ptr, reinterpret_cast<float2*>(yl), d.nleaf, LL.Q, R, d.n, d.w, st);
+      } else {
+        k_near_multi<V2><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.Z), d.zoff,
+                                                                      d.leaf_ptr, d.near_ptr, d.near_idx, xl, yl,
+                                                                      R, d.n);
+        k_recv_multi<T><<<dim3((unsigned)d.nleaf, rblk), NT, 0, st>>>(static_cast<const V2*>(d.V),
+                                                                     o + LL.s_off * R, d.leaf_ptr, yl, LL.Q, R, d.n,
+                                                                     (T)d.w[0], (T)d.w[1], (T)d.w[2], (T)d.w[3]);
+      }
     }
   }
   if (tm) tm->mark(st, 5, L, overlap ? K_RECV : K_NEAR_RECV);
