@@ -147,6 +147,8 @@ struct TmArgs {
   int nct_cols = 256;                     // split form from TM2_MIN_COLS: columns per workgroup tile (256 or 128)
   const uint4* s6 = nullptr;              // split form, NC >= TM2_MIN_COLS: sources pre-split
                                           // [box][Kp/16][4][NC][16] bf16 (rows of 64, 256-column tiles)
+  int tm_rows = 64;                       // split form with s6: 128 for 128 x 128 workgroup tiles
+                                          // (nct_cols must then be 128)
 };
 // columns per box (4 nrhs) from which the split translations use the pre-split
 // sources and 64 x 256 workgroup tiles

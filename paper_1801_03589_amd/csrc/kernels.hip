@@ -1752,6 +1752,18 @@ static int tm_split_cols() {
   return c;
 }
 
+// rows per workgroup of the split target-major kernel for M output rows: 128
+// x 128 tiles when M > 64 (every source block serves twice the rows per read,
+// each translation row is read by two column tiles), 64 x 256 below;
+// NESA_TM_ROWS=64 keeps 64-row tiles everywhere
+static int tm_split_rows(int M) {
+  static const bool only64 = []() {
+    const char* e = std::getenv("NESA_TM_ROWS");
+    return e && std::atoi(e) == 64;
+  }();
+  return (!only64 && M > 64) ? 128 : 64;
+}
+
 static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st,
                          bool translation) {
   const TileList& tl = p.by_nrhs[nrhs];
@@ -1961,7 +1973,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
       if (v2) {
         g.s6 = static_cast<const uint4*>(s6v);
-        g.nct_cols = tm_split_cols();
+        g.tm_rows = tm_split_rows(M);
+        g.nct_cols = g.tm_rows == 128 ? 128 : tm_split_cols();
         g.nct = (NC + g.nct_cols - 1) / g.nct_cols;
       }
       launch_translate_tm(g, nrt, rblocks, ct, ss);

@@ -459,28 +459,32 @@ __device__ __forceinline__ tm_bf16x8 tm_neg(tm_bf16x8 v) {
   return __builtin_bit_cast(tm_bf16x8, u);
 }
 
-template <int COLS>
-__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS == 128 ? 3 : 2))) void k_translate_tm_split2(TmArgs g) {
-  constexpr int ROWS = 64, NP = 4;
+template <int ROWS, int COLS>
+__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS == 128 && ROWS == 64 ? 3 : 2))) void k_translate_tm_split2(TmArgs g) {
+  constexpr int NP = 4;
   constexpr int WC = COLS / 4;                                 // columns per wave (64 or 32)
   constexpr int CTW = WC / 32;                                 // 32-column tiles per wave
+  constexpr int RTW = ROWS / 32;                               // 32-row tiles per wave (every wave takes all rows)
   constexpr int AQ = NP * ROWS * 2, BQ = NP * COLS * 2;        // uint4 per buffer (8 bf16 each)
-  constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;            // 2 and 8 per thread
+  constexpr int NAT = AQ / TM_NT, NBT = BQ / TM_NT;
   static_assert(AQ % TM_NT == 0 && BQ % TM_NT == 0, "staging must split evenly");
+  static_assert(RTW * CTW <= 4, "at most four 32 x 32 accumulator tiles per wave");
   __shared__ uint4 lds[2 * (AQ + BQ)];
   const int64_t nitems = g.nbox * g.nct;
   // workgroup L (dispatch order) runs on XCD L % 8: each XCD takes a
   // contiguous eighth of the items, and the row blocks of an item one after
   // the other, so that they run side by side and read every source block of
-  // the item once from the XCD's L2; column tile major: neighbouring targets
-  // of one column tile, whose sources overlap, follow each other
+  // the item once from the XCD's L2.  64 x 256 tiles: column tile major
+  // (neighbouring targets of one column tile, whose sources overlap, follow each
+  // other); 128 x 128 tiles: target major (the two column tiles of a target,
+  // which read the same translation rows, follow each other)
   const int nrb = (int)gridDim.y;
   const int64_t lin = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
   const int64_t per = (nitems + 7) / 8, seq = lin / 8;
   const int64_t item = (lin % 8) * per + seq / nrb;
   if (item >= nitems) return;
-  const int64_t a = item % g.nbox;
-  const int c0 = (int)(item / g.nbox) * COLS;
+  const int64_t a = ROWS == 64 ? item % g.nbox : item / g.nct;
+  const int c0 = (int)(ROWS == 64 ? item / g.nbox : item % g.nct) * COLS;
   const int ncol = min(COLS, g.NC - c0);
   const int r0 = (int)(seq % nrb) * ROWS;
   const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
@@ -504,9 +508,9 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
     bok[i] = col < ncol;
     ob[i] = (pl * NC + min(col, ncol - 1)) * 2 + hf;
   }
-  tm_f32x16 cre[2][CTW], cim[2][CTW];
+  tm_f32x16 cre[RTW][CTW], cim[RTW][CTW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RTW; ++i)
 #pragma unroll
     for (int j = 0; j < CTW; ++j)
 #pragma unroll
@@ -536,9 +540,9 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
     const uint4* Ab = lds + buf * (AQ + BQ);
     const uint4* Bb = Ab + AQ;
     const int hf = lane / 32;
-    tm_bf16x8 av[2][NP];
+    tm_bf16x8 av[RTW][NP];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
       for (int pl = 0; pl < NP; ++pl)
         av[rt][pl] = __builtin_bit_cast(tm_bf16x8, Ab[(pl * ROWS + rt * 32 + lane % 32) * 2 + hf]);
@@ -550,7 +554,7 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
         bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * WC + ct * 32 + lane % 32) * 2 + hf]);
       const tm_bf16x8 nbih = tm_neg(bv[2]), nbil = tm_neg(bv[3]);
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
+      for (int rt = 0; rt < RTW; ++rt) {
         // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br, each real product hi hi + hi lo + lo hi
         cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[0], cre[rt][ct], 0, 0, 0);
         cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[2], cim[rt][ct], 0, 0, 0);
@@ -582,10 +586,11 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
       __syncthreads();
     }
   }
-  // output through LDS in passes of PC columns ([column][row], stride 66)
+  // output through LDS in passes of PC columns ([column][row], stride ROWS + 2)
   constexpr int RS = ROWS + 2;
-  constexpr int PC = (2 * (AQ + BQ) * 16 >= 128 * RS * 8) ? 128 : 64;    // columns per output pass
-  static_assert(2 * (AQ + BQ) * 16 >= PC * RS * 8, "LDS tile too small");
+  constexpr int LB = 2 * (AQ + BQ) * 16;                                  // LDS bytes
+  constexpr int PC = LB >= 128 * RS * 8 ? 128 : (LB >= 64 * RS * 8 ? 64 : 32);   // columns per output pass
+  static_assert(LB >= PC * RS * 8 && PC >= WC, "LDS tile too small");
   float2* otile = reinterpret_cast<float2*>(&lds[0]);
   const int mloc = min(ROWS, M - r0);
   float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
@@ -593,7 +598,7 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
     __syncthreads();
     if (w * WC >= p0 && w * WC < p0 + PC) {
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CTW; ++ct) {
           const int lc = w * WC - p0 + ct * 32 + lane % 32;
@@ -684,13 +689,18 @@ void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStrea
   const int64_t nitems = g.nbox * g.nct;
   if (nitems == 0) return;
   if (g.Asplit && g.s6) {
-    // 64 x 256 (or 64 x 128) workgroup tiles: nct counts those column tiles,
-    // rows in blocks of 64
+    // 64 x 256, 64 x 128 or 128 x 128 workgroup tiles: nct counts the column
+    // tiles; g.tm_rows = 128 selects the last
+    if (g.tm_rows == 128) {
+      dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 127) / 128));
+      k_translate_tm_split2<128, 128><<<grid2, TM_NT, 0, st>>>(g);
+      return;
+    }
     dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 63) / 64));
     if (g.nct_cols == 128)
-      k_translate_tm_split2<128><<<grid2, TM_NT, 0, st>>>(g);
+      k_translate_tm_split2<64, 128><<<grid2, TM_NT, 0, st>>>(g);
     else
-      k_translate_tm_split2<256><<<grid2, TM_NT, 0, st>>>(g);
+      k_translate_tm_split2<64, 256><<<grid2, TM_NT, 0, st>>>(g);
     return;
   }
   dim3 grid((unsigned)((nitems + 7) / 8 * 8), (unsigned)rblocks);
