@@ -477,6 +477,37 @@ def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
             assert err <= tol, (i, r, err)
 
 
+def test_forest_schwarz_device_setup(torch_dev, nesa, monkeypatch):
+    """Schwarz preconditioner of a forest of uneven bodies factored on the
+    device (near lists stay inside each body): its application against each
+    body's FP64 oracle, bounded by the host FP32 factorisation's error."""
+    torch = torch_dev
+    f = _forest_case(nesa)
+    ptr = f["ptr"]
+    perm = f["tree"].perm()
+    r = synth.complex_normal(ptr[-1], 52)
+
+    def apply():
+        op = nesa.op_create(f["tree"], f["near"], f["far"], nesa.C64)
+        rd = torch.from_numpy(r[perm]).to(torch.complex64).cuda()
+        zd = torch.empty_like(rd)
+        nesa.precond_apply(op, nesa.PRECOND_SCHWARZ, rd, zd)
+        torch.cuda.synchronize()
+        z = np.empty(ptr[-1], dtype=np.complex128)
+        z[perm] = zd.cpu().numpy()
+        return z
+
+    z_dev = apply()
+    monkeypatch.setenv("NESA_SCHWARZ_HOST", "1")
+    z_host = apply()
+    for i, ref in enumerate(f["refs"]):
+        zo = _schwarz_oracle(ref)(r[ptr[i]:ptr[i + 1]])
+        e_dev = np.linalg.norm(z_dev[ptr[i]:ptr[i + 1]] - zo) / np.linalg.norm(zo)
+        e_host = np.linalg.norm(z_host[ptr[i]:ptr[i + 1]] - zo) / np.linalg.norm(zo)
+        print("forest body %d (N=%d) Schwarz FP32: device %.2e, host %.2e" % (i, ref.m.n, e_dev, e_host))
+        assert e_dev <= max(3 * e_host, 1e-5), (i, e_dev, e_host)
+
+
 @pytest.mark.parametrize("family", ["chunked", "resident", "direct", "narrow", "gauss"])
 @pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
 def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, tmp_path, name, family):
