@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--nu", type=int, default=82, help="icosphere frequency (82: 201,720 unknowns)")
     p.add_argument("--radius", type=float, default=4.0)
-    p.add_argument("--precision", default="c64", choices=["c64", "c128", "split"])
+    p.add_argument("--precision", default="c64", choices=["c64", "c128", "split", "split_fp16"])
     p.add_argument("--nrhs", type=int, default=8, help="right-hand sides of the batched product line")
     p.add_argument("--gmres-iters", type=int, default=1500)
     p.add_argument("--only-product", action="store_true",
@@ -197,7 +197,7 @@ def split_section(args, nesa, torch, tree, near, far, n, stream, fp32_ms, fp32_b
     """The bench sphere with split-bf16x3 translations and transfers: product
     time at one and at `nrhs` right-hand sides next to the complex64 (FP32
     matrix-core) times of the same operator, and the split product's error
-    against the complex64 one."""
+    against the complex64 one; the same for the split with fp16 parts."""
     R = max(1, args.nrhs)
     ops = nesa.op_create(tree, near, far, nesa.C64_SPLIT, max_nrhs=R)
     x = torch.from_numpy(synth_rhs(n, 1)[0]).to(torch.complex64).cuda()
@@ -227,7 +227,26 @@ def split_section(args, nesa, torch, tree, near, far, n, stream, fp32_ms, fp32_b
     nesa.matvec(ops, x, y, stream=stream)
     torch.cuda.synchronize()
     out["rel_diff_vs_complex64"] = float(torch.linalg.norm(y - y32) / torch.linalg.norm(y32))
-    del op32
+    # the same products with fp16 parts (scaled operands, about 22 bits each)
+    oph = nesa.op_create(tree, near, far, nesa.C64_SPLIT_FP16, max_nrhs=R)
+    fp16 = {}
+    for name, xx, yy, rr, reps in (("1", x, y, 1, args.steps), (str(R), X, Y, R, max(3, args.steps // 4))):
+        for _ in range(3):
+            nesa.matvec(oph, xx, yy, rr, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            nesa.matvec(oph, xx, yy, rr, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fp16["ms_per_product_nrhs" + name] = round(e0.elapsed_time(e1) / reps, 4)
+    nesa.matvec(oph, x, y, stream=stream)
+    torch.cuda.synchronize()
+    fp16["rel_diff_vs_complex64"] = float(torch.linalg.norm(y - y32) / torch.linalg.norm(y32))
+    out["fp16_parts"] = fp16
+    del oph, op32
     # the R incidences of the batched GMRES line solved in lock step with the
     # split operator and the near-list Schwarz preconditioner (set up on the
     # device), to 1e-4 (compare with gmres.batched.plain_fp32.one_at_a_time)
@@ -736,7 +755,8 @@ def main():
     if args.only_learned_family:
         print(json.dumps({"learned_family": learned_family_section(args, nesa, torch, torch.cuda.current_stream())}))
         return
-    prec = {"c64": nesa.C64, "c128": nesa.C128, "split": nesa.C64_SPLIT}[args.precision]
+    prec = {"c64": nesa.C64, "c128": nesa.C128, "split": nesa.C64_SPLIT,
+            "split_fp16": nesa.C64_SPLIT_FP16}[args.precision]
     esize = 16 if prec == nesa.C128 else 8
     dt = torch.complex128 if prec == nesa.C128 else torch.complex64
     setup = {}
@@ -900,7 +920,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"c64": "complex64", "c128": "complex128", "split": "complex64+bf16x3"}[args.precision],
+        "dtype": {"c64": "complex64", "c128": "complex128", "split": "complex64+bf16x3",
+                  "split_fp16": "complex64+fp16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "pec_sphere_r%gl_icosphere%d_%drwg" % (args.radius, args.nu, n),
                    "n_unknowns": n, "nrhs": 1, "leaf_lambda": 0.25, "levels": [info["l0"], info["L"]],

@@ -54,9 +54,15 @@ typedef enum {
 typedef enum {
   NESA_C128 = 0,         /* complex FP64 storage and arithmetic */
   NESA_C64 = 1,          /* complex FP32 storage and arithmetic */
-  NESA_C64_SPLIT = 2     /* complex FP32 vectors; translation and aggregation
+  NESA_C64_SPLIT = 2,    /* complex FP32 vectors; translation and aggregation
                             contractions as split-bf16 (hi*hi + hi*lo + lo*hi)
                             matrix-core products with FP32 accumulation */
+  NESA_C64_SPLIT_FP16 = 3 /* as NESA_C64_SPLIT with fp16 parts (11-bit
+                            mantissas, about 22 bits per operand): each
+                            matrix family and each level's sources or
+                            potentials carry one power-of-two scale that puts
+                            their largest part below 2^14 (the sources' scale
+                            is found on the device in every product) */
 } nesa_precision;
 
 typedef struct nesa_tree nesa_tree;

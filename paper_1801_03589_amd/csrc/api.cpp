@@ -173,27 +173,66 @@ static float bf16_to_float(uint16_t h) {
   std::memcpy(&v, &u, 4);
   return v;
 }
-static void attach_split(nesa_op* op, nesa::GemmPlan& p, const std::vector<cd>& Acm, int ngroups) {
+static uint16_t f16_rne_host(float v) {
+  const _Float16 h = (_Float16)v;
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+static float f16_to_float(uint16_t u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+static bool is_split(int precision) { return precision == NESA_C64_SPLIT || precision == NESA_C64_SPLIT_FP16; }
+static int split_fmt(int precision) {
+  return precision == NESA_C64_SPLIT_FP16 ? nesa::SPLIT_FP16 : nesa::SPLIT_BF16;
+}
+// v = hi + lo in the 16-bit format (round to nearest even both times)
+static void split_host(float v, int fmt, uint16_t& hi, uint16_t& lo) {
+  if (fmt == nesa::SPLIT_FP16) {
+    hi = f16_rne_host(v);
+    lo = f16_rne_host(v - f16_to_float(hi));
+  } else {
+    hi = bf16_rne_host(v);
+    lo = bf16_rne_host(v - bf16_to_float(hi));
+  }
+}
+static void attach_split(nesa_op* op, nesa::GemmPlan& p, const std::vector<cd>& Acm, int ngroups, int fmt,
+                         const int* bexp) {
   const int Kp = (p.K + 31) / 32 * 32;
   const size_t plane = (size_t)p.Mr * Kp;
+  // fp16: one power-of-two scale for all groups (split_shift of the largest
+  // exponent of the FP32 parts)
+  int shift = 0;
+  if (fmt == nesa::SPLIT_FP16) {
+    int E = nesa::EXP_NONE;
+    for (const cd& v : Acm)
+      for (const float x : {(float)v.real(), (float)v.imag()})
+        if (x != 0.f) {
+          int ex;
+          std::frexp(x, &ex);
+          E = std::max(E, ex);
+        }
+    shift = nesa::split_shift(E);
+  }
   std::vector<uint16_t> As((size_t)ngroups * 6 * plane, 0);
   nesa::parallel_for(ngroups, [&](int64_t gi) {
     for (int k = 0; k < p.K; ++k)
       for (int m = 0; m < p.Mr; ++m) {
         const cd v = Acm[((size_t)gi * p.K + k) * p.Mr + m];
-        const float re = (float)v.real(), im = (float)v.imag(), sm = re + im;
-        const uint16_t rh = bf16_rne_host(re), ih = bf16_rne_host(im), sh = bf16_rne_host(sm);
+        const float re = std::ldexp((float)v.real(), shift), im = std::ldexp((float)v.imag(), shift);
         const size_t base = (size_t)gi * 6 * plane + (size_t)m * Kp + k;
-        As[base] = rh;
-        As[base + plane] = bf16_rne_host(re - bf16_to_float(rh));
-        As[base + 2 * plane] = ih;
-        As[base + 3 * plane] = bf16_rne_host(im - bf16_to_float(ih));
-        As[base + 4 * plane] = sh;
-        As[base + 5 * plane] = bf16_rne_host(sm - bf16_to_float(sh));
+        split_host(re, fmt, As[base], As[base + plane]);
+        split_host(im, fmt, As[base + 2 * plane], As[base + 3 * plane]);
+        split_host(re + im, fmt, As[base + 4 * plane], As[base + 5 * plane]);
       }
   });
   p.A_split = upload(op, As);
   p.Kp = Kp;
+  p.split_fmt = fmt;
+  p.a_exp = shift;
+  p.bexp = fmt == nesa::SPLIT_FP16 ? bexp : nullptr;
 }
 
 // Grouped pair lists of a GEMM plan (items in their given order inside a group);
@@ -618,6 +657,13 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   d.w[2] = 0.0;
   d.w[3] = fr.eta / fr.k;
   d.lev.resize(t.L - t.l0 + 1);
+  d.split_fmt = split_fmt(op->precision);
+  if (op->precision == NESA_C64_SPLIT_FP16)
+    d.bexp = static_cast<int*>(dev_alloc(op, (size_t)2 * (t.L - t.l0 + 1) * sizeof(int)));
+  // exponent slot of a level's sources (which 0) or potentials (which 1)
+  auto exp_slot = [&](int l, int which) -> const int* {
+    return d.bexp ? d.bexp + 2 * (l - t.l0) + which : nullptr;
+  };
   {
     // right-hand sides up to which the offset-major form (per-pair and
     // per-child partial results) runs: at most PAIR_CAP_MAX, and its partial
@@ -656,8 +702,8 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       offs.push_back(s % SW - SH);
     }
     const int Qr = sizeof(T) == 4 ? nesa::row_alloc(fl.Q) : fl.Q;
-    void* d_split = nullptr;   // split precision: bf16 planes of D made on the device
-    int d_split_kp = 0;
+    void* d_split = nullptr;   // split precision: 16-bit planes of D made on the device
+    int d_split_kp = 0, d_split_shift = 0;
     {
       std::vector<double> Eh(2 * fl.E.size());
       for (size_t i = 0; i < fl.E.size(); ++i) {
@@ -667,10 +713,11 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       const double* Ed = upload(op, Eh);
       const int32_t* offd = offs.empty() ? nullptr : upload(op, offs);
       const size_t cnt = (size_t)nused * fl.Q * Qr;
-      if (op->precision == NESA_C64_SPLIT) {
-        // FP64 on the device, then its complex64 copy and the bf16 planes of
+      if (is_split(op->precision)) {
+        // FP64 on the device, then its complex64 copy and the 16-bit planes of
         // the split products (no host round trip: the coarsest level of a
-        // long body holds gigabytes)
+        // long body holds gigabytes); fp16 planes hold D x 2^shift, with the
+        // shift from the largest exponent of the level's D
         dl.D = dev_alloc(op, std::max<size_t>(cnt, 1) * 2 * sizeof(T));
         d_split_kp = (fl.Q + 31) / 32 * 32;
         d_split = dev_alloc(op, std::max<size_t>((size_t)nused * 6 * Qr * d_split_kp, 1) * sizeof(uint16_t));
@@ -678,7 +725,16 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
           void* tmp = nullptr;
           hip_check(hipMalloc(&tmp, cnt * sizeof(cd)), "hipMalloc");
           nesa::launch_fill_translation(Ed, offd, nused, fl.Q, Qr, lv.side, fr.k, tmp, true, nullptr);
-          nesa::launch_split_planes(tmp, nused, fl.Q, Qr, d_split_kp, dl.D, d_split, nullptr);
+          if (d.bexp) {
+            int* e = static_cast<int*>(dev_alloc(op, sizeof(int)));
+            nesa::launch_exp_reset(e, 1, nullptr);
+            nesa::launch_absmax_exp(tmp, (int64_t)cnt, true, e, nullptr);
+            int E = 0;
+            hip_check(hipMemcpy(&E, e, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy");
+            d_split_shift = nesa::split_shift(E);
+          }
+          nesa::launch_split_planes(tmp, nused, fl.Q, Qr, d_split_kp, dl.D, d_split, d.split_fmt, d_split_shift,
+                                    nullptr);
           hip_check(hipGetLastError(), "kernel launch");
           hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
           hip_check(hipFree(tmp), "hipFree");
@@ -705,9 +761,12 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
       for (int64_t a = 0; a < lv.nbox; ++a)
         for (int64_t k = lv.il_ptr[a]; k < lv.il_ptr[a + 1]; ++k) reg[k] = (int8_t)(a * 8 / lv.nbox);
       dl.trans = make_plan(op, dl.D, (int64_t)fl.Q * Qr, fl.Q, fl.Q, Qr, nrt, 0, slot, nused, src, dst, reg);
-      if (op->precision == NESA_C64_SPLIT) {
+      if (is_split(op->precision)) {
         dl.trans.A_split = d_split;
         dl.trans.Kp = d_split_kp;
+        dl.trans.split_fmt = d.split_fmt;
+        dl.trans.a_exp = d_split_shift;
+        dl.trans.bexp = exp_slot(l, 0);
       }
       // per-pair outputs serve the offset-major form only (up to pair_cap)
       dl.pair_out = dev_alloc(op, (size_t)dl.npairs * 4 * d.pair_cap * fl.Q * 2 * sizeof(T));
@@ -715,7 +774,7 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     // split form with many right-hand sides: the level's sources (and, in the
     // potential transfer, its potentials) split into four bf16 planes
     // (2 bytes x 4 x Kp x 4 max_nrhs per box, Kp = Q rounded up to 32)
-    if (sizeof(T) == 4 && op->precision == NESA_C64_SPLIT && 4 * op->max_nrhs >= nesa::TM2_MIN_COLS)
+    if (sizeof(T) == 4 && is_split(op->precision) && 4 * op->max_nrhs >= nesa::TM2_MIN_COLS)
       dl.s6 = dev_alloc(op, (size_t)lv.nbox * ((fl.Q + 31) / 32 * 32) * 4 * 4 * op->max_nrhs * sizeof(uint16_t));
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
@@ -760,12 +819,12 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         }
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx,
                            reg);
-        if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.up, au, 8);
+        if (is_split(op->precision)) attach_split(op, dl.up, au, 8, d.split_fmt, exp_slot(l, 0));
         // per-child outputs serve the offset-major form only (up to pair_cap)
         dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * d.pair_cap * Qp * 2 * sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx,
                              reg);
-        if (op->precision == NESA_C64_SPLIT) attach_split(op, dl.down, ad, 8);
+        if (is_split(op->precision)) attach_split(op, dl.down, ad, 8, d.split_fmt, exp_slot(l - 1, 1));
         // pair lists of the target-major transfers: the children of every box
         // of level l-1 in increasing index (CSR), and the parent of every box
         const int64_t np = t.level(l - 1).nbox;
@@ -1797,7 +1856,7 @@ int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far*
                    nesa_op** out) {
   return guarded([&]() {
     if (!tree || !near || !far || !out) return fail(NESA_EINVAL, "null argument");
-    if (precision != NESA_C128 && precision != NESA_C64 && precision != NESA_C64_SPLIT)
+    if (precision != NESA_C128 && precision != NESA_C64 && !is_split(precision))
       return fail(NESA_EINVAL, "unknown precision");
     if (max_nrhs < 1) return fail(NESA_EINVAL, "max_nrhs must be >= 1");
     std::unique_ptr<nesa_op> op(new nesa_op());

@@ -25,11 +25,18 @@ struct TileList {
   int64_t* col_src = nullptr;     // [ntiles][64] source offsets
   int64_t* col_dst = nullptr;     // [ntiles][64] destination offsets
 };
+// 16-bit formats of the split products: bf16 (8-bit mantissa, FP32 range) or
+// fp16 (11-bit mantissa, 5-bit exponent; operands carry a power-of-two scale)
+enum SplitFmt { SPLIT_BF16 = 0, SPLIT_FP16 = 1 };
+
 struct GemmPlan {
   const void* A = nullptr;       // [groups][K][Mr] column-major, rows padded with zeros
-  const void* A_split = nullptr; // split precision: [groups][6 planes][Mr][Kp] bf16 (re hi, re lo, im hi, im lo,
+  const void* A_split = nullptr; // split precision: [groups][6 planes][Mr][Kp] 16-bit (re hi, re lo, im hi, im lo,
                                  // (re + im) hi, (re + im) lo)
   int Kp = 0;                    // K rounded up to 32
+  int split_fmt = SPLIT_BF16;    // format of A_split and of the split sources
+  int a_exp = 0;                 // fp16: A_split holds A x 2^a_exp
+  const int* bexp = nullptr;     // fp16: device slot of the sources' largest binary exponent (see k_absmax_exp)
   int64_t a_stride = 0;
   int M = 0, K = 0, Mr = 0;      // Mr = rows of A allocated (row_alloc), >= rblocks x nrt x 16
   int nrt = 1;                    // default row tiles of 16 per workgroup (1..8)
@@ -104,6 +111,8 @@ struct DevOp {
   int max_nrhs = 1;              // right-hand sides the work buffers hold
   int pair_cap = 1;              // offset-major up to this many right-hand sides, target-major above
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
+  int split_fmt = SPLIT_BF16;    // split form: 16-bit format
+  int* bexp = nullptr;           // fp16 split form: [2 x levels] largest exponents of s_l (2 (l - l0)) and o_l (+1)
   std::vector<DevLevel> lev;
 };
 
@@ -149,13 +158,34 @@ struct TmArgs {
                                           // [box][Kp/16][4][NC][16] bf16 (rows of 64, 256-column tiles)
   int tm_rows = 64;                       // split form with s6: 128 for 128 x 128 workgroup tiles
                                           // (nct_cols must then be 128)
+  int split_fmt = SPLIT_BF16;             // split form: 16-bit format of Asplit and s6
+  int a_exp = 0;                          // fp16: Asplit holds D x 2^a_exp
+  const int* bexp = nullptr;              // fp16: slot of the sources' largest exponent E (scaled by 2^split_shift(E))
 };
+// fp16 operand scale: a set of values whose largest magnitude m lies below 2^E
+// (E from frexp, or EXP_NONE when every value is zero) is multiplied by
+// 2^split_shift(E), which puts m below 2^14 (and the sum of a real and an
+// imaginary part below 2^15, inside fp16's range); clamped so that the factor
+// and its inverse stay finite in FP32.
+constexpr int EXP_NONE = -1000;
+__host__ __device__ inline int split_shift(int E) {
+  const int s = 14 - E;
+  return s < -120 ? -120 : (s > 120 ? 120 : s);
+}
 // columns per box (4 nrhs) from which the split translations use the pre-split
 // sources and 64 x 256 workgroup tiles
 constexpr int TM2_MIN_COLS = 128;
 // s6 = four bf16 planes (re hi, re lo, im hi, im lo) of the sources s
 // [nbox][NC][K] (layout of TmArgs::s6)
-void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, hipStream_t st);
+// (fp16: scaled by 2^split_shift(*bexp) first)
+void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, int fmt, const int* bexp,
+                          hipStream_t st);
+// *slot = max(*slot, largest binary exponent E (frexp) over the nonzero real
+// and imaginary parts of n complex values); slots start at EXP_NONE
+// (launch_exp_reset).  The maximum does not depend on the order of the
+// atomic updates.
+void launch_absmax_exp(const void* v, int64_t n, bool fp64, int* slot, hipStream_t st);
+void launch_exp_reset(int* slots, int n, hipStream_t st);
 // Products of up to DevOp::pair_cap right-hand sides run the translations and
 // transfers offset-major (grouped GEMMs sharing each matrix over many pairs,
 // partial results per pair or child summed in a fixed order); more right-hand
@@ -171,8 +201,9 @@ void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStrea
 // complex128 [ngroups][K][Mr] -> bf16 [ngroups][6][Mr][Kp] (re hi, re lo, im
 // hi, im lo, (re + im) hi, (re + im) lo; zero for k >= K) and, if D32 is not
 // null, its complex64 copy [ngroups][K][Mr].
-void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes,
-                         hipStream_t st);
+// fmt = SPLIT_FP16: the planes hold the fp16 split of A x 2^shift.
+void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes, int fmt,
+                         int shift, hipStream_t st);
 
 // Leaf-level stages of products of LEAF_MFMA_MIN_R or more right-hand sides
 // (complex64) as per-leaf GEMMs on the FP32 matrix cores (leaf_mfma.hip): the

@@ -16,6 +16,7 @@
 #include <cstdlib>
 
 #include "kernels.h"
+#include "split16.h"
 
 namespace nesa {
 
@@ -483,9 +484,10 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
   }
 }
 
-// Split-precision variant (complex64 vectors, bf16x3 products): every FP32
-// value v is split as hi = bf16(v), lo = bf16(v - hi); a real product is
-// hi*hi + hi*lo + lo*hi on 16x16x32 bf16 MFMAs with FP32 accumulation, and a
+// Split-precision variant (complex64 vectors, x3 products, split16.h): every
+// FP32 value v is split as hi = r(v), lo = r(v - hi) (bf16 or fp16); a real
+// product is hi*hi + hi*lo + lo*hi on 16x16x32 MFMAs of that format with FP32
+// accumulation, and a
 // complex product is four real ones (twelve MFMAs per k step: at one right-hand
 // side the kernel is bound by staging, not by the matrix cores, and three real
 // products would need two more planes of both operands).  A is pre-split into
@@ -494,21 +496,16 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 // [Mr][Kp] with k contiguous (Kp = K rounded up to 32, zero padded); B is split
 // in the kernel from the FP32 tile in LDS.  Fragment layout of the 16x16x32
 // instruction: lane l holds rows/columns l % 16 and k = 8 (l / 16) .. +7.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// fp16: the planes hold A x 2^a_exp, B is scaled by 2^split_shift(*bexp)
+// before its split, and the results by 2^-(a_exp + shift).
+typedef s16x8 bf16x8;
 
-__device__ __forceinline__ unsigned short bf16_rne(float v) {
-  const unsigned u = __float_as_uint(v);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ __forceinline__ void split_bf16(float v, unsigned short& hi, unsigned short& lo) {
-  hi = bf16_rne(v);
-  lo = bf16_rne(v - __uint_as_float((unsigned)hi << 16));
-}
-
-template <int NRT>
+template <int NRT, int F>
 __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, const unsigned short* __restrict__ As,
-                                                        int Kp) {
+                                                        int Kp, int a_exp, const int* __restrict__ bexp) {
   static_assert(TR_KC == 32, "one bf16 MFMA k-step per chunk");
+  const int bshift = split_src_shift<F>(bexp);
+  const int oexp = -(a_exp + bshift);
   __shared__ uint4 Al[4][NRT * 16][4];                        // [plane][row][8 k], split planes of A
   __shared__ float2 Bs[TR_COLS][TR_KC + 1];                   // [column][k] FP32 B, split in place
   __shared__ int64_t col_src[TR_COLS];
@@ -584,12 +581,13 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
       const float2* bcol = &Bs[w * 16 + lane % 16][8 * (lane / 16)];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float2 v = bcol[j];
+        float2 v = bcol[j];
+        if (F == SPLIT_FP16) v = make_float2(ldexpf(v.x, bshift), ldexpf(v.y, bshift));
         unsigned short h, l;
-        split_bf16(v.x, h, l);
+        split16<F>(v.x, h, l);
         brh[j] = __builtin_bit_cast(__bf16, h);
         brl[j] = __builtin_bit_cast(__bf16, l);
-        split_bf16(v.y, h, l);
+        split16<F>(v.y, h, l);
         bih[j] = __builtin_bit_cast(__bf16, h);
         bil[j] = __builtin_bit_cast(__bf16, l);
         nbih[j] = __builtin_bit_cast(__bf16, (unsigned short)(h ^ 0x8000u));
@@ -602,18 +600,18 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         const bf16x8 arl = __builtin_bit_cast(bf16x8, Al[1][row][qu]);
         const bf16x8 aih = __builtin_bit_cast(bf16x8, Al[2][row][qu]);
         const bf16x8 ail = __builtin_bit_cast(bf16x8, Al[3][row][qu]);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbih, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nbil, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, cim[r], 0, 0, 0);
-        cre[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nbih, cre[r], 0, 0, 0);
-        cim[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, cim[r], 0, 0, 0);
+        cre[r] = mfma16x16x32<F>(arh, brh, cre[r]);
+        cim[r] = mfma16x16x32<F>(arh, bih, cim[r]);
+        cre[r] = mfma16x16x32<F>(arh, brl, cre[r]);
+        cim[r] = mfma16x16x32<F>(arh, bil, cim[r]);
+        cre[r] = mfma16x16x32<F>(arl, brh, cre[r]);
+        cim[r] = mfma16x16x32<F>(arl, bih, cim[r]);
+        cre[r] = mfma16x16x32<F>(aih, nbih, cre[r]);
+        cim[r] = mfma16x16x32<F>(aih, brh, cim[r]);
+        cre[r] = mfma16x16x32<F>(aih, nbil, cre[r]);
+        cim[r] = mfma16x16x32<F>(aih, brl, cim[r]);
+        cre[r] = mfma16x16x32<F>(ail, nbih, cre[r]);
+        cim[r] = mfma16x16x32<F>(ail, brh, cim[r]);
       }
     }
   }
@@ -627,6 +625,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         const int row = r0 + r * 16 + 4 * (lane / 16) + i;
         if (row < M) {
           float2 v = make_float2(cre[r][i], cim[r][i]);
+          if (F == SPLIT_FP16) v = make_float2(ldexpf(v.x, oexp), ldexpf(v.y, oexp));
           if (g.accumulate) {
             const float2 o = out[row];
             v.x += o.x;
@@ -639,13 +638,15 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   }
 }
 
-template <int NRT>
-__global__ __launch_bounds__(NT) void k_translate_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp) {
-  cgemm_tiles_bf16x3_body<NRT>(g, As, Kp);
+template <int NRT, int F>
+__global__ __launch_bounds__(NT) void k_translate_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp,
+                                                              int a_exp, const int* bexp) {
+  cgemm_tiles_bf16x3_body<NRT, F>(g, As, Kp, a_exp, bexp);
 }
-template <int NRT>
-__global__ __launch_bounds__(NT) void k_transfer_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp) {
-  cgemm_tiles_bf16x3_body<NRT>(g, As, Kp);
+template <int NRT, int F>
+__global__ __launch_bounds__(NT) void k_transfer_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp,
+                                                             int a_exp, const int* bexp) {
+  cgemm_tiles_bf16x3_body<NRT, F>(g, As, Kp, a_exp, bexp);
 }
 
 // Resident-A variant for small K (K <= KT): a workgroup takes a run of `tpw`
@@ -1856,10 +1857,16 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
 #define NESA_TILES(N)                                                                        \
   if (p.A_split) {                                                                           \
     const unsigned short* As = static_cast<const unsigned short*>(p.A_split);                \
-    if (translation)                                                                         \
-      k_translate_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                          \
-    else                                                                                     \
-      k_transfer_gemm_bf16x3<N><<<grid, NT, 0, st>>>(g, As, p.Kp);                           \
+    if (p.split_fmt == SPLIT_FP16) {                                                         \
+      if (translation)                                                                       \
+        k_translate_gemm_bf16x3<N, 1><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp);    \
+      else                                                                                   \
+        k_transfer_gemm_bf16x3<N, 1><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp);     \
+    } else if (translation) {                                                                \
+      k_translate_gemm_bf16x3<N, 0><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);           \
+    } else {                                                                                 \
+      k_transfer_gemm_bf16x3<N, 0><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);            \
+    }                                                                                        \
   } else if (tl.m3) {                                                                       \
     if (translation)                                                                         \
       k_translate_gemm<N, 4, 1><<<grid, NT, 0, st>>>(g);                                     \
@@ -1944,9 +1951,19 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   const bool tmode = mfma && R > d.pair_cap;
   bool v2 = tmode && NC >= TM2_MIN_COLS;
   for (const auto& lv : d.lev) v2 = v2 && lv.s6 != nullptr;     // (allocated for split operators only)
-  auto split_of = [&](const DevLevel& lv, const V2* src, hipStream_t ss) {
-    if constexpr (sizeof(T) == 4)
-      launch_split_sources(src, lv.nbox, NC, lv.Q, (lv.Q + 31) / 32 * 32, lv.s6, ss);
+  // fp16 split form: the largest exponent of every level's sources (slot
+  // 2 (l - l0)) and potentials (2 (l - l0) + 1), taken once the vector is
+  // complete and before the products that read it
+  auto exp_slot = [&](int l, int which) { return d.bexp + 2 * (l - l0) + which; };
+  auto absmax = [&](int l, int which, const V2* v) {
+    if (d.bexp) launch_absmax_exp(v, d.lev[l - l0].nbox * NC * d.lev[l - l0].Q, false, exp_slot(l, which), st);
+  };
+  auto split_of = [&](int l, int which, const V2* src, hipStream_t ss) {
+    if constexpr (sizeof(T) == 4) {
+      const auto& lv = d.lev[l - l0];
+      launch_split_sources(src, lv.nbox, NC, lv.Q, (lv.Q + 31) / 32 * 32, lv.s6, d.split_fmt,
+                           d.bexp ? exp_slot(l, which) : nullptr, ss);
+    }
   };
   auto tm_contract = [&](const GemmPlan& pl, const int32_t* ptr, const int32_t* src, const int32_t* slot,
                          int64_t ntarget, int M, int K, const V2* sv, const void* s6v, V2* ov, int acc,
@@ -1968,6 +1985,9 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       g.nbox = ntarget;
       g.NC = NC;
       g.accumulate = acc;
+      g.split_fmt = pl.split_fmt;
+      g.a_exp = pl.a_exp;
+      g.bexp = pl.bexp;
       int nrt = 0, rblocks = 0, ct = 0;
       tm_blocking(M, pl.Mr, NC, nrt, rblocks, ct);
       g.nct = (NC + 16 * (g.Asplit ? 4 : ct) - 1) / (16 * (g.Asplit ? 4 : ct));
@@ -1996,6 +2016,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     if (tm && ss == st) tm->mark(st, -1, l, K_TRANS_REDUCE);
   };
   if (tm) tm->mark(st, 0, -1, 0);
+  if (d.bexp) launch_exp_reset(d.bexp, 2 * (L - l0 + 1), st);
   if (R == 1) {
     k_radiate<T><<<(unsigned)d.nleaf, NT, 0, st>>>(static_cast<const V2*>(d.V), xl, d.leaf_ptr, s + LL.s_off, LL.Q);
   } else {
@@ -2009,7 +2030,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     }
   }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
-  if (v2) split_of(LL, s + LL.s_off * R, st);
+  absmax(L, 0, s + LL.s_off * R);
+  if (v2) split_of(L, 0, s + LL.s_off * R, st);
   // the near field starts once radiation (also HBM-bound) is done, and runs
   // beside the transfers and translations
   if (overlap) fork_near();
@@ -2037,7 +2059,8 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
       tm_contract(c.up, c.up_ptr, c.up_src, c.up_slot, p.nbox, p.Q, c.Q, s + c.s_off * R, c.s6, s + p.s_off * R, 0,
                   st);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
-      if (v2) split_of(p, s + p.s_off * R, st);
+      absmax(l - 1, 0, s + p.s_off * R);
+      if (v2) split_of(l - 1, 0, s + p.s_off * R, st);
     } else if (mfma) {
       launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
@@ -2045,6 +2068,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                                    s + p.s_off * R, p.child_ptr, p.child_end,
                                                                    NC * p.Q);
       if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
+      absmax(l - 1, 0, s + p.s_off * R);
     } else {
       dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
       k_upward<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off, p.child_ptr,
@@ -2075,10 +2099,11 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     const auto& c = d.lev[l - l0];
     const auto& p = d.lev[l - 1 - l0];
     if (side_ok(l)) hip_ok(hipStreamWaitEvent(st, d.ev_join2, 0));
+    if (mfma) absmax(l - 1, 1, o + p.s_off * R);
     if (tmode) {
       // the parent level's potentials split into its s6 planes (its
       // translations, which read them as sources, were launched before)
-      if (v2) split_of(p, o + p.s_off * R, st);
+      if (v2) split_of(l - 1, 1, o + p.s_off * R, st);
       tm_contract(c.down, c.dn_ptr, c.dn_src, c.dn_slot, c.nbox, c.Q, p.Q, o + p.s_off * R, p.s6, o + c.s_off * R, 1,
                   st);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);

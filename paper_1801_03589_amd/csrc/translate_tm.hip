@@ -20,7 +20,10 @@
 // the same three real products, i.e. nine bf16 MFMAs per complex k step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
+#include "split16.h"
 
 namespace nesa {
 
@@ -218,21 +221,15 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm(TmArgs g) {
 // of one column and writes them as 8 bf16 in each of six planes, which is the
 // operand layout of the 16x16x32 instruction (lane l: row or column l % 16,
 // k = 8 (l / 16) .. + 7).  Wave w owns column tile w and all row tiles.
-typedef __bf16 tm_bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned short tm_bf16_rne(float v) {
-  const unsigned u = __float_as_uint(v);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ __forceinline__ void tm_split(float v, unsigned short& hi, unsigned short& lo) {
-  hi = tm_bf16_rne(v);
-  lo = tm_bf16_rne(v - __uint_as_float((unsigned)hi << 16));
-}
+// The 16-bit format F (split16.h) is bf16 or fp16; with fp16 the planes of A
+// hold D x 2^a_exp, the sources are scaled by 2^split_shift(*bexp) before their
+// split, and the results by 2^-(a_exp + shift).
+typedef s16x8 tm_bf16x8;
 __device__ __forceinline__ unsigned tm_pack(unsigned short a, unsigned short b) {
   return (unsigned)a | ((unsigned)b << 16);
 }
 
-template <int NRT>
+template <int NRT, int F>
 __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
   constexpr int KC = TM_KC;
   constexpr int ROWS = NRT * 16;
@@ -301,6 +298,8 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
       for (int u = 0; u < 8; ++u) rb[u] = B[min(kb + u, K - 1)];
     }
   };
+  const int bshift = split_src_shift<F>(g.bexp);
+  const int oexp = -(g.a_exp + bshift);
   auto stage = [&](int ci) {
     const int kv = K - ci * KC - 8 * bq;        // valid k of this thread's quarter
     __syncthreads();
@@ -314,14 +313,15 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
     for (int u = 0; u < 8; ++u) {
       float2 v = rb[u];
       if (!(bok && u < kv)) v = make_float2(0.f, 0.f);
+      if (F == SPLIT_FP16) v = make_float2(ldexpf(v.x, bshift), ldexpf(v.y, bshift));
       unsigned short hi, lo;
-      tm_split(v.x, hi, lo);
+      split16<F>(v.x, hi, lo);
       h[0][u] = hi;
       h[1][u] = lo;
-      tm_split(v.y, hi, lo);
+      split16<F>(v.y, hi, lo);
       h[2][u] = hi;
       h[3][u] = lo;
-      tm_split(v.x + v.y, hi, lo);
+      split16<F>(v.x + v.y, hi, lo);
       h[4][u] = hi;
       h[5][u] = lo;
     }
@@ -348,15 +348,15 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
       const tm_bf16x8 ail = __builtin_bit_cast(tm_bf16x8, Al(3, row, qu));
       const tm_bf16x8 ash = __builtin_bit_cast(tm_bf16x8, Al(4, row, qu));
       const tm_bf16x8 asl = __builtin_bit_cast(tm_bf16x8, Al(5, row, qu));
-      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, c1[r], 0, 0, 0);
-      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bih, c2[r], 0, 0, 0);
-      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsh, c3[r], 0, 0, 0);
-      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, c1[r], 0, 0, 0);
-      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bil, c2[r], 0, 0, 0);
-      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bsl, c3[r], 0, 0, 0);
-      c1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, c1[r], 0, 0, 0);
-      c2[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bih, c2[r], 0, 0, 0);
-      c3[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asl, bsh, c3[r], 0, 0, 0);
+      c1[r] = mfma16x16x32<F>(arh, brh, c1[r]);
+      c2[r] = mfma16x16x32<F>(aih, bih, c2[r]);
+      c3[r] = mfma16x16x32<F>(ash, bsh, c3[r]);
+      c1[r] = mfma16x16x32<F>(arh, brl, c1[r]);
+      c2[r] = mfma16x16x32<F>(aih, bil, c2[r]);
+      c3[r] = mfma16x16x32<F>(ash, bsl, c3[r]);
+      c1[r] = mfma16x16x32<F>(arl, brh, c1[r]);
+      c2[r] = mfma16x16x32<F>(ail, bih, c2[r]);
+      c3[r] = mfma16x16x32<F>(asl, bsh, c3[r]);
     }
   };
   if (jb < je) {
@@ -386,7 +386,9 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         otile[lc * RS + r * 16 + 4 * (lane / 16) + i] =
-            make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
+            F == SPLIT_FP16 ? make_float2(ldexpf(c1[r][i] - c2[r][i], oexp),
+                                          ldexpf(c3[r][i] - c1[r][i] - c2[r][i], oexp))
+                            : make_float2(c1[r][i] - c2[r][i], c3[r][i] - c1[r][i] - c2[r][i]);
     }
   }
   __syncthreads();
@@ -403,9 +405,9 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
   }
 }
 
-template <int NRT>
+template <int NRT, int F>
 __global__ __launch_bounds__(TM_NT) void k_translate_tm_split(TmArgs g) {
-  translate_tm_split_body<NRT>(g);
+  translate_tm_split_body<NRT, F>(g);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,8 +428,9 @@ __global__ __launch_bounds__(TM_NT) void k_translate_tm_split(TmArgs g) {
 // of lane l is row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
 typedef float tm_f32x16 __attribute__((ext_vector_type(16)));
 
+template <int F>
 __global__ __launch_bounds__(TM_NT) void k_split_sources(const float2* __restrict__ s, int64_t nbox, int NC, int K,
-                                                         int Kp, uint4* __restrict__ s4) {
+                                                         int Kp, uint4* __restrict__ s4, const int* __restrict__ bexp) {
   // one thread per (box, column, 8 consecutive k)
   const int per_box = NC * (Kp / 8);
   const int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x;
@@ -435,12 +438,14 @@ __global__ __launch_bounds__(TM_NT) void k_split_sources(const float2* __restric
   const int64_t box = i / per_box;
   const int r = (int)(i % per_box), c = r / (Kp / 8), k0 = 8 * (r % (Kp / 8));
   const float2* src = s + ((size_t)box * NC + c) * K;
+  const int bshift = split_src_shift<F>(bexp);
   unsigned short h[4][8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const float2 v = (k0 + u < K) ? src[k0 + u] : make_float2(0.f, 0.f);
-    tm_split(v.x, h[0][u], h[1][u]);
-    tm_split(v.y, h[2][u], h[3][u]);
+    float2 v = (k0 + u < K) ? src[k0 + u] : make_float2(0.f, 0.f);
+    if (F == SPLIT_FP16) v = make_float2(ldexpf(v.x, bshift), ldexpf(v.y, bshift));
+    split16<F>(v.x, h[0][u], h[1][u]);
+    split16<F>(v.y, h[2][u], h[3][u]);
   }
   const int kc = k0 / 16, half = (k0 % 16) / 8;
   uint4* dst = s4 + ((((size_t)box * (Kp / 16) + kc) * 4) * NC + c) * 2 + half;
@@ -459,7 +464,7 @@ __device__ __forceinline__ tm_bf16x8 tm_neg(tm_bf16x8 v) {
   return __builtin_bit_cast(tm_bf16x8, u);
 }
 
-template <int ROWS, int COLS>
+template <int ROWS, int COLS, int F>
 __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS == 128 && ROWS == 64 ? 3 : 2))) void k_translate_tm_split2(TmArgs g) {
   constexpr int NP = 4;
   constexpr int WC = COLS / 4;                                 // columns per wave (64 or 32)
@@ -556,18 +561,18 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
 #pragma unroll
       for (int rt = 0; rt < RTW; ++rt) {
         // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br, each real product hi hi + hi lo + lo hi
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[0], cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[2], cim[rt][ct], 0, 0, 0);
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[1], cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][0], bv[3], cim[rt][ct], 0, 0, 0);
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[0], cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][1], bv[2], cim[rt][ct], 0, 0, 0);
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], nbih, cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[0], cim[rt][ct], 0, 0, 0);
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], nbil, cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][2], bv[1], cim[rt][ct], 0, 0, 0);
-        cre[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], nbih, cre[rt][ct], 0, 0, 0);
-        cim[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt][3], bv[0], cim[rt][ct], 0, 0, 0);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][0], bv[0], cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][0], bv[2], cim[rt][ct]);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][0], bv[1], cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][0], bv[3], cim[rt][ct]);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][1], bv[0], cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][1], bv[2], cim[rt][ct]);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][2], nbih, cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][2], bv[0], cim[rt][ct]);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][2], nbil, cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][2], bv[1], cim[rt][ct]);
+        cre[rt][ct] = mfma32x32x16<F>(av[rt][3], nbih, cre[rt][ct]);
+        cim[rt][ct] = mfma32x32x16<F>(av[rt][3], bv[0], cim[rt][ct]);
       }
     }
   };
@@ -594,6 +599,7 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
   float2* otile = reinterpret_cast<float2*>(&lds[0]);
   const int mloc = min(ROWS, M - r0);
   float2* obase = g.o + ((size_t)a * NC + c0) * M + r0;
+  const int oexp = F == SPLIT_FP16 ? -(g.a_exp + split_shift(*g.bexp)) : 0;
   for (int p0 = 0; p0 < COLS; p0 += PC) {
     __syncthreads();
     if (w * WC >= p0 && w * WC < p0 + PC) {
@@ -605,7 +611,9 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int row = rt * 32 + 8 * (u / 4) + 4 * (lane / 32) + u % 4;
-            otile[lc * RS + row] = make_float2(cre[rt][ct][u], cim[rt][ct][u]);
+            otile[lc * RS + row] = F == SPLIT_FP16 ? make_float2(ldexpf(cre[rt][ct][u], oexp),
+                                                                 ldexpf(cim[rt][ct][u], oexp))
+                                                   : make_float2(cre[rt][ct][u], cim[rt][ct][u]);
           }
         }
     }
@@ -625,11 +633,37 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
   }
 }
 
+// Largest binary exponent of a set of values (fp16 operand scale): a
+// grid-stride loop keeps the maximum of frexp's exponent over the nonzero
+// values, the wave reduces it, and one atomic maximum per wave updates the
+// slot (integer maxima: the result does not depend on their order).
+template <typename R>
+__global__ __launch_bounds__(TM_NT) void k_absmax_exp(const R* __restrict__ v, int64_t n, int* __restrict__ slot) {
+  int e = EXP_NONE;
+  for (int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * TM_NT) {
+    const R x = v[i];
+    if (x != R(0)) {
+      int ex;
+      frexp(x, &ex);
+      e = max(e, ex);
+    }
+  }
+#pragma unroll
+  for (int o = TM_WAVE / 2; o > 0; o /= 2) e = max(e, __shfl_xor(e, o));
+  if (threadIdx.x % TM_WAVE == 0 && e > EXP_NONE) atomicMax(slot, e);
+}
+
+__global__ void k_exp_reset(int* __restrict__ slots, int n) {
+  const int i = blockIdx.x * TM_NT + threadIdx.x;
+  if (i < n) slots[i] = EXP_NONE;
+}
+
 // Device form of the host split of a grouped GEMM's A: FP64 column-major
 // [g][K][Mr] -> bf16 planes [g][6][Mr][Kp] (k contiguous, zero for k >= K) and,
 // when D32 is set, the FP32 copy [g][K][Mr].  One thread per (g, m, k < Kp).
+template <int F>
 __global__ void k_split_planes(const double2* __restrict__ D, int64_t total, int K, int Mr, int Kp,
-                               float2* __restrict__ D32, unsigned short* __restrict__ P) {
+                               float2* __restrict__ D32, unsigned short* __restrict__ P, int shift) {
   const int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x;
   if (i >= total) return;
   const int64_t per = (int64_t)Mr * Kp;
@@ -637,11 +671,12 @@ __global__ void k_split_planes(const double2* __restrict__ D, int64_t total, int
   const int m = (int)((i / Kp) % Mr), k = (int)(i % Kp);
   double2 v = make_double2(0.0, 0.0);
   if (k < K) v = D[((size_t)g * K + k) * Mr + m];
-  const float re = (float)v.x, im = (float)v.y, sm = re + im;
+  const float re = (float)v.x, im = (float)v.y;
+  const float rs = F == SPLIT_FP16 ? ldexpf(re, shift) : re, is = F == SPLIT_FP16 ? ldexpf(im, shift) : im;
   unsigned short h[6];
-  tm_split(re, h[0], h[1]);
-  tm_split(im, h[2], h[3]);
-  tm_split(sm, h[4], h[5]);
+  split16<F>(rs, h[0], h[1]);
+  split16<F>(is, h[2], h[3]);
+  split16<F>(rs + is, h[4], h[5]);
   unsigned short* o = P + (size_t)g * 6 * per + (size_t)m * Kp + k;
 #pragma unroll
   for (int pl = 0; pl < 6; ++pl) o[pl * per] = h[pl];
@@ -650,13 +685,32 @@ __global__ void k_split_planes(const double2* __restrict__ D, int64_t total, int
 
 }  // namespace
 
-void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes,
-                         hipStream_t st) {
+void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp, void* D32, void* planes, int fmt,
+                         int shift, hipStream_t st) {
   const int64_t total = ngroups * Mr * (int64_t)Kp;
   if (total == 0) return;
-  k_split_planes<<<(unsigned)((total + TM_NT - 1) / TM_NT), TM_NT, 0, st>>>(
-      static_cast<const double2*>(D64), total, K, Mr, Kp, static_cast<float2*>(D32),
-      static_cast<unsigned short*>(planes));
+  const unsigned nb = (unsigned)((total + TM_NT - 1) / TM_NT);
+  if (fmt == SPLIT_FP16)
+    k_split_planes<1><<<nb, TM_NT, 0, st>>>(static_cast<const double2*>(D64), total, K, Mr, Kp,
+                                            static_cast<float2*>(D32), static_cast<unsigned short*>(planes), shift);
+  else
+    k_split_planes<0><<<nb, TM_NT, 0, st>>>(static_cast<const double2*>(D64), total, K, Mr, Kp,
+                                            static_cast<float2*>(D32), static_cast<unsigned short*>(planes), 0);
+}
+
+void launch_absmax_exp(const void* v, int64_t n, bool fp64, int* slot, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t vals = 2 * n;
+  const unsigned nb = (unsigned)std::min<int64_t>((vals + TM_NT - 1) / TM_NT, 2048);
+  if (fp64)
+    k_absmax_exp<double><<<nb, TM_NT, 0, st>>>(static_cast<const double*>(v), vals, slot);
+  else
+    k_absmax_exp<float><<<nb, TM_NT, 0, st>>>(static_cast<const float*>(v), vals, slot);
+}
+
+void launch_exp_reset(int* slots, int n, hipStream_t st) {
+  if (n <= 0) return;
+  k_exp_reset<<<(unsigned)((n + TM_NT - 1) / TM_NT), TM_NT, 0, st>>>(slots, n);
 }
 
 // Row blocking of the target-major kernel: the fewest row tiles per workgroup
@@ -678,11 +732,17 @@ void tm_blocking(int M, int Mr, int NC, int& nrt, int& rblocks, int& ct) {
   rblocks = 0;
 }
 
-void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, hipStream_t st) {
+void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, void* s6, int fmt, const int* bexp,
+                          hipStream_t st) {
   const int64_t total = nbox * NC * (int64_t)(Kp / 8);
   if (total == 0) return;
-  k_split_sources<<<(unsigned)((total + TM_NT - 1) / TM_NT), TM_NT, 0, st>>>(
-      static_cast<const float2*>(s), nbox, NC, K, Kp, static_cast<uint4*>(s6));
+  const unsigned nb = (unsigned)((total + TM_NT - 1) / TM_NT);
+  if (fmt == SPLIT_FP16)
+    k_split_sources<1><<<nb, TM_NT, 0, st>>>(static_cast<const float2*>(s), nbox, NC, K, Kp,
+                                             static_cast<uint4*>(s6), bexp);
+  else
+    k_split_sources<0><<<nb, TM_NT, 0, st>>>(static_cast<const float2*>(s), nbox, NC, K, Kp,
+                                             static_cast<uint4*>(s6), nullptr);
 }
 
 void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStream_t st) {
@@ -691,23 +751,36 @@ void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStrea
   if (g.Asplit && g.s6) {
     // 64 x 256, 64 x 128 or 128 x 128 workgroup tiles: nct counts the column
     // tiles; g.tm_rows = 128 selects the last
+    const bool h = g.split_fmt == SPLIT_FP16;
     if (g.tm_rows == 128) {
       dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 127) / 128));
-      k_translate_tm_split2<128, 128><<<grid2, TM_NT, 0, st>>>(g);
+      if (h)
+        k_translate_tm_split2<128, 128, 1><<<grid2, TM_NT, 0, st>>>(g);
+      else
+        k_translate_tm_split2<128, 128, 0><<<grid2, TM_NT, 0, st>>>(g);
       return;
     }
     dim3 grid2((unsigned)((nitems + 7) / 8 * 8), (unsigned)((g.M + 63) / 64));
-    if (g.nct_cols == 128)
-      k_translate_tm_split2<64, 128><<<grid2, TM_NT, 0, st>>>(g);
-    else
-      k_translate_tm_split2<64, 256><<<grid2, TM_NT, 0, st>>>(g);
+    if (g.nct_cols == 128) {
+      if (h)
+        k_translate_tm_split2<64, 128, 1><<<grid2, TM_NT, 0, st>>>(g);
+      else
+        k_translate_tm_split2<64, 128, 0><<<grid2, TM_NT, 0, st>>>(g);
+    } else if (h) {
+      k_translate_tm_split2<64, 256, 1><<<grid2, TM_NT, 0, st>>>(g);
+    } else {
+      k_translate_tm_split2<64, 256, 0><<<grid2, TM_NT, 0, st>>>(g);
+    }
     return;
   }
   dim3 grid((unsigned)((nitems + 7) / 8 * 8), (unsigned)rblocks);
   if (g.Asplit) {
-#define NESA_TMS(N) \
-  case N:           \
-    k_translate_tm_split<N><<<grid, TM_NT, 0, st>>>(g); \
+#define NESA_TMS(N)                                        \
+  case N:                                                  \
+    if (g.split_fmt == SPLIT_FP16)                         \
+      k_translate_tm_split<N, 1><<<grid, TM_NT, 0, st>>>(g); \
+    else                                                   \
+      k_translate_tm_split<N, 0><<<grid, TM_NT, 0, st>>>(g); \
     return;
     switch (nrt) {
       NESA_TMS(1) NESA_TMS(2) NESA_TMS(3) NESA_TMS(4) NESA_TMS(5) NESA_TMS(6) NESA_TMS(7) NESA_TMS(8)

@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnesa.so")
 
-C128, C64, C64_SPLIT = 0, 1, 2
+C128, C64, C64_SPLIT, C64_SPLIT_FP16 = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_BLOCKDIAG, PRECOND_LEARNED, PRECOND_SCHWARZ = 0, 1, 2, 3
 ETA0 = 376.730313668
 K0 = 2.0 * np.pi

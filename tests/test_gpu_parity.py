@@ -303,7 +303,7 @@ def test_matvec_multi_rhs_split(torch_dev, nesa, nrhs):
         assert err <= 1e-4, (r, err)
 
 
-@pytest.mark.parametrize("prec", ["c64", "split"])
+@pytest.mark.parametrize("prec", ["c64", "split", "split_fp16"])
 @pytest.mark.parametrize("nrhs", [8, 13])
 def test_matvec_target_major_below_cap(torch_dev, nesa, prec, nrhs, monkeypatch):
     """The target-major translations and transfers at 8 and 13 right-hand sides
@@ -312,14 +312,14 @@ def test_matvec_target_major_below_cap(torch_dev, nesa, prec, nrhs, monkeypatch)
     side, against the oracle and the offset-major product."""
     monkeypatch.setenv("NESA_PAIR_CAP", "1")
     ref, tr, near, far = _case(nesa, "sphere_3lev")
-    P = nesa.C64 if prec == "c64" else nesa.C64_SPLIT
+    P = {"c64": nesa.C64, "split": nesa.C64_SPLIT, "split_fp16": nesa.C64_SPLIT_FP16}[prec]
     op = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
     monkeypatch.delenv("NESA_PAIR_CAP")
     op_om = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
     X = synth.complex_normal((nrhs, ref.m.n), 30 + nrhs)
     Y = _run(torch_dev, nesa, op, X, nrhs=nrhs)
     Yo = _run(torch_dev, nesa, op_om, X, nrhs=nrhs)
-    tol = TOL["c64"] if prec == "c64" else 1e-4
+    tol = 1e-4 if prec == "split" else TOL["c64"]
     for r in sorted({0, nrhs - 1}):
         yr = ref.matvec(X[r])
         err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
@@ -360,6 +360,61 @@ def test_matvec_split_precision(torch_dev, nesa, name):
         err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
         print("%s split-bf16x3 rhs %d: rel err vs FP64 oracle %.3e" % (name, r, err))
         assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["sphere1_nested", "sphere_3lev", "box"])
+def test_matvec_split_fp16(torch_dev, nesa, name):
+    """Split products with fp16 parts (11-bit mantissas, each operand scaled by
+    a power of two that puts its largest part below 2^14): error against the
+    FP64 oracle within the complex64 bound, and below the bf16 split's on the
+    same vectors (about 2^-22 against 2^-16 per product)."""
+    ref, tr, near, far = _case(nesa, name)
+    X = synth.complex_normal((2, ref.m.n), 21)
+    errs = {}
+    for prec in (nesa.C64_SPLIT_FP16, nesa.C64_SPLIT):
+        op = nesa.op_create(tr, near, far, prec, max_nrhs=2)
+        Y = _run(torch_dev, nesa, op, X, nrhs=2)
+        errs[prec] = [np.linalg.norm(Y[r] - ref.matvec(X[r])) / np.linalg.norm(ref.matvec(X[r])) for r in range(2)]
+        Y1 = _run(torch_dev, nesa, op, X[1])
+        assert np.linalg.norm(Y1 - Y[1]) <= 2 * max(errs[prec]) * np.linalg.norm(Y[1])
+    e16, e3 = errs[nesa.C64_SPLIT_FP16], errs[nesa.C64_SPLIT]
+    print("%s split-fp16x3 rel err vs FP64 oracle %.3e %.3e, bf16x3 %.3e %.3e" % (name, *e16, *e3))
+    assert max(e16) <= TOL["c64"]
+    assert max(e16) < min(e3)
+
+
+@pytest.mark.parametrize("nrhs", [8, 37])
+def test_matvec_multi_rhs_split_fp16(torch_dev, nesa, nrhs):
+    """fp16 split products of several right-hand sides: offset-major at 8
+    (in-kernel split of the sources), target-major with the pre-split sources
+    and a partial column tile at 37, against the oracle."""
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    op = nesa.op_create(tr, near, far, nesa.C64_SPLIT_FP16, max_nrhs=nrhs)
+    X = synth.complex_normal((nrhs, ref.m.n), 40 + nrhs)
+    Y = _run(torch_dev, nesa, op, X, nrhs=nrhs)
+    for r in sorted({0, nrhs // 2, nrhs - 1}):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("split-fp16 nrhs %d rhs %d: rel err %.2e" % (nrhs, r, err))
+        assert err <= TOL["c64"], (r, err)
+
+
+@pytest.mark.parametrize("nrhs", [1, 37])
+def test_split_fp16_scale_follows_the_input(torch_dev, nesa, nrhs):
+    """The fp16 scales are found from the data in every product: inputs scaled
+    by 2^60 and 2^-60 (far outside fp16's range) give the product scaled by the
+    same power of two, bit for bit (every FP32 operation and every 16-bit part
+    is unchanged by the shift), and a zero input gives a zero output."""
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    op = nesa.op_create(tr, near, far, nesa.C64_SPLIT_FP16, max_nrhs=nrhs)
+    X = synth.complex_normal((nrhs, ref.m.n), 50).astype(np.complex64)
+    Y = _run(torch_dev, nesa, op, X, nrhs=nrhs)
+    assert np.all(np.isfinite(Y))
+    for e in (60, -60):
+        Ys = _run(torch_dev, nesa, op, np.ldexp(X.real, e) + 1j * np.ldexp(X.imag, e), nrhs=nrhs)
+        assert np.array_equal(np.ldexp(Ys.real, -e), Y.real) and np.array_equal(np.ldexp(Ys.imag, -e), Y.imag), e
+    Z = _run(torch_dev, nesa, op, np.zeros_like(X), nrhs=nrhs)
+    assert not np.any(Z)
 
 
 def _schwarz_oracle(ref):
