@@ -366,21 +366,26 @@ def test_matvec_split_precision(torch_dev, nesa, name):
 def test_matvec_split_fp16(torch_dev, nesa, name):
     """Split products with fp16 parts (11-bit mantissas, each operand scaled by
     a power of two that puts its largest part below 2^14): error against the
-    FP64 oracle within the complex64 bound, and below the bf16 split's on the
-    same vectors (about 2^-22 against 2^-16 per product)."""
+    FP64 oracle within the complex64 bound.  Against the complex64 product of
+    the same operator (same near field, FP32 contractions) the fp16 split
+    differs far less than the bf16 split (about 2^-22 against 2^-16 per
+    contraction; the FP32 contractions' own rounding sets the floor)."""
     ref, tr, near, far = _case(nesa, name)
     X = synth.complex_normal((2, ref.m.n), 21)
-    errs = {}
+    Y32 = _run(torch_dev, nesa, nesa.op_create(tr, near, far, nesa.C64, max_nrhs=2), X, nrhs=2)
+    errs, diffs = {}, {}
     for prec in (nesa.C64_SPLIT_FP16, nesa.C64_SPLIT):
         op = nesa.op_create(tr, near, far, prec, max_nrhs=2)
         Y = _run(torch_dev, nesa, op, X, nrhs=2)
-        errs[prec] = [np.linalg.norm(Y[r] - ref.matvec(X[r])) / np.linalg.norm(ref.matvec(X[r])) for r in range(2)]
+        errs[prec] = max(np.linalg.norm(Y[r] - ref.matvec(X[r])) / np.linalg.norm(ref.matvec(X[r])) for r in range(2))
+        diffs[prec] = np.linalg.norm(Y - Y32) / np.linalg.norm(Y32)
         Y1 = _run(torch_dev, nesa, op, X[1])
-        assert np.linalg.norm(Y1 - Y[1]) <= 2 * max(errs[prec]) * np.linalg.norm(Y[1])
-    e16, e3 = errs[nesa.C64_SPLIT_FP16], errs[nesa.C64_SPLIT]
-    print("%s split-fp16x3 rel err vs FP64 oracle %.3e %.3e, bf16x3 %.3e %.3e" % (name, *e16, *e3))
-    assert max(e16) <= TOL["c64"]
-    assert max(e16) < min(e3)
+        assert np.linalg.norm(Y1 - Y[1]) <= 2 * errs[prec] * np.linalg.norm(Y[1])
+    h, b = nesa.C64_SPLIT_FP16, nesa.C64_SPLIT
+    print("%s rel err vs FP64 oracle: fp16x3 %.3e, bf16x3 %.3e; vs complex64: fp16x3 %.3e, bf16x3 %.3e"
+          % (name, errs[h], errs[b], diffs[h], diffs[b]))
+    assert errs[h] <= TOL["c64"]
+    assert diffs[h] < diffs[b] / 3
 
 
 @pytest.mark.parametrize("nrhs", [8, 37])
