@@ -369,7 +369,7 @@ static void tune_load_locked() {
                      &c.nrt, &c.tpw, &c.kt, &c.regions, &c.width, &c.m3) == 12) {
     k.ntiles = nt;
     if (c.nrt >= 1 && c.nrt <= 8 && (c.tpw <= 0 || c.kt == 52 || c.kt == 84) && (c.regions == 1 || c.regions == 8) &&
-        (c.width == 32 || c.width == 64) && (c.m3 == 0 || c.m3 == 1))
+        (c.width == 32 || c.width == 64 || c.width == 128) && (c.m3 == 0 || c.m3 == 1))
       g_tune[k] = c;
   }
   std::fclose(fp);
@@ -392,6 +392,9 @@ static void tune_store_locked(const TuneKey& k, const TuneChoice& c) {
 static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice& c) {
   const int blocks = ((p.M + 15) / 16 + c.nrt - 1) / c.nrt;
   if (c.nrt < 1 || c.nrt > 8 || blocks * c.nrt * 16 > p.Mr) return false;
+  // width 128: the split kernel on the pre-split sources (its own row blocks
+  // of 64 or 128 rows)
+  if (c.width == 128 && (!p.A_split || !p.s6 || c.tpw != 0 || c.m3 || c.nrt != (p.M > 64 ? 8 : 4))) return false;
   if (c.tpw > 0 && (p.A_split || (c.kt != 52 && c.kt != 84) || p.K > c.kt)) return false;
   if (c.tpw < 0 && (p.A_split || (c.tpw != -13 && c.tpw != -21) || p.K > -4 * c.tpw ||
                     (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
@@ -436,8 +439,9 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   const bool res_ok = !p.A_split && p.K <= 84;
   // region ordering only pays when a group has many pairs per region
   const bool reg_ok = p.ngroups > 0 && (int64_t)p.h_src.size() / p.ngroups >= 64;
-  const TuneKey key{(translation ? 1 : (p.accumulate ? 3 : 2)) + 10 * mode, p.A_split ? 1 : 0, p.M, p.K, nrhs,
-                    base_tiles};
+  // (split plans with and without the pre-split candidate keep separate choices)
+  const TuneKey key{(translation ? 1 : (p.accumulate ? 3 : 2)) + 10 * mode, p.A_split ? (p.s6 ? 2 : 1) : 0, p.M, p.K,
+                    nrhs, base_tiles};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load_locked();
@@ -482,6 +486,11 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
       for (int nrt : {1, 2, 4})
         if (nrt <= tiles) cand.push_back({nrt, p.K <= 52 ? -13 : -21, 0, regions, 64, 0});
   }
+  // split plans: the kernel on the sources split once per level (tiles of
+  // 128 columns, both orderings)
+  if (p.A_split && p.s6 && mode == 1)
+    for (int regions : {1, 8})
+      if (regions == 1 || reg_ok) cand.push_back({p.M > 64 ? 8 : 4, 0, 0, regions, 128, 0});
   if (cand.empty()) cand.push_back(dflt);
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "hipEventCreate");
@@ -658,6 +667,17 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
   d.w[3] = fr.eta / fr.k;
   d.lev.resize(t.L - t.l0 + 1);
   d.split_fmt = split_fmt(op->precision);
+  {
+    // split operators run their offset-major products on the pre-split
+    // sources (NESA_OM2=0: the kernels that split the sources themselves)
+    const char* e = std::getenv("NESA_OM2");
+    d.om2 = sizeof(T) == 4 && is_split(op->precision) && !(e && std::atoi(e) == 0);
+    // (the kernel addresses a level's split sources with 32-bit offsets)
+    for (int l = t.l0; l <= t.L; ++l) {
+      const double kp = (fr.lev[l - t.l0].Q + 31) / 32 * 32;
+      if ((double)t.level(l).nbox * kp * 2 * op->max_nrhs >= 2147483647.0) d.om2 = false;   // uint4 of s6
+    }
+  }
   if (op->precision == NESA_C64_SPLIT_FP16)
     d.bexp = static_cast<int*>(dev_alloc(op, (size_t)2 * (t.L - t.l0 + 1) * sizeof(int)));
   // exponent slot of a level's sources (which 0) or potentials (which 1)
@@ -774,8 +794,10 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     // split form with many right-hand sides: the level's sources (and, in the
     // potential transfer, its potentials) split into four bf16 planes
     // (2 bytes x 4 x Kp x 4 max_nrhs per box, Kp = Q rounded up to 32)
-    if (sizeof(T) == 4 && is_split(op->precision) && 4 * op->max_nrhs >= nesa::TM2_MIN_COLS)
+    if (sizeof(T) == 4 && is_split(op->precision) && (d.om2 || 4 * op->max_nrhs >= nesa::TM2_MIN_COLS))
       dl.s6 = dev_alloc(op, (size_t)lv.nbox * ((fl.Q + 31) / 32 * 32) * 4 * 4 * op->max_nrhs * sizeof(uint16_t));
+    // offset-major split products may read the pre-split sources (autotuner)
+    if (d.om2) dl.trans.s6 = dl.s6;
     dl.il_ptr = upload(op, to_i32(lv.il_ptr));
     dl.il_src = upload(op, to_i32(lv.il_src));
     if (l < t.L) {
@@ -820,11 +842,13 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
         dl.up = make_plan(op, upload_complex<T>(op, au), (int64_t)Qc * Qpr, Qp, Qc, Qpr, nrt_u, 0, grp, 8, idx, idx,
                            reg);
         if (is_split(op->precision)) attach_split(op, dl.up, au, 8, d.split_fmt, exp_slot(l, 0));
+        if (d.om2) dl.up.s6 = dl.s6;           // this level's sources
         // per-child outputs serve the offset-major form only (up to pair_cap)
         dl.child_out = dev_alloc(op, (size_t)lv.nbox * 4 * d.pair_cap * Qp * 2 * sizeof(T));
         dl.down = make_plan(op, upload_complex<T>(op, ad), (int64_t)Qp * Qcr, Qc, Qp, Qcr, nrt_d, 1, grp, 8, par, idx,
                              reg);
         if (is_split(op->precision)) attach_split(op, dl.down, ad, 8, d.split_fmt, exp_slot(l - 1, 1));
+        if (d.om2) dl.down.s6 = d.lev[l - 1 - t.l0].s6;     // the parent level's potentials
         // pair lists of the target-major transfers: the children of every box
         // of level l-1 in increasing index (CSR), and the parent of every box
         const int64_t np = t.level(l - 1).nbox;

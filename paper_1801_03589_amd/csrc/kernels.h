@@ -17,7 +17,8 @@ struct TileList {
   int nrt = 0, rblocks = 0;       // row tiles per workgroup and row blocks chosen by the autotuner (0: plan default)
   int tpw = 0, kt = 0;            // resident-A kernel: tiles per workgroup and its K capacity (0: chunked kernel)
   int regions = 1;                // tiles ordered by (region, group) when 8: each XCD takes one region
-  int width = 64;                 // columns per tile (64; 32 for the chunked kernel on groups with few pairs)
+  int width = 64;                 // columns per tile (64; 32 for the chunked kernel on groups with few pairs;
+                                  // 128: split form on the pre-split sources, k_gemm_om_split2)
   int m3 = 0;                     // chunked kernel: complex products with three real MFMAs
   int64_t ntiles = 0;
   int32_t* tile_group = nullptr;
@@ -47,6 +48,7 @@ struct GemmPlan {
   std::vector<int32_t> h_src, h_dst;  // host: pairs, group by group (by source inside a group)
   std::vector<int8_t> h_region;       // host: region (1/8 of the Morton order of the owner box) of every pair
   std::vector<TileList> by_nrhs;  // index nrhs
+  const void* s6 = nullptr;       // split form: the pre-split planes of the source level (TileList::width 128)
 };
 
 // One level of the far-field hierarchy on the device.
@@ -112,6 +114,7 @@ struct DevOp {
   int pair_cap = 1;              // offset-major up to this many right-hand sides, target-major above
   double w[4] = {0, 0, 0, 0};    // channel weights: re/im of w_xyz, re/im of w_div
   int split_fmt = SPLIT_BF16;    // split form: 16-bit format
+  bool om2 = false;              // split form: the pre-split offset-major kernel is an autotuner candidate
   int* bexp = nullptr;           // fp16 split form: [2 x levels] largest exponents of s_l (2 (l - l0)) and o_l (+1)
   std::vector<DevLevel> lev;
 };
@@ -175,6 +178,10 @@ __host__ __device__ inline int split_shift(int E) {
 // columns per box (4 nrhs) from which the split translations use the pre-split
 // sources and 64 x 256 workgroup tiles
 constexpr int TM2_MIN_COLS = 128;
+// Offset-major split product of a grouped GEMM plan on the pre-split sources
+// s6 of its source level (tile list of width 128): dst(pair) = A_group
+// x_src(pair), written or added (p.accumulate).
+void launch_om_split2(const GemmPlan& p, const TileList& tl, int nrhs, const void* s6, void* dst, hipStream_t st);
 // s6 = four bf16 planes (re hi, re lo, im hi, im lo) of the sources s
 // [nbox][NC][K] (layout of TmArgs::s6)
 // (fp16: scaled by 2^split_shift(*bexp) first)

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <stdexcept>
 
 #include "kernels.h"
 #include "split16.h"
@@ -531,13 +532,15 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
     cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   // A staging: NRT x 16 B per thread per chunk (4 planes x NRT*16 rows x 4 quarters of 8 k)
-  uint4 ra[NRT];
-  const uint4* a_ptr[NRT];
+  // (native vectors: copies of HIP's uint4 struct kept these in private memory)
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 ra[NRT];
+  const u32x4* a_ptr[NRT];
 #pragma unroll
   for (int i = 0; i < NRT; ++i) {
     const int e = t + i * NT;
     const int pl = e / (NRT * 16 * 4), row = (e / 4) % (NRT * 16), qu = e % 4;
-    a_ptr[i] = reinterpret_cast<const uint4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
+    a_ptr[i] = reinterpret_cast<const u32x4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
   }
   // B staging: TR_NB float2 per thread per chunk
   float2 rb[TR_NB];
@@ -566,7 +569,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
 #pragma unroll
     for (int i = 0; i < NRT; ++i) {
       const int e = t + i * NT;
-      Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4] = ra[i];
+      *reinterpret_cast<u32x4*>(&Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < TR_NB; ++i) {
@@ -1405,8 +1408,12 @@ __global__ __launch_bounds__(NT) void k_radiate_multi(const V2* __restrict__ V, 
   const int b = blockIdx.x, r0 = blockIdx.y * RB, nr = min(RB, R - r0);
   const int p0 = leaf_ptr[b], S = leaf_ptr[b + 1] - p0;
   const int J = 4 * Q;
+  // (loops over the accumulators fully unrolled: a runtime index would keep
+  // them in private memory)
   V2 acc[2][RB];
+#pragma unroll
   for (int u = 0; u < 2; ++u)
+#pragma unroll
     for (int r = 0; r < RB; ++r) acc[u][r].x = acc[u][r].y = 0;
   for (int i0 = 0; i0 < S; i0 += 64) {
     const int ni = min(64, S - i0);
@@ -1416,6 +1423,7 @@ __global__ __launch_bounds__(NT) void k_radiate_multi(const V2* __restrict__ V, 
       if (r < nr && i < ni) xs[r][i] = x[(size_t)(r0 + r) * n + p0 + i0 + i];
     }
     __syncthreads();
+#pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int j = threadIdx.x + u * NT;
       if (j < J) {
@@ -1427,11 +1435,14 @@ __global__ __launch_bounds__(NT) void k_radiate_multi(const V2* __restrict__ V, 
       }
     }
   }
+#pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int j = threadIdx.x + u * NT;
     if (j < J) {
       const int c = j / Q, q = j % Q;
-      for (int r = 0; r < nr; ++r) s[((size_t)b * 4 * R + c * R + r0 + r) * Q + q] = acc[u][r];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) s[((size_t)b * 4 * R + c * R + r0 + r) * Q + q] = acc[u][r];
     }
   }
 }
@@ -1590,7 +1601,9 @@ __global__ __launch_bounds__(NT) void k_recv_multi(const typename C2<T>::type* _
         acc[r].y += __shfl_xor(acc[r].y, off);
       }
     if (c == 0 && row < S) {
-      for (int r = 0; r < nr; ++r) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (r >= nr) break;
         V2* yp = y + (size_t)(r0 + r) * n + p0 + row;
         V2 out = *yp;
         out.x += acc[r].x;
@@ -1768,6 +1781,11 @@ static int tm_split_rows(int M) {
 static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst, hipStream_t st,
                          bool translation) {
   const TileList& tl = p.by_nrhs[nrhs];
+  if (tl.width == 128) {
+    // split form on the sources split once per level
+    launch_om_split2(p, tl, nrhs, p.s6, dst, st);
+    return;
+  }
   GemmTiles g;
   g.A = static_cast<const float2*>(p.A);
   g.a_stride = p.a_stride;
@@ -1905,6 +1923,15 @@ static dim3 csr_grid(int64_t nbox, int J) {
   return dim3((unsigned)nbox, (unsigned)y);
 }
 
+// whether the offset-major product of a plan at R right-hand sides reads the
+// pre-split sources (the autotuner's choice; tiles are built before the
+// operator's first product at R)
+static bool presplit(const GemmPlan& p, int R) {
+  if ((int)p.by_nrhs.size() <= R || !p.by_nrhs[R].tile_group)
+    throw std::runtime_error("product tiles for this number of right-hand sides not built");
+  return p.by_nrhs[R].width == 128;
+}
+
 template <typename T>
 void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hipStream_t st, PhaseTimer* tm) {
   using V2 = typename C2<T>::type;
@@ -1951,6 +1978,17 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   const bool tmode = mfma && R > d.pair_cap;
   bool v2 = tmode && NC >= TM2_MIN_COLS;
   for (const auto& lv : d.lev) v2 = v2 && lv.s6 != nullptr;     // (allocated for split operators only)
+  // split operators at up to pair_cap right-hand sides: the offset-major
+  // products that the autotuner put on the pre-split sources need the level's
+  // sources (which 0) or potentials (which 1) split into its s6 planes
+  const bool om2 = mfma && !tmode && d.om2;
+  auto need = [&](int l, int which) {
+    if (v2) return true;
+    if (!om2) return false;
+    const auto& lv = d.lev[l - l0];
+    if (which == 1) return l < L && presplit(d.lev[l + 1 - l0].down, R);
+    return (lv.npairs > 0 && presplit(lv.trans, R)) || (l > l0 && presplit(lv.up, R));
+  };
   // fp16 split form: the largest exponent of every level's sources (slot
   // 2 (l - l0)) and potentials (2 (l - l0) + 1), taken once the vector is
   // complete and before the products that read it
@@ -2031,7 +2069,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
   }
   if (tm) tm->mark(st, 1, L, K_RADIATE);
   absmax(L, 0, s + LL.s_off * R);
-  if (v2) split_of(L, 0, s + LL.s_off * R, st);
+  if (need(L, 0)) split_of(L, 0, s + LL.s_off * R, st);
   // the near field starts once radiation (also HBM-bound) is done, and runs
   // beside the transfers and translations
   if (overlap) fork_near();
@@ -2060,7 +2098,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                   st);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
       absmax(l - 1, 0, s + p.s_off * R);
-      if (v2) split_of(l - 1, 0, s + p.s_off * R, st);
+      if (need(l - 1, 0)) split_of(l - 1, 0, s + p.s_off * R, st);
     } else if (mfma) {
       launch_tiles(c.up, R, s + c.s_off * R, c.child_out, st, false);
       if (tm) tm->mark(st, -1, l, K_UP_GEMM);
@@ -2069,6 +2107,7 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
                                                                    NC * p.Q);
       if (tm) tm->mark(st, -1, l, K_UP_REDUCE);
       absmax(l - 1, 0, s + p.s_off * R);
+      if (need(l - 1, 0)) split_of(l - 1, 0, s + p.s_off * R, st);
     } else {
       dim3 grid((unsigned)((p.Q + WAVE - 1) / WAVE), (unsigned)p.nbox);
       k_upward<T><<<grid, NT, 0, st>>>(static_cast<const V2*>(c.Ccm), s + c.s_off, s + p.s_off, p.child_ptr,
@@ -2103,11 +2142,15 @@ void launch_matvec_leaf(const DevOp<T>& d, const void* xl_, void* yl_, int R, hi
     if (tmode) {
       // the parent level's potentials split into its s6 planes (its
       // translations, which read them as sources, were launched before)
-      if (v2) split_of(l - 1, 1, o + p.s_off * R, st);
+      if (need(l - 1, 1)) split_of(l - 1, 1, o + p.s_off * R, st);
       tm_contract(c.down, c.dn_ptr, c.dn_src, c.dn_slot, c.nbox, c.Q, p.Q, o + p.s_off * R, p.s6, o + c.s_off * R, 1,
                   st);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
     } else if (mfma) {
+      // the parent level's potentials split into its s6 planes if the
+      // product reads them there (its translations, which read the sources
+      // there, were launched before)
+      if (need(l - 1, 1)) split_of(l - 1, 1, o + p.s_off * R, st);
       launch_tiles(c.down, R, o + p.s_off * R, o + c.s_off * R, st, false);
       if (tm) tm->mark(st, -1, l, K_DOWN_GEMM);
     } else {

@@ -279,12 +279,13 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
     c2[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
     c3[r] = tm_f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  uint4 ra[NAT];
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // (see k_translate_tm_split2)
+  u32x4 ra[NAT];
   float2 rb[8];
   auto load = [&](int j, int ci) {
     const int slot = g.il_slot[j], src = g.il_src[j];
     const int k0 = ci * KC;
-    const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp + k0);
+    const u32x4* A = reinterpret_cast<const u32x4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp + k0);
 #pragma unroll
     for (int i = 0; i < NAT; ++i)
       if (aok[i]) ra[i] = A[oa[i]];
@@ -306,7 +307,7 @@ __device__ __forceinline__ void translate_tm_split_body(const TmArgs& g) {
 #pragma unroll
     for (int i = 0; i < NAT; ++i) {
       const int e = t + i * TM_NT;
-      if (aok[i]) Al(e / (ROWS * 4), (e / 4) % ROWS, e % 4) = ra[i];
+      if (aok[i]) *reinterpret_cast<u32x4*>(&Al(e / (ROWS * 4), (e / 4) % ROWS, e % 4)) = ra[i];
     }
     unsigned short h[6][8];
 #pragma unroll
@@ -523,23 +524,27 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
         cre[i][j][u] = 0.f;
         cim[i][j][u] = 0.f;
       }
-  uint4 ra[NAT], rb[NBT];
+  // staging registers as native vectors (copies of HIP's uint4 struct can
+  // stay in private memory)
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 ra[NAT], rb[NBT];
   auto load = [&](int j, int kc) {
     const int slot = g.il_slot[j], src = g.il_src[j];
-    const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp) + kc * 2;
-    const uint4* B = g.s6 + (((size_t)src * KC + kc) * NP) * NC * 2 + (size_t)c0 * 2;
+    const u32x4* A =
+        reinterpret_cast<const u32x4*>(g.Asplit + (size_t)slot * 6 * plane + (size_t)r0 * Kp) + kc * 2;
+    const u32x4* B = reinterpret_cast<const u32x4*>(g.s6) + (((size_t)src * KC + kc) * NP) * NC * 2 + (size_t)c0 * 2;
 #pragma unroll
     for (int i = 0; i < NAT; ++i) ra[i] = A[oa[i]];
 #pragma unroll
     for (int i = 0; i < NBT; ++i) rb[i] = B[ob[i]];
   };
   auto store = [&](int buf) {
-    uint4* Ab = lds + buf * (AQ + BQ);
-    uint4* Bb = Ab + AQ;
+    u32x4* Ab = reinterpret_cast<u32x4*>(lds) + buf * (AQ + BQ);
+    u32x4* Bb = Ab + AQ;
 #pragma unroll
     for (int i = 0; i < NAT; ++i) Ab[t + i * TM_NT] = ra[i];
 #pragma unroll
-    for (int i = 0; i < NBT; ++i) Bb[t + i * TM_NT] = bok[i] ? rb[i] : make_uint4(0u, 0u, 0u, 0u);
+    for (int i = 0; i < NBT; ++i) Bb[t + i * TM_NT] = bok[i] ? rb[i] : u32x4{0u, 0u, 0u, 0u};
   };
   auto mfma = [&](int buf) {
     const uint4* Ab = lds + buf * (AQ + BQ);
@@ -633,12 +638,193 @@ __global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, COLS =
   }
 }
 
+// Offset-major split products (groups = offset slots or octants, the pairs of a
+// group sharing one matrix; up to 31 right-hand sides), with the operands of
+// k_translate_tm_split2: A from the pre-split planes [g][6][Mr][Kp] (first
+// four), B from the sources split once per level (s4[box][kc][plane][NC][16],
+// k_split_sources), complex products as four real hi*hi + hi*lo + lo*hi
+// products on 32x32x16 MFMAs.  A workgroup takes a tile of 128 (pair,
+// channel) columns of one group (tile lists of width 128: col_src / col_dst
+// hold the FP32 offsets (src NC + c) K and (dst NC + c) M of every column)
+// and a block of ROWS rows; wave w owns columns 32 w .. 32 w + 31 and every
+// row.  Chunks of 16 k are staged through registers into one of two LDS
+// buffers while the MFMAs of the other run; the results leave through LDS in
+// runs of consecutive rows of each column (one pair's NC columns are M
+// contiguous rows each), written or added to the destination.
+struct OmArgs {
+  const unsigned short* Asplit;
+  int Mr, Kp, M, K, NC;
+  const uint4* s6;
+  float2* dst;
+  int accumulate;
+  int64_t ntiles;
+  const int32_t* tile_group;
+  const int32_t* tile_ncols;
+  const int64_t* col_src;
+  const int64_t* col_dst;
+  int a_exp;
+  const int* bexp;
+};
+
+template <int ROWS, int F>
+__global__ __launch_bounds__(TM_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_om_split2(OmArgs g) {
+  constexpr int NP = 4;
+  constexpr int COLS = 128;                                    // 32 per wave
+  constexpr int RTW = ROWS / 32;
+  constexpr int AQ = NP * ROWS * 2, BQ = NP * COLS * 2;        // uint4 per buffer
+  constexpr int NAT = AQ / TM_NT;
+  static_assert(AQ % TM_NT == 0 && BQ == 4 * TM_NT, "staging must split evenly");
+  __shared__ uint4 lds[2 * (AQ + BQ)];
+  __shared__ int64_t cdst[COLS];
+  const int nrb = (int)gridDim.y;
+  const int64_t lin = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+  const int64_t per = (g.ntiles + 7) / 8, seq = lin / 8;
+  const int64_t tile = (lin % 8) * per + seq / nrb;
+  if (tile >= g.ntiles) return;
+  const int r0 = (int)(seq % nrb) * ROWS;
+  const int t = threadIdx.x, lane = t % TM_WAVE, w = t / TM_WAVE;
+  const int cnt = g.tile_ncols[tile];
+  const int NC = g.NC, M = g.M, K = g.K, Kp = g.Kp, KC = g.Kp / 16;
+  const size_t plane = (size_t)g.Mr * Kp;
+  if (t < COLS) cdst[t] = g.col_dst[tile * COLS + t];
+  const bool active = 32 * w < cnt;
+  // A element e = t + i TM_NT of a chunk = (plane e / (2 ROWS), row
+  // (e / 2) % ROWS, half e % 2): planes advance by TM_NT / (2 ROWS) per i, the
+  // row and half are the thread's own; B: thread t takes column t / 2, half
+  // t % 2 of every plane
+  static_assert(TM_NT % (2 * ROWS) == 0, "A staging: whole planes per step");
+  const int oa0 = (t / (2 * ROWS)) * (int)(plane / 8) + ((t / 2) % ROWS) * (Kp / 8) + t % 2;
+  const int oastep = TM_NT / (2 * ROWS) * (int)(plane / 8);
+  const int bcol = t / 2, bhf = t % 2;
+  const bool bok = bcol < cnt;
+  // (32-bit offsets in uint4: a level's split sources stay below 2^31 of
+  // them, checked by the host)
+  unsigned bbase;
+  {
+    const int64_t q = g.col_src[tile * COLS + min(bcol, cnt - 1)] / K;     // src NC + c
+    const int64_t box = q / NC, c = q % NC;
+    bbase = (unsigned)((box * KC * NP * NC + c) * 2 + bhf);
+  }
+  const unsigned bstep = (unsigned)(NP * NC * 2);                // uint4 per chunk of one box
+  const uint4* A = reinterpret_cast<const uint4*>(g.Asplit + (size_t)g.tile_group[tile] * 6 * plane + (size_t)r0 * Kp);
+  tm_f32x16 cre[RTW], cim[RTW];
+#pragma unroll
+  for (int i = 0; i < RTW; ++i)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      cre[i][u] = 0.f;
+      cim[i][u] = 0.f;
+    }
+  // staging registers as native vectors (HIP's uint4 struct copies kept them
+  // in private memory)
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 ra[NAT], rb[NP];
+  const u32x4* A4 = reinterpret_cast<const u32x4*>(A);
+  const u32x4* S4 = reinterpret_cast<const u32x4*>(g.s6);
+  u32x4* L4 = reinterpret_cast<u32x4*>(lds);
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int i = 0; i < NAT; ++i) ra[i] = (A4 + kc * 2)[oa0 + i * oastep];
+    const u32x4* B = S4 + (size_t)kc * bstep;
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl) rb[pl] = B[bbase + (unsigned)(pl * NC * 2)];
+  };
+  auto store = [&](int buf) {
+    u32x4* Ab = L4 + buf * (AQ + BQ);
+    u32x4* Bb = Ab + AQ;
+#pragma unroll
+    for (int i = 0; i < NAT; ++i) Ab[t + i * TM_NT] = ra[i];
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl) Bb[t + pl * TM_NT] = bok ? rb[pl] : u32x4{0u, 0u, 0u, 0u};
+  };
+  auto mfma = [&](int buf) {
+    const uint4* Ab = lds + buf * (AQ + BQ);
+    const uint4* Bb = Ab + AQ;
+    const int hf = lane / 32;
+    tm_bf16x8 av[RTW][NP];
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+      for (int pl = 0; pl < NP; ++pl)
+        av[rt][pl] = __builtin_bit_cast(tm_bf16x8, Ab[(pl * ROWS + rt * 32 + lane % 32) * 2 + hf]);
+    tm_bf16x8 bv[NP];
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl)
+      bv[pl] = __builtin_bit_cast(tm_bf16x8, Bb[(pl * COLS + w * 32 + lane % 32) * 2 + hf]);
+    const tm_bf16x8 nbih = tm_neg(bv[2]), nbil = tm_neg(bv[3]);
+#pragma unroll
+    for (int rt = 0; rt < RTW; ++rt) {
+      // re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br, each real product hi hi + hi lo + lo hi
+      cre[rt] = mfma32x32x16<F>(av[rt][0], bv[0], cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][0], bv[2], cim[rt]);
+      cre[rt] = mfma32x32x16<F>(av[rt][0], bv[1], cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][0], bv[3], cim[rt]);
+      cre[rt] = mfma32x32x16<F>(av[rt][1], bv[0], cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][1], bv[2], cim[rt]);
+      cre[rt] = mfma32x32x16<F>(av[rt][2], nbih, cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][2], bv[0], cim[rt]);
+      cre[rt] = mfma32x32x16<F>(av[rt][2], nbil, cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][2], bv[1], cim[rt]);
+      cre[rt] = mfma32x32x16<F>(av[rt][3], nbih, cre[rt]);
+      cim[rt] = mfma32x32x16<F>(av[rt][3], bv[0], cim[rt]);
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kc = 0; kc < KC; ++kc) {
+    const int buf = kc & 1;
+    const bool more = kc + 1 < KC;
+    if (more) load(kc + 1);                                  // in flight during the MFMAs
+    if (active) mfma(buf);
+    if (more) store(buf ^ 1);                                // the other buffer: last read two chunks ago
+    __syncthreads();
+  }
+  // output through LDS in passes of PC columns ([column][row], stride ROWS + 2)
+  constexpr int RS = ROWS + 2;
+  constexpr int LB = 2 * (AQ + BQ) * 16;
+  constexpr int PC = LB >= 64 * RS * 8 ? 64 : 32;
+  static_assert(LB >= PC * RS * 8, "LDS tile too small");
+  float2* otile = reinterpret_cast<float2*>(&lds[0]);
+  const int mloc = min(ROWS, M - r0);
+  const int oexp = F == SPLIT_FP16 ? -(g.a_exp + split_shift(*g.bexp)) : 0;
+  for (int p0 = 0; p0 < COLS; p0 += PC) {
+    __syncthreads();
+    if (w * 32 >= p0 && w * 32 < p0 + PC) {
+      const int lc = w * 32 - p0 + lane % 32;
+#pragma unroll
+      for (int rt = 0; rt < RTW; ++rt)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int row = rt * 32 + 8 * (u / 4) + 4 * (lane / 32) + u % 4;
+          otile[lc * RS + row] = F == SPLIT_FP16 ? make_float2(ldexpf(cre[rt][u], oexp), ldexpf(cim[rt][u], oexp))
+                                                 : make_float2(cre[rt][u], cim[rt][u]);
+        }
+    }
+    __syncthreads();
+    const int nc = min(PC, cnt - p0);
+    for (int e = t; e < nc * mloc; e += TM_NT) {
+      const int lc = e / mloc, row = e % mloc;
+      float2 v = otile[lc * RS + row];
+      float2* out = g.dst + cdst[p0 + lc] + r0 + row;
+      if (g.accumulate) {
+        const float2 ov = *out;
+        v.x += ov.x;
+        v.y += ov.y;
+      }
+      *out = v;
+    }
+  }
+}
+
 // Largest binary exponent of a set of values (fp16 operand scale): a
 // grid-stride loop keeps the maximum of frexp's exponent over the nonzero
-// values, the wave reduces it, and one atomic maximum per wave updates the
-// slot (integer maxima: the result does not depend on their order).
+// values, the workgroup reduces it, and one atomic maximum per workgroup
+// updates the slot (integer maxima: the result does not depend on their
+// order; few workgroups, since atomics on one address serialize).
 template <typename R>
 __global__ __launch_bounds__(TM_NT) void k_absmax_exp(const R* __restrict__ v, int64_t n, int* __restrict__ slot) {
+  __shared__ int red[TM_NT / TM_WAVE];
   int e = EXP_NONE;
   for (int64_t i = (int64_t)blockIdx.x * TM_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * TM_NT) {
     const R x = v[i];
@@ -650,7 +836,12 @@ __global__ __launch_bounds__(TM_NT) void k_absmax_exp(const R* __restrict__ v, i
   }
 #pragma unroll
   for (int o = TM_WAVE / 2; o > 0; o /= 2) e = max(e, __shfl_xor(e, o));
-  if (threadIdx.x % TM_WAVE == 0 && e > EXP_NONE) atomicMax(slot, e);
+  if (threadIdx.x % TM_WAVE == 0) red[threadIdx.x / TM_WAVE] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < TM_NT / TM_WAVE; ++w) e = max(e, red[w]);
+    if (e > EXP_NONE) atomicMax(slot, e);
+  }
 }
 
 __global__ void k_exp_reset(int* __restrict__ slots, int n) {
@@ -701,7 +892,8 @@ void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp
 void launch_absmax_exp(const void* v, int64_t n, bool fp64, int* slot, hipStream_t st) {
   if (n <= 0) return;
   const int64_t vals = 2 * n;
-  const unsigned nb = (unsigned)std::min<int64_t>((vals + TM_NT - 1) / TM_NT, 2048);
+  // at least 16 values per thread, at most 512 workgroups (two per CU)
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((vals + 16 * TM_NT - 1) / (16 * TM_NT), 512));
   if (fp64)
     k_absmax_exp<double><<<nb, TM_NT, 0, st>>>(static_cast<const double*>(v), vals, slot);
   else
@@ -743,6 +935,42 @@ void launch_split_sources(const void* s, int64_t nbox, int NC, int K, int Kp, vo
   else
     k_split_sources<0><<<nb, TM_NT, 0, st>>>(static_cast<const float2*>(s), nbox, NC, K, Kp,
                                              static_cast<uint4*>(s6), nullptr);
+}
+
+void launch_om_split2(const GemmPlan& p, const TileList& tl, int nrhs, const void* s6, void* dst, hipStream_t st) {
+  if (tl.ntiles == 0) return;
+  OmArgs g;
+  g.Asplit = static_cast<const unsigned short*>(p.A_split);
+  g.Mr = p.Mr;
+  g.Kp = p.Kp;
+  g.M = p.M;
+  g.K = p.K;
+  g.NC = 4 * nrhs;
+  g.s6 = static_cast<const uint4*>(s6);
+  g.dst = static_cast<float2*>(dst);
+  g.accumulate = p.accumulate;
+  g.ntiles = tl.ntiles;
+  g.tile_group = tl.tile_group;
+  g.tile_ncols = tl.tile_ncols;
+  g.col_src = tl.col_src;
+  g.col_dst = tl.col_dst;
+  g.a_exp = p.a_exp;
+  g.bexp = p.bexp;
+  const bool h = p.split_fmt == SPLIT_FP16;
+  const unsigned gx = (unsigned)((tl.ntiles + 7) / 8 * 8);
+  if (p.M > 64) {
+    const dim3 grid(gx, (unsigned)((p.M + 127) / 128));
+    if (h)
+      k_gemm_om_split2<128, 1><<<grid, TM_NT, 0, st>>>(g);
+    else
+      k_gemm_om_split2<128, 0><<<grid, TM_NT, 0, st>>>(g);
+  } else {
+    const dim3 grid(gx, 1);
+    if (h)
+      k_gemm_om_split2<64, 1><<<grid, TM_NT, 0, st>>>(g);
+    else
+      k_gemm_om_split2<64, 0><<<grid, TM_NT, 0, st>>>(g);
+  }
 }
 
 void launch_translate_tm(const TmArgs& g, int nrt, int rblocks, int ct, hipStream_t st) {

@@ -404,6 +404,33 @@ def test_matvec_multi_rhs_split_fp16(torch_dev, nesa, nrhs):
         assert err <= TOL["c64"], (r, err)
 
 
+@pytest.mark.parametrize("prec", ["split", "split_fp16"])
+@pytest.mark.parametrize("name,nrhs", [("sphere_3lev", 1), ("sphere_3lev", 8), ("sphere_3lev", 13), ("box", 3)])
+def test_split_offset_major_forms_agree(torch_dev, nesa, monkeypatch, prec, name, nrhs):
+    """The offset-major split products on sources split once per level
+    (32x32x16 MFMAs, 128-column tiles; the default) and the kernels that split
+    the sources themselves (16x16x32 MFMAs, NESA_OM2=0) compute the same
+    16-bit products in another summation order: both within the bound against
+    the oracle, and within a few FP32 roundings of each other."""
+    ref, tr, near, far = _case(nesa, name)
+    P = {"split": nesa.C64_SPLIT, "split_fp16": nesa.C64_SPLIT_FP16}[prec]
+    op = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
+    monkeypatch.setenv("NESA_OM2", "0")
+    op_old = nesa.op_create(tr, near, far, P, max_nrhs=nrhs)
+    monkeypatch.delenv("NESA_OM2")
+    X = synth.complex_normal((nrhs, ref.m.n), 60 + nrhs)
+    Y = _run(torch_dev, nesa, op, X, nrhs=nrhs).reshape(nrhs, -1)
+    Yo = _run(torch_dev, nesa, op_old, X, nrhs=nrhs).reshape(nrhs, -1)
+    tol = 1e-4 if prec == "split" else TOL["c64"]
+    X = X.reshape(nrhs, -1)
+    for r in sorted({0, nrhs - 1}):
+        yr = ref.matvec(X[r])
+        e, eo = (np.linalg.norm(v[r] - yr) / np.linalg.norm(yr) for v in (Y, Yo))
+        print("%s %s nrhs %d rhs %d: rel err pre-split %.2e, in-kernel split %.2e" % (name, prec, nrhs, r, e, eo))
+        assert e <= tol and eo <= tol
+    assert np.linalg.norm(Y - Yo) <= 2e-6 * np.linalg.norm(Yo)
+
+
 @pytest.mark.parametrize("nrhs", [1, 37])
 def test_split_fp16_scale_follows_the_input(torch_dev, nesa, nrhs):
     """The fp16 scales are found from the data in every product: inputs scaled
