@@ -341,7 +341,8 @@ static bool g_tune_loaded = false;
 // "chunked" / "resident" / "direct" / "narrow" = only that kernel family
 // (resident and direct where K <= 84, narrow = chunked with 32-column tiles
 // where the row tiles split over the waves, gauss = chunked with three real
-// MFMAs per complex product; else the plain chunked kernel)
+// MFMAs per complex product, presplit = split plans on the pre-split sources;
+// else the plain chunked kernel)
 static int autotune_mode() {
   const char* e = std::getenv("NESA_AUTOTUNE");
   if (!e) return 1;
@@ -352,6 +353,7 @@ static int autotune_mode() {
   if (v == "direct") return 4;
   if (v == "narrow") return 5;
   if (v == "gauss") return 6;
+  if (v == "presplit") return 7;
   return 1;
 }
 
@@ -399,7 +401,7 @@ static bool set_blocking(nesa::GemmPlan& p, nesa::TileList& tl, const TuneChoice
   if (c.tpw < 0 && (p.A_split || (c.tpw != -13 && c.tpw != -21) || p.K > -4 * c.tpw ||
                     (c.nrt != 1 && c.nrt != 2 && c.nrt != 4)))
     return false;
-  if (c.width != (tl.width) || (c.width == 32 && (c.tpw != 0 || p.A_split || c.nrt % 2))) return false;
+  if (c.width != (tl.width) || (c.width == 32 && (c.tpw != 0 || c.nrt % 2 || (p.A_split && c.m3)))) return false;
   if (c.m3 && (c.tpw != 0 || p.A_split)) return false;
   tl.nrt = c.nrt;
   tl.m3 = c.m3;
@@ -439,9 +441,10 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   const bool res_ok = !p.A_split && p.K <= 84;
   // region ordering only pays when a group has many pairs per region
   const bool reg_ok = p.ngroups > 0 && (int64_t)p.h_src.size() / p.ngroups >= 64;
-  // (split plans with and without the pre-split candidate keep separate choices)
-  const TuneKey key{(translation ? 1 : (p.accumulate ? 3 : 2)) + 10 * mode, p.A_split ? (p.s6 ? 2 : 1) : 0, p.M, p.K,
-                    nrhs, base_tiles};
+  // (split plans of either 16-bit format, with and without the pre-split
+  // candidate, keep separate choices)
+  const TuneKey key{(translation ? 1 : (p.accumulate ? 3 : 2)) + 10 * mode,
+                    p.A_split ? 1 + (p.s6 ? 1 : 0) + 2 * p.split_fmt : 0, p.M, p.K, nrhs, base_tiles};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_load_locked();
@@ -477,7 +480,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
                 (mode == 6 && p.A_split);
         if (!use) continue;
         if (mode != 5) cand.push_back({nrt, 0, 0, regions, 64, m3});
-        if (!p.A_split && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, m3});
+        if ((!p.A_split || !m3) && nrt % 2 == 0) cand.push_back({nrt, 0, 0, regions, 32, m3});
       }
       if (res_ok && (mode == 1 || mode == 3))
         for (int tpw : {4, 16}) cand.push_back({nrt, tpw, p.K <= 52 ? 52 : 84, regions, 64, 0});
@@ -488,7 +491,7 @@ static void tune_plan(nesa_op* op, nesa::GemmPlan& p, int nrhs, const void* src,
   }
   // split plans: the kernel on the sources split once per level (tiles of
   // 128 columns, both orderings)
-  if (p.A_split && p.s6 && mode == 1)
+  if (p.A_split && p.s6 && (mode == 1 || mode == 7))
     for (int regions : {1, 8})
       if (regions == 1 || reg_ok) cand.push_back({p.M > 64 ? 8 : 4, 0, 0, regions, 128, 0});
   if (cand.empty()) cand.push_back(dflt);

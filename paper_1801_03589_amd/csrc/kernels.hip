@@ -501,33 +501,41 @@ __device__ __forceinline__ void cgemm_tiles_body(const GemmTiles& g) {
 // before its split, and the results by 2^-(a_exp + shift).
 typedef s16x8 bf16x8;
 
-template <int NRT, int F>
+// CT = column tiles of 16 per workgroup: 4 (64-column tiles, wave w owns
+// column tile w and every row tile) or 2 (32-column tiles for groups with few
+// pairs, wave w owns column tile w % 2 and half of the row tiles).
+template <int NRT, int F, int CT>
 __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, const unsigned short* __restrict__ As,
                                                         int Kp, int a_exp, const int* __restrict__ bexp) {
   static_assert(TR_KC == 32, "one bf16 MFMA k-step per chunk");
+  static_assert(CT == 4 || (CT == 2 && NRT % 2 == 0), "32-column tiles split an even number of row tiles");
+  constexpr int COLS = 16 * CT;                   // columns of a tile
+  constexpr int RPW = NRT * CT / 4;               // row tiles per wave
+  constexpr int NB = TR_KC * COLS / NT;           // float2 of B per thread per chunk
   const int bshift = split_src_shift<F>(bexp);
   const int oexp = -(a_exp + bshift);
   __shared__ uint4 Al[4][NRT * 16][4];                        // [plane][row][8 k], split planes of A
-  __shared__ float2 Bs[TR_COLS][TR_KC + 1];                   // [column][k] FP32 B, split in place
-  __shared__ int64_t col_src[TR_COLS];
-  __shared__ int64_t col_dst[TR_COLS];
+  __shared__ float2 Bs[COLS][TR_KC + 1];                      // [column][k] FP32 B, split in place
+  __shared__ int64_t col_src[COLS];
+  __shared__ int64_t col_dst[COLS];
   const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   if (tile >= g.ntiles) return;
   const int r0 = blockIdx.y * NRT * 16;
   const int cnt = g.tile_ncols[tile];
   const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
   const int K = g.K, M = g.M;
-  if (t < TR_COLS) {
-    col_src[t] = g.col_src[tile * TR_COLS + t];
-    col_dst[t] = g.col_dst[tile * TR_COLS + t];
+  if (t < COLS) {
+    col_src[t] = g.col_src[tile * COLS + t];
+    col_dst[t] = g.col_dst[tile * COLS + t];
   }
   __syncthreads();
-  const bool active = 16 * w < cnt;
+  const int ct = w % CT, rt0 = (w / CT) * RPW;     // this wave's column tile and first row tile
+  const bool active = 16 * ct < cnt;
   const size_t plane = (size_t)g.Mr * Kp;
   const unsigned short* Ag = As + (size_t)g.tile_group[tile] * 6 * plane + (size_t)r0 * Kp;   // planes 0-3
-  f32x4 cre[NRT], cim[NRT];
+  f32x4 cre[RPW], cim[RPW];
 #pragma unroll
-  for (int r = 0; r < NRT; ++r) {
+  for (int r = 0; r < RPW; ++r) {
     cre[r] = f32x4{0.f, 0.f, 0.f, 0.f};
     cim[r] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -542,13 +550,13 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
     const int pl = e / (NRT * 16 * 4), row = (e / 4) % (NRT * 16), qu = e % 4;
     a_ptr[i] = reinterpret_cast<const u32x4*>(Ag + pl * plane + (size_t)row * Kp + 8 * qu);
   }
-  // B staging: TR_NB float2 per thread per chunk
-  float2 rb[TR_NB];
-  const float2* b_ptr[TR_NB];
-  int b_k[TR_NB];
-  bool b_ok[TR_NB];
+  // B staging: NB float2 per thread per chunk
+  float2 rb[NB];
+  const float2* b_ptr[NB];
+  int b_k[NB];
+  bool b_ok[NB];
 #pragma unroll
-  for (int i = 0; i < TR_NB; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const int e = t + i * NT;
     const int col = e / TR_KC;
     b_k[i] = e % TR_KC;
@@ -561,7 +569,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
 #pragma unroll
     for (int i = 0; i < NRT; ++i) ra[i] = a_ptr[i][k0 / 8];
 #pragma unroll
-    for (int i = 0; i < TR_NB; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
+    for (int i = 0; i < NB; ++i) rb[i] = b_ptr[i][min(k0 + b_k[i], K - 1)];
   };
   load(0);
   for (int k0 = 0; k0 < K; k0 += TR_KC) {
@@ -572,7 +580,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
       *reinterpret_cast<u32x4*>(&Al[e / (NRT * 16 * 4)][(e / 4) % (NRT * 16)][e % 4]) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < TR_NB; ++i) {
+    for (int i = 0; i < NB; ++i) {
       const int e = t + i * NT;
       Bs[e / TR_KC][e % TR_KC] = (k0 + b_k[i] < K && b_ok[i]) ? rb[i] : make_float2(0.f, 0.f);
     }
@@ -581,7 +589,7 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
     if (active) {
       // B fragments of this wave's column tile as bf16 hi / lo planes
       bf16x8 brh, brl, bih, bil, nbih, nbil;
-      const float2* bcol = &Bs[w * 16 + lane % 16][8 * (lane / 16)];
+      const float2* bcol = &Bs[ct * 16 + lane % 16][8 * (lane / 16)];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         float2 v = bcol[j];
@@ -597,8 +605,8 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
         nbil[j] = __builtin_bit_cast(__bf16, (unsigned short)(l ^ 0x8000u));
       }
 #pragma unroll
-      for (int r = 0; r < NRT; ++r) {
-        const int row = r * 16 + lane % 16, qu = lane / 16;
+      for (int r = 0; r < RPW; ++r) {
+        const int row = (rt0 + r) * 16 + lane % 16, qu = lane / 16;
         const bf16x8 arh = __builtin_bit_cast(bf16x8, Al[0][row][qu]);
         const bf16x8 arl = __builtin_bit_cast(bf16x8, Al[1][row][qu]);
         const bf16x8 aih = __builtin_bit_cast(bf16x8, Al[2][row][qu]);
@@ -618,14 +626,14 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
       }
     }
   }
-  const int col = w * 16 + lane % 16;
+  const int col = ct * 16 + lane % 16;
   if (col < cnt) {
     float2* out = g.dst + col_dst[col];
 #pragma unroll
-    for (int r = 0; r < NRT; ++r) {
+    for (int r = 0; r < RPW; ++r) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = r0 + r * 16 + 4 * (lane / 16) + i;
+        const int row = r0 + (rt0 + r) * 16 + 4 * (lane / 16) + i;
         if (row < M) {
           float2 v = make_float2(cre[r][i], cim[r][i]);
           if (F == SPLIT_FP16) v = make_float2(ldexpf(v.x, oexp), ldexpf(v.y, oexp));
@@ -641,15 +649,15 @@ __device__ __forceinline__ void cgemm_tiles_bf16x3_body(const GemmTiles& g, cons
   }
 }
 
-template <int NRT, int F>
+template <int NRT, int F, int CT>
 __global__ __launch_bounds__(NT) void k_translate_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp,
                                                               int a_exp, const int* bexp) {
-  cgemm_tiles_bf16x3_body<NRT, F>(g, As, Kp, a_exp, bexp);
+  cgemm_tiles_bf16x3_body<NRT, F, CT>(g, As, Kp, a_exp, bexp);
 }
-template <int NRT, int F>
+template <int NRT, int F, int CT>
 __global__ __launch_bounds__(NT) void k_transfer_gemm_bf16x3(GemmTiles g, const unsigned short* As, int Kp,
                                                              int a_exp, const int* bexp) {
-  cgemm_tiles_bf16x3_body<NRT, F>(g, As, Kp, a_exp, bexp);
+  cgemm_tiles_bf16x3_body<NRT, F, CT>(g, As, Kp, a_exp, bexp);
 }
 
 // Resident-A variant for small K (K <= KT): a workgroup takes a run of `tpw`
@@ -1850,6 +1858,32 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
 #undef NESA_RES
   }
   dim3 grid((unsigned)((tl.ntiles + 7) / 8 * 8), (unsigned)rblocks);
+  if (tl.width == 32 && p.A_split) {
+    // split form, 32-column tiles: waves split the rows (NRT even)
+    const unsigned short* As = static_cast<const unsigned short*>(p.A_split);
+    const bool h = p.split_fmt == SPLIT_FP16;
+    const int ae = h ? p.a_exp : 0;
+    const int* be = h ? p.bexp : nullptr;
+#define NESA_SPLIT32(N)                                                              \
+  if (h) {                                                                           \
+    if (translation)                                                                 \
+      k_translate_gemm_bf16x3<N, 1, 2><<<grid, NT, 0, st>>>(g, As, p.Kp, ae, be);    \
+    else                                                                             \
+      k_transfer_gemm_bf16x3<N, 1, 2><<<grid, NT, 0, st>>>(g, As, p.Kp, ae, be);     \
+  } else if (translation) {                                                          \
+    k_translate_gemm_bf16x3<N, 0, 2><<<grid, NT, 0, st>>>(g, As, p.Kp, ae, be);      \
+  } else {                                                                           \
+    k_transfer_gemm_bf16x3<N, 0, 2><<<grid, NT, 0, st>>>(g, As, p.Kp, ae, be);       \
+  }                                                                                  \
+  return;
+    switch (nrt) {
+      case 2: NESA_SPLIT32(2)
+      case 4: NESA_SPLIT32(4)
+      case 6: NESA_SPLIT32(6)
+      default: NESA_SPLIT32(8)
+    }
+#undef NESA_SPLIT32
+  }
   if (tl.width == 32 && !p.A_split) {
     // 32-column tiles: waves split the rows (NRT even)
 #define NESA_TILES32(N)                                                   \
@@ -1877,13 +1911,13 @@ static void launch_tiles(const GemmPlan& p, int nrhs, const void* src, void* dst
     const unsigned short* As = static_cast<const unsigned short*>(p.A_split);                \
     if (p.split_fmt == SPLIT_FP16) {                                                         \
       if (translation)                                                                       \
-        k_translate_gemm_bf16x3<N, 1><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp);    \
+        k_translate_gemm_bf16x3<N, 1, 4><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp); \
       else                                                                                   \
-        k_transfer_gemm_bf16x3<N, 1><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp);     \
+        k_transfer_gemm_bf16x3<N, 1, 4><<<grid, NT, 0, st>>>(g, As, p.Kp, p.a_exp, p.bexp);  \
     } else if (translation) {                                                                \
-      k_translate_gemm_bf16x3<N, 0><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);           \
+      k_translate_gemm_bf16x3<N, 0, 4><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);        \
     } else {                                                                                 \
-      k_transfer_gemm_bf16x3<N, 0><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);            \
+      k_transfer_gemm_bf16x3<N, 0, 4><<<grid, NT, 0, st>>>(g, As, p.Kp, 0, nullptr);         \
     }                                                                                        \
   } else if (tl.m3) {                                                                       \
     if (translation)                                                                         \

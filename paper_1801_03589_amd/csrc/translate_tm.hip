@@ -892,8 +892,9 @@ void launch_split_planes(const void* D64, int64_t ngroups, int K, int Mr, int Kp
 void launch_absmax_exp(const void* v, int64_t n, bool fp64, int* slot, hipStream_t st) {
   if (n <= 0) return;
   const int64_t vals = 2 * n;
-  // at least 16 values per thread, at most 512 workgroups (two per CU)
-  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((vals + 16 * TM_NT - 1) / (16 * TM_NT), 512));
+  // at least 16 values per thread, at most 64 workgroups (their atomics on
+  // one address serialize: 512 of them took about 20 us)
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((vals + 16 * TM_NT - 1) / (16 * TM_NT), 64));
   if (fp64)
     k_absmax_exp<double><<<nb, TM_NT, 0, st>>>(static_cast<const double*>(v), vals, slot);
   else

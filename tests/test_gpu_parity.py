@@ -635,6 +635,36 @@ def test_matvec_kernel_families(torch_dev, nesa, monkeypatch, tmp_path, name, fa
         assert all(v == 0 for v in tpw) and all(v == 0 for v in m3)
 
 
+@pytest.mark.parametrize("prec,family", [("split", "chunked"), ("split", "narrow"), ("split", "presplit"),
+                                         ("split_fp16", "narrow"), ("split_fp16", "presplit")])
+@pytest.mark.parametrize("name", ["sphere_3lev", "box"])
+def test_split_kernel_families(torch_dev, nesa, monkeypatch, tmp_path, name, prec, family):
+    """Split products with the autotuner restricted to one kernel family (the
+    in-kernel split on 64- and 32-column tiles, on 32-column tiles only, or the
+    pre-split sources on 128-column tiles) match the oracle for one and five
+    right-hand sides, and the recorded blockings show the family that ran."""
+    monkeypatch.setenv("NESA_AUTOTUNE", family)
+    tune_file = tmp_path / "tune.txt"
+    monkeypatch.setenv("NESA_TUNE_FILE", str(tune_file))
+    ref, tr, near, far = _case(nesa, name)
+    P = {"split": nesa.C64_SPLIT, "split_fp16": nesa.C64_SPLIT_FP16}[prec]
+    op = nesa.op_create(tr, near, far, P, max_nrhs=5)
+    X = synth.complex_normal((5, ref.m.n), 81)
+    Y = _run(torch_dev, nesa, op, X, nrhs=5)
+    Y1 = _run(torch_dev, nesa, op, X[2])
+    tol = 1e-4 if prec == "split" else TOL["c64"]
+    for r in (0, 2, 4):
+        yr = ref.matvec(X[r])
+        err = np.linalg.norm(Y[r] - yr) / np.linalg.norm(yr)
+        print("%s %s %s rhs %d: rel err %.2e" % (name, prec, family, r, err))
+        assert err <= tol
+    assert np.linalg.norm(Y1 - ref.matvec(X[2])) <= tol * np.linalg.norm(Y1)
+    rows = [list(map(int, ln.split())) for ln in tune_file.read_text().splitlines() if ln.strip()]
+    width = [r[10] for r in rows if r[1] > 0]         # split plans
+    assert width, "no split blocking was tuned"
+    assert all(v in {"chunked": (32, 64), "narrow": (32,), "presplit": (128,)}[family] for v in width), width
+
+
 def test_product_on_user_stream_and_in_hip_graph(torch_dev, nesa):
     """The product on a caller's (non-default) stream equals the default-stream
     result bit for bit, and a HIP graph captured from it (side-stream fork and
