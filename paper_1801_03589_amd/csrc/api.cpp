@@ -1160,12 +1160,20 @@ static void learned_apply(nesa_mlp* h, nesa::DevOp<T>& d, const void* r, void* z
 }
 
 // ------------------------------------------------------------------ GMRES driver
+// Workgroups of the FP64 dot products (k_multidot): about four elements per
+// thread, at most 512 workgroups (on the 201,720-unknown sphere a GMRES(50)
+// iteration takes 1.156 ms with two or four elements per thread, 1.175 with
+// eight and 1.191 with one).
+static int dot_blocks(int64_t n) {
+  return (int)std::min<int64_t>(512, std::max<int64_t>(1, (n + 4 * 256 - 1) / (4 * 256)));
+}
+
 // Device workspace of one GMRES(m) solve (bytes), carved in this order:
 // basis V (m + 1 vectors), preconditioned basis Z (m vectors, flexible only),
 // b, x, w, tmp in leaf order, the FP64 coefficients and the block partials.
 static size_t gmres_workspace_bytes(int64_t n, int m, bool flex, size_t es) {
   auto r256 = [](size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; };
-  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  const int nblocks = dot_blocks(n);
   size_t b = r256((size_t)(m + 1) * n * es) + (flex ? r256((size_t)m * n * es) : 0) + 4 * r256(n * es);
   b += r256(sizeof(double2) * (2 * (m + 2) + 2)) + r256(sizeof(double2) * nblocks * (m + 2));
   return b;
@@ -1203,7 +1211,7 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       if (host) (void)hipHostFree(host);
     }
   };
-  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  const int nblocks = dot_blocks(n);
   char* Vb = static_cast<char*>(alloc((size_t)(m + 1) * n * es));
   char* Zb = flex ? static_cast<char*>(alloc((size_t)m * n * es)) : nullptr;
   void* bl = alloc(n * es);
@@ -1212,9 +1220,29 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
   void* tmp = alloc(n * es);
   double2* hd = static_cast<double2*>(alloc(sizeof(double2) * (2 * (m + 2) + 2)));
   double2* partial = static_cast<double2*>(alloc(sizeof(double2) * nblocks * (m + 2)));
+  // Pipelined Arnoldi (the allocating form): the device normalises v_{j+1}
+  // itself and step j + 1 is enqueued before the host reads step j's
+  // coefficients back, so the GPU does not wait for the host's Givens
+  // rotations; the read-backs alternate between two pinned slots, a third
+  // carries the solution coefficients.  The form without allocation (caller's
+  // workspace) keeps one slot and one synchronisation per step.
+  const bool ahead = ws == nullptr;
+  const int HS = 2 * (m + 2) + 2;
   double2* hh = hws;
-  if (!hh) hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * (2 * (m + 2) + 2)), "hipHostMalloc");
+  if (!hh) hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * HS * (ahead ? 3 : 1)), "hipHostMalloc");
   Free guard{mine, hws ? nullptr : hh};
+  double2* hslot[2] = {hh, ahead ? hh + HS : hh};
+  double2* hy = ahead ? hh + 2 * HS : hh;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct EvFree {
+    hipEvent_t* e;
+    ~EvFree() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
+  if (ahead)
+    for (int i = 0; i < 2; ++i) hip_check(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming), "hipEventCreate");
   auto vec = [&](char* base, int i) { return static_cast<void*>(base + (size_t)i * n * es); };
   auto matvec = [&](const void* src, void* dst) { nesa::launch_matvec_leaf<T>(d, src, dst, 1, st, nullptr); };
   auto norm = [&](const void* v) {
@@ -1267,7 +1295,9 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
     std::fill(g.begin(), g.end(), cd(0, 0));
     g[0] = beta;
     int k = 0;
-    for (int j = 0; j < m; ++j) {
+    // Arnoldi step j up to its coefficients (read back into hslot[j % 2]) and,
+    // pipelined, v_{j+1} = w / ||w|| on the device
+    auto enqueue = [&](int j) {
       const void* src = vec(Vb, j);
       if (flex) {
         precond(vec(Vb, j), vec(Zb, j));
@@ -1280,12 +1310,26 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       nesa::launch_multidot<T>(Vb, n, j + 1, w, n, partial, nblocks, hd + (m + 2), 0, st);
       nesa::launch_combine<T>(Vb, n, j + 1, hd + (m + 2), w, n, -1.0, st);
       nesa::launch_multidot<T>(w, n, 1, w, n, partial, nblocks, hd + 2 * (m + 2), 0, st);
-      hip_check(hipMemcpyAsync(hh, hd, sizeof(double2) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, st),
+      hip_check(hipMemcpyAsync(hslot[j % 2], hd, sizeof(double2) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, st),
                 "hipMemcpyAsync");
-      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      if (ahead) {
+        hip_check(hipEventRecord(ev[j % 2], st), "hipEventRecord");
+        nesa::launch_scale_norm<T>(w, vec(Vb, j + 1), n, hd + 2 * (m + 2), st);
+      }
+    };
+    enqueue(0);
+    for (int j = 0; j < m; ++j) {
+      // (pipelined: step j + 1 runs while the host finishes step j; if the
+      // cycle ends at j its result is not used)
+      if (ahead && j + 1 < m) enqueue(j + 1);
+      if (ahead)
+        hip_check(hipEventSynchronize(ev[j % 2]), "hipEventSynchronize");
+      else
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      const double2* hc = hslot[j % 2];
       for (int i = 0; i <= j; ++i)
-        H[(size_t)j * (m + 1) + i] = cd(hh[i].x + hh[m + 2 + i].x, hh[i].y + hh[m + 2 + i].y);
-      const double hn = std::sqrt(std::max(0.0, hh[2 * (m + 2)].x));
+        H[(size_t)j * (m + 1) + i] = cd(hc[i].x + hc[m + 2 + i].x, hc[i].y + hc[m + 2 + i].y);
+      const double hn = std::sqrt(std::max(0.0, hc[2 * (m + 2)].x));
       bool finite = std::isfinite(hn);
       for (int i = 0; i <= j && finite; ++i) finite = std::isfinite(std::abs(H[(size_t)j * (m + 1) + i]));
       if (!finite) {
@@ -1332,7 +1376,10 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       k = j + 1;
       push_hist(std::abs(g[j + 1]) / nb);
       if (std::abs(g[j + 1]) / nb <= prm.tol || iters >= prm.max_iters || hn == 0) break;
-      nesa::launch_scale<T>(w, vec(Vb, j + 1), n, 1.0 / hn, st);
+      if (!ahead && j + 1 < m) {
+        nesa::launch_scale<T>(w, vec(Vb, j + 1), n, 1.0 / hn, st);
+        enqueue(j + 1);
+      }
     }
     if (status != NESA_OK) break;
     if (discard) {                        // restart from the same x with the base preconditioner
@@ -1345,8 +1392,10 @@ static int gmres_one(nesa_op* op, nesa::DevOp<T>& d, const void* b_c, void* x_c,
       for (int c2 = i + 1; c2 < k; ++c2) acc -= H[(size_t)c2 * (m + 1) + i] * y[c2];
       y[i] = acc / H[(size_t)i * (m + 1) + i];
     }
-    for (int i = 0; i < k; ++i) hh[i] = make_double2(y[i].real(), y[i].imag());
-    hip_check(hipMemcpyAsync(hd, hh, sizeof(double2) * k, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    // (pipelined: a step enqueued past the end of the cycle may still be
+    // copying into hslot; the coefficients go through their own slot)
+    for (int i = 0; i < k; ++i) hy[i] = make_double2(y[i].real(), y[i].imag());
+    hip_check(hipMemcpyAsync(hd, hy, sizeof(double2) * k, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     nesa::launch_combine<T>(flex ? Zb : Vb, n, k, hd, xl, n, +1.0, st);
     matvec(xl, tmp);
     nesa::launch_sub<T>(bl, tmp, vec(Vb, 0), n, st);
@@ -1401,7 +1450,7 @@ static int gmres_batch(nesa_op* op, nesa::DevOp<float>& d, const void* b_c, void
     }
   } guard{mine, hh};
   hip_check(hipHostMalloc((void**)&hh, sizeof(double2) * HS * R), "hipHostMalloc");
-  const int nblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  const int nblocks = dot_blocks(n);
   double2* hd = static_cast<double2*>(alloc(sizeof(double2) * HS * R));
   double2* partial = static_cast<double2*>(alloc(sizeof(double2) * nblocks * (m + 2)));
   // product input / output and preconditioned vectors, one slot per RHS; the

@@ -267,6 +267,9 @@ void launch_combine(const void* basis, int64_t ld, int nvec, const double2* h, v
                     hipStream_t st);
 template <typename T>
 void launch_scale(const void* x, void* y, int64_t n, double alpha, hipStream_t st);
+// y = x / sqrt(nrm->x) (nrm on the device; zero vector for a zero norm)
+template <typename T>
+void launch_scale_norm(const void* x, void* y, int64_t n, const double2* nrm, hipStream_t st);
 template <typename T>
 void launch_sub(const void* a, const void* b, void* y, int64_t n, hipStream_t st);
 template <typename T>

@@ -1634,15 +1634,20 @@ __global__ __launch_bounds__(NT) void k_multidot(const V* __restrict__ basis, in
   for (int i0 = 0; i0 < nvec; i0 += MD_CH) {
     const int ni = min(MD_CH, nvec - i0);
     double2 acc[MD_CH];
+#pragma unroll
     for (int i = 0; i < MD_CH; ++i) acc[i] = make_double2(0, 0);
     for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
       const V we = w[e];
+      // all MD_CH loads issued before the sums (a guarded load per vector
+      // waited for each in turn); past the last vector the chunk reads the
+      // last one again, and those sums are never stored
+      V b[MD_CH];
+#pragma unroll
+      for (int i = 0; i < MD_CH; ++i) b[i] = basis[(size_t)(i0 + min(i, ni - 1)) * ld + e];
+#pragma unroll
       for (int i = 0; i < MD_CH; ++i) {
-        if (i < ni) {
-          const V b = basis[(size_t)(i0 + i) * ld + e];
-          acc[i].x += (double)b.x * (double)we.x + (double)b.y * (double)we.y;
-          acc[i].y += (double)b.x * (double)we.y - (double)b.y * (double)we.x;
-        }
+        acc[i].x += (double)b[i].x * (double)we.x + (double)b[i].y * (double)we.y;
+        acc[i].y += (double)b[i].x * (double)we.y - (double)b[i].y * (double)we.x;
       }
     }
     for (int i = 0; i < MD_CH; ++i) {
@@ -1722,6 +1727,21 @@ template <typename V>
 __global__ void k_scale(const V* __restrict__ x, V* __restrict__ y, int64_t n, double alpha) {
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (e >= n) return;
+  V v = x[e];
+  v.x = (decltype(v.x))((double)v.x * alpha);
+  v.y = (decltype(v.y))((double)v.y * alpha);
+  y[e] = v;
+}
+
+// y = x / sqrt(nrm->x): the Arnoldi normalisation with the squared norm taken
+// on the device (FP64, the host's arithmetic: alpha = 1 / sqrt(max(0, s)));
+// a zero norm gives a zero vector
+template <typename V>
+__global__ void k_scale_norm(const V* __restrict__ x, V* __restrict__ y, int64_t n, const double2* __restrict__ nrm) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  const double s = nrm->x;
+  const double alpha = s > 0 ? 1.0 / sqrt(s) : 0.0;
   V v = x[e];
   v.x = (decltype(v.x))((double)v.x * alpha);
   v.y = (decltype(v.y))((double)v.y * alpha);
@@ -2266,6 +2286,11 @@ void launch_combine(const void* basis, int64_t ld, int nvec, const double2* h, v
   k_combine<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(basis), ld, nvec, h, static_cast<V2*>(w), n, sign);
 }
 template <typename T>
+void launch_scale_norm(const void* x, void* y, int64_t n, const double2* nrm, hipStream_t st) {
+  using V2 = typename C2<T>::type;
+  k_scale_norm<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(x), static_cast<V2*>(y), n, nrm);
+}
+template <typename T>
 void launch_scale(const void* x, void* y, int64_t n, double alpha, hipStream_t st) {
   using V2 = typename C2<T>::type;
   k_scale<V2><<<nblk(n), NT, 0, st>>>(static_cast<const V2*>(x), static_cast<V2*>(y), n, alpha);
@@ -2324,6 +2349,7 @@ void launch_blockdiag(const DevOp<T>& d, const void* r, void* z, hipStream_t st)
   template void launch_combine<T>(const void*, int64_t, int, const double2*, void*, int64_t, double,        \
                                   hipStream_t);                                                              \
   template void launch_scale<T>(const void*, void*, int64_t, double, hipStream_t);                           \
+  template void launch_scale_norm<T>(const void*, void*, int64_t, const double2*, hipStream_t);              \
   template void launch_sub<T>(const void*, const void*, void*, int64_t, hipStream_t);                       \
   template void launch_blockdiag<T>(const DevOp<T>&, const void*, void*, hipStream_t);                      \
   template void launch_near_apply<T>(const DevOp<T>&, const void*, const void*, void*, hipStream_t, int);
