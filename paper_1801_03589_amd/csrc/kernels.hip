@@ -1626,6 +1626,7 @@ __global__ __launch_bounds__(NT) void k_recv_multi(const typename C2<T>::type* _
 // partial[blk][i] = sum over the block's chunk of conj(basis_i) * w, FP64
 // accumulation; basis vectors taken 8 at a time.
 constexpr int MD_CH = 8;
+constexpr int MD_U = 4;      // elements per thread whose loads are in flight together
 template <typename V>
 __global__ __launch_bounds__(NT) void k_multidot(const V* __restrict__ basis, int64_t ld, int nvec,
                                                  const V* __restrict__ w, int64_t n, double2* __restrict__ partial) {
@@ -1636,19 +1637,31 @@ __global__ __launch_bounds__(NT) void k_multidot(const V* __restrict__ basis, in
     double2 acc[MD_CH];
 #pragma unroll
     for (int i = 0; i < MD_CH; ++i) acc[i] = make_double2(0, 0);
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
-      const V we = w[e];
-      // all MD_CH loads issued before the sums (a guarded load per vector
-      // waited for each in turn); past the last vector the chunk reads the
-      // last one again, and those sums are never stored
-      V b[MD_CH];
+    // MD_U elements per thread in flight at once, each with its MD_CH basis
+    // values: every load is issued before the sums (a guarded load per vector
+    // had waited for each in turn).  Past the last vector the chunk reads the
+    // last one again (those sums are never stored); past n an element reads
+    // element e0 with w taken as zero.  Each thread adds its elements in
+    // increasing order.
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t e0 = (int64_t)blockIdx.x * NT + threadIdx.x; e0 < n; e0 += MD_U * stride) {
+      V we[MD_U], b[MD_U][MD_CH];
 #pragma unroll
-      for (int i = 0; i < MD_CH; ++i) b[i] = basis[(size_t)(i0 + min(i, ni - 1)) * ld + e];
+      for (int u = 0; u < MD_U; ++u) {
+        const int64_t e = e0 + u * stride;
+        const int64_t ec = e < n ? e : e0;
+        we[u] = w[ec];
 #pragma unroll
-      for (int i = 0; i < MD_CH; ++i) {
-        acc[i].x += (double)b[i].x * (double)we.x + (double)b[i].y * (double)we.y;
-        acc[i].y += (double)b[i].x * (double)we.y - (double)b[i].y * (double)we.x;
+        for (int i = 0; i < MD_CH; ++i) b[u][i] = basis[(size_t)(i0 + min(i, ni - 1)) * ld + ec];
+        if (e >= n) we[u].x = we[u].y = 0;
       }
+#pragma unroll
+      for (int u = 0; u < MD_U; ++u)
+#pragma unroll
+        for (int i = 0; i < MD_CH; ++i) {
+          acc[i].x += (double)b[u][i].x * (double)we[u].x + (double)b[u][i].y * (double)we[u].y;
+          acc[i].y += (double)b[u][i].x * (double)we[u].y - (double)b[u][i].y * (double)we[u].x;
+        }
     }
     for (int i = 0; i < MD_CH; ++i) {
       double2 s = acc[i];

@@ -525,6 +525,36 @@ def test_schwarz_fgmres_matches_oracle(torch_dev, nesa):
     assert rep[0]["iters"] < 326 / 4
 
 
+@pytest.mark.parametrize("prec", ["split", "split_fp16"])
+def test_split_schwarz_fgmres_matches_complex64(torch_dev, nesa, prec):
+    """FGMRES with the Schwarz preconditioner on split operators (the
+    preconditioner set up on the device from the same near field) to 1e-5:
+    the iteration count and the solution of the complex64 operator's solve,
+    and the true residual of the split solve below the tolerance."""
+    torch = torch_dev
+    ref, tr, near, far = _case(nesa, "sphere_3lev")
+    b = efie.plane_wave_rhs(ref.m, [0, 0, 1], [1, 0, 0])
+    bd = torch.from_numpy(b).to(torch.complex64).cuda()
+    out = {}
+    for name, p in (("c64", nesa.C64), (prec, {"split": nesa.C64_SPLIT, "split_fp16": nesa.C64_SPLIT_FP16}[prec])):
+        op = nesa.op_create(tr, near, far, p)
+        nesa.precond_setup(op, nesa.PRECOND_SCHWARZ)
+        xd = torch.zeros_like(bd)
+        rc, rep, hist = nesa.gmres_solve(op, bd, xd, restart=30, max_iters=300, tol=1e-5,
+                                         precond=nesa.PRECOND_SCHWARZ, history_len=300, check=False)
+        print("%s: rc %d, %d iters, true residual %.2e, estimates %s" % (
+            name, rc, rep[0]["iters"], rep[0]["true_rel_residual"], np.array2string(hist[:rep[0]["iters"] + 1:10], precision=2)))
+        out[name] = (rc, rep[0], xd.cpu().numpy().astype(np.complex128))
+    (c64rc, r64, x64), (rcs, rs, xs) = out["c64"], out[prec]
+    dx = np.linalg.norm(xs - x64) / np.linalg.norm(x64)
+    print("Schwarz FGMRES: complex64 %d iters, %s %d iters, solutions differ %.2e, true residual %.2e"
+          % (r64["iters"], prec, rs["iters"], dx, rs["true_rel_residual"]))
+    assert c64rc == 0 and rcs == 0
+    assert abs(rs["iters"] - r64["iters"]) <= 3
+    assert rs["true_rel_residual"] <= 1e-5
+    assert dx <= 1e-4
+
+
 _forest = {}
 
 
@@ -544,12 +574,13 @@ def _forest_case(nesa):
     return _forest
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64", "split"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "split", "split_fp16"])
 def test_forest_matvec_matches_per_body_oracle(torch_dev, nesa, prec):
     """One product over a batch of uneven bodies (one launch per stage for all
-    of them) against each body's oracle product, for three right-hand sides."""
+    of them) against each body's oracle product, for three right-hand sides
+    (split fp16: one scale per level shared by bodies of very different sizes)."""
     f = _forest_case(nesa)
-    p = {"c128": nesa.C128, "c64": nesa.C64, "split": nesa.C64_SPLIT}[prec]
+    p = {"c128": nesa.C128, "c64": nesa.C64, "split": nesa.C64_SPLIT, "split_fp16": nesa.C64_SPLIT_FP16}[prec]
     op = nesa.op_create(f["tree"], f["near"], f["far"], p, max_nrhs=3)
     ptr = f["ptr"]
     X = synth.complex_normal((3, ptr[-1]), 50)
