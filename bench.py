@@ -697,7 +697,7 @@ def bodies_section(args, nesa, torch, prec, dt, stream):
     bodies = synth.body_family(args.bodies, seed=4)
     tree = nesa.build_forest([(v, t) for v, t, _ in bodies], 0.25)
     log("bodies: forest of %d unknowns built" % tree.info()["n_rwg"])
-    near = nesa.assemble_near(tree)
+    near = nesa.assemble_near_device(tree)      # near-field blocks assembled on the GPU
     log("bodies: near field assembled")
     far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
     log("bodies: far-field operators assembled")
