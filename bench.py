@@ -631,7 +631,7 @@ def aircraft_section(args, nesa, torch, stream):
             ach = tr_["flops"] / (tr_["ms"] * 1e-3)
             sec["translate_roofline"] = {"bound": "mfma", "achieved": round(ach / 1e12, 1),
                                          "peak": peak / 1e12, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                                         "kernel": "k_translate_tm_split" if prec == nesa.C64_SPLIT
+                                         "kernel": "k_translate_tm_split2" if prec == nesa.C64_SPLIT
                                          else "k_translate_tm"}
         out[name] = sec
         log("aircraft %s: %d right-hand sides, %.2f ms per product" % (name, R, ms))
@@ -866,12 +866,17 @@ def main():
     kd = kern[dom]
     sec = kd["ms"] * 1e-3
     if kd["bytes"] == 0 or dom.endswith("gemm") or dom.endswith("fp64"):
-        peak = PEAK_FP32 if prec != nesa.C128 else 78.6e12
+        # (split products: 16-bit matrix cores; their flops counted as complex
+        # FP32 products, the x3 form issues three times as many)
+        peak = 78.6e12 if prec == nesa.C128 else (PEAK_BF16 if prec in (nesa.C64_SPLIT, nesa.C64_SPLIT_FP16)
+                                                  else PEAK_FP32)
         roof = {"bound": "mfma", "achieved": kd["flops"] / sec / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": kd["bytes"] / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"translate_gemm": "k_translate_gemm", "near_recv": "k_near_half",
+    split_prec = prec in (nesa.C64_SPLIT, nesa.C64_SPLIT_FP16)
+    roof["kernel"] = {"translate_gemm": "k_translate_gemm_bf16x3 / k_gemm_om_split2" if split_prec
+                      else "k_translate_gemm", "near_recv": "k_near_half",
                       "upward_gemm": "k_transfer_gemm", "downward_gemm": "k_transfer_gemm"}.get(dom, dom)
     roof["traffic"] = profiled_traffic(roof["kernel"], args.precision)
     roof["launches_per_product"] = kd["launches"]
