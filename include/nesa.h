@@ -190,11 +190,14 @@ int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em,
 int nesa_far_get_q(const nesa_far* far, int* Q, int nmax);
 void nesa_far_free(nesa_far* far);
 
-/* Upload near and far operators to the current device in the given precision,
- * assemble V and D there, and allocate work buffers for up to max_nrhs
- * right-hand sides.  Products of one right-hand side read the near field in
- * reciprocity half storage (the blocks Z_ab of near leaves b >= a, Z_ba =
- * Z_ab^T); the full blocks are uploaded as well when max_nrhs > 1. */
+/* Upload near and far operators to the current device in the given precision
+ * (nesa_precision; EINVAL for any other value), assemble V and D there, and
+ * allocate work buffers for up to max_nrhs right-hand sides.  Products of one
+ * right-hand side read the near field in reciprocity half storage (the blocks
+ * Z_ab of near leaves b >= a, Z_ba = Z_ab^T); the full blocks are uploaded as
+ * well when max_nrhs > 1.  Split precisions also keep the 16-bit planes of the
+ * translation and transfer matrices, and per level a buffer for the sources
+ * split once per product (4 max_nrhs x Q rounded up to 32 values per box). */
 int nesa_op_create(const nesa_tree* tree, const nesa_near* near, const nesa_far* far,
                    int precision, int max_nrhs, nesa_op** out);
 void nesa_op_free(nesa_op* op);
