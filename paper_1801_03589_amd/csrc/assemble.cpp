@@ -20,6 +20,7 @@
 // k_fill_translation).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 
 #include "nesa_host.h"
@@ -507,6 +508,11 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
     const FarLevel& fp = F->lev[l - 1 - t.l0];
     const CMat& Rp = R[l - 1 - t.l0];
     const double a = t.level(l).side;
+    // on the device when there is one (NESA_C_HOST=1: on the host)
+    const char* on_host = std::getenv("NESA_C_HOST");
+    if (!(on_host && std::atoi(on_host) == 1) &&
+        transfer_matrices_device(Rp.a, fp.Q, fp.M, fp.X, fc.E, fc.Q, a, k, fc.Cup))
+      continue;
     fc.Cup.assign((size_t)8 * fp.Q * fc.Q, cd(0, 0));
     // G(X_p, E_c + delta) = g(|X_p - delta - E_c|) per octant (column-major, so
     // that column q is contiguous over the check points j)

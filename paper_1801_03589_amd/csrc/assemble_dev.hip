@@ -9,6 +9,7 @@
 // the plain integral.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <memory>
 #include <string>
 #include <vector>
@@ -276,7 +277,115 @@ std::vector<int32_t> i32(const std::vector<X>& v) {
   return std::vector<int32_t>(v.begin(), v.end());
 }
 
+// ------------------------------------------------------------------ transfer matrices
+// G_o[q][j] = g(X_j - delta_o - E_q), g = exp(-ikR) / (4 pi R) with R the
+// principal square root of the summed squared (complex) coordinate
+// differences; one thread per (o, q, j), j fastest.
+__global__ void k_fill_transfer_g(const double2* __restrict__ X, const double2* __restrict__ E, int Mp, int Qc,
+                                  double a, double k, double2* __restrict__ G) {
+  const int64_t i = (int64_t)blockIdx.x * NTA + threadIdx.x;
+  const int64_t total = (int64_t)8 * Qc * Mp;
+  if (i >= total) return;
+  const int j = (int)(i % Mp);
+  const int64_t rest = i / Mp;
+  const int q = (int)(rest % Qc), o = (int)(rest / Qc);
+  const double d[3] = {((o & 1) - 0.5) * a, (((o >> 1) & 1) - 0.5) * a, (((o >> 2) & 1) - 0.5) * a};
+  double zr = 0, zi = 0;
+  for (int c = 0; c < 3; ++c) {
+    const double er = X[3 * j + c].x - d[c] - E[3 * q + c].x;
+    const double ei = X[3 * j + c].y - E[3 * q + c].y;
+    zr += er * er - ei * ei;
+    zi += 2.0 * er * ei;
+  }
+  // principal square root of zr + i zi: the branch without cancellation first
+  const double m = hypot(zr, zi);
+  double sr, si;
+  if (zr >= 0) {
+    sr = sqrt(0.5 * (m + zr));
+    si = sr > 0 ? zi / (2.0 * sr) : 0.0;
+  } else {
+    si = sqrt(0.5 * (m - zr));
+    if (zi < 0) si = -si;
+    sr = zi / (2.0 * si);
+  }
+  // exp(-ik R) / (4 pi R) with R = sr + i si
+  const double ex = exp(k * si) / (4.0 * PI_D);
+  const double cr = ex * cos(k * sr), ci = -ex * sin(k * sr);      // exp(-ikR) / (4 pi)
+  const double den = sr * sr + si * si;
+  G[i] = make_double2((cr * sr + ci * si) / den, (ci * sr - cr * si) / den);
+}
+
+// cup[o][p][q] = sum_j R[j][p] G_o[q][j] (R column-major Qp x Mp): 32 x 32
+// output tiles, j in chunks of 16 staged in LDS, four outputs per thread,
+// FP64 complex sums in increasing j.
+constexpr int TG_T = 32, TG_K = 16;
+__global__ __launch_bounds__(NTA) void k_transfer_gemm_f64(const double2* __restrict__ R, const double2* __restrict__ G,
+                                                           int Qp, int Mp, int Qc, double2* __restrict__ cup) {
+  __shared__ double2 Rs[TG_K][TG_T];          // [j][p]
+  __shared__ double2 Gs[TG_T][TG_K + 1];      // [q][j]
+  const int o = blockIdx.z, p0 = blockIdx.y * TG_T, q0 = blockIdx.x * TG_T;
+  const int t = threadIdx.x, tp = t % TG_T, tq = (t / TG_T) * 4;   // 4 consecutive q per thread
+  const double2* Go = G + (size_t)o * Qc * Mp;
+  double2 acc[4];
+  for (int u = 0; u < 4; ++u) acc[u] = make_double2(0.0, 0.0);
+  for (int j0 = 0; j0 < Mp; j0 += TG_K) {
+    __syncthreads();
+    for (int e = t; e < TG_K * TG_T; e += NTA) {
+      const int jj = e / TG_T, pp = e % TG_T;
+      Rs[jj][pp] = (j0 + jj < Mp && p0 + pp < Qp) ? R[(size_t)(j0 + jj) * Qp + p0 + pp] : make_double2(0.0, 0.0);
+      const int qq = e / TG_K, jk = e % TG_K;
+      Gs[qq][jk] = (j0 + jk < Mp && q0 + qq < Qc) ? Go[(size_t)(q0 + qq) * Mp + j0 + jk] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < TG_K; ++jj) {
+      const double2 r = Rs[jj][tp];
+      for (int u = 0; u < 4; ++u) {
+        const double2 g = Gs[tq + u][jj];
+        acc[u].x += r.x * g.x - r.y * g.y;
+        acc[u].y += r.x * g.y + r.y * g.x;
+      }
+    }
+  }
+  for (int u = 0; u < 4; ++u)
+    if (p0 + tp < Qp && q0 + tq + u < Qc) cup[((size_t)o * Qp + p0 + tp) * Qc + q0 + tq + u] = acc[u];
+}
+
 }  // namespace
+
+bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const std::vector<cd>& X,
+                              const std::vector<cd>& E, int Qc, double a, double k, std::vector<cd>& cup) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();           // (no device: the caller computes on the host)
+    return false;
+  }
+  if ((int64_t)Rcm.size() != (int64_t)Qp * Mp || (int64_t)X.size() != 3 * (int64_t)Mp ||
+      (int64_t)E.size() != 3 * (int64_t)Qc)
+    throw Error(-1, "transfer matrix operand sizes");
+  DevBuffers buf;
+  const double2* Rd = reinterpret_cast<const double2*>(buf.put(Rcm));
+  const double2* Xd = reinterpret_cast<const double2*>(buf.put(X));
+  const double2* Ed = reinterpret_cast<const double2*>(buf.put(E));
+  void* Gd = nullptr;
+  void* Cd = nullptr;
+  const int64_t ng = (int64_t)8 * Qc * Mp, nc = (int64_t)8 * Qp * Qc;
+  check(hipMalloc(&Gd, std::max<size_t>(ng * sizeof(cd), 16)), "hipMalloc");
+  buf.p.push_back(Gd);
+  check(hipMalloc(&Cd, std::max<size_t>(nc * sizeof(cd), 16)), "hipMalloc");
+  buf.p.push_back(Cd);
+  cup.assign(nc, cd(0, 0));
+  if (ng > 0) {
+    k_fill_transfer_g<<<(unsigned)((ng + NTA - 1) / NTA), NTA>>>(Xd, Ed, Mp, Qc, a, k, static_cast<double2*>(Gd));
+    check(hipGetLastError(), "kernel launch");
+  }
+  if (nc > 0) {
+    const dim3 grid((unsigned)((Qc + TG_T - 1) / TG_T), (unsigned)((Qp + TG_T - 1) / TG_T), 8);
+    k_transfer_gemm_f64<<<grid, NTA>>>(Rd, static_cast<const double2*>(Gd), Qp, Mp, Qc, static_cast<double2*>(Cd));
+    check(hipGetLastError(), "kernel launch");
+    check(hipMemcpy(cup.data(), Cd, nc * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");
+  }
+  return true;
+}
 
 Near* assemble_near_device(const Tree& t, double k, double eta) {
   std::unique_ptr<Near> N(new Near());

@@ -121,6 +121,14 @@ Near* assemble_near(const Tree& t, double k, double eta);
 // the same blocks computed on the current device (FP64) and copied back
 Near* assemble_near_device(const Tree& t, double k, double eta);
 Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double tau, double eps);
+// Transfer matrices of one pair of levels on the current device (FP64, Sec. 3,
+// Eq. 11): cup[o][p][q] = sum_j R(p, j) g(X_j - delta_o - E_q) for the eight
+// child octants o (delta_o = (+-a/2, +-a/2, +-a/2), a the child box side), R
+// the parent's fitting operator column-major (Qp x Mp), X its Mp check points
+// and E the child's Qc equivalent points ([n][3], complex); cup row-major
+// [8][Qp][Qc].  Returns false, leaving cup untouched, when no device is present.
+bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const std::vector<cd>& X,
+                              const std::vector<cd>& E, int Qc, double a, double k, std::vector<cd>& cup);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);
 // Rows of the restricted near-field inverses (Schwarz preconditioner), in the

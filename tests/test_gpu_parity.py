@@ -525,6 +525,29 @@ def test_schwarz_fgmres_matches_oracle(torch_dev, nesa):
     assert rep[0]["iters"] < 326 / 4
 
 
+@pytest.mark.parametrize("name", ["sphere1_nested", "sphere_2lev", "sphere_3lev"])
+def test_transfer_matrices_device_match_host(torch_dev, nesa, monkeypatch, name):
+    """The transfer matrices C (Sec. 3, Eq. 11) computed on the device (FP64
+    Green's function between the parent's check points and the child's
+    equivalent points, times the parent's fitting operator) against the
+    host's loops (NESA_C_HOST=1): complex128 products of the two operators agree
+    to 1e-12, and both match the oracle."""
+    ref, tr, near, _ = _case(nesa, name)
+    far_dev = nesa.assemble_translations(tr, d0=3, tau=1e-8)
+    monkeypatch.setenv("NESA_C_HOST", "1")
+    far_host = nesa.assemble_translations(tr, d0=3, tau=1e-8)
+    monkeypatch.delenv("NESA_C_HOST")
+    x = synth.complex_normal(ref.m.n, 6)
+    yd = _run(torch_dev, nesa, nesa.op_create(tr, near, far_dev, nesa.C128), x)
+    yh = _run(torch_dev, nesa, nesa.op_create(tr, near, far_host, nesa.C128), x)
+    yr = ref.matvec(x)
+    d = np.linalg.norm(yd - yh) / np.linalg.norm(yh)
+    e = np.linalg.norm(yd - yr) / np.linalg.norm(yr)
+    print("%s: device vs host transfer matrices, products differ %.2e; device vs oracle %.2e" % (name, d, e))
+    assert d <= 1e-12
+    assert e <= TOL["c128"]
+
+
 @pytest.mark.parametrize("prec", ["split", "split_fp16"])
 def test_split_schwarz_fgmres_matches_complex64(torch_dev, nesa, prec):
     """FGMRES with the Schwarz preconditioner on split operators (the
