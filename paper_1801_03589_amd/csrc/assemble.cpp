@@ -303,7 +303,8 @@ static CMat gmat(const std::vector<cd>& A, P3 shift, const std::vector<cd>& B, d
   int64_t na = A.size() / 3, nb = B.size() / 3;
   CMat G(na, nb);
   const double sh[3] = {shift.x, shift.y, shift.z};
-  for (int64_t j = 0; j < nb; ++j)
+  // (threads only where the matrix is large enough to pay for them)
+  auto col = [&](int64_t j) {
     for (int64_t i = 0; i < na; ++i) {
       cd r2 = 0;
       for (int d = 0; d < 3; ++d) {
@@ -313,6 +314,11 @@ static CMat gmat(const std::vector<cd>& A, P3 shift, const std::vector<cd>& B, d
       cd R = std::sqrt(r2);
       G(i, j) = std::exp(cd(0.0, -k) * R) / (4.0 * PI * R);
     }
+  };
+  if (na * nb >= ((int64_t)1 << 16))
+    parallel_for(nb, col);
+  else
+    for (int64_t j = 0; j < nb; ++j) col(j);
   return G;
 }
 
@@ -358,13 +364,26 @@ static double sigma_max(const CMat& G) {
   double est = 0;
   for (int j = 0; j < kmax; ++j) {
     qs.push_back(q);
-    for (int64_t i = 0; i < M; ++i) u[i] = 0;
-    for (int64_t c = 0; c < Q; ++c)
-      for (int64_t i = 0; i < M; ++i) u[i] += G(i, c) * q[c];
-    for (int64_t c = 0; c < Q; ++c) {
+    // u = G q by blocks of rows, w = G^H u by columns (every sum in the same
+    // order as one loop over the whole matrix)
+    constexpr int64_t RB = 256;
+    auto rows = [&](int64_t rb) {
+      const int64_t i0 = rb * RB, i1 = std::min(M, i0 + RB);
+      for (int64_t i = i0; i < i1; ++i) u[i] = 0;
+      for (int64_t c = 0; c < Q; ++c)
+        for (int64_t i = i0; i < i1; ++i) u[i] += G(i, c) * q[c];
+    };
+    auto cols = [&](int64_t c) {
       cd s = 0;
       for (int64_t i = 0; i < M; ++i) s += std::conj(G(i, c)) * u[i];
       w[c] = s;
+    };
+    if (M * Q >= ((int64_t)1 << 18)) {
+      parallel_for((M + RB - 1) / RB, rows);
+      parallel_for(Q, cols);
+    } else {
+      for (int64_t rb = 0; rb < (M + RB - 1) / RB; ++rb) rows(rb);
+      for (int64_t c = 0; c < Q; ++c) cols(c);
     }
     cd aj = 0;
     for (int64_t c = 0; c < Q; ++c) aj += std::conj(q[c]) * w[c];
@@ -396,6 +415,12 @@ static double sigma_max(const CMat& G) {
 static CMat tikhonov_fit(const CMat& G, double tau) {
   const int64_t M = G.m, Q = G.n, m = M + Q;
   const double lam = tau * sigma_max(G);
+  // the same steps on the device when there is one (NESA_FIT_HOST=1: here)
+  const char* on_host = std::getenv("NESA_FIT_HOST");
+  if (!(on_host && std::atoi(on_host) == 1)) {
+    CMat X(Q, M);
+    if (tikhonov_fit_device(G.a, M, Q, lam, X.a)) return X;
+  }
   CMat A(m, Q);
   for (int64_t j = 0; j < Q; ++j) {
     for (int64_t i = 0; i < M; ++i) A(i, j) = G(i, j);

@@ -350,6 +350,112 @@ __global__ __launch_bounds__(NTA) void k_transfer_gemm_f64(const double2* __rest
     if (p0 + tp < Qp && q0 + tq + u < Qc) cup[((size_t)o * Qp + p0 + tp) * Qc + q0 + tq + u] = acc[u];
 }
 
+// ------------------------------------------------------------------ Tikhonov fits
+// Householder QR of the stacked matrix A = [G; lambda I] (m = M + Q rows, Q
+// columns, column-major), one reflector per column in order, the thin
+// orthogonal factor accumulated backwards from [I_Q; 0], then the fitting
+// operator X = R^-1 Q^H [I_M; 0] by back substitution.  FP64 complex; the sums
+// over rows are workgroup reductions.
+constexpr int NTF = 256;
+
+// complex sum over the workgroup, returned to every thread (red: NTF / 64 slots)
+__device__ double2 fit_wg_sum(double2 v, double2* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();                    // earlier reads of red are done
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double2 s = red[0];
+  for (int i = 1; i < NTF / 64; ++i) {
+    s.x += red[i].x;
+    s.y += red[i].y;
+  }
+  return s;
+}
+
+// reflector of column j (one workgroup): with x = A[j:, j] and
+// alpha = -(x_0 / |x_0|) |x| (-|x| for x_0 = 0), v = (x - alpha e_1) / |x - alpha e_1|
+// into rows j .. m-1 of column j of V
+__global__ __launch_bounds__(NTF) void k_fit_reflector(const double2* __restrict__ A, int64_t m, int j,
+                                                       double2* __restrict__ V) {
+  __shared__ double2 red[NTF / 64];
+  const double2* a = A + (int64_t)j * m;
+  double2* v = V + (int64_t)j * m;
+  double2 p = make_double2(0.0, 0.0);
+  for (int64_t i = j + threadIdx.x; i < m; i += NTF) {
+    const double2 x = a[i];
+    p.x += x.x * x.x + x.y * x.y;
+  }
+  const double nx = sqrt(fit_wg_sum(p, red).x);
+  const double2 x0 = a[j];
+  const double ax0 = hypot(x0.x, x0.y);
+  const double2 alpha = ax0 > 0 ? make_double2(-x0.x / ax0 * nx, -x0.y / ax0 * nx) : make_double2(-nx, 0.0);
+  double2 q = make_double2(0.0, 0.0);
+  for (int64_t i = j + threadIdx.x; i < m; i += NTF) {
+    double2 x = a[i];
+    if (i == j) x = make_double2(x.x - alpha.x, x.y - alpha.y);
+    q.x += x.x * x.x + x.y * x.y;
+  }
+  const double nv = sqrt(fit_wg_sum(q, red).x);
+  for (int64_t i = j + threadIdx.x; i < m; i += NTF) {
+    double2 x = a[i];
+    if (i == j) x = make_double2(x.x - alpha.x, x.y - alpha.y);
+    if (nv > 0) x = make_double2(x.x / nv, x.y / nv);
+    v[i] = x;
+  }
+}
+
+// B[j:, c] -= 2 v (v^H B[j:, c]) for column c = c0 + blockIdx.x of B (m rows),
+// v = rows j .. m-1 of column j of V
+__global__ __launch_bounds__(NTF) void k_fit_reflect(double2* __restrict__ B, int64_t m, int j, int c0,
+                                                     const double2* __restrict__ V) {
+  __shared__ double2 red[NTF / 64];
+  const double2* v = V + (int64_t)j * m;
+  double2* b = B + (int64_t)(c0 + (int)blockIdx.x) * m;
+  double2 p = make_double2(0.0, 0.0);
+  for (int64_t i = j + threadIdx.x; i < m; i += NTF) {
+    const double2 vi = v[i], bi = b[i];
+    p.x += vi.x * bi.x + vi.y * bi.y;
+    p.y += vi.x * bi.y - vi.y * bi.x;
+  }
+  double2 s = fit_wg_sum(p, red);
+  s = make_double2(2.0 * s.x, 2.0 * s.y);
+  for (int64_t i = j + threadIdx.x; i < m; i += NTF) {
+    const double2 vi = v[i];
+    double2 bi = b[i];
+    bi.x -= vi.x * s.x - vi.y * s.y;
+    bi.y -= vi.x * s.y + vi.y * s.x;
+    b[i] = bi;
+  }
+}
+
+// X = R^-1 Y, R the upper triangle of A (Q x Q), Y(i, col) = conj(Qt(col, i))
+// for the M columns: one thread per column, rows from the last up, FP64
+// complex sums in increasing column of R; Xt row-major (Q x M), so that the
+// threads of a wave touch consecutive entries
+constexpr int NTS = 64;
+__global__ __launch_bounds__(NTS) void k_fit_solve(const double2* __restrict__ A, const double2* __restrict__ Qt,
+                                                   int64_t m, int Q, int M, double2* __restrict__ Xt) {
+  const int col = blockIdx.x * NTS + threadIdx.x;
+  if (col >= M) return;
+  for (int i = Q - 1; i >= 0; --i) {
+    const double2 y = Qt[(int64_t)i * m + col];
+    double sx = y.x, sy = -y.y;
+    for (int c = i + 1; c < Q; ++c) {
+      const double2 r = A[(int64_t)c * m + i];
+      const double2 x = Xt[(int64_t)c * M + col];
+      sx -= r.x * x.x - r.y * x.y;
+      sy -= r.x * x.y + r.y * x.x;
+    }
+    const double2 d = A[(int64_t)i * m + i];
+    const double den = d.x * d.x + d.y * d.y;
+    Xt[(int64_t)i * M + col] = make_double2((sx * d.x + sy * d.y) / den, (sy * d.x - sx * d.y) / den);
+  }
+}
+
 }  // namespace
 
 bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const std::vector<cd>& X,
@@ -384,6 +490,49 @@ bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const 
     check(hipGetLastError(), "kernel launch");
     check(hipMemcpy(cup.data(), Cd, nc * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");
   }
+  return true;
+}
+
+bool tikhonov_fit_device(const std::vector<cd>& G, int64_t M, int64_t Q, double lam, std::vector<cd>& X) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();           // (no device: the caller computes on the host)
+    return false;
+  }
+  if ((int64_t)G.size() != M * Q || M < 1 || Q < 1 || (M + Q) * Q > (int64_t)1 << 31)
+    throw Error(-1, "fit operand sizes");
+  const int64_t m = M + Q;
+  // A = [G; lambda I] and the start [I_Q; 0] of the orthogonal factor
+  std::vector<cd> A((size_t)(m * Q), cd(0, 0)), Qt((size_t)(m * Q), cd(0, 0));
+  for (int64_t j = 0; j < Q; ++j) {
+    std::copy(G.begin() + j * M, G.begin() + (j + 1) * M, A.begin() + j * m);
+    A[(size_t)(j * m + M + j)] = lam;
+    Qt[(size_t)(j * m + j)] = 1.0;
+  }
+  DevBuffers buf;
+  double2* Ad = reinterpret_cast<double2*>(const_cast<cd*>(buf.put(A)));
+  double2* Qd = reinterpret_cast<double2*>(const_cast<cd*>(buf.put(Qt)));
+  void* Vd = nullptr;
+  void* Xd = nullptr;
+  check(hipMalloc(&Vd, (size_t)(m * Q) * sizeof(cd)), "hipMalloc");
+  buf.p.push_back(Vd);
+  check(hipMalloc(&Xd, (size_t)(Q * M) * sizeof(cd)), "hipMalloc");
+  buf.p.push_back(Xd);
+  double2* V = static_cast<double2*>(Vd);
+  for (int j = 0; j < (int)Q; ++j) {
+    k_fit_reflector<<<1, NTF>>>(Ad, m, j, V);
+    k_fit_reflect<<<(unsigned)(Q - j), NTF>>>(Ad, m, j, j, V);
+  }
+  // columns left of j are still unit vectors with zero rows from j on
+  for (int j = (int)Q - 1; j >= 0; --j) k_fit_reflect<<<(unsigned)(Q - j), NTF>>>(Qd, m, j, j, V);
+  double2* Xt = static_cast<double2*>(Xd);
+  k_fit_solve<<<(unsigned)((M + NTS - 1) / NTS), NTS>>>(Ad, Qd, m, (int)Q, (int)M, Xt);
+  check(hipGetLastError(), "kernel launch");
+  std::vector<cd> xt((size_t)(Q * M));
+  check(hipMemcpy(xt.data(), Xt, xt.size() * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");
+  X.assign((size_t)(Q * M), cd(0, 0));
+  for (int64_t i = 0; i < Q; ++i)
+    for (int64_t col = 0; col < M; ++col) X[(size_t)(col * Q + i)] = xt[(size_t)(i * M + col)];
   return true;
 }
 

@@ -129,6 +129,13 @@ Far* assemble_far(const Tree& t, double k, double eta, int d0, int q_min, double
 // [8][Qp][Qc].  Returns false, leaving cup untouched, when no device is present.
 bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const std::vector<cd>& X,
                               const std::vector<cd>& E, int Qc, double a, double k, std::vector<cd>& cup);
+// Fitting operator of one level on the current device (FP64; Sec. 2 matches
+// the equivalent sources to the field on a test surface, read here as the
+// Tikhonov-regularised least-squares fit X = argmin ||G X - I_M||^2 +
+// lam^2 ||X||^2), by Householder QR of [G; lam I]; G column-major (M x Q), X
+// column-major (Q x M).  Returns false, leaving X untouched, when no device
+// is present.
+bool tikhonov_fit_device(const std::vector<cd>& G, int64_t M, int64_t Q, double lam, std::vector<cd>& X);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);
 // Rows of the restricted near-field inverses (Schwarz preconditioner), in the

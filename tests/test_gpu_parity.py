@@ -548,6 +548,29 @@ def test_transfer_matrices_device_match_host(torch_dev, nesa, monkeypatch, name)
     assert e <= TOL["c128"]
 
 
+@pytest.mark.parametrize("name", ["sphere1_nested", "sphere_2lev", "sphere_3lev"])
+def test_fits_device_match_host(torch_dev, nesa, monkeypatch, name):
+    """The fitting operators (Householder QR of [G; lambda I], one per level)
+    computed on the device against the host's loops (NESA_FIT_HOST=1): every
+    operator built from them (radiation V, transfers C) follows, so complex128
+    products of the two far operators agree to 1e-12, and both match the
+    oracle, whose fit is the SVD form of the same Tikhonov pseudo-inverse."""
+    ref, tr, near, _ = _case(nesa, name)
+    far_dev = nesa.assemble_translations(tr, d0=3, tau=1e-8)
+    monkeypatch.setenv("NESA_FIT_HOST", "1")
+    far_host = nesa.assemble_translations(tr, d0=3, tau=1e-8)
+    monkeypatch.delenv("NESA_FIT_HOST")
+    x = synth.complex_normal(ref.m.n, 7)
+    yd = _run(torch_dev, nesa, nesa.op_create(tr, near, far_dev, nesa.C128), x)
+    yh = _run(torch_dev, nesa, nesa.op_create(tr, near, far_host, nesa.C128), x)
+    yr = ref.matvec(x)
+    d = np.linalg.norm(yd - yh) / np.linalg.norm(yh)
+    e = np.linalg.norm(yd - yr) / np.linalg.norm(yr)
+    print("%s: device vs host fits, products differ %.2e; device vs oracle %.2e" % (name, d, e))
+    assert d <= 1e-12
+    assert e <= TOL["c128"]
+
+
 @pytest.mark.parametrize("prec", ["split", "split_fp16"])
 def test_split_schwarz_fgmres_matches_complex64(torch_dev, nesa, prec):
     """FGMRES with the Schwarz preconditioner on split operators (the
