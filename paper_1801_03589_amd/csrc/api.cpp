@@ -112,11 +112,16 @@ static void* dev_alloc(nesa_op* op, size_t bytes) {
 
 template <typename T>
 static void* upload_complex(nesa_op* op, const std::vector<cd>& h) {
+  // conversion in chunks on the host's threads (near fields reach 10^9 entries)
   std::vector<T> buf(2 * h.size());
-  for (size_t i = 0; i < h.size(); ++i) {
-    buf[2 * i] = (T)h[i].real();
-    buf[2 * i + 1] = (T)h[i].imag();
-  }
+  constexpr int64_t CH = 1 << 20;
+  const int64_t n = (int64_t)h.size();
+  nesa::parallel_for((n + CH - 1) / CH, [&](int64_t c) {
+    for (int64_t i = c * CH; i < std::min(n, (c + 1) * CH); ++i) {
+      buf[2 * i] = (T)h[i].real();
+      buf[2 * i + 1] = (T)h[i].imag();
+    }
+  });
   return upload(op, buf);
 }
 
@@ -617,14 +622,20 @@ static void build_dev(nesa_op* op, nesa::DevOp<T>& d, const nesa::Tree& t, const
     for (int64_t b = 0; b < nleaf; ++b)
       for (int64_t k = t.near_ptr[b]; k < nh[b]; ++k)
         if (tsrc[k] < 0) throw Error(NESA_EINVAL, "transposed near block without a slot");
-    std::vector<cd> zh(zh_off[nleaf]);
+    // the half blocks, converted to T on the way
+    std::vector<T> zh(2 * zh_off[nleaf]);
     nesa::parallel_for(nleaf, [&](int64_t a) {
       const int64_t S = t.leaf_ptr[a + 1] - t.leaf_ptr[a];
-      std::copy(nr.z.begin() + nr.off[a] + col0[a] * S, nr.z.begin() + nr.off[a + 1], zh.begin() + zh_off[a]);
+      const cd* z = nr.z.data() + nr.off[a] + col0[a] * S;
+      T* o = zh.data() + 2 * zh_off[a];
+      for (int64_t i = 0; i < zh_off[a + 1] - zh_off[a]; ++i) {
+        o[2 * i] = (T)z[i].real();
+        o[2 * i + 1] = (T)z[i].imag();
+      }
     });
     d.nh_ptr = upload(op, nh);
     d.zh_off = upload(op, zh_off);
-    d.Zh = upload_complex<T>(op, zh);
+    d.Zh = upload(op, zh);
     std::vector<int32_t> to32(toff.begin(), toff.end() - 1);
     d.toff = upload(op, to32);
     d.tsrc = upload(op, tsrc);
