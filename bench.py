@@ -694,16 +694,22 @@ def bodies_section(args, nesa, torch, prec, dt, stream):
     if args.bodies <= 0:
         return None
     t0 = time.perf_counter()
+    parts = {}
     bodies = synth.body_family(args.bodies, seed=4)
+    parts["meshes_s"] = time.perf_counter() - t0
     tree = nesa.build_forest([(v, t) for v, t, _ in bodies], 0.25)
+    parts["forest_s"] = time.perf_counter() - t0 - sum(parts.values())
     log("bodies: forest of %d unknowns built" % tree.info()["n_rwg"])
     near = nesa.assemble_near_device(tree)      # near-field blocks assembled on the GPU
+    parts["near_s"] = time.perf_counter() - t0 - sum(parts.values())
     log("bodies: near field assembled")
     far = nesa.assemble_translations(tree, d0=3, tau=1e-8)
+    parts["far_s"] = time.perf_counter() - t0 - sum(parts.values())
     log("bodies: far-field operators assembled")
     R = max(1, args.nrhs)
     op = nesa.op_create(tree, near, far, prec, max_nrhs=R)
     del near, far
+    parts["op_s"] = time.perf_counter() - t0 - sum(parts.values())
     log("bodies: operator on the GPU")
     setup = time.perf_counter() - t0
     info = tree.info()
@@ -725,7 +731,8 @@ def bodies_section(args, nesa, torch, prec, dt, stream):
     sizes = [len(t) * 3 // 2 for _, t, _ in bodies]
     return {"bodies": args.bodies, "nrhs": R, "n_unknowns": n, "min_body": min(sizes), "max_body": max(sizes),
             "levels": [info["l0"], info["L"]], "ms_per_product": round(ms, 4),
-            "Munknowns_matvec_per_s": round(n * R / (ms * 1e-3) / 1e6, 2), "setup_s": round(setup, 1)}
+            "Munknowns_matvec_per_s": round(n * R / (ms * 1e-3) / 1e6, 2), "setup_s": round(setup, 1),
+            "setup_parts_s": {k: round(v, 2) for k, v in parts.items()}}
 
 
 def synth_rhs(n, nrhs):

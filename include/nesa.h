@@ -180,10 +180,14 @@ void nesa_near_free(nesa_near* near);
 
 /* Far-field operators (Sec. 2, Eq. 4-7): per level the equivalent and check
  * points and the Tikhonov fitting operator, and the transfer matrices C (and
- * B = C^T), computed on the host; the radiation matrices V (U = V^T) and the
- * translation matrices D are assembled on the device by nesa_op_create from
- * what this call records (the finest level's fitting operator, the points, the
- * offsets that occur).  Host-only. */
+ * B = C^T); the fits and C are computed in FP64 on the current device when
+ * there is one (environment NESA_FIT_HOST=1, NESA_C_HOST=1: on the host; the
+ * results agree to rounding), on the host otherwise, and copied into the host
+ * handle.  The radiation matrices V (U = V^T) and the translation matrices D
+ * are assembled on the device by nesa_op_create from what this call records
+ * (the finest level's fitting operator, the points, the offsets that occur).
+ * Errors: NESA_EINVAL for bad parameters, NESA_EMESH for a mesh too coarse for
+ * the leaf size, NESA_EHIP when a device call fails, NESA_ENOMEM. */
 int nesa_assemble_translations(const nesa_tree* tree, const nesa_em_params* em,
                                const nesa_far_params* params, nesa_far** out);
 /* Q of every level l0..L into Q[0 .. nmax-1]. */
