@@ -433,26 +433,35 @@ __global__ __launch_bounds__(NTF) void k_fit_reflect(double2* __restrict__ B, in
 }
 
 // X = R^-1 Y, R the upper triangle of A (Q x Q), Y(i, col) = conj(Qt(col, i))
-// for the M columns: one thread per column, rows from the last up, FP64
-// complex sums in increasing column of R; Xt row-major (Q x M), so that the
-// threads of a wave touch consecutive entries
+// for the M columns: one wave per column, y in LDS, rows from the last up;
+// each step divides by the diagonal and takes the row's multiple of column i
+// of R (contiguous above the diagonal) from the rows above it, the lanes
+// sharing those rows.  Xt row-major (Q x M).  Dynamic LDS: Q complex values.
 constexpr int NTS = 64;
 __global__ __launch_bounds__(NTS) void k_fit_solve(const double2* __restrict__ A, const double2* __restrict__ Qt,
                                                    int64_t m, int Q, int M, double2* __restrict__ Xt) {
-  const int col = blockIdx.x * NTS + threadIdx.x;
-  if (col >= M) return;
+  extern __shared__ double2 fit_y[];
+  const int col = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < Q; i += NTS) {
+    const double2 q = Qt[(int64_t)i * m + col];
+    fit_y[i] = make_double2(q.x, -q.y);
+  }
+  __syncthreads();
   for (int i = Q - 1; i >= 0; --i) {
-    const double2 y = Qt[(int64_t)i * m + col];
-    double sx = y.x, sy = -y.y;
-    for (int c = i + 1; c < Q; ++c) {
-      const double2 r = A[(int64_t)c * m + i];
-      const double2 x = Xt[(int64_t)c * M + col];
-      sx -= r.x * x.x - r.y * x.y;
-      sy -= r.x * x.y + r.y * x.x;
-    }
     const double2 d = A[(int64_t)i * m + i];
+    const double2 s = fit_y[i];
     const double den = d.x * d.x + d.y * d.y;
-    Xt[(int64_t)i * M + col] = make_double2((sx * d.x + sy * d.y) / den, (sy * d.x - sx * d.y) / den);
+    const double2 x = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+    if (lane == 0) Xt[(int64_t)i * M + col] = x;
+    const double2* r = A + (int64_t)i * m;
+    for (int j = lane; j < i; j += NTS) {
+      const double2 a = r[j];
+      double2 v = fit_y[j];
+      v.x -= a.x * x.x - a.y * x.y;
+      v.y -= a.x * x.y + a.y * x.x;
+      fit_y[j] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -501,6 +510,7 @@ bool tikhonov_fit_device(const std::vector<cd>& G, int64_t M, int64_t Q, double 
   }
   if ((int64_t)G.size() != M * Q || M < 1 || Q < 1 || (M + Q) * Q > (int64_t)1 << 31)
     throw Error(-1, "fit operand sizes");
+  if (Q > 4096) return false;          // (the solve keeps a column of Q values in LDS: larger fits on the host)
   const int64_t m = M + Q;
   // A = [G; lambda I] and the start [I_Q; 0] of the orthogonal factor
   std::vector<cd> A((size_t)(m * Q), cd(0, 0)), Qt((size_t)(m * Q), cd(0, 0));
@@ -526,7 +536,7 @@ bool tikhonov_fit_device(const std::vector<cd>& G, int64_t M, int64_t Q, double 
   // columns left of j are still unit vectors with zero rows from j on
   for (int j = (int)Q - 1; j >= 0; --j) k_fit_reflect<<<(unsigned)(Q - j), NTF>>>(Qd, m, j, j, V);
   double2* Xt = static_cast<double2*>(Xd);
-  k_fit_solve<<<(unsigned)((M + NTS - 1) / NTS), NTS>>>(Ad, Qd, m, (int)Q, (int)M, Xt);
+  k_fit_solve<<<(unsigned)M, NTS, (size_t)Q * sizeof(double2)>>>(Ad, Qd, m, (int)Q, (int)M, Xt);
   check(hipGetLastError(), "kernel launch");
   std::vector<cd> xt((size_t)(Q * M));
   check(hipMemcpy(xt.data(), Xt, xt.size() * sizeof(cd), hipMemcpyDeviceToHost), "hipMemcpy");

@@ -134,7 +134,7 @@ bool transfer_matrices_device(const std::vector<cd>& Rcm, int Qp, int Mp, const 
 // Tikhonov-regularised least-squares fit X = argmin ||G X - I_M||^2 +
 // lam^2 ||X||^2), by Householder QR of [G; lam I]; G column-major (M x Q), X
 // column-major (Q x M).  Returns false, leaving X untouched, when no device
-// is present.
+// is present or Q exceeds 4096.
 bool tikhonov_fit_device(const std::vector<cd>& G, int64_t M, int64_t Q, double lam, std::vector<cd>& X);
 void plane_wave_rhs(const Tree& t, double k, const double* khat, const double* pol,
                     cd* b_canonical);
